@@ -1,0 +1,227 @@
+"""CPU oracle for the register-state dataflow analysis -- TEST INFRASTRUCTURE.
+
+Only tests/, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product path (the HIP library and
+its binding) never does.  The oracle is plain C (``dc_oracle.c``), compiled
+with gcc, and shares no code with the GPU path; this module is its ctypes
+wrapper.
+
+Parity: pinned by tests/test_oracle_*.py (the paper's worked statements,
+textbook basic blocks, meet-over-all-paths for the distributive tiers,
+schedule independence, lattice laws).  The payload tier beyond those pins is
+"parity unpinned" except for the invariants listed in the design doc.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("DC_ORACLE_LIB") or os.path.join(HERE, "libdcoracle.so")
+SRC = os.path.join(HERE, "dc_oracle.c")
+
+NSLOT = 368
+SLOT_DTYPE = np.dtype([("prov", "<u4"), ("type", "u1"), ("flags", "u1"), ("pad0", "u1"), ("pad1", "u1"),
+                       ("val", "<u8")])
+ACCESS_DTYPE = np.dtype([("instr", "<u4"), ("kind", "u1"), ("space", "u1"), ("width", "u1"), ("dtype", "u1"),
+                         ("addr", "<u8")])
+SYSVAL_DTYPE = np.dtype([("instr", "<u4"), ("slot", "<u2"), ("kind", "u1"), ("dim", "u1")])
+SUMMARY_DTYPE = np.dtype([("status", "<i4"), ("n_blocks", "<u4"), ("sweeps", "<u4"), ("n_acc", "<u4"),
+                          ("n_sys", "<u4"), ("pad", "<u4"), ("digest", "<u8")])
+assert SLOT_DTYPE.itemsize == 16 and ACCESS_DTYPE.itemsize == 16 and SYSVAL_DTYPE.itemsize == 8
+assert SUMMARY_DTYPE.itemsize == 32
+
+OK, E_BADOP, E_BADREG, E_BADTARGET, E_NOEND, E_UNSUPPORTED, E_NOFIX = 0, -10, -11, -12, -13, -14, -15
+TOP = 0xFFFFFFFFFFFFFFFF
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("n_blocks", ctypes.c_uint32), ("n_reach", ctypes.c_uint32),
+                ("sweeps", ctypes.c_uint32), ("n_acc", ctypes.c_uint32), ("n_sys", ctypes.c_uint32),
+                ("n_pred", ctypes.c_uint32), ("digest", ctypes.c_uint64),
+                ("block_start", ctypes.c_void_p), ("succ", ctypes.c_void_p), ("pred_off", ctypes.c_void_p),
+                ("pred", ctypes.c_void_p), ("rpo", ctypes.c_void_p), ("in_states", ctypes.c_void_p),
+                ("reached", ctypes.c_void_p), ("acc", ctypes.c_void_p), ("sys", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def build(force: bool = False, extra=()) -> str:
+    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC):
+        tmp = LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-Wall", *extra, "-o", tmp, SRC])
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = ctypes.CDLL(LIB_PATH)
+        L.or_n_ops.restype = ctypes.c_int
+        L.or_op_name.restype = ctypes.c_char_p
+        L.or_op_name.argtypes = [ctypes.c_int]
+        L.or_kernel_status.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        L.or_kernel_status.restype = ctypes.c_int
+        L.or_analyze.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int,
+                                 ctypes.c_uint64, ctypes.POINTER(_Result)]
+        L.or_analyze.restype = ctypes.c_int
+        L.or_analyze_batch.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]
+        L.or_apply_path.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_uint32, ctypes.c_void_p]
+        L.or_apply_path.restype = ctypes.c_int
+        L.or_apply_path_from.argtypes = L.or_apply_path.argtypes
+        L.or_apply_path_from.restype = ctypes.c_int
+        L.or_check_record.argtypes = [ctypes.c_void_p, ctypes.c_uint32]
+        L.or_check_record.restype = ctypes.c_int
+        L.or_entry_state.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        L.or_transfer.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.or_join.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        _lib = L
+    return _lib
+
+
+def op_names():
+    L = lib()
+    return [L.or_op_name(i).decode() for i in range(L.or_n_ops())]
+
+
+def _ptr(a):
+    return a.ctypes.data if a is not None and a.size else None
+
+
+def _desc(desc):
+    from dcgen import KERNEL_DTYPE
+    d = np.array(desc, KERNEL_DTYPE).reshape(1).copy()
+    return d
+
+
+def kernel_status(recs, desc) -> int:
+    d = _desc(desc)
+    recs = np.ascontiguousarray(recs)
+    return lib().or_kernel_status(d.ctypes.data, _ptr(recs))
+
+
+def analyze(recs, desc, args, sweep_cap: int = 0, schedule: int = 0, seed: int = 0, states: bool = True) -> dict:
+    """Analyse one kernel. Returns a dict of numpy arrays (CFG, IN states,
+    accesses, system values) plus status, sweeps and digest."""
+    d = _desc(desc)
+    n = int(d[0]["n_instr"])
+    recs = np.ascontiguousarray(recs)
+    args = np.ascontiguousarray(args)
+    cap = max(n, 1)
+    bs = np.zeros(cap + 1, np.uint32)
+    succ = np.zeros(2 * cap, np.int32)
+    po = np.zeros(cap + 1, np.uint32)
+    pred = np.zeros(2 * cap, np.uint32)
+    rpo = np.zeros(cap, np.uint32)
+    st = np.zeros(cap * NSLOT if states else 0, SLOT_DTYPE)
+    reached = np.zeros(cap, np.uint8)
+    acc = np.zeros(cap, ACCESS_DTYPE)
+    sys = np.zeros(4 * cap, SYSVAL_DTYPE)
+    R = _Result()
+    R.block_start, R.succ, R.pred_off, R.pred, R.rpo = bs.ctypes.data, succ.ctypes.data, po.ctypes.data, \
+        pred.ctypes.data, rpo.ctypes.data
+    R.in_states = st.ctypes.data if states else None
+    R.reached, R.acc, R.sys = reached.ctypes.data, acc.ctypes.data, sys.ctypes.data
+    lib().or_analyze(d.ctypes.data, _ptr(recs), _ptr(args), sweep_cap, schedule, seed, ctypes.byref(R))
+    nb = R.n_blocks
+    out = dict(status=R.status, n_blocks=nb, n_reach=R.n_reach, sweeps=R.sweeps, digest=R.digest,
+               block_start=bs[:nb + 1] if nb else np.zeros(0, np.uint32), succ=succ[:2 * nb],
+               pred_off=po[:nb + 1] if nb else np.zeros(0, np.uint32), pred=pred[:R.n_pred],
+               rpo=rpo[:R.n_reach], reached=reached[:nb], accesses=acc[:R.n_acc], sysvals=sys[:R.n_sys])
+    if states:
+        out["in_states"] = st[:nb * NSLOT].reshape(nb, NSLOT)
+    return out
+
+
+def analyze_batch(batch, sweep_cap: int = 0):
+    """Per-kernel summaries plus dense access/sysval arrays for a dcgen.Batch."""
+    n = batch.n_kernels
+    N = max(batch.n_instr, 1)
+    summ = np.zeros(n, SUMMARY_DTYPE)
+    acc = np.zeros(N, ACCESS_DTYPE)
+    sys = np.zeros(4 * N, SYSVAL_DTYPE)
+    na, ns = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    lib().or_analyze_batch(_ptr(batch.kernels), n, _ptr(batch.instrs), _ptr(batch.args), sweep_cap,
+                           _ptr(summ), acc.ctypes.data, sys.ctypes.data, ctypes.byref(na), ctypes.byref(ns))
+    return summ, acc[:na.value], sys[:ns.value]
+
+
+def entry_state(desc):
+    d = _desc(desc)
+    st = np.zeros(NSLOT, SLOT_DTYPE)
+    lib().or_entry_state(d.ctypes.data, st.ctypes.data)
+    return st
+
+
+def transfer(desc, args, rec, state):
+    """Apply one record to a copy of `state`."""
+    d = _desc(desc)
+    st = np.array(state, SLOT_DTYPE).copy()
+    r = np.ascontiguousarray(np.array(rec).reshape(1))
+    args = np.ascontiguousarray(args)
+    lib().or_transfer(d.ctypes.data, _ptr(args), r.ctypes.data, st.ctypes.data)
+    return st
+
+
+def join(a, b):
+    out = np.array(a, SLOT_DTYPE).copy()
+    bb = np.ascontiguousarray(np.array(b, SLOT_DTYPE))
+    lib().or_join(out.ctypes.data, bb.ctypes.data)
+    return out
+
+
+def apply_path(recs, desc, args, path):
+    d = _desc(desc)
+    p = np.array(path, np.uint32)
+    out = np.zeros(NSLOT, SLOT_DTYPE)
+    recs = np.ascontiguousarray(recs)
+    args = np.ascontiguousarray(args)
+    rc = lib().or_apply_path(d.ctypes.data, _ptr(recs), _ptr(args), _ptr(p), len(p), out.ctypes.data)
+    assert rc == 0
+    return out
+
+
+def apply_blocks(recs, desc, args, state, path):
+    """Apply the blocks in `path` to a copy of `state`."""
+    d = _desc(desc)
+    p = np.array(path, np.uint32)
+    st = np.array(state, SLOT_DTYPE).copy()
+    recs = np.ascontiguousarray(recs)
+    args = np.ascontiguousarray(args)
+    rc = lib().or_apply_path_from(d.ctypes.data, _ptr(recs), _ptr(args), _ptr(p), len(p), st.ctypes.data)
+    assert rc == 0
+    return st
+
+
+def check_record(rec, n: int) -> int:
+    r = np.ascontiguousarray(np.array(rec).reshape(1))
+    return lib().or_check_record(r.ctypes.data, n)
+
+
+# ---- payload encoding helpers (for reading results in tests) ----
+TAGS = {0: "CONST", 1: "SYSPTR", 2: "KARG", 3: "WGID", 4: "IDX", 5: "SHL", 6: "PTR", 7: "SYS", 8: "UNINIT",
+        15: "TOP"}
+
+
+def val(tag, integ=0, dim=0, aux=0, shift=0, arg=0, c=0) -> int:
+    return (tag << 60) | (integ << 58) | (dim << 56) | (aux << 52) | (shift << 48) | (arg << 40) | (c & 0xFFFFFFFF)
+
+
+def decode(v: int) -> str:
+    v = int(v)
+    if v == TOP:
+        return "TOP"
+    t = v >> 60
+    return "%s(integ=%d,d=%d,aux=%d,s=%d,arg=%d,c=%d)" % (TAGS.get(t, t), (v >> 58) & 3, (v >> 56) & 3,
+                                                          (v >> 52) & 15, (v >> 48) & 15, (v >> 40) & 255,
+                                                          v & 0xFFFFFFFF)

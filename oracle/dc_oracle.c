@@ -1,0 +1,1200 @@
+/*
+ * dc_oracle.c -- plain CPU oracle for the register-state dataflow analysis.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only tests/, the smoke check and the bench's
+ * CPU-baseline leg may load this.  It shares no code with the GPU path.
+ *
+ * What it computes: the least fixpoint (Kildall 1973; Kam & Ullman 1977) of
+ * a forward dataflow problem over each GCN kernel's control flow graph, whose
+ * lattice value per register is the triple (provenance bits, type bits,
+ * payload).  This is the analysis behind the paper's "search for memory
+ * accesses" and "data type recovery" steps (Section "Statement of the
+ * problem", method steps 2 and 3):
+ *   - the entry state is the ABI's register initialisation (Section "Search
+ *     for memory accesses": s[4:5] holds the kernel-argument pointer, v0..v2
+ *     the local ids, s6..s8 the work-group ids when "useargs" is set);
+ *   - a load from s[4:5] at a known offset is a call of a work-item built-in
+ *     or the value of a kernel argument (same section; Listing 3 layout);
+ *   - work-group id times the work-group size from .cws, plus local id, plus
+ *     global offset, is get_global_id (same section, steps 4-5);
+ *   - types come from instruction suffixes and from the .arg table (Section
+ *     "Data type recovery");
+ *   - at a block with several predecessors a register whose incoming values
+ *     differ becomes ambiguous (Section "Search for control structures",
+ *     paragraph on vertices with several ancestors): the payload joins to TOP.
+ * The rule tables that make these passages exact are this build's reading
+ * of the paper and are listed in the design doc.
+ *
+ * Everything here is deliberately simple: full 368-slot states, plain loops,
+ * no blocking.  The reference schedule is round-robin in reverse postorder
+ * (pull form, IN[b] = join of the OUT of reached predecessors); a FIFO and a
+ * randomly ordered worklist are provided so tests can check that the result
+ * does not depend on the schedule.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------ */
+/* wire formats                                                         */
+/* ------------------------------------------------------------------ */
+typedef struct { uint16_t op, r0, r1, r2; int32_t imm, target; } or_instr;
+typedef struct {
+    uint64_t instr_begin; uint32_t n_instr; uint8_t dims, useargs; uint16_t n_args;
+    uint32_t cws[3]; uint32_t arg_begin;
+} or_kernel;
+typedef struct { uint32_t offset; uint16_t size; uint8_t type, flags; } or_arg;
+typedef struct { uint32_t prov; uint8_t type, flags, pad0, pad1; uint64_t val; } or_slot;
+typedef struct { uint32_t instr; uint8_t kind, space, width, dtype; uint64_t addr; } or_access;
+typedef struct { uint32_t instr; uint16_t slot; uint8_t kind, dim; } or_sysval;
+
+_Static_assert(sizeof(or_instr) == 16, "instr");
+_Static_assert(sizeof(or_kernel) == 32, "kernel");
+_Static_assert(sizeof(or_arg) == 8, "arg");
+_Static_assert(sizeof(or_slot) == 16, "slot");
+_Static_assert(sizeof(or_access) == 16, "access");
+_Static_assert(sizeof(or_sysval) == 8, "sysval");
+
+#define NSLOT 368
+
+/* status codes */
+enum {
+    OK = 0, E_BADOP = -10, E_BADREG = -11, E_BADTARGET = -12, E_NOEND = -13,
+    E_UNSUPPORTED = -14, E_NOFIX = -15
+};
+
+/* provenance bits */
+#define P_LID(d) (1u << (0 + (d)))
+#define P_WGID(d) (1u << (3 + (d)))
+#define P_GOFF(d) (1u << (6 + (d)))
+#define P_GSIZE(d) (1u << (9 + (d)))
+#define P_WORKDIM (1u << 12)
+#define P_SYSPTR (1u << 13)
+#define P_CONST (1u << 14)
+#define P_LOADG (1u << 15)
+#define P_LOADL (1u << 16)
+#define P_UNINIT (1u << 17)
+#define P_MASK (1u << 18)
+#define P_HIDDEN (1u << 19)
+static uint32_t P_KARG(unsigned k) { return 1u << (20 + (k < 11 ? k : 11)); }
+
+/* type bits */
+#define TY_INT 1
+#define TY_UINT 2
+#define TY_FLOAT 4
+#define TY_DOUBLE 8
+#define TY_PTR 16
+
+/* payload tags and fields */
+enum { CONSTV = 0, SYSPTR = 1, KARG = 2, WGID = 3, IDX = 4, SHL = 5, PTR = 6, SYS = 7, UNINIT = 8, TOPTAG = 15 };
+enum { ENTIRE = 0, LOW = 1, HIGH = 2 };
+enum { SYS_GOFF_HI = 0, SYS_GSIZE = 1, SYS_NUMGROUPS = 2, SYS_WORKDIM = 3, SYS_HIDDEN = 4 };
+#define M_WG 1
+#define M_LID 2
+#define M_GOFF 4
+#define TOP 0xFFFFFFFFFFFFFFFFull
+
+static uint64_t mk(unsigned tag, unsigned integ, unsigned dim, unsigned aux, unsigned shift, unsigned arg, uint32_t c) {
+    return ((uint64_t)tag << 60) | ((uint64_t)integ << 58) | ((uint64_t)dim << 56) | ((uint64_t)aux << 52) |
+           ((uint64_t)shift << 48) | ((uint64_t)arg << 40) | (uint64_t)c;
+}
+static unsigned tag_of(uint64_t v) { return (unsigned)(v >> 60); }
+static unsigned integ_of(uint64_t v) { return (unsigned)(v >> 58) & 3; }
+static unsigned dim_of(uint64_t v) { return (unsigned)(v >> 56) & 3; }
+static unsigned aux_of(uint64_t v) { return (unsigned)(v >> 52) & 15; }
+static unsigned shift_of(uint64_t v) { return (unsigned)(v >> 48) & 15; }
+static unsigned arg_of(uint64_t v) { return (unsigned)(v >> 40) & 255; }
+static uint32_t c_of(uint64_t v) { return (uint32_t)v; }
+static uint64_t CONST32(uint32_t c) { return mk(CONSTV, ENTIRE, 0, 0, 0, 0, c); }
+static int is_const(uint64_t v) { return v != TOP && tag_of(v) == CONSTV; }
+
+/* sysval kinds, access kinds/spaces */
+enum { SV_GLOBAL_ID, SV_GLOBAL_ID_MINUS_OFFSET, SV_GLOBAL_OFFSET, SV_GLOBAL_SIZE, SV_NUM_GROUPS,
+       SV_WORK_DIM, SV_GROUP_BASE, SV_LOCAL_ID, SV_GROUP_ID };
+enum { AK_LOAD = 0, AK_STORE = 1 };
+enum { SP_GLOBAL = 0, SP_FLAT = 1, SP_LDS = 2 };
+
+/* ------------------------------------------------------------------ */
+/* the instruction subset                                               */
+/* ------------------------------------------------------------------ */
+/* Operand roles.  A role names what a field holds and how wide it is.    */
+enum role {
+    NO,      /* field must be none (0xFFFF) */
+    SD,      /* scalar register def */
+    SU,      /* scalar register use (no constants) */
+    SC,      /* scalar register use or constant */
+    VD,      /* vector register def */
+    VU,      /* vector register use (no constants) */
+    VC,      /* vector or scalar register use, or constant */
+    SADDR    /* scalar pair use, or none */
+};
+/* type rules (Section "Data type recovery"; mnemonic suffixes) */
+enum trule { T_NONE, T_SUF, T_ADD, T_B, T_MOVE, T_SMEM };
+/* payload rules */
+enum prule { R_TOP, R_SMEM, R_MOV, R_ADD, R_ADDC, R_SUB, R_MUL, R_MUL24, R_MAD24, R_SHL32, R_LSHR32,
+             R_ASHR, R_AND, R_OR, R_XOR, R_FOLD64_AND, R_FOLD64_OR, R_FOLD64_XOR, R_FOLD64_ANDN2,
+             R_SHL64, R_SEL, R_NOEFFECT };
+/* classes */
+enum cls { C_SMEM, C_SALU, C_SCMP, C_BRANCH, C_CBRANCH, C_NOP, C_END, C_VALU, C_VCMP, C_GLOAD, C_GSTORE,
+           C_FLOAD, C_FSTORE, C_DSREAD, C_DSWRITE };
+/* implicit register sets */
+#define I_VCC 1
+#define I_SCC 2
+#define I_EXEC 4
+
+typedef struct {
+    const char *name;
+    enum cls cls;
+    enum role r0, r1, r2, src2;   /* src2 lives in imm's low 16 bits */
+    int w0, w1, w2, w_src2;       /* dword widths */
+    int imm_is_offset;
+    int imp_use, imp_def;
+    enum trule trule;
+    int suffix;                   /* type bits of the first suffix */
+    enum prule prule;
+    int value_srcs;               /* bitmask of which of r1/r2/src2 are value sources for T_B (1,2,4) */
+    int mask_def;                 /* explicit defs also get MASK (exec-mask ops) */
+} opinfo;
+
+#define SMEM(n, w) {n, C_SMEM, SD, SU, NO, NO, w, 2, 0, 0, 1, 0, 0, T_SMEM, 0, R_SMEM, 0, 0}
+#define SALU2(n, imp_u, imp_d, tr, suf, pr, vs) {n, C_SALU, SD, SC, SC, NO, 1, 1, 1, 0, 0, imp_u, imp_d, tr, suf, pr, vs, 0}
+#define SALU64(n, pr) {n, C_SALU, SD, SC, SC, NO, 2, 2, 2, 0, 0, 0, I_SCC, T_B, 0, pr, 3, 0}
+#define SCMP(n) {n, C_SCMP, NO, SC, SC, NO, 0, 1, 1, 0, 0, 0, I_SCC, T_NONE, 0, R_NOEFFECT, 0, 0}
+#define CBR(n, imp) {n, C_CBRANCH, NO, NO, NO, NO, 0, 0, 0, 0, 0, imp, 0, T_NONE, 0, R_NOEFFECT, 0, 0}
+#define PLAIN(n, c) {n, c, NO, NO, NO, NO, 0, 0, 0, 0, 0, 0, 0, T_NONE, 0, R_NOEFFECT, 0, 0}
+#define VALU2(n, wd, ws, imp_u, imp_d, tr, suf, pr, vs) {n, C_VALU, VD, VC, VC, NO, wd, ws, ws, 0, 0, imp_u, imp_d, tr, suf, pr, vs, 0}
+#define VALU3(n, wd, ws, tr, suf, pr) {n, C_VALU, VD, VC, VC, VC, wd, ws, ws, ws, 0, 0, 0, tr, suf, pr, 0, 0}
+#define VCMP(n) {n, C_VCMP, NO, VC, VC, NO, 0, 1, 1, 0, 0, 0, I_VCC, T_NONE, 0, R_NOEFFECT, 0, 0}
+
+static const opinfo OPS[] = {
+    SMEM("s_load_dword", 1),
+    SMEM("s_load_dwordx2", 2),
+    SMEM("s_load_dwordx4", 4),
+    {"s_mov_b32", C_SALU, SD, SC, NO, NO, 1, 1, 0, 0, 0, 0, 0, T_MOVE, 0, R_MOV, 1, 0},
+    {"s_mov_b64", C_SALU, SD, SC, NO, NO, 2, 2, 0, 0, 0, 0, 0, T_MOVE, 0, R_MOV, 1, 0},
+    {"s_and_saveexec_b64", C_SALU, SD, SC, NO, NO, 2, 2, 0, 0, 0, I_EXEC, I_EXEC | I_SCC, T_NONE, 0, R_TOP, 0, 1},
+    {"s_or_saveexec_b64", C_SALU, SD, SC, NO, NO, 2, 2, 0, 0, 0, I_EXEC, I_EXEC | I_SCC, T_NONE, 0, R_TOP, 0, 1},
+    SALU2("s_add_u32", 0, I_SCC, T_ADD, TY_UINT, R_ADD, 3),
+    SALU2("s_add_i32", 0, I_SCC, T_ADD, TY_INT, R_ADD, 3),
+    SALU2("s_addc_u32", I_SCC, I_SCC, T_ADD, TY_UINT, R_ADDC, 3),
+    SALU2("s_sub_u32", 0, I_SCC, T_SUF, TY_UINT, R_SUB, 3),
+    SALU2("s_mul_i32", 0, 0, T_SUF, TY_INT, R_MUL, 3),
+    SALU2("s_lshl_b32", 0, I_SCC, T_B, 0, R_SHL32, 1),    /* value r1, amount r2 */
+    SALU2("s_lshr_b32", 0, I_SCC, T_B, 0, R_LSHR32, 1),
+    SALU2("s_and_b32", 0, I_SCC, T_B, 0, R_AND, 3),
+    SALU2("s_or_b32", 0, I_SCC, T_B, 0, R_OR, 3),
+    SALU64("s_and_b64", R_FOLD64_AND),
+    SALU64("s_or_b64", R_FOLD64_OR),
+    SALU64("s_xor_b64", R_FOLD64_XOR),
+    SALU64("s_andn2_b64", R_FOLD64_ANDN2),
+    SCMP("s_cmp_eq_u32"),
+    SCMP("s_cmp_lt_u32"),
+    SCMP("s_cmp_gt_u32"),
+    SCMP("s_cmp_lt_i32"),
+    PLAIN("s_branch", C_BRANCH),
+    CBR("s_cbranch_scc0", I_SCC),
+    CBR("s_cbranch_scc1", I_SCC),
+    CBR("s_cbranch_vccz", I_VCC),
+    CBR("s_cbranch_vccnz", I_VCC),
+    CBR("s_cbranch_execz", I_EXEC),
+    CBR("s_cbranch_execnz", I_EXEC),
+    PLAIN("s_waitcnt", C_NOP),
+    PLAIN("s_barrier", C_NOP),
+    PLAIN("s_nop", C_NOP),
+    PLAIN("s_endpgm", C_END),
+    {"v_mov_b32", C_VALU, VD, VC, NO, NO, 1, 1, 0, 0, 0, 0, 0, T_MOVE, 0, R_MOV, 1, 0},
+    {"v_cvt_f32_u32", C_VALU, VD, VC, NO, NO, 1, 1, 0, 0, 0, 0, 0, T_SUF, TY_FLOAT, R_TOP, 0, 0},
+    {"v_cvt_u32_f32", C_VALU, VD, VC, NO, NO, 1, 1, 0, 0, 0, 0, 0, T_SUF, TY_UINT, R_TOP, 0, 0},
+    {"v_cvt_f64_f32", C_VALU, VD, VC, NO, NO, 2, 1, 0, 0, 0, 0, 0, T_SUF, TY_DOUBLE, R_TOP, 0, 0},
+    VALU2("v_add_co_u32", 1, 1, 0, I_VCC, T_ADD, TY_UINT, R_ADD, 3),
+    VALU2("v_addc_co_u32", 1, 1, I_VCC, I_VCC, T_ADD, TY_UINT, R_ADDC, 3),
+    VALU2("v_sub_co_u32", 1, 1, 0, I_VCC, T_SUF, TY_UINT, R_SUB, 3),
+    VALU2("v_add_u32", 1, 1, 0, 0, T_ADD, TY_UINT, R_ADD, 3),
+    VALU2("v_mul_lo_u32", 1, 1, 0, 0, T_SUF, TY_UINT, R_MUL, 3),
+    VALU2("v_mul_u32_u24", 1, 1, 0, 0, T_SUF, TY_UINT, R_MUL24, 3),
+    VALU2("v_mul_hi_u32", 1, 1, 0, 0, T_SUF, TY_UINT, R_TOP, 3),
+    VALU3("v_mad_u32_u24", 1, 1, T_SUF, TY_UINT, R_MAD24),
+    VALU2("v_lshlrev_b32", 1, 1, 0, 0, T_B, 0, R_SHL32, 2),   /* amount r1, value r2 */
+    VALU2("v_lshrrev_b32", 1, 1, 0, 0, T_B, 0, R_LSHR32, 2),
+    VALU2("v_ashrrev_i32", 1, 1, 0, 0, T_SUF, TY_INT, R_ASHR, 2),
+    VALU2("v_and_b32", 1, 1, 0, 0, T_B, 0, R_AND, 3),
+    VALU2("v_or_b32", 1, 1, 0, 0, T_B, 0, R_OR, 3),
+    VALU2("v_xor_b32", 1, 1, 0, 0, T_B, 0, R_XOR, 3),
+    {"v_lshlrev_b64", C_VALU, VD, VC, VC, NO, 2, 1, 2, 0, 0, 0, 0, T_B, 0, R_SHL64, 2, 0},
+    VALU2("v_cndmask_b32", 1, 1, I_VCC, 0, T_B, 0, R_SEL, 3),
+    VALU2("v_add_f32", 1, 1, 0, 0, T_SUF, TY_FLOAT, R_TOP, 3),
+    VALU2("v_sub_f32", 1, 1, 0, 0, T_SUF, TY_FLOAT, R_TOP, 3),
+    VALU2("v_mul_f32", 1, 1, 0, 0, T_SUF, TY_FLOAT, R_TOP, 3),
+    VALU2("v_max_f32", 1, 1, 0, 0, T_SUF, TY_FLOAT, R_TOP, 3),
+    VALU3("v_mad_f32", 1, 1, T_SUF, TY_FLOAT, R_TOP),
+    VALU3("v_fma_f32", 1, 1, T_SUF, TY_FLOAT, R_TOP),
+    VALU2("v_add_f64", 2, 2, 0, 0, T_SUF, TY_DOUBLE, R_TOP, 3),
+    VALU2("v_mul_f64", 2, 2, 0, 0, T_SUF, TY_DOUBLE, R_TOP, 3),
+    VALU3("v_fma_f64", 2, 2, T_SUF, TY_DOUBLE, R_TOP),
+    VCMP("v_cmp_eq_u32"),
+    VCMP("v_cmp_gt_u32"),
+    VCMP("v_cmp_lt_u32"),
+    VCMP("v_cmp_lt_i32"),
+    VCMP("v_cmp_gt_f32"),
+    {"global_load_dword", C_GLOAD, VD, VU, SADDR, NO, 1, 2, 2, 0, 1, 0, 0, T_NONE, 0, R_TOP, 0, 0},
+    {"global_load_dwordx2", C_GLOAD, VD, VU, SADDR, NO, 2, 2, 2, 0, 1, 0, 0, T_NONE, 0, R_TOP, 0, 0},
+    {"flat_load_dword", C_FLOAD, VD, VU, NO, NO, 1, 2, 0, 0, 1, 0, 0, T_NONE, 0, R_TOP, 0, 0},
+    {"global_store_dword", C_GSTORE, VU, VU, SADDR, NO, 1, 2, 2, 0, 1, 0, 0, T_NONE, 0, R_NOEFFECT, 0, 0},
+    {"global_store_dwordx2", C_GSTORE, VU, VU, SADDR, NO, 2, 2, 2, 0, 1, 0, 0, T_NONE, 0, R_NOEFFECT, 0, 0},
+    {"flat_store_dword", C_FSTORE, VU, VU, NO, NO, 1, 2, 0, 0, 1, 0, 0, T_NONE, 0, R_NOEFFECT, 0, 0},
+    {"ds_read_b32", C_DSREAD, VD, VU, NO, NO, 1, 1, 0, 0, 1, 0, 0, T_NONE, 0, R_TOP, 0, 0},
+    {"ds_write_b32", C_DSWRITE, VU, VU, NO, NO, 1, 1, 0, 0, 1, 0, 0, T_NONE, 0, R_NOEFFECT, 0, 0},
+};
+#define N_OPS ((int)(sizeof(OPS) / sizeof(OPS[0])))
+
+int or_n_ops(void) { return N_OPS; }
+const char *or_op_name(int id) { return (id >= 0 && id < N_OPS) ? OPS[id].name : 0; }
+
+/* ------------------------------------------------------------------ */
+/* validation                                                            */
+/* ------------------------------------------------------------------ */
+#define NONE_ID 0xFFFF
+#define LIT_ID 0xFFFE
+
+static int is_inline_const(unsigned id) { return (id >= 0x8000 && id <= 0x8050) || (id >= 0x8060 && id <= 0x8067); }
+
+/* a scalar register operand of width w starting at id */
+static int scalar_reg_ok(unsigned id, int w) {
+    if (w == 1) return id <= 107 || id == 109;
+    if (w == 2) return (id % 2 == 0) && (id <= 102 || id == 104 || id == 106);
+    if (w == 4) return (id % 4 == 0) && id <= 100;
+    return 0;
+}
+static int vector_reg_ok(unsigned id, int w) { return id >= 112 && id + (unsigned)w - 1 <= 367; }
+
+static int field_ok(enum role r, unsigned id, int w, int lit_ok) {
+    switch (r) {
+    case NO: return id == NONE_ID;
+    case SD: return scalar_reg_ok(id, w);
+    case SU: return scalar_reg_ok(id, w);
+    case SC: return scalar_reg_ok(id, w) || is_inline_const(id) || (lit_ok && id == LIT_ID);
+    case VD: return vector_reg_ok(id, w);
+    case VU: return vector_reg_ok(id, w);
+    case VC: return vector_reg_ok(id, w) || scalar_reg_ok(id, w) || is_inline_const(id) || (lit_ok && id == LIT_ID);
+    case SADDR: return id == NONE_ID || (scalar_reg_ok(id, 2) && id <= 102);
+    }
+    return 0;
+}
+
+/* status of one record at index i of a kernel with n records */
+static int check_record(const or_instr *I, uint32_t n) {
+    if (I->op >= N_OPS) return E_BADOP;
+    const opinfo *o = &OPS[I->op];
+    int imm_free = !o->imm_is_offset && o->src2 == NO;
+    /* s_load destinations are plain SGPRs; sbase is an SGPR pair */
+    if (o->cls == C_SMEM) {
+        if (!(scalar_reg_ok(I->r0, o->w0) && I->r0 + (unsigned)o->w0 - 1 <= 103)) return E_BADREG;
+        if (!(scalar_reg_ok(I->r1, 2) && I->r1 <= 102)) return E_BADREG;
+        if (I->r2 != NONE_ID) return E_BADREG;
+    } else {
+        if (!field_ok(o->r0, I->r0, o->w0, 0)) return E_BADREG;
+        if (!field_ok(o->r1, I->r1, o->w1, imm_free)) return E_BADREG;
+        if (!field_ok(o->r2, I->r2, o->w2, imm_free)) return E_BADREG;
+        if (o->src2 != NO) {
+            if (I->imm < 0 || I->imm > 0xFFFF) return E_BADREG;
+            if (!field_ok(o->src2, (unsigned)I->imm, o->w_src2, 0)) return E_BADREG;
+        }
+    }
+    if (o->cls == C_BRANCH || o->cls == C_CBRANCH) {
+        if (I->target < 0 || (uint32_t)I->target >= n) return E_BADTARGET;
+    } else if (I->target != -1) {
+        return E_BADTARGET;
+    }
+    return OK;
+}
+
+int or_check_record(const or_instr *I, uint32_t n) { return check_record(I, n); }
+
+static int descriptor_status(const or_kernel *K) {
+    if (K->useargs != 1) return E_UNSUPPORTED;          /* only the useargs ABI is described */
+    if (K->dims < 1 || K->dims > 3) return E_UNSUPPORTED;
+    for (int d = 0; d < K->dims; d++)
+        if (K->cws[d] == 0) return E_UNSUPPORTED;
+    if (K->n_args > 255) return E_UNSUPPORTED;
+    return OK;
+}
+
+static int is_terminator(uint16_t op) {
+    return op < N_OPS && (OPS[op].cls == C_BRANCH || OPS[op].cls == C_END);
+}
+static int ends_block(uint16_t op) {
+    return op < N_OPS && (OPS[op].cls == C_BRANCH || OPS[op].cls == C_CBRANCH || OPS[op].cls == C_END);
+}
+
+/* status before the fixpoint: descriptor, then records in order, then end */
+int or_kernel_status(const or_kernel *K, const or_instr *I) {
+    int st = descriptor_status(K);
+    if (st != OK) return st;
+    for (uint32_t i = 0; i < K->n_instr; i++) {
+        st = check_record(&I[i], K->n_instr);
+        if (st != OK) return st;
+    }
+    if (K->n_instr == 0 || !is_terminator(I[K->n_instr - 1].op)) return E_NOEND;
+    return OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* control flow graph (textbook basic blocks)                           */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    uint32_t n_blocks;
+    uint32_t *block_start;   /* n_blocks + 1 */
+    uint32_t *block_of;      /* per instruction */
+    int32_t *succ;           /* 2 per block: fall-through, taken (or -1) */
+    uint32_t *pred_off;      /* n_blocks + 1 */
+    uint32_t *pred;          /* ascending per block */
+    uint32_t *rpo;           /* reachable blocks in reverse postorder */
+    uint32_t n_reach;
+} cfg_t;
+
+static void dfs_post(const cfg_t *G, uint32_t b, uint8_t *seen, uint32_t *post, uint32_t *np) {
+    seen[b] = 1;
+    for (int e = 0; e < 2; e++) {
+        int32_t s = G->succ[2 * b + e];
+        if (s >= 0 && !seen[s]) dfs_post(G, (uint32_t)s, seen, post, np);
+    }
+    post[(*np)++] = b;
+}
+
+static void build_cfg(const or_instr *I, uint32_t n, cfg_t *G) {
+    uint8_t *leader = (uint8_t *)calloc(n + 1, 1);
+    leader[0] = 1;
+    for (uint32_t i = 0; i < n; i++) {
+        if (OPS[I[i].op].cls == C_BRANCH || OPS[I[i].op].cls == C_CBRANCH) leader[I[i].target] = 1;
+        if (ends_block(I[i].op) && i + 1 < n) leader[i + 1] = 1;
+    }
+    uint32_t nb = 0;
+    for (uint32_t i = 0; i < n; i++) nb += leader[i];
+    G->n_blocks = nb;
+    G->block_start = (uint32_t *)malloc(sizeof(uint32_t) * (nb + 1));
+    G->block_of = (uint32_t *)malloc(sizeof(uint32_t) * n);
+    uint32_t b = 0;
+    for (uint32_t i = 0; i < n; i++) {
+        if (leader[i]) G->block_start[b++] = i;
+        G->block_of[i] = b - 1;
+    }
+    G->block_start[nb] = n;
+    G->succ = (int32_t *)malloc(sizeof(int32_t) * 2 * nb);
+    for (b = 0; b < nb; b++) {
+        uint32_t last = G->block_start[b + 1] - 1;
+        const or_instr *L = &I[last];
+        enum cls c = OPS[L->op].cls;
+        int32_t fall = -1, taken = -1;
+        if (c == C_END) {
+        } else if (c == C_BRANCH) {
+            taken = (int32_t)G->block_of[L->target];
+        } else {
+            if (b + 1 < nb) fall = (int32_t)(b + 1);
+            if (c == C_CBRANCH) taken = (int32_t)G->block_of[L->target];
+        }
+        if (taken == fall) taken = -1;
+        G->succ[2 * b] = fall;
+        G->succ[2 * b + 1] = taken;
+    }
+    /* predecessors: for each block, every block that names it, ascending */
+    G->pred_off = (uint32_t *)calloc(nb + 1, sizeof(uint32_t));
+    for (b = 0; b < nb; b++)
+        for (int e = 0; e < 2; e++)
+            if (G->succ[2 * b + e] >= 0) G->pred_off[G->succ[2 * b + e] + 1]++;
+    for (b = 0; b < nb; b++) G->pred_off[b + 1] += G->pred_off[b];
+    G->pred = (uint32_t *)malloc(sizeof(uint32_t) * (G->pred_off[nb] + 1));
+    uint32_t *fill = (uint32_t *)calloc(nb + 1, sizeof(uint32_t));
+    for (uint32_t s = 0; s < nb; s++)           /* ascending scan over p gives ascending lists */
+        for (uint32_t p = 0; p < nb; p++)
+            if (G->succ[2 * p] == (int32_t)s || G->succ[2 * p + 1] == (int32_t)s)
+                G->pred[G->pred_off[s] + fill[s]++] = p;
+    free(fill);
+    /* reverse postorder of a depth-first search from block 0, fall-through first */
+    uint8_t *seen = (uint8_t *)calloc(nb, 1);
+    uint32_t *post = (uint32_t *)malloc(sizeof(uint32_t) * nb);
+    uint32_t np = 0;
+    dfs_post(G, 0, seen, post, &np);
+    G->rpo = (uint32_t *)malloc(sizeof(uint32_t) * (nb ? nb : 1));
+    for (uint32_t i = 0; i < np; i++) G->rpo[i] = post[np - 1 - i];
+    G->n_reach = np;
+    free(seen);
+    free(post);
+    free(leader);
+}
+
+static void free_cfg(cfg_t *G) {
+    free(G->block_start); free(G->block_of); free(G->succ); free(G->pred_off); free(G->pred); free(G->rpo);
+}
+
+/* ------------------------------------------------------------------ */
+/* entry state (ABI initialisation)                                     */
+/* ------------------------------------------------------------------ */
+void or_entry_state(const or_kernel *K, or_slot *st) {
+    memset(st, 0, sizeof(or_slot) * NSLOT);
+    for (int s = 0; s < NSLOT; s++) {
+        st[s].prov = P_UNINIT;
+        st[s].val = mk(UNINIT, 0, 0, 0, 0, 0, 0);
+    }
+    /* s[4:5]: pointer to the kernel settings / arguments */
+    st[4].prov = P_SYSPTR; st[4].type = 0; st[4].val = mk(SYSPTR, LOW, 0, 0, 0, 0, 0);
+    st[5].prov = P_SYSPTR; st[5].type = 0; st[5].val = mk(SYSPTR, HIGH, 0, 0, 0, 0, 0);
+    for (int d = 0; d < K->dims; d++) {
+        /* s6.. : work-group ids; v0.. : local ids */
+        st[6 + d].prov = P_WGID(d); st[6 + d].type = TY_UINT; st[6 + d].val = mk(WGID, ENTIRE, (unsigned)d, 0, 0, 0, 0);
+        st[112 + d].prov = P_LID(d); st[112 + d].type = TY_UINT; st[112 + d].val = mk(IDX, ENTIRE, (unsigned)d, M_LID, 0, 0, 0);
+    }
+    st[106].prov = P_MASK; st[106].type = 0; st[106].val = TOP;
+    st[107].prov = P_MASK; st[107].type = 0; st[107].val = TOP;
+}
+
+/* ------------------------------------------------------------------ */
+/* operand reads                                                         */
+/* ------------------------------------------------------------------ */
+static const uint32_t FLOAT_BITS[8] = {0x3F000000u, 0xBF000000u, 0x3F800000u, 0xBF800000u,
+                                       0x40000000u, 0xC0000000u, 0x40800000u, 0xC0800000u};
+static const uint32_t DOUBLE_HI_BITS[8] = {0x3FE00000u, 0xBFE00000u, 0x3FF00000u, 0xBFF00000u,
+                                           0x40000000u, 0xC0000000u, 0x40100000u, 0xC0100000u};
+
+/* dword j of operand `id` used as a w-dword source */
+static or_slot read_op(const or_slot *st, unsigned id, int j, int w, int32_t imm) {
+    or_slot s;
+    memset(&s, 0, sizeof(s));
+    if (id < NSLOT) return st[id + (unsigned)j];
+    s.prov = P_CONST;
+    s.type = 0;
+    if (id >= 0x8000 && id <= 0x8050) {
+        int32_t v = (int32_t)(id - 0x8000) - 16;
+        s.val = CONST32(j == 0 ? (uint32_t)v : (v < 0 ? 0xFFFFFFFFu : 0u));
+    } else if (id >= 0x8060 && id <= 0x8067) {
+        unsigned q = id - 0x8060;
+        if (w == 1) s.val = CONST32(FLOAT_BITS[q]);
+        else s.val = CONST32(j == 0 ? 0u : DOUBLE_HI_BITS[q]);
+    } else { /* literal */
+        s.val = CONST32(j == 0 ? (uint32_t)imm : (imm < 0 ? 0xFFFFFFFFu : 0u));
+    }
+    return s;
+}
+
+/* ------------------------------------------------------------------ */
+/* payload rules                                                         */
+/* ------------------------------------------------------------------ */
+static int idx_lowish(uint64_t v) { return v != TOP && tag_of(v) == IDX && (integ_of(v) == ENTIRE || integ_of(v) == LOW); }
+
+static uint64_t add_once(uint64_t a, uint64_t b) {
+    /* patterns tried with a on the left; add_rule tries both orders */
+    if (is_const(a) && is_const(b)) return CONST32(c_of(a) + c_of(b));
+    if (idx_lowish(a) && idx_lowish(b) && dim_of(a) == dim_of(b) && (aux_of(a) & aux_of(b)) == 0)
+        return mk(IDX, ENTIRE, dim_of(a), aux_of(a) | aux_of(b), 0, 0, c_of(a) + c_of(b));
+    if (idx_lowish(a) && is_const(b)) return mk(IDX, ENTIRE, dim_of(a), aux_of(a), 0, 0, c_of(a) + c_of(b));
+    if (tag_of(a) == SHL && integ_of(a) == ENTIRE && is_const(b))
+        return mk(SHL, ENTIRE, dim_of(a), aux_of(a), shift_of(a), 0, c_of(a) + c_of(b));
+    if (tag_of(a) == KARG && integ_of(a) == LOW && tag_of(b) == SHL && integ_of(b) == LOW)
+        return mk(PTR, LOW, dim_of(b), aux_of(b), shift_of(b), arg_of(a), c_of(b));
+    if (tag_of(a) == KARG && integ_of(a) == LOW && is_const(b)) return mk(PTR, LOW, 0, 0, 0, arg_of(a), c_of(b));
+    if (tag_of(a) == PTR && integ_of(a) == LOW && is_const(b))
+        return mk(PTR, LOW, dim_of(a), aux_of(a), shift_of(a), arg_of(a), c_of(a) + c_of(b));
+    if (tag_of(a) == PTR && integ_of(a) == LOW && dim_of(a) == 0 && aux_of(a) == 0 && shift_of(a) == 0 &&
+        tag_of(b) == SHL && integ_of(b) == LOW)
+        return mk(PTR, LOW, dim_of(b), aux_of(b), shift_of(b), arg_of(a), c_of(a) + c_of(b));
+    return TOP;
+}
+static uint64_t add_rule(uint64_t a, uint64_t b) {
+    if (a == TOP || b == TOP) return TOP;
+    uint64_t r = add_once(a, b);
+    return r != TOP ? r : add_once(b, a);
+}
+
+static uint64_t addc_rule(uint64_t a, uint64_t b) {
+    if (a == TOP || b == TOP) return TOP;
+    for (int k = 0; k < 2; k++) {
+        uint64_t p = k ? b : a, q = k ? a : b;
+        int ptr_hi = (tag_of(p) == KARG || tag_of(p) == PTR) && integ_of(p) == HIGH;
+        int ext_hi = (tag_of(q) == SHL && integ_of(q) == HIGH) || (tag_of(q) == IDX && integ_of(q) == HIGH) ||
+                     (is_const(q) && c_of(q) == 0);
+        if (ptr_hi && ext_hi) return mk(PTR, HIGH, 0, 0, 0, arg_of(p), 0);
+    }
+    return TOP;
+}
+
+static int log2_exact(uint32_t x, unsigned *s) {
+    if (x == 0 || (x & (x - 1))) return 0;
+    unsigned k = 0;
+    while ((1u << k) != x) k++;
+    *s = k;
+    return 1;
+}
+
+/* IDX(d,m,c) shifted left by s (s already reduced) */
+static uint64_t idx_shift(uint64_t a, unsigned s) {
+    if (s == 0) return mk(IDX, ENTIRE, dim_of(a), aux_of(a), 0, 0, c_of(a));
+    if (s > 15) return TOP;
+    return mk(SHL, ENTIRE, dim_of(a), aux_of(a), s, 0, c_of(a) << s);
+}
+
+static uint64_t mul_once(const or_kernel *K, uint64_t a, uint64_t b) {
+    if (is_const(a) && is_const(b)) return CONST32(c_of(a) * c_of(b));
+    if (tag_of(a) == WGID && is_const(b)) {
+        unsigned d = dim_of(a);
+        if (K->cws[d] > 0 && c_of(b) == K->cws[d]) return mk(IDX, ENTIRE, d, M_WG, 0, 0, 0);
+        return TOP;
+    }
+    if (idx_lowish(a) && is_const(b)) {
+        unsigned s;
+        if (log2_exact(c_of(b), &s)) return idx_shift(a, s);
+    }
+    return TOP;
+}
+static uint64_t mul_rule(const or_kernel *K, uint64_t a, uint64_t b) {
+    if (a == TOP || b == TOP) return TOP;
+    uint64_t r = mul_once(K, a, b);
+    return r != TOP ? r : mul_once(K, b, a);
+}
+static uint64_t mask24(uint64_t v) { return is_const(v) ? CONST32(c_of(v) & 0xFFFFFFu) : v; }
+
+static uint64_t shl32_rule(const or_kernel *K, uint64_t val, uint64_t amt) {
+    if (val == TOP || amt == TOP || !is_const(amt)) return TOP;
+    unsigned s = c_of(amt) & 31;
+    if (is_const(val)) return CONST32(c_of(val) << s);
+    if (idx_lowish(val)) return idx_shift(val, s);
+    if (tag_of(val) == WGID) {
+        unsigned d = dim_of(val), lg;
+        if (log2_exact(K->cws[d], &lg) && lg == s) return mk(IDX, ENTIRE, d, M_WG, 0, 0, 0);
+    }
+    return TOP;
+}
+
+static uint64_t lshr32_rule(const or_kernel *K, uint64_t val, uint64_t amt) {
+    if (val == TOP || amt == TOP || !is_const(amt)) return TOP;
+    unsigned s = c_of(amt) & 31;
+    if (is_const(val)) return CONST32(c_of(val) >> s);
+    if (tag_of(val) == SYS && aux_of(val) == SYS_GSIZE && integ_of(val) == ENTIRE) {
+        unsigned d = dim_of(val), lg;
+        if (log2_exact(K->cws[d], &lg) && lg == s) return mk(SYS, ENTIRE, d, SYS_NUMGROUPS, 0, 0, 0);
+    }
+    return TOP;
+}
+
+static uint64_t ashr_rule(uint64_t val, uint64_t amt) {
+    if (val == TOP || amt == TOP || !is_const(amt)) return TOP;
+    unsigned s = c_of(amt) & 31;
+    if (is_const(val)) return CONST32((uint32_t)((int32_t)c_of(val) >> s));
+    if (idx_lowish(val) && s == 31) return mk(IDX, HIGH, dim_of(val), aux_of(val), 0, 0, 0);
+    return TOP;
+}
+
+static uint64_t fold_rule(enum prule r, uint64_t a, uint64_t b) {
+    if (!is_const(a) || !is_const(b)) return TOP;
+    uint32_t x = c_of(a), y = c_of(b);
+    switch (r) {
+    case R_SUB: return CONST32(x - y);
+    case R_AND: return CONST32(x & y);
+    case R_OR: return CONST32(x | y);
+    case R_XOR: return CONST32(x ^ y);
+    default: return TOP;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* s_load resolution against the kernel-argument area                   */
+/* ------------------------------------------------------------------ */
+typedef struct { uint32_t prov; uint8_t type; uint64_t val; } dword_info;
+
+static dword_info resolve_dword(const or_kernel *K, const or_arg *args, uint32_t o) {
+    dword_info r = {P_LOADG, 0, TOP};
+    if (o < 0x18 && o % 4 == 0) {                 /* global offsets 0..2, 8 bytes each */
+        unsigned g = o / 8, half = (o / 4) & 1;
+        r.prov = P_GOFF(g); r.type = TY_UINT;
+        r.val = half == 0 ? mk(IDX, LOW, g, M_GOFF, 0, 0, 0) : mk(SYS, HIGH, g, SYS_GOFF_HI, 0, 0, 0);
+        return r;
+    }
+    if (o >= 0x18 && o < 0x30 && o % 4 == 0) {    /* printf buffer, vqueue, aqlwrap */
+        unsigned h = (o - 0x18) / 8, half = (o / 4) & 1;
+        r.prov = P_HIDDEN; r.type = 0;
+        r.val = mk(SYS, half == 0 ? LOW : HIGH, h, SYS_HIDDEN, 0, 0, 0);
+        return r;
+    }
+    if (o == 0x20010) {
+        r.prov = P_WORKDIM; r.type = TY_UINT; r.val = mk(SYS, ENTIRE, 0, SYS_WORKDIM, 0, 0, 0);
+        return r;
+    }
+    for (unsigned k = 0; k < K->n_args; k++) {
+        const or_arg *a = &args[k];
+        if ((uint64_t)a->offset <= o && (uint64_t)o < (uint64_t)a->offset + a->size) {
+            r.prov = P_KARG(k);
+            r.type = a->type;
+            if (a->size == 4 && o == a->offset) r.val = mk(KARG, ENTIRE, 0, 0, 0, k, 0);
+            else if (a->size == 8 && o == a->offset) r.val = mk(KARG, LOW, 0, 0, 0, k, 0);
+            else if (a->size == 8 && o == a->offset + 4) r.val = mk(KARG, HIGH, 0, 0, 0, k, 0);
+            else r.val = TOP;
+            return r;
+        }
+    }
+    return r;
+}
+
+/* ------------------------------------------------------------------ */
+/* one instruction                                                       */
+/* ------------------------------------------------------------------ */
+typedef struct { unsigned slot; or_slot v; } def_t;
+
+/* Computes the defs of instruction I from state st (which it does not
+ * modify).  Returns the number of defs; explicit defs come first, then
+ * implicit ones, so writing them in order lets implicit defs win. */
+static int compute_defs(const or_kernel *K, const or_arg *args, const or_instr *I, const or_slot *st, def_t *defs) {
+    const opinfo *o = &OPS[I->op];
+    int nd = 0;
+    if (o->cls == C_BRANCH || o->cls == C_CBRANCH || o->cls == C_NOP || o->cls == C_END ||
+        o->cls == C_GSTORE || o->cls == C_FSTORE || o->cls == C_DSWRITE)
+        return 0;
+
+    if (o->cls == C_SMEM) {
+        int w = o->w0;
+        int via_ptr = I->r1 == 4;
+        int ptr_ok = st[4].val == mk(SYSPTR, LOW, 0, 0, 0, 0, 0) && st[5].val == mk(SYSPTR, HIGH, 0, 0, 0, 0, 0);
+        uint32_t off = (uint32_t)I->imm;
+        dword_info di[4];
+        for (int j = 0; j < w; j++) {
+            if (via_ptr) di[j] = resolve_dword(K, args, off + 4u * (uint32_t)j);
+            else { di[j].prov = P_LOADG; di[j].type = 0; di[j].val = TOP; }
+        }
+        if (via_ptr) {   /* exact (offset, width) matches take precedence */
+            if (w == 2 && (off == 0x0 || off == 0x8 || off == 0x10)) {
+                unsigned d = off / 8;
+                di[0].prov = di[1].prov = P_GOFF(d);
+                di[0].type = di[1].type = TY_UINT;
+                di[0].val = mk(IDX, LOW, d, M_GOFF, 0, 0, 0);
+                di[1].val = mk(SYS, HIGH, d, SYS_GOFF_HI, 0, 0, 0);
+            }
+            if (w == 1 && (off == 0xc || off == 0x10 || off == 0x14)) {
+                unsigned d = (off - 0xc) / 4;
+                di[0].prov = P_GSIZE(d); di[0].type = TY_UINT; di[0].val = mk(SYS, ENTIRE, d, SYS_GSIZE, 0, 0, 0);
+            }
+            if (w == 1 && off == 0x20010) {
+                di[0].prov = P_WORKDIM; di[0].type = TY_UINT; di[0].val = mk(SYS, ENTIRE, 0, SYS_WORKDIM, 0, 0, 0);
+            }
+        }
+        for (int j = 0; j < w; j++) {
+            defs[nd].slot = I->r0 + (unsigned)j;
+            memset(&defs[nd].v, 0, sizeof(or_slot));
+            defs[nd].v.prov = di[j].prov;
+            defs[nd].v.type = di[j].type;
+            defs[nd].v.val = (via_ptr && ptr_ok) ? di[j].val : TOP;
+            nd++;
+        }
+        return nd;
+    }
+
+    if (o->cls == C_GLOAD || o->cls == C_FLOAD || o->cls == C_DSREAD) {
+        for (int j = 0; j < o->w0; j++) {
+            defs[nd].slot = I->r0 + (unsigned)j;
+            memset(&defs[nd].v, 0, sizeof(or_slot));
+            defs[nd].v.prov = o->cls == C_DSREAD ? P_LOADL : P_LOADG;
+            defs[nd].v.val = TOP;
+            nd++;
+        }
+        return nd;
+    }
+
+    /* ALU and compares: gather every source dword first */
+    or_slot s1[2], s2[2], s3[2];
+    int n1 = 0, n2 = 0, n3 = 0;
+    uint32_t rp = 0;
+    if (o->r1 != NO) { n1 = o->w1; for (int j = 0; j < n1; j++) s1[j] = read_op(st, I->r1, j, o->w1, I->imm); }
+    if (o->r2 != NO) { n2 = o->w2; for (int j = 0; j < n2; j++) s2[j] = read_op(st, I->r2, j, o->w2, I->imm); }
+    if (o->src2 != NO) { n3 = o->w_src2; for (int j = 0; j < n3; j++) s3[j] = read_op(st, (unsigned)I->imm, j, o->w_src2, 0); }
+    for (int j = 0; j < n1; j++) rp |= s1[j].prov;
+    for (int j = 0; j < n2; j++) rp |= s2[j].prov;
+    for (int j = 0; j < n3; j++) rp |= s3[j].prov;
+    if (o->imp_use & I_VCC) rp |= st[104].prov | st[105].prov;
+    if (o->imp_use & I_EXEC) rp |= st[106].prov | st[107].prov;
+    if (o->imp_use & I_SCC) rp |= st[108].prov;
+
+    if (o->r0 == SD || o->r0 == VD) {
+        int w = o->w0;
+        uint8_t ty[2] = {0, 0};
+        uint8_t src_types = 0;
+        for (int j = 0; j < n1; j++) if (o->value_srcs & 1) src_types |= s1[j].type;
+        for (int j = 0; j < n2; j++) if (o->value_srcs & 2) src_types |= s2[j].type;
+        switch (o->trule) {
+        case T_NONE: break;
+        case T_SUF: ty[0] = ty[1] = (uint8_t)o->suffix; break;
+        case T_ADD: {
+            uint8_t u = 0;
+            for (int j = 0; j < n1; j++) u |= s1[j].type;
+            for (int j = 0; j < n2; j++) u |= s2[j].type;
+            ty[0] = ty[1] = (uint8_t)(o->suffix | (u & TY_PTR));
+            break;
+        }
+        case T_B: ty[0] = ty[1] = src_types; break;
+        case T_MOVE: ty[0] = s1[0].type; ty[1] = w == 2 ? s1[1].type : 0; break;
+        case T_SMEM: break;
+        }
+        uint64_t v[2] = {TOP, TOP};
+        uint64_t a = n1 ? s1[0].val : TOP, b = n2 ? s2[0].val : TOP;
+        switch (o->prule) {
+        case R_TOP: case R_NOEFFECT: case R_SMEM: break;
+        case R_MOV: v[0] = s1[0].val; v[1] = w == 2 ? s1[1].val : TOP; break;
+        case R_ADD: v[0] = add_rule(a, b); break;
+        case R_ADDC: v[0] = addc_rule(a, b); break;
+        case R_SUB: case R_AND: case R_OR: case R_XOR: v[0] = fold_rule(o->prule, a, b); break;
+        case R_MUL: v[0] = mul_rule(K, a, b); break;
+        case R_MUL24: v[0] = mul_rule(K, mask24(a), mask24(b)); break;
+        case R_MAD24: v[0] = add_rule(mul_rule(K, mask24(a), mask24(b)), s3[0].val); break;
+        /* shifts: the value is r1 in the scalar forms, r2 in the vector "rev" forms */
+        case R_SHL32: v[0] = o->value_srcs == 1 ? shl32_rule(K, a, b) : shl32_rule(K, b, a); break;
+        case R_LSHR32: v[0] = o->value_srcs == 1 ? lshr32_rule(K, a, b) : lshr32_rule(K, b, a); break;
+        case R_ASHR: v[0] = o->value_srcs == 1 ? ashr_rule(a, b) : ashr_rule(b, a); break;
+        case R_SEL: v[0] = (a == b) ? a : TOP; break;
+        case R_FOLD64_AND: case R_FOLD64_OR: case R_FOLD64_XOR: case R_FOLD64_ANDN2: {
+            if (is_const(s1[0].val) && is_const(s1[1].val) && is_const(s2[0].val) && is_const(s2[1].val)) {
+                for (int j = 0; j < 2; j++) {
+                    uint32_t x = c_of(s1[j].val), y = c_of(s2[j].val), z;
+                    if (o->prule == R_FOLD64_AND) z = x & y;
+                    else if (o->prule == R_FOLD64_OR) z = x | y;
+                    else if (o->prule == R_FOLD64_XOR) z = x ^ y;
+                    else z = x & ~y;
+                    v[j] = CONST32(z);
+                }
+            }
+            break;
+        }
+        case R_SHL64: {
+            uint64_t amt = s1[0].val, lo = s2[0].val, hi = s2[1].val;
+            if (amt == TOP || lo == TOP || hi == TOP || !is_const(amt)) break;
+            unsigned s = c_of(amt) & 63;
+            if (is_const(lo) && is_const(hi)) {
+                uint64_t x = ((uint64_t)c_of(hi) << 32 | c_of(lo)) << s;
+                v[0] = CONST32((uint32_t)x);
+                v[1] = CONST32((uint32_t)(x >> 32));
+            } else if (idx_lowish(lo) &&
+                       ((is_const(hi) && c_of(hi) == 0) ||
+                        (tag_of(hi) == IDX && integ_of(hi) == HIGH && dim_of(hi) == dim_of(lo) && aux_of(hi) == aux_of(lo)))) {
+                if (s == 0) { v[0] = lo; v[1] = hi; }
+                else if (s <= 15) {
+                    v[0] = mk(SHL, LOW, dim_of(lo), aux_of(lo), s, 0, c_of(lo) << s);
+                    v[1] = mk(SHL, HIGH, dim_of(lo), aux_of(lo), s, 0, 0);
+                }
+            }
+            break;
+        }
+        }
+        for (int j = 0; j < w; j++) {
+            defs[nd].slot = I->r0 + (unsigned)j;
+            memset(&defs[nd].v, 0, sizeof(or_slot));
+            defs[nd].v.prov = rp | (o->mask_def ? P_MASK : 0);
+            defs[nd].v.type = ty[j];
+            defs[nd].v.val = v[j];
+            nd++;
+        }
+    }
+    /* implicit defs: masks and condition codes carry no value */
+    unsigned imp[5];
+    int ni = 0;
+    if (o->imp_def & I_VCC) { imp[ni++] = 104; imp[ni++] = 105; }
+    if (o->imp_def & I_EXEC) { imp[ni++] = 106; imp[ni++] = 107; }
+    if (o->imp_def & I_SCC) imp[ni++] = 108;
+    for (int j = 0; j < ni; j++) {
+        defs[nd].slot = imp[j];
+        memset(&defs[nd].v, 0, sizeof(or_slot));
+        defs[nd].v.prov = rp | P_MASK;
+        defs[nd].v.type = 0;
+        defs[nd].v.val = TOP;
+        nd++;
+    }
+    return nd;
+}
+
+static void apply(const or_kernel *K, const or_arg *args, const or_instr *I, or_slot *st) {
+    def_t defs[16];
+    int nd = compute_defs(K, args, I, st, defs);
+    for (int j = 0; j < nd; j++) st[defs[j].slot] = defs[j].v;
+}
+
+/* exported for property tests: apply one instruction in place */
+void or_transfer(const or_kernel *K, const or_arg *args, const or_instr *I, or_slot *st) { apply(K, args, I, st); }
+
+/* ------------------------------------------------------------------ */
+/* join                                                                  */
+/* ------------------------------------------------------------------ */
+static void join_into(or_slot *dst, const or_slot *src) {
+    for (int s = 0; s < NSLOT; s++) {
+        dst[s].prov |= src[s].prov;
+        dst[s].type |= src[s].type;
+        if (dst[s].val != src[s].val) dst[s].val = TOP;
+    }
+}
+void or_join(or_slot *dst, const or_slot *src) { join_into(dst, src); }
+
+static int state_eq(const or_slot *a, const or_slot *b) { return memcmp(a, b, sizeof(or_slot) * NSLOT) == 0; }
+
+/* ------------------------------------------------------------------ */
+/* extraction                                                            */
+/* ------------------------------------------------------------------ */
+static int sysval_kind(uint64_t v, unsigned *kind, unsigned *dim) {
+    if (v == TOP) return 0;
+    unsigned t = tag_of(v), ig = integ_of(v), m = aux_of(v), d = dim_of(v);
+    *dim = d;
+    if (t == IDX && c_of(v) == 0) {
+        if (ig == ENTIRE && m == (M_WG | M_LID | M_GOFF)) { *kind = SV_GLOBAL_ID; return 1; }
+        if (ig == ENTIRE && m == (M_WG | M_LID)) { *kind = SV_GLOBAL_ID_MINUS_OFFSET; return 1; }
+        if (ig == LOW && m == M_GOFF) { *kind = SV_GLOBAL_OFFSET; return 1; }
+        if (ig == ENTIRE && m == M_WG) { *kind = SV_GROUP_BASE; return 1; }
+        if (ig == ENTIRE && m == M_LID) { *kind = SV_LOCAL_ID; return 1; }
+    }
+    if (t == SYS && ig == ENTIRE) {
+        if (m == SYS_GSIZE) { *kind = SV_GLOBAL_SIZE; return 1; }
+        if (m == SYS_NUMGROUPS) { *kind = SV_NUM_GROUPS; return 1; }
+        if (m == SYS_WORKDIM) { *kind = SV_WORK_DIM; *dim = 0; return 1; }
+    }
+    if (t == WGID) { *kind = SV_GROUP_ID; return 1; }
+    return 0;
+}
+
+static uint64_t global_address(const or_instr *I, const or_slot *st) {
+    if (I->r2 != NONE_ID) return TOP;
+    uint64_t lo = st[I->r1].val, hi = st[I->r1 + 1].val;
+    if (lo == TOP || hi == TOP) return TOP;
+    if (tag_of(lo) == PTR && integ_of(lo) == LOW && tag_of(hi) == PTR && integ_of(hi) == HIGH && arg_of(lo) == arg_of(hi))
+        return mk(PTR, ENTIRE, dim_of(lo), aux_of(lo), shift_of(lo), arg_of(lo), c_of(lo) + (uint32_t)I->imm);
+    if (tag_of(lo) == KARG && integ_of(lo) == LOW && tag_of(hi) == KARG && integ_of(hi) == HIGH && arg_of(lo) == arg_of(hi))
+        return mk(PTR, ENTIRE, 0, 0, 0, arg_of(lo), (uint32_t)I->imm);
+    return TOP;
+}
+
+static uint64_t lds_address(const or_instr *I, const or_slot *st) {
+    uint64_t v = st[I->r1].val;
+    if (v == TOP) return TOP;
+    uint32_t c = c_of(v) + (uint32_t)I->imm;
+    if (tag_of(v) == SHL && integ_of(v) == ENTIRE) return mk(SHL, ENTIRE, dim_of(v), aux_of(v), shift_of(v), 0, c);
+    if (idx_lowish(v)) return mk(IDX, ENTIRE, dim_of(v), aux_of(v), 0, 0, c);
+    if (is_const(v)) return CONST32(c);
+    return TOP;
+}
+
+/* emit the access record of a memory instruction at pre-state st */
+static int make_access(const or_kernel *K, const or_arg *args, const or_instr *I, uint32_t idx, const or_slot *st, or_access *out) {
+    const opinfo *o = &OPS[I->op];
+    memset(out, 0, sizeof(*out));
+    out->instr = idx;
+    switch (o->cls) {
+    case C_GLOAD: case C_FLOAD: case C_GSTORE: case C_FSTORE:
+        out->kind = (o->cls == C_GLOAD || o->cls == C_FLOAD) ? AK_LOAD : AK_STORE;
+        out->space = (o->cls == C_GLOAD || o->cls == C_GSTORE) ? SP_GLOBAL : SP_FLAT;
+        out->width = (uint8_t)(4 * o->w0);
+        out->addr = global_address(I, st);
+        break;
+    case C_DSREAD: case C_DSWRITE:
+        out->kind = o->cls == C_DSREAD ? AK_LOAD : AK_STORE;
+        out->space = SP_LDS;
+        out->width = 4;
+        out->addr = lds_address(I, st);
+        break;
+    default:
+        return 0;
+    }
+    if (out->kind == AK_STORE) {
+        uint8_t t = 0;
+        for (int j = 0; j < o->w0; j++) t |= st[I->r0 + (unsigned)j].type;
+        out->dtype = t;
+    } else if (out->addr != TOP && tag_of(out->addr) == PTR && arg_of(out->addr) < K->n_args) {
+        out->dtype = (uint8_t)(args[arg_of(out->addr)].flags & 31);
+    }
+    return 1;
+}
+
+/* ------------------------------------------------------------------ */
+/* digest of the fixpoint states                                         */
+/* ------------------------------------------------------------------ */
+static uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+static uint64_t states_digest(uint32_t nb, const or_slot *IN, const uint8_t *reached) {
+    uint64_t h = 0;
+    for (uint32_t b = 0; b < nb; b++) {
+        if (!reached[b]) continue;
+        h += mix64(0xB10C0000ull + b);
+        for (uint32_t s = 0; s < NSLOT; s++) {
+            const or_slot *x = &IN[(size_t)b * NSLOT + s];
+            uint64_t z = mix64(x->val + 0x9E3779B97F4A7C15ull * ((uint64_t)b * NSLOT + s + 1));
+            h += mix64(z ^ ((uint64_t)x->prov | ((uint64_t)x->type << 32)));
+        }
+    }
+    return h;
+}
+
+/* ------------------------------------------------------------------ */
+/* the analysis of one kernel                                           */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int32_t status;
+    uint32_t n_blocks, n_reach, sweeps, n_acc, n_sys, n_pred;
+    uint64_t digest;
+    /* caller buffers (capacities: n_instr+1, 2*(n_instr), n_instr+1, 2*n_instr, n_instr,
+     * n_instr*368 slots or NULL, n_instr, n_instr, 4*n_instr) */
+    uint32_t *block_start;
+    int32_t *succ;
+    uint32_t *pred_off;
+    uint32_t *pred;
+    uint32_t *rpo;
+    or_slot *in_states;
+    uint8_t *reached;
+    or_access *acc;
+    or_sysval *sys;
+} or_result;
+
+static void apply_block(const or_kernel *K, const or_arg *args, const or_instr *I, const cfg_t *G, uint32_t b, or_slot *st) {
+    for (uint32_t i = G->block_start[b]; i < G->block_start[b + 1]; i++) apply(K, args, &I[i], st);
+}
+
+/* next-state pseudo-random generator for worklist shuffles (splitmix64) */
+static uint64_t sm_next(uint64_t *s) {
+    uint64_t z = (*s += 0x9E3779B97F4A7C15ull);
+    return mix64(z);
+}
+
+/*
+ * schedule 0: round-robin passes over the reverse postorder, IN[b] pulled
+ *             from the reached predecessors (the reference; defines `sweeps`:
+ *             the number of passes in which some block's IN changed).
+ * schedule 1: FIFO worklist, IN[s] joined as each predecessor finishes.
+ * schedule 2: worklist that pops a uniformly random queued block (seeded).
+ */
+int or_analyze(const or_kernel *K, const or_instr *I, const or_arg *args, uint32_t sweep_cap, int schedule,
+               uint64_t seed, or_result *R) {
+    R->status = or_kernel_status(K, I);
+    R->n_blocks = R->n_reach = R->sweeps = R->n_acc = R->n_sys = R->n_pred = 0;
+    R->digest = 0;
+    if (R->status != OK) return R->status;
+    uint32_t n = K->n_instr;
+    cfg_t G;
+    build_cfg(I, n, &G);
+    uint32_t nb = G.n_blocks;
+    or_slot *IN = (or_slot *)calloc((size_t)nb * NSLOT, sizeof(or_slot));
+    or_slot *OUT = (or_slot *)calloc((size_t)nb * NSLOT, sizeof(or_slot));
+    uint8_t *reached = (uint8_t *)calloc(nb, 1);
+    or_slot entry[NSLOT], tmp[NSLOT];
+    or_entry_state(K, entry);
+    uint32_t cap = sweep_cap ? sweep_cap : 64 + 2 * nb;
+    uint32_t sweeps = 0;
+    int status = OK;
+
+    if (schedule == 0) {
+        for (;;) {
+            int changed = 0;
+            for (uint32_t r = 0; r < G.n_reach; r++) {
+                uint32_t b = G.rpo[r];
+                int any = 0;
+                if (b == 0) { memcpy(tmp, entry, sizeof(tmp)); any = 1; }
+                for (uint32_t q = G.pred_off[b]; q < G.pred_off[b + 1]; q++) {
+                    uint32_t p = G.pred[q];
+                    if (!reached[p]) continue;
+                    if (!any) { memcpy(tmp, &OUT[(size_t)p * NSLOT], sizeof(tmp)); any = 1; }
+                    else join_into(tmp, &OUT[(size_t)p * NSLOT]);
+                }
+                if (!any) continue;
+                if (!reached[b] || !state_eq(tmp, &IN[(size_t)b * NSLOT])) {
+                    memcpy(&IN[(size_t)b * NSLOT], tmp, sizeof(tmp));
+                    reached[b] = 1;
+                    changed = 1;
+                    memcpy(&OUT[(size_t)b * NSLOT], tmp, sizeof(tmp));
+                    apply_block(K, args, I, &G, b, &OUT[(size_t)b * NSLOT]);
+                }
+            }
+            if (!changed) break;
+            sweeps++;
+            if (sweeps > cap) { status = E_NOFIX; break; }
+        }
+    } else {
+        /* worklist: IN[0] = entry; push-style joins */
+        uint32_t *queue = (uint32_t *)malloc(sizeof(uint32_t) * (nb + 1));
+        uint8_t *queued = (uint8_t *)calloc(nb, 1);
+        uint32_t qh = 0, qn = 0;   /* circular FIFO of at most nb entries */
+        uint64_t rs = seed;
+        uint64_t visits = 0, visit_cap = (uint64_t)(cap + 1) * nb * 64 + 1024;
+        memcpy(&IN[0], entry, sizeof(entry));
+        reached[0] = 1;
+        queue[0] = 0; qn = 1; queued[0] = 1;
+        while (qn) {
+            uint32_t b;
+            if (schedule == 2) {
+                uint32_t k = (uint32_t)(sm_next(&rs) % qn);
+                uint32_t pos = (qh + k) % nb;
+                b = queue[pos];
+                queue[pos] = queue[qh];
+            } else {
+                b = queue[qh];
+            }
+            qh = (qh + 1) % nb;
+            qn--;
+            queued[b] = 0;
+            if (++visits > visit_cap) { status = E_NOFIX; break; }
+            memcpy(&OUT[(size_t)b * NSLOT], &IN[(size_t)b * NSLOT], sizeof(tmp));
+            apply_block(K, args, I, &G, b, &OUT[(size_t)b * NSLOT]);
+            for (int e = 0; e < 2; e++) {
+                int32_t s = G.succ[2 * b + e];
+                if (s < 0) continue;
+                or_slot *dst = &IN[(size_t)s * NSLOT];
+                int upd;
+                if (!reached[s]) {
+                    memcpy(dst, &OUT[(size_t)b * NSLOT], sizeof(tmp));
+                    if (s == 0) join_into(dst, entry);
+                    reached[s] = 1;
+                    upd = 1;
+                } else {
+                    memcpy(tmp, dst, sizeof(tmp));
+                    join_into(dst, &OUT[(size_t)b * NSLOT]);
+                    upd = !state_eq(tmp, dst);
+                }
+                if (upd && !queued[s]) {
+                    queue[(qh + qn) % nb] = (uint32_t)s;
+                    qn++;
+                    queued[s] = 1;
+                }
+            }
+        }
+        free(queue);
+        free(queued);
+        sweeps = 0;   /* not defined for worklist schedules */
+    }
+
+    if (status == OK) {
+        /* fixpoint check: each reached IN equals the join of its inputs */
+        for (uint32_t b = 0; b < nb; b++) {
+            if (!reached[b]) continue;
+            int any = 0;
+            if (b == 0) { memcpy(tmp, entry, sizeof(tmp)); any = 1; }
+            for (uint32_t q = G.pred_off[b]; q < G.pred_off[b + 1]; q++) {
+                uint32_t p = G.pred[q];
+                if (!reached[p]) continue;
+                or_slot o2[NSLOT];
+                memcpy(o2, &IN[(size_t)p * NSLOT], sizeof(o2));
+                apply_block(K, args, I, &G, p, o2);
+                if (!any) { memcpy(tmp, o2, sizeof(tmp)); any = 1; }
+                else join_into(tmp, o2);
+            }
+            if (!any || !state_eq(tmp, &IN[(size_t)b * NSLOT])) { status = -99; break; }
+        }
+    }
+
+    R->status = status;
+    if (status == OK) {
+        R->n_blocks = nb;
+        R->n_reach = G.n_reach;
+        R->sweeps = sweeps;
+        R->n_pred = G.pred_off[nb];
+        if (R->block_start) memcpy(R->block_start, G.block_start, sizeof(uint32_t) * (nb + 1));
+        if (R->succ) memcpy(R->succ, G.succ, sizeof(int32_t) * 2 * nb);
+        if (R->pred_off) memcpy(R->pred_off, G.pred_off, sizeof(uint32_t) * (nb + 1));
+        if (R->pred) memcpy(R->pred, G.pred, sizeof(uint32_t) * G.pred_off[nb]);
+        if (R->rpo) memcpy(R->rpo, G.rpo, sizeof(uint32_t) * G.n_reach);
+        if (R->reached) memcpy(R->reached, reached, nb);
+        for (uint32_t b = 0; b < nb; b++)
+            if (!reached[b]) memset(&IN[(size_t)b * NSLOT], 0, sizeof(or_slot) * NSLOT);
+        if (R->in_states) memcpy(R->in_states, IN, sizeof(or_slot) * NSLOT * nb);
+        R->digest = states_digest(nb, IN, reached);
+        /* extraction: reached blocks in index order, from their IN states */
+        uint32_t na = 0, ns = 0;
+        for (uint32_t b = 0; b < nb; b++) {
+            if (!reached[b]) continue;
+            memcpy(tmp, &IN[(size_t)b * NSLOT], sizeof(tmp));
+            for (uint32_t i = G.block_start[b]; i < G.block_start[b + 1]; i++) {
+                or_access a;
+                if (make_access(K, args, &I[i], i, tmp, &a)) { if (R->acc) R->acc[na] = a; na++; }
+                def_t defs[16];
+                int nd = compute_defs(K, args, &I[i], tmp, defs);
+                for (int j = 0; j < nd; j++) tmp[defs[j].slot] = defs[j].v;
+                /* distinct def slots, ascending */
+                unsigned slots[16];
+                int nslots = 0;
+                for (int j = 0; j < nd; j++) {
+                    int dup = 0;
+                    for (int q = 0; q < nslots; q++) if (slots[q] == defs[j].slot) dup = 1;
+                    if (!dup) slots[nslots++] = defs[j].slot;
+                }
+                for (int x = 1; x < nslots; x++)
+                    for (int y = x; y > 0 && slots[y - 1] > slots[y]; y--) { unsigned t = slots[y]; slots[y] = slots[y - 1]; slots[y - 1] = t; }
+                for (int q = 0; q < nslots; q++) {
+                    unsigned kind, dim;
+                    if (sysval_kind(tmp[slots[q]].val, &kind, &dim)) {
+                        if (R->sys) {
+                            R->sys[ns].instr = i;
+                            R->sys[ns].slot = (uint16_t)slots[q];
+                            R->sys[ns].kind = (uint8_t)kind;
+                            R->sys[ns].dim = (uint8_t)dim;
+                        }
+                        ns++;
+                    }
+                }
+            }
+        }
+        R->n_acc = na;
+        R->n_sys = ns;
+    }
+    free(IN); free(OUT); free(reached);
+    free_cfg(&G);
+    return R->status;
+}
+
+/* Apply the blocks of `path` in order starting from the entry state
+ * (used by the meet-over-all-paths test). */
+int or_apply_path(const or_kernel *K, const or_instr *I, const or_arg *args, const uint32_t *path, uint32_t len, or_slot *out) {
+    if (or_kernel_status(K, I) != OK) return -1;
+    cfg_t G;
+    build_cfg(I, K->n_instr, &G);
+    or_entry_state(K, out);
+    for (uint32_t j = 0; j < len; j++) {
+        if (path[j] >= G.n_blocks) { free_cfg(&G); return -1; }
+        apply_block(K, args, I, &G, path[j], out);
+    }
+    free_cfg(&G);
+    return 0;
+}
+
+/* Apply the blocks of `path` in order to the state in `st` (in place). */
+int or_apply_path_from(const or_kernel *K, const or_instr *I, const or_arg *args, const uint32_t *path, uint32_t len,
+                       or_slot *st) {
+    if (or_kernel_status(K, I) != OK) return -1;
+    cfg_t G;
+    build_cfg(I, K->n_instr, &G);
+    for (uint32_t j = 0; j < len; j++) {
+        if (path[j] >= G.n_blocks) { free_cfg(&G); return -1; }
+        apply_block(K, args, I, &G, path[j], st);
+    }
+    free_cfg(&G);
+    return 0;
+}
+
+/*
+ * Batch driver: per kernel summary (status, n_blocks, sweeps, counts, digest)
+ * and the accesses and system values packed densely in kernel order.
+ * acc/sys capacities are the batch's instruction count and 4x that.
+ */
+typedef struct { int32_t status; uint32_t n_blocks, sweeps, n_acc, n_sys, pad; uint64_t digest; } or_summary;
+
+int or_analyze_batch(const or_kernel *kernels, uint32_t n_kernels, const or_instr *instrs, const or_arg *args,
+                     uint32_t sweep_cap, or_summary *sum, or_access *acc, or_sysval *sys, uint64_t *n_acc_total,
+                     uint64_t *n_sys_total) {
+    uint64_t na = 0, ns = 0;
+    for (uint32_t k = 0; k < n_kernels; k++) {
+        const or_kernel *K = &kernels[k];
+        or_result R;
+        memset(&R, 0, sizeof(R));
+        R.acc = acc ? acc + na : 0;
+        R.sys = sys ? sys + ns : 0;
+        or_analyze(K, instrs + K->instr_begin, args + K->arg_begin, sweep_cap, 0, 0, &R);
+        sum[k].status = R.status;
+        sum[k].n_blocks = R.n_blocks;
+        sum[k].sweeps = R.sweeps;
+        sum[k].n_acc = R.n_acc;
+        sum[k].n_sys = R.n_sys;
+        sum[k].pad = 0;
+        sum[k].digest = R.digest;
+        na += R.n_acc;
+        ns += R.n_sys;
+    }
+    if (n_acc_total) *n_acc_total = na;
+    if (n_sys_total) *n_sys_total = ns;
+    return 0;
+}
