@@ -1,0 +1,211 @@
+/*
+ * dc.h -- C ABI of libdc, the MI355X engine for the register-state dataflow
+ * analysis of GCN kernels (Mihajlenko, Lukin & Stankevich, "A method for
+ * decompilation of AMD GCN kernels to OpenCL").
+ *
+ * The engine runs the part of the paper's method that its Section
+ * "Statement of the problem" lists as steps 2 and 3 -- register and
+ * kernel-parameter initialisation from the ABI, then instruction processing
+ * that builds the control flow graph and determines what each register holds
+ * -- together with the searches of Sections "Search for memory accesses"
+ * (array accesses and work-item built-ins such as get_global_id) and "Data
+ * type recovery" (types from .arg lines and from instruction suffixes).
+ * Input is pre-tokenized: one 16-byte record per instruction (the text front
+ * end of Section "The body extraction" is not part of this library).
+ *
+ * Conventions for every function:
+ *   - the return value is a dc_status_t: DC_OK (0) or a negative code; no
+ *     function aborts or throws;
+ *   - pointers documented as "device" must be HIP device memory of the
+ *     context's device (for example a torch tensor's data_ptr()); all others
+ *     are host memory;
+ *   - the caller owns every input buffer and must keep device inputs alive
+ *     and unchanged until dc_batch_wait / dc_cfg_view returns;
+ *   - the library owns dc_cfg_t / dc_batch_t and their results until the
+ *     matching *_free call;
+ *   - `stream` is a hipStream_t (NULL = the default stream); work is enqueued
+ *     asynchronously on it.
+ * Per-kernel problems (bad records, unsupported descriptors, no fixpoint
+ * within the sweep cap) are reported per kernel and never fail the batch;
+ * call-level errors (DC_E_INVAL, DC_E_HIP, DC_E_OOM) fail the call.
+ */
+#ifndef DC_H
+#define DC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dc_status_t;
+#define DC_OK 0
+#define DC_E_INVAL (-1)        /* null pointer, size out of range, bad option */
+#define DC_E_HIP (-2)          /* a HIP runtime call failed (no device, launch error) */
+#define DC_E_OOM (-3)          /* device or host allocation failed */
+#define DC_E_NOTREADY (-4)     /* result asked for before it exists (e.g. states not exported) */
+#define DC_E_BADOP (-10)       /* per kernel: opcode id outside the instruction subset */
+#define DC_E_BADREG (-11)      /* per kernel: operand id invalid for its role, width or alignment */
+#define DC_E_BADTARGET (-12)   /* per kernel: branch target outside the kernel, or target on a non-branch */
+#define DC_E_NOEND (-13)       /* per kernel: control can fall off the end (last record not s_endpgm/s_branch) */
+#define DC_E_UNSUPPORTED (-14) /* per kernel: descriptor outside the described ABI (useargs=0, dims, cws, args) */
+#define DC_E_NOFIX (-15)       /* per kernel: no fixpoint within the sweep cap */
+
+#define DC_NSLOT 368           /* s0..s103, vcc, exec, scc, m0, 2 reserved, v0..v255 */
+
+/* One instruction (16 bytes, little endian).  Operand ids: 0..103 s0..s103,
+ * 104/105 vcc_lo/hi, 106/107 exec_lo/hi, 108 scc, 109 m0, 112..367 v0..v255,
+ * 0x8000+k inline integer k-16 (k <= 80), 0x8060..0x8067 inline floats
+ * +-0.5, +-1, +-2, +-4, 0xFFFE a literal held in imm, 0xFFFF none.  A
+ * multi-dword operand names its first register.  imm holds a byte offset for
+ * memory instructions and the third source's operand id for three-source ops.
+ * target is the branch target as an instruction index within the kernel, -1
+ * for non-branches.  The opcode numbering is dc_opcode_name(). */
+typedef struct { uint16_t op, r0, r1, r2; int32_t imm; int32_t target; } dc_instr_t;
+
+/* One kernel (32 bytes): its records are instrs[instr_begin .. +n_instr),
+ * its user arguments args[arg_begin .. +n_args).  dims, cws and useargs are
+ * the .dims, .cws and .useargs entries of the kernel's .config section
+ * (Listing 1 and Listing 3 of the paper). */
+typedef struct {
+    uint64_t instr_begin; uint32_t n_instr; uint8_t dims, useargs; uint16_t n_args;
+    uint32_t cws[3]; uint32_t arg_begin;
+} dc_kernel_t;
+
+/* One user kernel argument (.arg line of Listing 3): byte offset in the
+ * argument area addressed by s[4:5] (user arguments follow the six hidden
+ * 8-byte slots, so they start at 0x30), size in bytes (4 or 8), type as a
+ * type-tier bit set (DC_TY_*), flags = pointee type bits for pointers. */
+typedef struct { uint32_t offset; uint16_t size; uint8_t type, flags; } dc_arg_t;
+
+#define DC_TY_INT 1
+#define DC_TY_UINT 2
+#define DC_TY_FLOAT 4
+#define DC_TY_DOUBLE 8
+#define DC_TY_PTR 16
+
+/* Abstract value of one register slot (16 bytes): provenance bits, type
+ * bits, payload (see the design doc for the bit layouts). */
+typedef struct { uint32_t prov; uint8_t type, flags, pad0, pad1; uint64_t val; } dc_reg_state_t;
+
+/* A memory access (16 bytes): instruction index, kind (0 load, 1 store),
+ * space (0 global, 1 flat, 2 LDS), width in bytes, data type bits, address
+ * payload (TOP = 0xFFFFFFFFFFFFFFFF when unresolved). */
+typedef struct { uint32_t instr; uint8_t kind, space, width, dtype; uint64_t addr; } dc_access_t;
+
+/* A recognised work-item built-in (8 bytes): instruction index, register
+ * slot that holds it after the instruction, kind (DC_SV_*), dimension. */
+typedef struct { uint32_t instr; uint16_t slot; uint8_t kind, dim; } dc_sysval_t;
+
+#define DC_SV_GLOBAL_ID 0
+#define DC_SV_GLOBAL_ID_MINUS_OFFSET 1
+#define DC_SV_GLOBAL_OFFSET 2
+#define DC_SV_GLOBAL_SIZE 3
+#define DC_SV_NUM_GROUPS 4
+#define DC_SV_WORK_DIM 5
+#define DC_SV_GROUP_BASE 6
+#define DC_SV_LOCAL_ID 7
+#define DC_SV_GROUP_ID 8
+
+/* Per-kernel result summary (32 bytes).  For a failed kernel everything but
+ * status is zero.  digest is filled only with DC_OPT_DIGEST. */
+typedef struct {
+    int32_t status; uint32_t n_blocks, sweeps, n_access, n_sysval, pad; uint64_t digest;
+} dc_kernel_result_t;
+
+/* Options.  flags: */
+#define DC_OPT_EXPORT_STATES 1u  /* keep every block's fixpoint IN state for dc_get_block_state */
+#define DC_OPT_DIGEST 2u         /* compute the per-kernel digest of the fixpoint states */
+#define DC_OPT_TIMING 4u         /* record HIP events around the stages (dc_get_stats ms_*) */
+typedef struct {
+    uint32_t flags;
+    uint32_t sweep_cap;          /* 0 = 64 + 2 * n_blocks per kernel */
+    uint32_t waves_per_group;    /* fixpoint kernel: waves per workgroup (0 = 4) */
+    uint32_t groups_per_cu;      /* fixpoint kernel: resident workgroups per CU in the persistent grid (0 = auto) */
+    uint32_t block_cap;          /* blocks a kernel may have in the main pass (0 = 256); larger go to the overflow pass */
+    uint32_t reserved[3];
+} dc_options_t;
+
+typedef struct {
+    uint64_t n_kernels, n_instr, n_blocks, n_unreached, sweeps_sum, n_access, n_sysval, bytes_alg;
+    uint32_t sweeps_max, n_failed, n_overflow, pad;
+    float ms_total, ms_decode, ms_cfg, ms_fixpoint, ms_compact, ms_pad;
+} dc_stats_t;
+
+typedef struct {
+    int32_t status;
+    uint32_t n_blocks, n_reach, n_pred;
+    const uint32_t *block_start;   /* n_blocks + 1 instruction indices */
+    const int32_t *succ;           /* 2 per block: fall-through, taken (-1 = none) */
+    const uint32_t *pred_off;      /* n_blocks + 1 */
+    const uint32_t *pred;          /* predecessors per block, ascending */
+    const uint32_t *rpo;           /* reachable blocks in reverse postorder (DFS from block 0, fall-through first) */
+} dc_cfg_view_t;
+
+typedef struct dc_ctx dc_ctx_t;
+typedef struct dc_cfg dc_cfg_t;
+typedef struct dc_batch dc_batch_t;
+
+/* Context on one HIP device.  Fails with DC_E_HIP when the device is absent. */
+dc_status_t dc_ctx_create(int hip_device, dc_ctx_t **out);
+void dc_ctx_destroy(dc_ctx_t *ctx);
+
+/* Steps a1-a4 only (decode and validate, leaders, block numbering, edges,
+ * predecessor CSR, reverse postorder) for n_kernels kernels whose records
+ * are in `instrs` (device, n_records entries).  Section "Search for control
+ * structures": the control flow graph is built first.  Synchronous w.r.t.
+ * the returned object: dc_cfg_view waits for the stream. */
+dc_status_t dc_build_cfg(dc_ctx_t *ctx, const dc_kernel_t *kernels, uint32_t n_kernels, const dc_instr_t *instrs,
+                         uint64_t n_records, void *stream, dc_cfg_t **out);
+/* Host view of kernel k's graph; the arrays stay valid until dc_cfg_free. */
+dc_status_t dc_cfg_view(dc_cfg_t *cfg, uint32_t k, dc_cfg_view_t *view);
+void dc_cfg_free(dc_cfg_t *cfg);
+
+/* The whole analysis (steps a1-a9) for a batch.  kernels and args are host
+ * arrays (copied before return); instrs is device memory.  opts may be NULL.
+ * Enqueues on `stream` and returns; results are ready after dc_batch_wait.
+ * With DC_OPT_EXPORT_STATES the call synchronises the stream once to size
+ * the state export. */
+dc_status_t dc_analyze_batch(dc_ctx_t *ctx, const dc_kernel_t *kernels, uint32_t n_kernels, const dc_instr_t *instrs,
+                             uint64_t n_records, const dc_arg_t *args, uint64_t n_args_total,
+                             const dc_options_t *opts, void *stream, dc_batch_t **out);
+/* Run the same batch again on `instrs` (same layout; NULL = the previous
+ * pointer).  Results are overwritten.  Allocates nothing. */
+dc_status_t dc_batch_run(dc_batch_t *batch, const dc_instr_t *instrs, void *stream);
+dc_status_t dc_batch_wait(dc_batch_t *batch);
+
+dc_status_t dc_get_kernel_status(const dc_batch_t *batch, uint32_t k, dc_status_t *st);
+dc_status_t dc_get_kernel_result(const dc_batch_t *batch, uint32_t k, dc_kernel_result_t *out);
+/* All n_kernels summaries into out[cap]. */
+dc_status_t dc_get_results(const dc_batch_t *batch, dc_kernel_result_t *out, uint32_t cap);
+/* Two-call idiom: always sets *n_total, copies min(cap, n_total) records. */
+dc_status_t dc_get_accesses(const dc_batch_t *batch, uint32_t k, dc_access_t *buf, uint32_t cap, uint32_t *n_total);
+dc_status_t dc_get_sysvals(const dc_batch_t *batch, uint32_t k, dc_sysval_t *buf, uint32_t cap, uint32_t *n_total);
+/* Every kernel's records packed in kernel order; offsets (n_kernels + 1
+ * entries, may be NULL) give each kernel's range. */
+dc_status_t dc_get_all_accesses(const dc_batch_t *batch, dc_access_t *buf, uint64_t cap, uint64_t *n_total,
+                                uint64_t *offsets);
+dc_status_t dc_get_all_sysvals(const dc_batch_t *batch, dc_sysval_t *buf, uint64_t cap, uint64_t *n_total,
+                               uint64_t *offsets);
+/* Fixpoint IN state of one block (needs DC_OPT_EXPORT_STATES). */
+dc_status_t dc_get_block_state(const dc_batch_t *batch, uint32_t k, uint32_t block, dc_reg_state_t *out368,
+                               uint8_t *reached);
+dc_status_t dc_get_stats(const dc_batch_t *batch, dc_stats_t *out);
+
+/* Stage times summed over the runs enqueued since the last reset (at most
+ * the last 64), from HIP events recorded on the batch's stream (needs
+ * DC_OPT_TIMING).  ms_fixpoint brackets exactly the main fixpoint kernel
+ * launch.  Waits for the stream. */
+typedef struct { uint32_t runs, pad; float ms_total, ms_decode, ms_cfg, ms_fixpoint, ms_compact, ms_pad; } dc_timing_t;
+dc_status_t dc_get_timing(const dc_batch_t *batch, dc_timing_t *out);
+dc_status_t dc_timing_reset(dc_batch_t *batch);
+void dc_batch_free(dc_batch_t *batch);
+
+const char *dc_status_str(dc_status_t st);
+int dc_opcode_count(void);
+const char *dc_opcode_name(int id);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,696 @@
+/*
+ * dc_api.cpp -- the C ABI of libdc (declared in include/dc.h): batch
+ * planning and checks on the host, device allocation, stage enqueue on the
+ * caller's stream, and result getters.
+ */
+#include <hip/hip_runtime_api.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "dc.h"
+#include "dc_internal.h"
+
+using namespace dc;
+
+static const char *const OPCODE_NAMES[N_OPS] = {
+    "s_load_dword", "s_load_dwordx2", "s_load_dwordx4", "s_mov_b32", "s_mov_b64", "s_and_saveexec_b64",
+    "s_or_saveexec_b64", "s_add_u32", "s_add_i32", "s_addc_u32", "s_sub_u32", "s_mul_i32", "s_lshl_b32",
+    "s_lshr_b32", "s_and_b32", "s_or_b32", "s_and_b64", "s_or_b64", "s_xor_b64", "s_andn2_b64", "s_cmp_eq_u32",
+    "s_cmp_lt_u32", "s_cmp_gt_u32", "s_cmp_lt_i32", "s_branch", "s_cbranch_scc0", "s_cbranch_scc1",
+    "s_cbranch_vccz", "s_cbranch_vccnz", "s_cbranch_execz", "s_cbranch_execnz", "s_waitcnt", "s_barrier", "s_nop",
+    "s_endpgm", "v_mov_b32", "v_cvt_f32_u32", "v_cvt_u32_f32", "v_cvt_f64_f32", "v_add_co_u32", "v_addc_co_u32",
+    "v_sub_co_u32", "v_add_u32", "v_mul_lo_u32", "v_mul_u32_u24", "v_mul_hi_u32", "v_mad_u32_u24",
+    "v_lshlrev_b32", "v_lshrrev_b32", "v_ashrrev_i32", "v_and_b32", "v_or_b32", "v_xor_b32", "v_lshlrev_b64",
+    "v_cndmask_b32", "v_add_f32", "v_sub_f32", "v_mul_f32", "v_max_f32", "v_mad_f32", "v_fma_f32", "v_add_f64",
+    "v_mul_f64", "v_fma_f64", "v_cmp_eq_u32", "v_cmp_gt_u32", "v_cmp_lt_u32", "v_cmp_lt_i32", "v_cmp_gt_f32",
+    "global_load_dword", "global_load_dwordx2", "flat_load_dword", "global_store_dword", "global_store_dwordx2",
+    "flat_store_dword", "ds_read_b32", "ds_write_b32",
+};
+
+struct dc_ctx {
+    int device;
+    int n_cu;
+    size_t lds_per_cu;
+};
+
+/* one device allocation list per object, freed together */
+struct DevMem {
+    std::vector<void *> ptrs;
+    bool failed = false;
+    template <typename T>
+    T *alloc(uint64_t count) {
+        void *p = nullptr;
+        uint64_t bytes = count * sizeof(T);
+        if (bytes == 0) bytes = 16;
+        bytes = (bytes + 255) & ~255ull;
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            failed = true;
+            return nullptr;
+        }
+        ptrs.push_back(p);
+        return static_cast<T *>(p);
+    }
+    void release(void *p) {
+        auto it = std::find(ptrs.begin(), ptrs.end(), p);
+        if (it != ptrs.end()) {
+            hipFree(p);
+            ptrs.erase(it);
+        }
+    }
+    ~DevMem() {
+        for (void *p : ptrs) hipFree(p);
+    }
+};
+
+/* HIP events per run: start, after a1-a2, after a3-a4, right before and
+ * right after the main fixpoint launch, end */
+enum { EV_START, EV_DECODE, EV_CFG, EV_FIXB, EV_FIX, EV_END, N_EV };
+constexpr int TIMING_RING = 64;
+
+struct dc_batch {
+    dc_ctx *ctx = nullptr;
+    hipStream_t stream = nullptr;
+    bool cfg_only = false;
+    dc_options_t opts{};
+    uint32_t K = 0;
+    uint64_t N = 0;
+    uint64_t n_records = 0, n_args_total = 0;
+    DevMem mem;
+    Plan P{};
+    Plan *dP = nullptr;
+    FixCfg fc{};
+    std::vector<dc_kernel_t> kernels;
+    std::vector<uint32_t> pos_begin;
+    hipEvent_t ev[TIMING_RING][N_EV] = {};
+    bool have_events = false;
+    uint64_t runs = 0, runs_at_reset = 0;   /* enqueued runs; ring slot = run % TIMING_RING */
+    uint64_t export_blocks = 0;
+    /* host copies, filled on first use after a run */
+    bool host_valid = false;
+    std::vector<dc_kernel_result_t> results;
+    std::vector<uint32_t> acc_off, sys_off;
+    std::vector<dc_access_t> acc;
+    std::vector<dc_sysval_t> sys;
+    std::vector<uint32_t> first_block;
+    std::vector<dc_reg_state_t> states;
+    std::vector<uint8_t> reached;
+    /* CFG view copies */
+    std::vector<int32_t> k_status;
+    std::vector<uint32_t> k_nblocks, k_nreach, h_block_start, h_pred_off, h_pred, h_rpo;
+    std::vector<int32_t> h_succ;
+    std::vector<uint32_t> v_block_start, v_pred_off;   /* scratch for one view */
+};
+struct dc_cfg {
+    dc_batch b;
+};
+
+static dc_status_t hip_fail(hipError_t e) { return e == hipErrorOutOfMemory ? DC_E_OOM : DC_E_HIP; }
+
+extern "C" const char *dc_status_str(dc_status_t st) {
+    switch (st) {
+    case DC_OK: return "ok";
+    case DC_E_INVAL: return "invalid argument";
+    case DC_E_HIP: return "HIP runtime error";
+    case DC_E_OOM: return "out of memory";
+    case DC_E_NOTREADY: return "result not available";
+    case DC_E_BADOP: return "opcode outside the instruction subset";
+    case DC_E_BADREG: return "operand invalid for its role";
+    case DC_E_BADTARGET: return "branch target out of range";
+    case DC_E_NOEND: return "control falls off the end";
+    case DC_E_UNSUPPORTED: return "unsupported kernel descriptor";
+    case DC_E_NOFIX: return "no fixpoint within the sweep cap";
+    }
+    return "unknown status";
+}
+
+extern "C" int dc_opcode_count(void) { return N_OPS; }
+extern "C" const char *dc_opcode_name(int id) { return (id >= 0 && id < N_OPS) ? OPCODE_NAMES[id] : nullptr; }
+
+extern "C" dc_status_t dc_ctx_create(int hip_device, dc_ctx_t **out) {
+    if (!out) return DC_E_INVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || hip_device < 0 || hip_device >= n) return DC_E_HIP;
+    if (hipSetDevice(hip_device) != hipSuccess) return DC_E_HIP;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) return DC_E_HIP;
+    dc_ctx *c = new (std::nothrow) dc_ctx;
+    if (!c) return DC_E_OOM;
+    c->device = hip_device;
+    c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
+    c->lds_per_cu = prop.maxSharedMemoryPerMultiProcessor ? prop.maxSharedMemoryPerMultiProcessor : 65536;
+    *out = c;
+    return DC_OK;
+}
+
+extern "C" void dc_ctx_destroy(dc_ctx_t *ctx) { delete ctx; }
+
+/* descriptor checks that need no records (per kernel) */
+static int32_t descriptor_status(const dc_kernel_t &k) {
+    if (k.useargs != 1) return DC_E_UNSUPPORTED;
+    if (k.dims < 1 || k.dims > 3) return DC_E_UNSUPPORTED;
+    for (int d = 0; d < k.dims; d++)
+        if (k.cws[d] == 0) return DC_E_UNSUPPORTED;
+    if (k.n_args > 255) return DC_E_UNSUPPORTED;
+    return DC_OK;
+}
+
+static dc_status_t plan_batch(dc_batch *B, dc_ctx *ctx, const dc_kernel_t *kernels, uint32_t n_kernels,
+                              const dc_instr_t *instrs, uint64_t n_records, const dc_arg_t *args, uint64_t n_args_total,
+                              const dc_options_t *opts, void *stream, bool cfg_only) {
+    if (!ctx || (n_kernels && !kernels) || (n_records && !instrs) || (n_args_total && !args)) return DC_E_INVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return DC_E_HIP;
+    B->ctx = ctx;
+    B->stream = (hipStream_t)stream;
+    B->cfg_only = cfg_only;
+    if (opts) B->opts = *opts;
+    if (B->opts.flags & ~(DC_OPT_EXPORT_STATES | DC_OPT_DIGEST | DC_OPT_TIMING)) return DC_E_INVAL;
+    if (B->opts.waves_per_group == 0) B->opts.waves_per_group = 4;
+    if (B->opts.waves_per_group > 4) return DC_E_INVAL;
+    if (B->opts.block_cap == 0) B->opts.block_cap = 256;
+    if (B->opts.block_cap > 2048) return DC_E_INVAL;   /* the main pass keeps its bitmaps in LDS */
+    B->K = n_kernels;
+    B->n_records = n_records;
+    B->n_args_total = n_args_total;
+    B->kernels.assign(kernels, kernels + n_kernels);
+    B->pos_begin.resize((size_t)n_kernels + 1);
+    std::vector<int32_t> dstat(n_kernels);
+    uint64_t pos = 0, max_len = 0;
+    for (uint32_t k = 0; k < n_kernels; k++) {
+        const dc_kernel_t &d = kernels[k];
+        if (d.instr_begin > n_records || d.n_instr > n_records - d.instr_begin) return DC_E_INVAL;
+        dstat[k] = descriptor_status(d);
+        if (dstat[k] == DC_OK && ((uint64_t)d.arg_begin + d.n_args > n_args_total)) return DC_E_INVAL;
+        B->pos_begin[k] = (uint32_t)pos;
+        pos += d.n_instr;
+        max_len = std::max<uint64_t>(max_len, d.n_instr);
+        if (pos >= 0xFFFFFFF0ull) return DC_E_INVAL;   /* positions are 32-bit */
+    }
+    B->pos_begin[n_kernels] = (uint32_t)pos;
+    B->N = pos;
+    const uint64_t N = pos, K = n_kernels;
+    DevMem &M = B->mem;
+    Plan &P = B->P;
+    P.instrs = instrs;
+    P.n_kernels = n_kernels;
+    P.n_pos = (uint32_t)N;
+    P.n_records = n_records;
+    P.n_args = n_args_total;
+    dc_kernel_t *d_k = M.alloc<dc_kernel_t>(K);
+    dc_arg_t *d_a = M.alloc<dc_arg_t>(n_args_total);
+    uint32_t *d_pb = M.alloc<uint32_t>(K + 1);
+    int32_t *d_ds = M.alloc<int32_t>(K);
+    P.kernels = d_k;
+    P.args = d_a;
+    P.pos_begin = d_pb;
+    P.desc_status = d_ds;
+    P.leader = M.alloc<uint8_t>(N + 16);
+    P.block_id = M.alloc<uint32_t>(N);
+    P.block_start = M.alloc<uint32_t>(N + 1);
+    P.block_kernel = M.alloc<uint32_t>(N);
+    P.succ = M.alloc<int32_t>(2 * N);
+    P.pred_cnt = M.alloc<uint32_t>(N + 1);
+    P.pred_fill = M.alloc<uint32_t>(N);
+    P.pred = M.alloc<uint32_t>(2 * N);
+    P.rpo = M.alloc<uint32_t>(N);
+    P.rpo_pos = M.alloc<int32_t>(N);
+    P.dfs_stack = M.alloc<uint32_t>(N);
+    P.dfs_seen = M.alloc<uint8_t>(N);
+    P.kbad = M.alloc<uint32_t>(K);
+    P.status = M.alloc<int32_t>(K);
+    P.first_block = M.alloc<uint32_t>(K);
+    P.n_blocks = M.alloc<uint32_t>(K);
+    P.n_reach = M.alloc<uint32_t>(K);
+    P.total_blocks = M.alloc<uint32_t>(4);
+    P.scan_tmp_words = scan_tmp_words_needed(std::max<uint64_t>(N + 1, K + 1));
+    P.scan_tmp = M.alloc<uint32_t>(P.scan_tmp_words);
+    if (!cfg_only) {
+        const uint32_t wpg = B->opts.waves_per_group;
+        /* resident groups: LDS, then the register budget of the fixpoint kernel */
+        const size_t lds_group = (size_t)wpg * ((NSLOT + 64) * 16 + (2 * 64 + 64) * 4);
+        uint32_t per_cu = B->opts.groups_per_cu;
+        if (per_cu == 0) {
+            per_cu = (uint32_t)std::max<size_t>(1, std::min<size_t>(ctx->lds_per_cu / lds_group, 12 / wpg));
+        }
+        B->fc.waves_per_group = (int)wpg;
+        B->fc.groups = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)ctx->n_cu * per_cu, (K + wpg - 1) / wpg));
+        P.block_cap = B->opts.block_cap;
+        const uint64_t waves = (uint64_t)B->fc.groups * wpg;
+        P.arena = M.alloc<uint4>(waves * P.block_cap * NSLOT);
+        P.bitmaps = nullptr;
+        /* overflow pass: kernels with more blocks than block_cap; a kernel has
+         * at most as many blocks as instructions */
+        uint64_t ovf_cap = std::max<uint64_t>(max_len, 1);
+        uint64_t ovf_waves = 64;
+        const uint64_t budget = 8ull << 30;
+        while (ovf_waves > 1 && ovf_waves * ovf_cap * NSLOT * 16 > budget) ovf_waves /= 2;
+        if (max_len <= P.block_cap) { ovf_cap = 1; ovf_waves = 1; }
+        P.ovf_block_cap = (uint32_t)ovf_cap;
+        P.ovf_waves = (uint32_t)ovf_waves;
+        P.ovf_arena = M.alloc<uint4>(ovf_waves * ovf_cap * NSLOT);
+        P.ovf_bitmaps = M.alloc<uint32_t>(ovf_waves * (2 * ((ovf_cap + 31) / 32) + 64));
+        P.ovf_list = M.alloc<uint32_t>(K);
+        P.counters = M.alloc<uint32_t>(4);
+        P.sweep_cap = B->opts.sweep_cap;
+        P.flags = B->opts.flags;
+        P.acc_sparse = M.alloc<dc_access_t>(N);
+        P.sys_sparse = M.alloc<dc_sysval_t>(4 * N);
+        P.results = M.alloc<dc_kernel_result_t>(K);
+        P.acc_count = M.alloc<uint32_t>(K + 1);
+        P.sys_count = M.alloc<uint32_t>(K + 1);
+        P.acc_dense = M.alloc<dc_access_t>(N);
+        P.sys_dense = M.alloc<dc_sysval_t>(4 * N);
+        P.export_states = nullptr;
+        P.export_reached = nullptr;
+    }
+    B->dP = M.alloc<Plan>(1);
+    if (M.failed) return DC_E_OOM;
+    hipStream_t s = B->stream;
+    hipError_t e = hipSuccess;
+    if (K) e = hipMemcpyAsync(d_k, kernels, K * sizeof(dc_kernel_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && n_args_total)
+        e = hipMemcpyAsync(d_a, args, n_args_total * sizeof(dc_arg_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_pb, B->pos_begin.data(), (K + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && K) e = hipMemcpyAsync(d_ds, dstat.data(), K * sizeof(int32_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(B->dP, &P, sizeof(Plan), hipMemcpyHostToDevice, s);
+    /* the host vectors above are stack/batch owned: make the copies complete */
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e);
+    if (B->opts.flags & DC_OPT_TIMING) {
+        for (int r = 0; r < TIMING_RING; r++)
+            for (int i = 0; i < N_EV; i++)
+                if (hipEventCreate(&B->ev[r][i]) != hipSuccess) return DC_E_HIP;
+        B->have_events = true;
+    }
+    return DC_OK;
+}
+
+static dc_status_t enqueue(dc_batch *B) {
+    Plan &P = B->P;
+    hipStream_t s = B->stream;
+    hipError_t e = hipSuccess;
+    B->host_valid = false;
+    hipEvent_t *ev = B->ev[B->runs % TIMING_RING];
+#define TRY(x)                                  \
+    do {                                        \
+        e = (x);                                \
+        if (e != hipSuccess) return hip_fail(e); \
+    } while (0)
+    if (B->have_events) TRY(hipEventRecord(ev[EV_START], s));
+    TRY(launch_fill_u8(P.leader, B->N, 0, s));
+    TRY(launch_fill_u32(P.kbad, B->K, 0xFFFFFFFFu, s));
+    TRY(launch_decode(P, s));
+    if (B->have_events) TRY(hipEventRecord(ev[EV_DECODE], s));
+    TRY(launch_number_blocks(P, s));
+    TRY(launch_edges(P, s));
+    if (B->have_events) TRY(hipEventRecord(ev[EV_CFG], s));
+    if (B->cfg_only) {
+        if (B->have_events) {
+            TRY(hipEventRecord(ev[EV_FIXB], s));
+            TRY(hipEventRecord(ev[EV_FIX], s));
+            TRY(hipEventRecord(ev[EV_END], s));
+        }
+        B->runs++;
+        return DC_OK;
+    }
+    if (B->opts.flags & DC_OPT_EXPORT_STATES) {
+        /* size the state export from the block count */
+        uint32_t total = 0;
+        TRY(hipMemcpyAsync(&total, P.total_blocks, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        TRY(hipStreamSynchronize(s));
+        if (total > B->export_blocks || !P.export_states) {
+            if (P.export_states) B->mem.release(P.export_states);
+            if (P.export_reached) B->mem.release(P.export_reached);
+            P.export_states = B->mem.alloc<dc_reg_state_t>((uint64_t)std::max<uint32_t>(total, 1) * NSLOT);
+            P.export_reached = B->mem.alloc<uint8_t>(std::max<uint32_t>(total, 1));
+            if (B->mem.failed) return DC_E_OOM;
+            B->export_blocks = total;
+        }
+        TRY(hipMemcpyAsync(B->dP, &P, sizeof(Plan), hipMemcpyHostToDevice, s));
+        TRY(hipStreamSynchronize(s));
+    }
+    TRY(launch_fixpoint(P, B->dP, B->fc, s, B->have_events ? ev[EV_FIXB] : nullptr,
+                        B->have_events ? ev[EV_FIX] : nullptr));
+    TRY(launch_compact(P, s));
+    if (B->have_events) TRY(hipEventRecord(ev[EV_END], s));
+    B->runs++;
+#undef TRY
+    return DC_OK;
+}
+
+extern "C" dc_status_t dc_analyze_batch(dc_ctx_t *ctx, const dc_kernel_t *kernels, uint32_t n_kernels,
+                                        const dc_instr_t *instrs, uint64_t n_records, const dc_arg_t *args,
+                                        uint64_t n_args_total, const dc_options_t *opts, void *stream,
+                                        dc_batch_t **out) {
+    if (!out) return DC_E_INVAL;
+    *out = nullptr;
+    dc_batch *B = new (std::nothrow) dc_batch;
+    if (!B) return DC_E_OOM;
+    dc_status_t st = plan_batch(B, ctx, kernels, n_kernels, instrs, n_records, args, n_args_total, opts, stream, false);
+    if (st == DC_OK) st = enqueue(B);
+    if (st != DC_OK) {
+        hipStreamSynchronize(B->stream);
+        delete B;
+        return st;
+    }
+    *out = B;
+    return DC_OK;
+}
+
+extern "C" dc_status_t dc_batch_run(dc_batch_t *B, const dc_instr_t *instrs, void *stream) {
+    if (!B || B->cfg_only) return DC_E_INVAL;
+    if (hipSetDevice(B->ctx->device) != hipSuccess) return DC_E_HIP;
+    B->stream = (hipStream_t)stream;
+    if (instrs && instrs != B->P.instrs) {
+        B->P.instrs = instrs;
+        if (hipMemcpyAsync(B->dP, &B->P, sizeof(Plan), hipMemcpyHostToDevice, B->stream) != hipSuccess) return DC_E_HIP;
+        if (hipStreamSynchronize(B->stream) != hipSuccess) return DC_E_HIP;
+    }
+    return enqueue(B);
+}
+
+extern "C" dc_status_t dc_batch_wait(dc_batch_t *B) {
+    if (!B) return DC_E_INVAL;
+    if (hipSetDevice(B->ctx->device) != hipSuccess) return DC_E_HIP;
+    hipError_t e = hipStreamSynchronize(B->stream);
+    return e == hipSuccess ? DC_OK : hip_fail(e);
+}
+
+/* copy results to the host once per run */
+static dc_status_t fetch(dc_batch *B) {
+    if (B->host_valid) return DC_OK;
+    dc_status_t st = dc_batch_wait(B);
+    if (st != DC_OK) return st;
+    const Plan &P = B->P;
+    const uint32_t K = B->K;
+    hipError_t e = hipSuccess;
+    B->results.resize(K);
+    B->acc_off.resize((size_t)K + 1);
+    B->sys_off.resize((size_t)K + 1);
+    if (K) e = hipMemcpy(B->results.data(), P.results, K * sizeof(dc_kernel_result_t), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(B->acc_off.data(), P.acc_count, (K + 1) * sizeof(uint32_t), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(B->sys_off.data(), P.sys_count, (K + 1) * sizeof(uint32_t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e);
+    const uint64_t na = B->acc_off[K], ns = B->sys_off[K];
+    B->acc.resize(na);
+    B->sys.resize(ns);
+    if (na) e = hipMemcpy(B->acc.data(), P.acc_dense, na * sizeof(dc_access_t), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && ns) e = hipMemcpy(B->sys.data(), P.sys_dense, ns * sizeof(dc_sysval_t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e);
+    if (B->opts.flags & DC_OPT_EXPORT_STATES) {
+        B->first_block.resize(K);
+        B->states.resize(B->export_blocks * NSLOT);
+        B->reached.resize(B->export_blocks);
+        if (K) e = hipMemcpy(B->first_block.data(), P.first_block, K * sizeof(uint32_t), hipMemcpyDeviceToHost);
+        if (e == hipSuccess && B->export_blocks)
+            e = hipMemcpy(B->states.data(), P.export_states, B->export_blocks * NSLOT * sizeof(dc_reg_state_t),
+                          hipMemcpyDeviceToHost);
+        if (e == hipSuccess && B->export_blocks)
+            e = hipMemcpy(B->reached.data(), P.export_reached, B->export_blocks, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    B->host_valid = true;
+    return DC_OK;
+}
+
+extern "C" dc_status_t dc_get_kernel_result(const dc_batch_t *cb, uint32_t k, dc_kernel_result_t *out) {
+    dc_batch *B = const_cast<dc_batch *>(cb);
+    if (!B || !out || B->cfg_only || k >= B->K) return DC_E_INVAL;
+    dc_status_t st = fetch(B);
+    if (st != DC_OK) return st;
+    *out = B->results[k];
+    return DC_OK;
+}
+
+extern "C" dc_status_t dc_get_kernel_status(const dc_batch_t *cb, uint32_t k, dc_status_t *out) {
+    dc_kernel_result_t r;
+    if (!out) return DC_E_INVAL;
+    dc_status_t st = dc_get_kernel_result(cb, k, &r);
+    if (st == DC_OK) *out = r.status;
+    return st;
+}
+
+extern "C" dc_status_t dc_get_results(const dc_batch_t *cb, dc_kernel_result_t *out, uint32_t cap) {
+    dc_batch *B = const_cast<dc_batch *>(cb);
+    if (!B || (cap && !out) || B->cfg_only) return DC_E_INVAL;
+    dc_status_t st = fetch(B);
+    if (st != DC_OK) return st;
+    if (std::min<uint64_t>(cap, B->K)) memcpy(out, B->results.data(), sizeof(dc_kernel_result_t) * std::min<uint64_t>(cap, B->K));
+    return DC_OK;
+}
+
+template <typename T>
+static dc_status_t get_records(dc_batch *B, const std::vector<T> &all, const std::vector<uint32_t> &off, uint32_t k,
+                               T *buf, uint32_t cap, uint32_t *n_total) {
+    if (!n_total || (cap && !buf) || k >= B->K) return DC_E_INVAL;
+    const uint32_t n = off[k + 1] - off[k];
+    *n_total = n;
+    if (std::min(cap, n)) memcpy(buf, all.data() + off[k], sizeof(T) * std::min(cap, n));
+    return DC_OK;
+}
+
+extern "C" dc_status_t dc_get_accesses(const dc_batch_t *cb, uint32_t k, dc_access_t *buf, uint32_t cap,
+                                       uint32_t *n_total) {
+    dc_batch *B = const_cast<dc_batch *>(cb);
+    if (!B || B->cfg_only) return DC_E_INVAL;
+    dc_status_t st = fetch(B);
+    if (st != DC_OK) return st;
+    return get_records(B, B->acc, B->acc_off, k, buf, cap, n_total);
+}
+
+extern "C" dc_status_t dc_get_sysvals(const dc_batch_t *cb, uint32_t k, dc_sysval_t *buf, uint32_t cap,
+                                      uint32_t *n_total) {
+    dc_batch *B = const_cast<dc_batch *>(cb);
+    if (!B || B->cfg_only) return DC_E_INVAL;
+    dc_status_t st = fetch(B);
+    if (st != DC_OK) return st;
+    return get_records(B, B->sys, B->sys_off, k, buf, cap, n_total);
+}
+
+template <typename T>
+static dc_status_t get_all(dc_batch *B, const std::vector<T> &all, const std::vector<uint32_t> &off, T *buf,
+                           uint64_t cap, uint64_t *n_total, uint64_t *offsets) {
+    if (!n_total || (cap && !buf)) return DC_E_INVAL;
+    *n_total = all.size();
+    if (std::min<uint64_t>(cap, all.size())) memcpy(buf, all.data(), sizeof(T) * std::min<uint64_t>(cap, all.size()));
+    if (offsets)
+        for (uint32_t k = 0; k <= B->K; k++) offsets[k] = off[k];
+    return DC_OK;
+}
+
+extern "C" dc_status_t dc_get_all_accesses(const dc_batch_t *cb, dc_access_t *buf, uint64_t cap, uint64_t *n_total,
+                                           uint64_t *offsets) {
+    dc_batch *B = const_cast<dc_batch *>(cb);
+    if (!B || B->cfg_only) return DC_E_INVAL;
+    dc_status_t st = fetch(B);
+    if (st != DC_OK) return st;
+    return get_all(B, B->acc, B->acc_off, buf, cap, n_total, offsets);
+}
+
+extern "C" dc_status_t dc_get_all_sysvals(const dc_batch_t *cb, dc_sysval_t *buf, uint64_t cap, uint64_t *n_total,
+                                          uint64_t *offsets) {
+    dc_batch *B = const_cast<dc_batch *>(cb);
+    if (!B || B->cfg_only) return DC_E_INVAL;
+    dc_status_t st = fetch(B);
+    if (st != DC_OK) return st;
+    return get_all(B, B->sys, B->sys_off, buf, cap, n_total, offsets);
+}
+
+extern "C" dc_status_t dc_get_block_state(const dc_batch_t *cb, uint32_t k, uint32_t block, dc_reg_state_t *out368,
+                                          uint8_t *reached) {
+    dc_batch *B = const_cast<dc_batch *>(cb);
+    if (!B || !out368 || B->cfg_only || k >= B->K) return DC_E_INVAL;
+    if (!(B->opts.flags & DC_OPT_EXPORT_STATES)) return DC_E_NOTREADY;
+    dc_status_t st = fetch(B);
+    if (st != DC_OK) return st;
+    const dc_kernel_result_t &r = B->results[k];
+    if (r.status != DC_OK || block >= r.n_blocks) return DC_E_INVAL;
+    const uint64_t g = (uint64_t)B->first_block[k] + block;
+    memcpy(out368, B->states.data() + g * NSLOT, sizeof(dc_reg_state_t) * NSLOT);
+    if (reached) *reached = B->reached[g];
+    return DC_OK;
+}
+
+extern "C" dc_status_t dc_get_stats(const dc_batch_t *cb, dc_stats_t *out) {
+    dc_batch *B = const_cast<dc_batch *>(cb);
+    if (!B || !out || B->cfg_only) return DC_E_INVAL;
+    dc_status_t st = fetch(B);
+    if (st != DC_OK) return st;
+    memset(out, 0, sizeof(*out));
+    out->n_kernels = B->K;
+    out->n_instr = B->N;
+    uint32_t ovf = 0;
+    for (const dc_kernel_result_t &r : B->results) {
+        if (r.status != DC_OK) {
+            out->n_failed++;
+            continue;
+        }
+        out->n_blocks += r.n_blocks;
+        out->sweeps_sum += r.sweeps;
+        out->sweeps_max = std::max(out->sweeps_max, r.sweeps);
+        out->n_access += r.n_access;
+        out->n_sysval += r.n_sysval;
+    }
+    if (hipMemcpy(&ovf, B->P.counters + 1, sizeof(uint32_t), hipMemcpyDeviceToHost) == hipSuccess)
+        out->n_overflow = ovf;
+    /* records read once, descriptors, outputs written once, per-kernel results */
+    out->bytes_alg = 16ull * B->N + 32ull * B->K + 16ull * out->n_access + 8ull * out->n_sysval + 32ull * B->K;
+    if (B->have_events && B->runs) {
+        dc_timing_t t;
+        if (dc_get_timing(B, &t) == DC_OK && t.runs) {
+            out->ms_total = t.ms_total / t.runs;
+            out->ms_decode = t.ms_decode / t.runs;
+            out->ms_cfg = t.ms_cfg / t.runs;
+            out->ms_fixpoint = t.ms_fixpoint / t.runs;
+            out->ms_compact = t.ms_compact / t.runs;
+        }
+    }
+    return DC_OK;
+}
+
+extern "C" dc_status_t dc_timing_reset(dc_batch_t *B) {
+    if (!B) return DC_E_INVAL;
+    B->runs_at_reset = B->runs;
+    return DC_OK;
+}
+
+extern "C" dc_status_t dc_get_timing(const dc_batch_t *cb, dc_timing_t *out) {
+    dc_batch *B = const_cast<dc_batch *>(cb);
+    if (!B || !out) return DC_E_INVAL;
+    memset(out, 0, sizeof(*out));
+    if (!B->have_events) return DC_E_NOTREADY;
+    dc_status_t st = dc_batch_wait(B);
+    if (st != DC_OK) return st;
+    uint64_t first = B->runs_at_reset;
+    if (B->runs - first > (uint64_t)TIMING_RING) first = B->runs - TIMING_RING;
+    for (uint64_t r = first; r < B->runs; r++) {
+        hipEvent_t *ev = B->ev[r % TIMING_RING];
+        float a = 0, b = 0, c = 0, d = 0, e = 0;
+        if (hipEventElapsedTime(&a, ev[EV_START], ev[EV_END]) != hipSuccess ||
+            hipEventElapsedTime(&b, ev[EV_START], ev[EV_DECODE]) != hipSuccess ||
+            hipEventElapsedTime(&c, ev[EV_DECODE], ev[EV_CFG]) != hipSuccess ||
+            hipEventElapsedTime(&d, ev[EV_FIXB], ev[EV_FIX]) != hipSuccess ||
+            hipEventElapsedTime(&e, ev[EV_FIX], ev[EV_END]) != hipSuccess)
+            return DC_E_HIP;
+        out->ms_total += a;
+        out->ms_decode += b;
+        out->ms_cfg += c;
+        out->ms_fixpoint += d;
+        out->ms_compact += e;
+        out->runs++;
+    }
+    return DC_OK;
+}
+
+extern "C" void dc_batch_free(dc_batch_t *B) {
+    if (!B) return;
+    hipSetDevice(B->ctx->device);
+    hipStreamSynchronize(B->stream);
+    if (B->have_events)
+        for (int r = 0; r < TIMING_RING; r++)
+            for (int i = 0; i < N_EV; i++) hipEventDestroy(B->ev[r][i]);
+    delete B;
+}
+
+/* ---------------------------------------------------------------- CFG only */
+extern "C" dc_status_t dc_build_cfg(dc_ctx_t *ctx, const dc_kernel_t *kernels, uint32_t n_kernels,
+                                    const dc_instr_t *instrs, uint64_t n_records, void *stream, dc_cfg_t **out) {
+    if (!out) return DC_E_INVAL;
+    *out = nullptr;
+    dc_cfg *C = new (std::nothrow) dc_cfg;
+    if (!C) return DC_E_OOM;
+    dc_batch *B = &C->b;
+    /* argument tables play no part in the graph: plan without them, then
+     * restore the descriptor verdicts of the real descriptors */
+    std::vector<dc_kernel_t> ks_noargs(kernels, kernels + (kernels ? n_kernels : 0));
+    for (auto &k : ks_noargs) {
+        k.n_args = 0;
+        k.arg_begin = 0;
+    }
+    dc_status_t st = plan_batch(B, ctx, kernels ? ks_noargs.data() : nullptr, n_kernels, instrs, n_records, nullptr, 0,
+                                nullptr, stream, true);
+    if (st == DC_OK) {
+        std::vector<int32_t> ds(n_kernels);
+        for (uint32_t k = 0; k < n_kernels; k++) ds[k] = descriptor_status(kernels[k]);
+        if (n_kernels &&
+            hipMemcpy((void *)B->P.desc_status, ds.data(), n_kernels * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess)
+            st = DC_E_HIP;
+    }
+    if (st == DC_OK) st = enqueue(B);
+    if (st != DC_OK) {
+        hipStreamSynchronize(B->stream);
+        delete C;
+        return st;
+    }
+    *out = C;
+    return DC_OK;
+}
+
+static dc_status_t fetch_cfg(dc_batch *B) {
+    if (B->host_valid) return DC_OK;
+    if (hipStreamSynchronize(B->stream) != hipSuccess) return DC_E_HIP;
+    const Plan &P = B->P;
+    const uint32_t K = B->K;
+    uint32_t total = 0;
+    hipError_t e = hipMemcpy(&total, P.total_blocks, sizeof(uint32_t), hipMemcpyDeviceToHost);
+    B->k_status.resize(K);
+    B->k_nblocks.resize(K);
+    B->k_nreach.resize(K);
+    B->first_block.resize(K);
+    B->h_block_start.resize((size_t)total + 1);
+    B->h_succ.resize(2 * (size_t)total);
+    B->h_pred_off.resize((size_t)total + 1);
+    B->h_rpo.resize(total);
+    if (e == hipSuccess && K) e = hipMemcpy(B->k_status.data(), P.status, K * 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && K) e = hipMemcpy(B->k_nblocks.data(), P.n_blocks, K * 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && K) e = hipMemcpy(B->k_nreach.data(), P.n_reach, K * 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && K) e = hipMemcpy(B->first_block.data(), P.first_block, K * 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(B->h_block_start.data(), P.block_start, ((size_t)total + 1) * 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && total) e = hipMemcpy(B->h_succ.data(), P.succ, (size_t)total * 8, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(B->h_pred_off.data(), P.pred_cnt, ((size_t)total + 1) * 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && total) e = hipMemcpy(B->h_rpo.data(), P.rpo, (size_t)total * 4, hipMemcpyDeviceToHost);
+    const uint32_t npred = total ? B->h_pred_off[total] : 0;
+    B->h_pred.resize(npred);
+    if (e == hipSuccess && npred) e = hipMemcpy(B->h_pred.data(), P.pred, (size_t)npred * 4, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e);
+    B->host_valid = true;
+    return DC_OK;
+}
+
+extern "C" dc_status_t dc_cfg_view(dc_cfg_t *C, uint32_t k, dc_cfg_view_t *v) {
+    if (!C || !v || k >= C->b.K) return DC_E_INVAL;
+    dc_batch *B = &C->b;
+    dc_status_t st = fetch_cfg(B);
+    if (st != DC_OK) return st;
+    memset(v, 0, sizeof(*v));
+    v->status = B->k_status[k];
+    if (v->status != DC_OK) return DC_OK;
+    const uint32_t fb = B->first_block[k], nb = B->k_nblocks[k], pb = B->pos_begin[k];
+    B->v_block_start.resize((size_t)nb + 1);
+    B->v_pred_off.resize((size_t)nb + 1);
+    for (uint32_t b = 0; b <= nb; b++) {
+        B->v_block_start[b] = B->h_block_start[fb + b] - pb;
+        B->v_pred_off[b] = B->h_pred_off[fb + b] - B->h_pred_off[fb];
+    }
+    v->n_blocks = nb;
+    v->n_reach = B->k_nreach[k];
+    v->n_pred = B->v_pred_off[nb];
+    v->block_start = B->v_block_start.data();
+    v->succ = B->h_succ.data() + 2 * (size_t)fb;
+    v->pred_off = B->v_pred_off.data();
+    v->pred = B->h_pred.data() + B->h_pred_off[fb];
+    v->rpo = B->h_rpo.data() + fb;
+    return DC_OK;
+}
+
+extern "C" void dc_cfg_free(dc_cfg_t *C) {
+    if (!C) return;
+    hipSetDevice(C->b.ctx->device);
+    hipStreamSynchronize(C->b.stream);
+    delete C;
+}

@@ -1,0 +1,95 @@
+/* dc_internal.h -- device buffers and stage launchers shared by the HIP
+ * kernels (dc_kernels.hip) and the host API (dc_api.cpp). */
+#pragma once
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+#include "dc.h"
+
+namespace dc {
+
+constexpr int NSLOT = DC_NSLOT;
+constexpr int N_OPS = 77;
+
+/* Device-side view of one planned batch.  Positions are this batch's own
+ * dense numbering of instructions: kernel k owns [pos_begin[k], pos_begin[k+1]). */
+struct Plan {
+    /* inputs (device) */
+    const dc_instr_t *instrs;
+    const dc_kernel_t *kernels;
+    const dc_arg_t *args;
+    const uint32_t *pos_begin;      /* K + 1 */
+    const int32_t *desc_status;     /* K: descriptor check done on the host */
+    uint32_t n_kernels;
+    uint32_t n_pos;                 /* total instructions */
+    uint64_t n_records;
+    uint64_t n_args;
+
+    /* CFG stage (device, sized by n_pos as the block-count bound) */
+    uint8_t *leader;                /* n_pos */
+    uint32_t *block_id;             /* n_pos: global block id of each position */
+    uint32_t *block_start;          /* n_pos + 1: first position of each global block; [total] = n_pos */
+    uint32_t *block_kernel;         /* n_pos */
+    int32_t *succ;                  /* 2 * n_pos: local ids */
+    uint32_t *pred_cnt;             /* n_pos + 1 (count, then exclusive offsets) */
+    uint32_t *pred_fill;            /* n_pos */
+    uint32_t *pred;                 /* 2 * n_pos: local ids */
+    uint32_t *rpo;                  /* n_pos: local ids, per kernel at first_block */
+    int32_t *rpo_pos;               /* n_pos: position of each block in its kernel's RPO, -1 unreachable */
+    uint32_t *dfs_stack;            /* n_pos */
+    uint8_t *dfs_seen;              /* n_pos */
+    uint32_t *kbad;                 /* K: first bad record, (index << 2) | code */
+    int32_t *status;                /* K */
+    uint32_t *first_block;          /* K */
+    uint32_t *n_blocks;             /* K */
+    uint32_t *n_reach;              /* K */
+    uint32_t *total_blocks;         /* 1 */
+
+    /* fixpoint + extraction */
+    uint4 *arena;                   /* per resident wave: block_cap * NSLOT slots */
+    uint32_t *bitmaps;              /* per resident wave: 2 * ceil(block_cap/32) words (overflow pass) */
+    uint32_t block_cap;
+    uint4 *ovf_arena;               /* overflow pass: per wave max_blocks * NSLOT slots */
+    uint32_t *ovf_bitmaps;
+    uint32_t ovf_block_cap;
+    uint32_t ovf_waves;
+    uint32_t *ovf_list;             /* K */
+    uint32_t *counters;             /* [0] work counter, [1] overflow count, [2] overflow work counter */
+    uint32_t sweep_cap;
+    uint32_t flags;
+    dc_access_t *acc_sparse;        /* n_pos: kernel k at pos_begin[k] */
+    dc_sysval_t *sys_sparse;        /* 4 * n_pos: kernel k at 4 * pos_begin[k] */
+    dc_kernel_result_t *results;    /* K */
+    dc_reg_state_t *export_states;  /* total_blocks * NSLOT (DC_OPT_EXPORT_STATES) */
+    uint8_t *export_reached;        /* total_blocks */
+
+    /* compaction */
+    uint32_t *acc_count;            /* K + 1 -> exclusive offsets */
+    uint32_t *sys_count;            /* K + 1 */
+    dc_access_t *acc_dense;         /* n_pos */
+    dc_sysval_t *sys_dense;         /* 4 * n_pos */
+
+    /* scan scratch */
+    uint32_t *scan_tmp;             /* scan_tmp_words */
+    uint64_t scan_tmp_words;
+};
+
+/* launch configuration of the fixpoint kernel */
+struct FixCfg {
+    int waves_per_group;
+    int groups;
+};
+
+/* stage launchers (enqueue only; return hipSuccess or the launch error) */
+hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
+hipError_t launch_fill_u8(uint8_t *p, uint64_t n, uint8_t v, hipStream_t s);
+hipError_t launch_decode(const Plan &P, hipStream_t s);                 /* a1 + a2 */
+hipError_t launch_number_blocks(const Plan &P, hipStream_t s);          /* a3 */
+hipError_t launch_edges(const Plan &P, hipStream_t s);                  /* a4 (+ statuses) */
+/* a5-a9; dP = device copy of P; optional events bracket the main launch */
+hipError_t launch_fixpoint(const Plan &P, const Plan *dP, const FixCfg &c, hipStream_t s, hipEvent_t before,
+                           hipEvent_t after);
+hipError_t launch_compact(const Plan &P, hipStream_t s);                /* dense outputs */
+uint64_t scan_tmp_words_needed(uint64_t n);
+
+}  // namespace dc

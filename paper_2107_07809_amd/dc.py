@@ -1,0 +1,312 @@
+"""Python binding of libdc (include/dc.h): argument marshalling only.
+
+Every step of the analysis runs in the HIP kernels of libdc.so; this module
+converts numpy/torch buffers to pointers and results back to numpy arrays.
+It fails loudly when libdc.so is missing: there is no fallback path.
+Device memory and streams come from torch (ROCm).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdc.so")
+
+DC_OK = 0
+STATUS = {0: "OK", -1: "INVAL", -2: "HIP", -3: "OOM", -4: "NOTREADY", -10: "BADOP", -11: "BADREG",
+          -12: "BADTARGET", -13: "NOEND", -14: "UNSUPPORTED", -15: "NOFIX"}
+OPT_EXPORT_STATES, OPT_DIGEST, OPT_TIMING = 1, 2, 4
+NSLOT = 368
+
+INSTR_DTYPE = np.dtype([("op", "<u2"), ("r0", "<u2"), ("r1", "<u2"), ("r2", "<u2"), ("imm", "<i4"),
+                        ("target", "<i4")])
+KERNEL_DTYPE = np.dtype([("instr_begin", "<u8"), ("n_instr", "<u4"), ("dims", "u1"), ("useargs", "u1"),
+                         ("n_args", "<u2"), ("cws", "<u4", (3,)), ("arg_begin", "<u4")])
+ARG_DTYPE = np.dtype([("offset", "<u4"), ("size", "<u2"), ("type", "u1"), ("flags", "u1")])
+REG_DTYPE = np.dtype([("prov", "<u4"), ("type", "u1"), ("flags", "u1"), ("pad0", "u1"), ("pad1", "u1"),
+                      ("val", "<u8")])
+ACCESS_DTYPE = np.dtype([("instr", "<u4"), ("kind", "u1"), ("space", "u1"), ("width", "u1"), ("dtype", "u1"),
+                         ("addr", "<u8")])
+SYSVAL_DTYPE = np.dtype([("instr", "<u4"), ("slot", "<u2"), ("kind", "u1"), ("dim", "u1")])
+RESULT_DTYPE = np.dtype([("status", "<i4"), ("n_blocks", "<u4"), ("sweeps", "<u4"), ("n_access", "<u4"),
+                         ("n_sysval", "<u4"), ("pad", "<u4"), ("digest", "<u8")])
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("flags", ctypes.c_uint32), ("sweep_cap", ctypes.c_uint32), ("waves_per_group", ctypes.c_uint32),
+                ("groups_per_cu", ctypes.c_uint32), ("block_cap", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 3)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n_kernels", ctypes.c_uint64), ("n_instr", ctypes.c_uint64), ("n_blocks", ctypes.c_uint64),
+                ("n_unreached", ctypes.c_uint64), ("sweeps_sum", ctypes.c_uint64), ("n_access", ctypes.c_uint64),
+                ("n_sysval", ctypes.c_uint64), ("bytes_alg", ctypes.c_uint64), ("sweeps_max", ctypes.c_uint32),
+                ("n_failed", ctypes.c_uint32), ("n_overflow", ctypes.c_uint32), ("pad", ctypes.c_uint32),
+                ("ms_total", ctypes.c_float), ("ms_decode", ctypes.c_float), ("ms_cfg", ctypes.c_float),
+                ("ms_fixpoint", ctypes.c_float), ("ms_compact", ctypes.c_float), ("ms_pad", ctypes.c_float)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k not in ("pad", "ms_pad")}
+
+
+class Timing(ctypes.Structure):
+    _fields_ = [("runs", ctypes.c_uint32), ("pad", ctypes.c_uint32), ("ms_total", ctypes.c_float),
+                ("ms_decode", ctypes.c_float), ("ms_cfg", ctypes.c_float), ("ms_fixpoint", ctypes.c_float),
+                ("ms_compact", ctypes.c_float), ("ms_pad", ctypes.c_float)]
+
+
+class CfgView(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("n_blocks", ctypes.c_uint32), ("n_reach", ctypes.c_uint32),
+                ("n_pred", ctypes.c_uint32), ("block_start", ctypes.POINTER(ctypes.c_uint32)),
+                ("succ", ctypes.POINTER(ctypes.c_int32)), ("pred_off", ctypes.POINTER(ctypes.c_uint32)),
+                ("pred", ctypes.POINTER(ctypes.c_uint32)), ("rpo", ctypes.POINTER(ctypes.c_uint32))]
+
+
+VP = ctypes.c_void_p
+U32, U64, I32 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32
+
+# (name, restype, argtypes): every symbol include/dc.h declares
+SIGNATURES = [
+    ("dc_ctx_create", I32, [ctypes.c_int, ctypes.POINTER(VP)]),
+    ("dc_ctx_destroy", None, [VP]),
+    ("dc_build_cfg", I32, [VP, VP, U32, VP, U64, VP, ctypes.POINTER(VP)]),
+    ("dc_cfg_view", I32, [VP, U32, ctypes.POINTER(CfgView)]),
+    ("dc_cfg_free", None, [VP]),
+    ("dc_analyze_batch", I32, [VP, VP, U32, VP, U64, VP, U64, ctypes.POINTER(Options), VP, ctypes.POINTER(VP)]),
+    ("dc_batch_run", I32, [VP, VP, VP]),
+    ("dc_batch_wait", I32, [VP]),
+    ("dc_get_kernel_status", I32, [VP, U32, ctypes.POINTER(I32)]),
+    ("dc_get_kernel_result", I32, [VP, U32, VP]),
+    ("dc_get_results", I32, [VP, VP, U32]),
+    ("dc_get_accesses", I32, [VP, U32, VP, U32, ctypes.POINTER(U32)]),
+    ("dc_get_sysvals", I32, [VP, U32, VP, U32, ctypes.POINTER(U32)]),
+    ("dc_get_all_accesses", I32, [VP, VP, U64, ctypes.POINTER(U64), VP]),
+    ("dc_get_all_sysvals", I32, [VP, VP, U64, ctypes.POINTER(U64), VP]),
+    ("dc_get_block_state", I32, [VP, U32, U32, VP, ctypes.POINTER(ctypes.c_uint8)]),
+    ("dc_get_stats", I32, [VP, ctypes.POINTER(Stats)]),
+    ("dc_get_timing", I32, [VP, ctypes.POINTER(Timing)]),
+    ("dc_timing_reset", I32, [VP]),
+    ("dc_batch_free", None, [VP]),
+    ("dc_status_str", ctypes.c_char_p, [I32]),
+    ("dc_opcode_count", ctypes.c_int, []),
+    ("dc_opcode_name", ctypes.c_char_p, [ctypes.c_int]),
+]
+
+_lib = None
+
+
+class DCError(RuntimeError):
+    def __init__(self, where, code):
+        super().__init__(f"{where}: {STATUS.get(code, code)} ({code})")
+        self.code = code
+
+
+def lib():
+    """Load libdc.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(where, code):
+    if code != DC_OK:
+        raise DCError(where, code)
+
+
+def opcode_names():
+    L = lib()
+    return [L.dc_opcode_name(i).decode() for i in range(L.dc_opcode_count())]
+
+
+def status_str(code: int) -> str:
+    return lib().dc_status_str(code).decode()
+
+
+def _np_ptr(a):
+    return a.ctypes.data if a is not None and a.size else None
+
+
+def _dev_ptr(t):
+    return t.data_ptr() if t is not None and t.numel() else None
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def to_device(records: np.ndarray, device="cuda:0"):
+    """Records (numpy, INSTR_DTYPE) -> a torch uint8 tensor on the GPU."""
+    import torch
+    raw = np.ascontiguousarray(records).view(np.uint8).reshape(-1)
+    return torch.from_numpy(raw).to(device)
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        h = VP()
+        check("dc_ctx_create", lib().dc_ctx_create(device, ctypes.byref(h)))
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if self.h:
+            lib().dc_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def analyze(self, kernels, instrs_dev, n_records, args=None, flags=0, sweep_cap=0, waves_per_group=0,
+                groups_per_cu=0, block_cap=0, stream=None) -> "Batch":
+        kernels = np.ascontiguousarray(np.asarray(kernels, KERNEL_DTYPE))
+        args = np.ascontiguousarray(np.asarray(args if args is not None else np.zeros(0, ARG_DTYPE), ARG_DTYPE))
+        o = Options(flags, sweep_cap, waves_per_group, groups_per_cu, block_cap)
+        h = VP()
+        check("dc_analyze_batch", lib().dc_analyze_batch(self.h, _np_ptr(kernels), len(kernels), _dev_ptr(instrs_dev),
+                                                         n_records, _np_ptr(args), len(args), ctypes.byref(o),
+                                                         _stream_ptr(stream), ctypes.byref(h)))
+        return Batch(h, len(kernels), instrs_dev, stream)
+
+    def build_cfg(self, kernels, instrs_dev, n_records, stream=None) -> "Cfg":
+        kernels = np.ascontiguousarray(np.asarray(kernels, KERNEL_DTYPE))
+        h = VP()
+        check("dc_build_cfg", lib().dc_build_cfg(self.h, _np_ptr(kernels), len(kernels), _dev_ptr(instrs_dev),
+                                                 n_records, _stream_ptr(stream), ctypes.byref(h)))
+        return Cfg(h, len(kernels))
+
+
+class Batch:
+    def __init__(self, h, n_kernels, instrs_dev, stream):
+        self.h = h
+        self.n_kernels = n_kernels
+        self._keep = instrs_dev     # caller memory must outlive the run
+        self.stream = stream
+
+    def run(self, instrs_dev=None, stream=None):
+        if instrs_dev is not None:
+            self._keep = instrs_dev
+        check("dc_batch_run", lib().dc_batch_run(self.h, _dev_ptr(instrs_dev) if instrs_dev is not None else None,
+                                                 _stream_ptr(stream if stream is not None else self.stream)))
+
+    def wait(self):
+        check("dc_batch_wait", lib().dc_batch_wait(self.h))
+
+    def results(self) -> np.ndarray:
+        out = np.zeros(self.n_kernels, RESULT_DTYPE)
+        check("dc_get_results", lib().dc_get_results(self.h, _np_ptr(out), self.n_kernels))
+        return out
+
+    def status(self, k: int) -> int:
+        s = I32()
+        check("dc_get_kernel_status", lib().dc_get_kernel_status(self.h, k, ctypes.byref(s)))
+        return s.value
+
+    def accesses(self, k: int) -> np.ndarray:
+        n = U32()
+        check("dc_get_accesses", lib().dc_get_accesses(self.h, k, None, 0, ctypes.byref(n)))
+        out = np.zeros(n.value, ACCESS_DTYPE)
+        check("dc_get_accesses", lib().dc_get_accesses(self.h, k, _np_ptr(out), n.value, ctypes.byref(n)))
+        return out
+
+    def sysvals(self, k: int) -> np.ndarray:
+        n = U32()
+        check("dc_get_sysvals", lib().dc_get_sysvals(self.h, k, None, 0, ctypes.byref(n)))
+        out = np.zeros(n.value, SYSVAL_DTYPE)
+        check("dc_get_sysvals", lib().dc_get_sysvals(self.h, k, _np_ptr(out), n.value, ctypes.byref(n)))
+        return out
+
+    def all_accesses(self):
+        n = U64()
+        check("dc_get_all_accesses", lib().dc_get_all_accesses(self.h, None, 0, ctypes.byref(n), None))
+        out = np.zeros(n.value, ACCESS_DTYPE)
+        off = np.zeros(self.n_kernels + 1, np.uint64)
+        check("dc_get_all_accesses", lib().dc_get_all_accesses(self.h, _np_ptr(out), n.value, ctypes.byref(n),
+                                                               off.ctypes.data))
+        return out, off
+
+    def all_sysvals(self):
+        n = U64()
+        check("dc_get_all_sysvals", lib().dc_get_all_sysvals(self.h, None, 0, ctypes.byref(n), None))
+        out = np.zeros(n.value, SYSVAL_DTYPE)
+        off = np.zeros(self.n_kernels + 1, np.uint64)
+        check("dc_get_all_sysvals", lib().dc_get_all_sysvals(self.h, _np_ptr(out), n.value, ctypes.byref(n),
+                                                             off.ctypes.data))
+        return out, off
+
+    def block_state(self, k: int, b: int):
+        out = np.zeros(NSLOT, REG_DTYPE)
+        r = ctypes.c_uint8()
+        check("dc_get_block_state", lib().dc_get_block_state(self.h, k, b, out.ctypes.data, ctypes.byref(r)))
+        return out, r.value
+
+    def stats(self) -> dict:
+        s = Stats()
+        check("dc_get_stats", lib().dc_get_stats(self.h, ctypes.byref(s)))
+        return s.as_dict()
+
+    def timing(self) -> dict:
+        t = Timing()
+        check("dc_get_timing", lib().dc_get_timing(self.h, ctypes.byref(t)))
+        return {k: getattr(t, k) for k, _ in t._fields_ if k not in ("pad", "ms_pad")}
+
+    def timing_reset(self):
+        check("dc_timing_reset", lib().dc_timing_reset(self.h))
+
+    def free(self):
+        if self.h:
+            lib().dc_batch_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Cfg:
+    def __init__(self, h, n_kernels):
+        self.h = h
+        self.n_kernels = n_kernels
+
+    def view(self, k: int) -> dict:
+        v = CfgView()
+        check("dc_cfg_view", lib().dc_cfg_view(self.h, k, ctypes.byref(v)))
+        nb = v.n_blocks
+
+        def arr(p, n, dt):
+            return np.ctypeslib.as_array(p, shape=(n,)).astype(dt).copy() if n else np.zeros(0, dt)
+        if v.status != DC_OK:
+            return dict(status=v.status, n_blocks=0)
+        return dict(status=v.status, n_blocks=nb, n_reach=v.n_reach,
+                    block_start=arr(v.block_start, nb + 1, np.uint32), succ=arr(v.succ, 2 * nb, np.int32),
+                    pred_off=arr(v.pred_off, nb + 1, np.uint32), pred=arr(v.pred, v.n_pred, np.uint32),
+                    rpo=arr(v.rpo, v.n_reach, np.uint32))
+
+    def free(self):
+        if self.h:
+            lib().dc_cfg_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

@@ -1,0 +1,39 @@
+"""Helpers shared by the GPU parity tests (test infrastructure)."""
+import os
+from concurrent.futures import ProcessPoolExecutor
+
+import numpy as np
+
+import dcgen
+import oracle
+
+
+def _oracle_chunk(args):
+    cfg, i0, n = args
+    b = dcgen.generate(cfg, n, i0=i0, threads=1)
+    return oracle.analyze_batch(b)
+
+
+def oracle_config(cfg: int, n: int, procs: int = 0):
+    """Oracle summaries and dense records for kernels [0, n) of a config,
+    computed in parallel worker processes (each regenerates its shard)."""
+    procs = procs or min(16, os.cpu_count() or 1)
+    step = max(1, (n + procs * 4 - 1) // (procs * 4))
+    jobs = [(cfg, i, min(step, n - i)) for i in range(0, n, step)]
+    with ProcessPoolExecutor(procs) as ex:
+        parts = list(ex.map(_oracle_chunk, jobs))
+    summ = np.concatenate([p[0] for p in parts])
+    acc = np.concatenate([p[1] for p in parts])
+    sys = np.concatenate([p[2] for p in parts])
+    return summ, acc, sys
+
+
+def compare_summaries(gpu_res, summ):
+    """Per-kernel status, block count, sweeps, counts and state digest."""
+    assert len(gpu_res) == len(summ)
+    for f_gpu, f_or in [("status", "status"), ("n_blocks", "n_blocks"), ("sweeps", "sweeps"),
+                        ("n_access", "n_acc"), ("n_sysval", "n_sys")]:
+        bad = np.nonzero(gpu_res[f_gpu] != summ[f_or])[0]
+        assert len(bad) == 0, (f_gpu, bad[:10], gpu_res[f_gpu][bad[:10]], summ[f_or][bad[:10]])
+    bad = np.nonzero(gpu_res["digest"] != summ["digest"])[0]
+    assert len(bad) == 0, ("digest", bad[:10])

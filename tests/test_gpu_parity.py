@@ -1,0 +1,243 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+The bar is bit-exact: every output of the analysis is integer or bit-set
+work, so per-kernel status, block count, sweep count, access and system-value
+records and the fixpoint IN state of every block must match byte for byte
+(at full size through a digest of the states plus every record)."""
+import glob
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import asmtext
+import dcgen
+import oracle
+from gpu_common import compare_summaries, oracle_config
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2107_07809_amd import dc  # noqa: E402
+
+GOLDEN = sorted(glob.glob(os.path.join(os.path.dirname(__file__), "golden", "*.txt")))
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = dc.Context(0)
+    yield c
+    c.close()
+
+
+def run(ctx, b, **kw):
+    dev = dc.to_device(b.instrs)
+    batch = ctx.analyze(b.kernels, dev, b.n_instr, b.args, **kw)
+    return batch, dev
+
+
+def full_compare(ctx, b, **kw):
+    """Byte-exact comparison of everything, states included."""
+    say(f"full_compare: {b.n_kernels} kernels, {b.n_instr} instructions, {kw}")
+    batch, dev = run(ctx, b, flags=dc.OPT_EXPORT_STATES | dc.OPT_DIGEST, **kw)
+    res = batch.results()
+    for k in range(b.n_kernels):
+        r = oracle.analyze(*b.kernel(k))
+        g = res[k]
+        assert (g["status"], g["n_blocks"], g["sweeps"]) == (r["status"], r["n_blocks"], r["sweeps"]), k
+        assert g["digest"] == r["digest"], k
+        assert batch.accesses(k).tobytes() == r["accesses"].tobytes(), k
+        assert batch.sysvals(k).tobytes() == r["sysvals"].tobytes(), k
+        for blk in range(r["n_blocks"]):
+            st, reached = batch.block_state(k, blk)
+            assert reached == r["reached"][blk], (k, blk)
+            if st.tobytes() != r["in_states"][blk].tobytes():
+                diff = np.nonzero(st.view(np.uint8).reshape(368, 16) != r["in_states"][blk].view(np.uint8).reshape(
+                    368, 16))[0]
+                slot = int(diff[0])
+                raise AssertionError(f"kernel {k} block {blk} slot {slot}: gpu {st[slot]} oracle "
+                                     f"{r['in_states'][blk][slot]} ({oracle.decode(st[slot]['val'])} vs "
+                                     f"{oracle.decode(r['in_states'][blk][slot]['val'])})")
+    batch.free()
+    return res
+
+
+def test_c1_full(ctx):
+    """All 32 kernels of the small configuration, every output byte."""
+    full_compare(ctx, dcgen.generate(1, 32))
+
+
+def test_golden_fixtures(ctx):
+    """The paper's worked statements, analysed on the GPU in one batch."""
+    import test_oracle_golden as tg
+    fxs = [asmtext.Fixture(p) for p in GOLDEN]
+    b = dcgen.concat([fx.kernel() for fx in fxs])
+    batch, dev = run(ctx, b, flags=dc.OPT_EXPORT_STATES | dc.OPT_DIGEST)
+    res = batch.results()
+    for k, fx in enumerate(fxs):
+        r = oracle.analyze(*fx.kernel())
+        g = dict(status=int(res[k]["status"]), n_blocks=int(res[k]["n_blocks"]), sweeps=int(res[k]["sweeps"]),
+                 accesses=batch.accesses(k), sysvals=batch.sysvals(k))
+        g["in_states"] = [batch.block_state(k, i)[0] for i in range(g["n_blocks"])] if g["status"] == 0 else []
+        tg.check_fixture(fx, g, None, None, where="gpu")
+        assert g["accesses"].tobytes() == r["accesses"].tobytes(), fx.path
+        assert g["sysvals"].tobytes() == r["sysvals"].tobytes(), fx.path
+        assert int(res[k]["digest"]) == r["digest"], fx.path
+    batch.free()
+
+
+def test_c2_subset_states(ctx):
+    """Ragged lengths 200-2000 with loops: 600 kernels, states byte-exact
+    (including kernels that use the full register range)."""
+    b = dcgen.generate(2, 600)
+    full_compare(ctx, b)
+
+
+def test_c3_and_c5_shapes(ctx):
+    """Zipf and log-normal lengths (short kernels of 20 instructions, long
+    ones with hundreds of blocks)."""
+    full_compare(ctx, dcgen.generate(3, 300))
+    full_compare(ctx, dcgen.generate(5, 100))
+
+
+def test_c2_full_digest(ctx):
+    """All 65,536 kernels of the 51.2M-instruction workload in the bench's
+    launch configuration: every record and every kernel's state digest."""
+    n = 65536
+    b = dcgen.generate(2, n)
+    say("c2 full: generated", b.n_instr)
+    batch, dev = run(ctx, b, flags=dc.OPT_DIGEST)
+    res = batch.results()
+    acc, _ = batch.all_accesses()
+    sysv, _ = batch.all_sysvals()
+    say("c2 full: gpu done; running the oracle")
+    summ, oacc, osys = oracle_config(2, n)
+    say("c2 full: oracle done")
+    compare_summaries(res, summ)
+    assert acc.tobytes() == oacc.tobytes()
+    assert sysv.tobytes() == osys.tobytes()
+    batch.free()
+
+
+def test_cfg_parity(ctx):
+    b = dcgen.generate(2, 300)
+    dev = dc.to_device(b.instrs)
+    cfg = ctx.build_cfg(b.kernels, dev, b.n_instr)
+    for k in range(b.n_kernels):
+        v = cfg.view(k)
+        r = oracle.analyze(*b.kernel(k), states=False)
+        assert v["status"] == r["status"]
+        for key in ("block_start", "succ", "pred_off", "pred", "rpo"):
+            assert np.array_equal(v[key], r[key]), (k, key)
+        assert v["n_reach"] == r["n_reach"]
+    cfg.free()
+
+
+def _rec(name, r0=0xFFFF, r1=0xFFFF, r2=0xFFFF, imm=0, target=-1):
+    x = np.zeros(1, dcgen.INSTR_DTYPE)
+    x[0] = (dcgen.opcode(name), r0, r1, r2, imm, target)
+    return x
+
+
+def test_errors_do_not_poison_batch(ctx):
+    """Bad records, bad descriptors and empty kernels mixed with good ones:
+    each kernel gets its own status and the good ones are unaffected."""
+    good = dcgen.generate(2, 6)
+    parts = [good.kernel(k) for k in range(6)]
+    end = _rec("s_endpgm")
+    r, d, a = good.kernel(0)
+    bad_op = r.copy(); bad_op[5]["op"] = 200
+    bad_reg = r.copy(); bad_reg[7]["r0"] = 111
+    bad_tgt = r.copy(); bad_tgt[3]["target"] = 5
+    no_end = r[:-1].copy()
+    d_unsup = d.copy(); d_unsup["useargs"] = 0
+    d_dims = d.copy(); d_dims["dims"] = 4
+    empty = np.zeros(0, dcgen.INSTR_DTYPE)
+    mixed = [parts[0], (bad_op, d, a), parts[1], (bad_reg, d, a), (bad_tgt, d, a), parts[2], (no_end, d, a),
+             (r, d_unsup, a), (r, d_dims, a), (empty, dcgen.descriptor(0), np.zeros(0, dcgen.ARG_DTYPE)),
+             (end, dcgen.descriptor(1), np.zeros(0, dcgen.ARG_DTYPE)), parts[3], parts[4], parts[5]]
+    b = dcgen.concat(mixed)
+    res = full_compare(ctx, b)
+    want = [0, -10, 0, -11, -12, 0, -13, -14, -14, -13, 0, 0, 0, 0]
+    assert list(res["status"]) == want
+
+
+def test_nofix_cap(ctx):
+    b = dcgen.generate(2, 200)
+    s, _, _ = oracle.analyze_batch(b)
+    for cap in (1, 2, 3):
+        batch, dev = run(ctx, b, sweep_cap=cap, flags=dc.OPT_DIGEST)
+        res = batch.results()
+        s2, _, _ = oracle.analyze_batch(b, sweep_cap=cap)
+        compare_summaries(res, s2)
+        assert np.any(res["status"] == -15)
+        batch.free()
+
+
+def test_empty_batch(ctx):
+    b = dcgen.concat([])
+    dev = torch.zeros(16, dtype=torch.uint8, device="cuda")
+    batch = ctx.analyze(b.kernels, dev, 0, b.args)
+    assert len(batch.results()) == 0
+    acc, off = batch.all_accesses()
+    assert len(acc) == 0 and list(off) == [0]
+    batch.free()
+
+
+def test_launch_shapes_invariant(ctx):
+    """Batching invariance: waves per group, resident groups and the
+    overflow pass (tiny block cap) leave every byte unchanged."""
+    b = dcgen.generate(2, 400, i0=1000)
+    ref = None
+    for kw in [dict(), dict(waves_per_group=1), dict(waves_per_group=2, groups_per_cu=1),
+               dict(block_cap=8), dict(block_cap=1, waves_per_group=3)]:
+        batch, dev = run(ctx, b, flags=dc.OPT_DIGEST, **kw)
+        res = batch.results()
+        acc, _ = batch.all_accesses()
+        sysv, _ = batch.all_sysvals()
+        cur = (res.tobytes(), acc.tobytes(), sysv.tobytes())
+        if ref is None:
+            ref = cur
+            s, oacc, osys = oracle.analyze_batch(b)
+            compare_summaries(res, s)
+            assert acc.tobytes() == oacc.tobytes() and sysv.tobytes() == osys.tobytes()
+        assert cur == ref, kw
+        batch.free()
+
+
+def test_rerun_identical(ctx):
+    b = dcgen.generate(2, 300, i0=7)
+    batch, dev = run(ctx, b, flags=dc.OPT_DIGEST | dc.OPT_TIMING)
+    r1 = batch.results().tobytes()
+    a1 = batch.all_accesses()[0].tobytes()
+    for _ in range(3):
+        batch.run()
+        assert batch.results().tobytes() == r1
+        assert batch.all_accesses()[0].tobytes() == a1
+    st = batch.stats()
+    assert st["ms_total"] > 0 and st["n_failed"] == 0
+    batch.free()
+
+
+def test_single_and_alone_vs_batch(ctx):
+    """A kernel analysed alone gives the same bytes as inside a batch."""
+    b = dcgen.generate(2, 50, i0=321)
+    batch, dev = run(ctx, b, flags=dc.OPT_DIGEST)
+    res = batch.results()
+    for k in (0, 17, 49):
+        sub = dcgen.concat([b.kernel(k)])
+        b1, d1 = run(ctx, sub, flags=dc.OPT_DIGEST)
+        r1 = b1.results()
+        assert r1.tobytes() == res[k:k + 1].tobytes()
+        assert b1.accesses(0).tobytes() == batch.accesses(k).tobytes()
+        b1.free()
+    batch.free()

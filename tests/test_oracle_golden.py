@@ -32,8 +32,12 @@ def check_fixture(fx, res, entry, after_state, where="oracle"):
             assert res["sweeps"] == int(rest[0]), (where, line)
         elif key in ("after", "in", "entry"):
             if key == "entry":
+                if entry is None:
+                    continue
                 st, slot, fields = entry, _slot(rest[0]), rest[1:]
             elif key == "after":
+                if after_state is None:
+                    continue
                 st, slot, fields = after_state(int(rest[0])), _slot(rest[1]), rest[2:]
             else:
                 st, slot, fields = res["in_states"][int(rest[0])], _slot(rest[1]), rest[2:]
