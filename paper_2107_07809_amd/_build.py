@@ -6,8 +6,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdc.so")
-SOURCES = [os.path.join(CSRC, "dc_kernels.hip"), os.path.join(CSRC, "dc_api.cpp")]
-HEADERS = [os.path.join(CSRC, "dc_internal.h"), os.path.join(CSRC, "dc_isa.h"), os.path.join(ROOT, "include", "dc.h")]
+SOURCES = [os.path.join(CSRC, "dc_kernels.hip"), os.path.join(CSRC, "dc_fixpoint.hip"), os.path.join(CSRC, "dc_api.cpp")]
+HEADERS = [os.path.join(CSRC, "dc_internal.h"), os.path.join(CSRC, "dc_isa.h"), os.path.join(CSRC, "dc_device.h"),
+           os.path.join(ROOT, "include", "dc.h")]
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          # no packed fp32 instructions anywhere in the library

@@ -172,7 +172,7 @@ static dc_status_t plan_batch(dc_batch *B, dc_ctx *ctx, const dc_kernel_t *kerne
     if (B->opts.waves_per_group == 0) B->opts.waves_per_group = 4;
     if (B->opts.waves_per_group > 4) return DC_E_INVAL;
     if (B->opts.block_cap == 0) B->opts.block_cap = 256;
-    if (B->opts.block_cap > 2048) return DC_E_INVAL;   /* the main pass keeps its bitmaps in LDS */
+    if (B->opts.block_cap > 2048) return DC_E_INVAL;   /* the main pass keeps its bitmaps in one VGPR */
     B->K = n_kernels;
     B->n_records = n_records;
     B->n_args_total = n_args_total;
@@ -230,35 +230,43 @@ static dc_status_t plan_batch(dc_batch *B, dc_ctx *ctx, const dc_kernel_t *kerne
     P.scan_tmp = M.alloc<uint32_t>(P.scan_tmp_words);
     if (!cfg_only) {
         const uint32_t wpg = B->opts.waves_per_group;
-        /* resident groups: LDS, then the register budget of the fixpoint kernel */
-        const size_t lds_group = (size_t)wpg * ((NSLOT + 64) * 16 + (2 * 64 + 64) * 4);
+        /* persistent grid: as many groups per CU as the fixpoint kernel's
+         * registers and LDS allow */
         uint32_t per_cu = B->opts.groups_per_cu;
-        if (per_cu == 0) {
-            per_cu = (uint32_t)std::max<size_t>(1, std::min<size_t>(ctx->lds_per_cu / lds_group, 12 / wpg));
-        }
+        if (per_cu == 0) per_cu = fixpoint_groups_per_cu(wpg);
         B->fc.waves_per_group = (int)wpg;
         B->fc.groups = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)ctx->n_cu * per_cu, (K + wpg - 1) / wpg));
-        P.block_cap = B->opts.block_cap;
         const uint64_t waves = (uint64_t)B->fc.groups * wpg;
-        P.arena = M.alloc<uint4>(waves * P.block_cap * NSLOT);
-        P.bitmaps = nullptr;
-        /* overflow pass: kernels with more blocks than block_cap; a kernel has
-         * at most as many blocks as instructions */
+        /* main pass arena: block_cap blocks of two state rows (kernels with up
+         * to 128 named register slots), or fewer blocks of six rows */
+        P.arena_rows = 2 * B->opts.block_cap;
+        P.main_waves = (uint32_t)waves;
+        P.arena = M.alloc<uint32_t>(waves * P.arena_rows * FIX_ROW_DWORDS);
+        /* overflow pass: kernels with more than 2048 blocks or whose states do
+         * not fit the main arena; a kernel has at most as many blocks as
+         * instructions */
+        const uint64_t main_blocks = std::min<uint64_t>(2048, P.arena_rows / FIX_MAX_ROWS);
         uint64_t ovf_cap = std::max<uint64_t>(max_len, 1);
         uint64_t ovf_waves = 64;
         const uint64_t budget = 8ull << 30;
-        while (ovf_waves > 1 && ovf_waves * ovf_cap * NSLOT * 16 > budget) ovf_waves /= 2;
-        if (max_len <= P.block_cap) { ovf_cap = 1; ovf_waves = 1; }
+        while (ovf_waves > 1 && ovf_waves * ovf_cap * FIX_MAX_ROWS * FIX_ROW_DWORDS * 4 > budget) ovf_waves /= 2;
+        if (max_len <= main_blocks) { ovf_cap = 1; ovf_waves = 1; }
         P.ovf_block_cap = (uint32_t)ovf_cap;
+        P.ovf_rows = (uint32_t)(ovf_cap * FIX_MAX_ROWS);
         P.ovf_waves = (uint32_t)ovf_waves;
-        P.ovf_arena = M.alloc<uint4>(ovf_waves * ovf_cap * NSLOT);
+        P.ovf_arena = M.alloc<uint32_t>(ovf_waves * P.ovf_rows * FIX_ROW_DWORDS);
         P.ovf_bitmaps = M.alloc<uint32_t>(ovf_waves * (2 * ((ovf_cap + 31) / 32) + 64));
+        P.dummy = M.alloc<uint4>((waves + ovf_waves) * 64);
         P.ovf_list = M.alloc<uint32_t>(K);
         P.counters = M.alloc<uint32_t>(4);
         P.sweep_cap = B->opts.sweep_cap;
         P.flags = B->opts.flags;
         P.acc_sparse = M.alloc<dc_access_t>(N);
         P.sys_sparse = M.alloc<dc_sysval_t>(4 * N);
+        P.blk_acc = M.alloc<uint32_t>(N);
+        P.blk_sys = M.alloc<uint32_t>(N);
+        P.blk_acc_off = M.alloc<uint32_t>(N);
+        P.blk_sys_off = M.alloc<uint32_t>(N);
         P.results = M.alloc<dc_kernel_result_t>(K);
         P.acc_count = M.alloc<uint32_t>(K + 1);
         P.sys_count = M.alloc<uint32_t>(K + 1);

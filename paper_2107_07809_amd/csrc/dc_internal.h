@@ -46,24 +46,30 @@ struct Plan {
     uint32_t *total_blocks;         /* 1 */
 
     /* fixpoint + extraction */
-    uint4 *arena;                   /* per resident wave: block_cap * NSLOT slots */
-    uint32_t *bitmaps;              /* per resident wave: 2 * ceil(block_cap/32) words (overflow pass) */
-    uint32_t block_cap;
-    uint4 *ovf_arena;               /* overflow pass: per wave max_blocks * NSLOT slots */
-    uint32_t *ovf_bitmaps;
+    uint32_t *arena;                /* per main-pass wave: arena_rows state rows of 192 dwords */
+    uint32_t arena_rows;
+    uint32_t main_waves;
+    uint32_t *ovf_arena;            /* per overflow wave: ovf_rows state rows */
+    uint32_t ovf_rows;
+    uint32_t *ovf_bitmaps;          /* per overflow wave: 2 * ceil(ovf_block_cap / 32) + 64 words */
     uint32_t ovf_block_cap;
     uint32_t ovf_waves;
     uint32_t *ovf_list;             /* K */
+    uint4 *dummy;                   /* (main_waves + ovf_waves) * 64: per-lane scratch stores */
     uint32_t *counters;             /* [0] work counter, [1] overflow count, [2] overflow work counter */
     uint32_t sweep_cap;
     uint32_t flags;
-    dc_access_t *acc_sparse;        /* n_pos: kernel k at pos_begin[k] */
-    dc_sysval_t *sys_sparse;        /* 4 * n_pos: kernel k at 4 * pos_begin[k] */
+    dc_access_t *acc_sparse;        /* n_pos: a block's records from its first position */
+    dc_sysval_t *sys_sparse;        /* 4 * n_pos: a block's records from 4 x its first position */
+    uint32_t *blk_acc;              /* n_pos (per global block): access records of the last visit */
+    uint32_t *blk_sys;              /* n_pos: built-in records of the last visit */
     dc_kernel_result_t *results;    /* K */
     dc_reg_state_t *export_states;  /* total_blocks * NSLOT (DC_OPT_EXPORT_STATES) */
     uint8_t *export_reached;        /* total_blocks */
 
     /* compaction */
+    uint32_t *blk_acc_off;          /* n_pos: exclusive scan of blk_acc over the blocks */
+    uint32_t *blk_sys_off;          /* n_pos */
     uint32_t *acc_count;            /* K + 1 -> exclusive offsets */
     uint32_t *sys_count;            /* K + 1 */
     dc_access_t *acc_dense;         /* n_pos */
@@ -90,6 +96,9 @@ hipError_t launch_edges(const Plan &P, hipStream_t s);                  /* a4 (+
 hipError_t launch_fixpoint(const Plan &P, const Plan *dP, const FixCfg &c, hipStream_t s, hipEvent_t before,
                            hipEvent_t after);
 hipError_t launch_compact(const Plan &P, hipStream_t s);                /* dense outputs */
+uint32_t fixpoint_groups_per_cu(uint32_t waves_per_group);              /* resident fixpoint groups per CU */
+constexpr uint32_t FIX_ROW_DWORDS = 192;                                /* arena dwords per state row */
+constexpr uint32_t FIX_MAX_ROWS = 6;                                    /* state rows of the largest kernel */
 uint64_t scan_tmp_words_needed(uint64_t n);
 
 }  // namespace dc
