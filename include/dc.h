@@ -120,7 +120,8 @@ typedef struct {
 typedef struct {
     uint32_t flags;
     uint32_t sweep_cap;          /* 0 = 64 + 2 * n_blocks per kernel */
-    uint32_t waves_per_group;    /* fixpoint kernel: waves per workgroup (0 = 4) */
+    uint32_t waves_per_group;    /* fixpoint kernel: waves per workgroup, at most 4 and within the device's LDS
+                                    per workgroup (0 = the most that fit, up to 4) */
     uint32_t groups_per_cu;      /* fixpoint kernel: resident workgroups per CU in the persistent grid (0 = auto) */
     uint32_t block_cap;          /* blocks a kernel may have in the main pass (0 = 256); larger go to the overflow pass */
     uint32_t reserved[3];

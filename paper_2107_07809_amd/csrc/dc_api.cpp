@@ -35,6 +35,7 @@ struct dc_ctx {
     int device;
     int n_cu;
     size_t lds_per_cu;
+    size_t lds_per_group;
 };
 
 /* one device allocation list per object, freed together */
@@ -143,6 +144,7 @@ extern "C" dc_status_t dc_ctx_create(int hip_device, dc_ctx_t **out) {
     c->device = hip_device;
     c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
     c->lds_per_cu = prop.maxSharedMemoryPerMultiProcessor ? prop.maxSharedMemoryPerMultiProcessor : 65536;
+    c->lds_per_group = prop.sharedMemPerBlock ? prop.sharedMemPerBlock : 65536;
     *out = c;
     return DC_OK;
 }
@@ -169,8 +171,11 @@ static dc_status_t plan_batch(dc_batch *B, dc_ctx *ctx, const dc_kernel_t *kerne
     B->cfg_only = cfg_only;
     if (opts) B->opts = *opts;
     if (B->opts.flags & ~(DC_OPT_EXPORT_STATES | DC_OPT_DIGEST | DC_OPT_TIMING)) return DC_E_INVAL;
-    if (B->opts.waves_per_group == 0) B->opts.waves_per_group = 4;
-    if (B->opts.waves_per_group > 4) return DC_E_INVAL;
+    /* waves per group: the fixpoint kernel's LDS per wave must fit a group */
+    const size_t lds_wave = fixpoint_lds_per_wave();
+    if (B->opts.waves_per_group == 0)
+        B->opts.waves_per_group = (uint32_t)std::max<size_t>(1, std::min<size_t>(4, ctx->lds_per_group / lds_wave));
+    if (B->opts.waves_per_group > 4 || B->opts.waves_per_group * lds_wave > ctx->lds_per_group) return DC_E_INVAL;
     if (B->opts.block_cap == 0) B->opts.block_cap = 256;
     if (B->opts.block_cap > 2048) return DC_E_INVAL;   /* the main pass keeps its bitmaps in one VGPR */
     B->K = n_kernels;

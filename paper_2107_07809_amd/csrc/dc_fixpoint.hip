@@ -13,22 +13,28 @@
  *      name (plus vcc, exec, scc and the argument pointer s[4:5]); a ballot
  *      prefix numbers them.  A slot no record names keeps its ABI entry value
  *      on every path, so only the U named slots are carried (U <= 368).
- *   2. Register-resident state.  The working state of a block lives in VGPRs:
- *      compact slot c is lane c % 64 of row c / 64, three words per slot
- *      (provenance bits; payload low word; payload high word with the type bits
- *      in its low byte).  Two rows hold up to 128 slots, six rows any kernel.
- *   3. Chunks.  A block's records are staged 64 at a time, one per lane:
- *      descriptor lookup, compact operand indices and constant operand values
- *      are computed lane-parallel.  A wave-uniform loop then applies the
- *      transfer of each instruction in order, reading sources with readlane
- *      and writing definitions with a lane select.
- *   4. Emission on every visit.  Access and built-in records of a visit are
- *      written into the block's own region of the sparse outputs (one slot per
- *      instruction, four per instruction for built-ins) with the block's counts;
- *      a block's last visit runs on its fixpoint IN state, so the last write
- *      is the result and no extraction walk is needed.
- *   5. Joins.  The OUT state is joined lane-parallel into each successor's IN
- *      state in an HBM arena; a ballot detects change and marks the successor
+ *   2. Block state in LDS.  A visit loads the block's IN state from the HBM
+ *      arena into LDS tables (provenance and type bits; payload).
+ *   3. Chunks of 64 instructions, one per lane.  Each lane finds, for every
+ *      source dword of its instruction, the latest earlier definition in the
+ *      chunk (a per-slot bit mask of defining lanes) or else the block state.
+ *      Provenance, type bits and two liveness bits of every definition (can
+ *      the payload be other than TOP; other than TOP and uninitialised) then
+ *      follow from a few lane-parallel passes over that def-use graph: the
+ *      graph is acyclic, so the passes reach its unique solution after as many
+ *      passes as the longest def-use chain.
+ *   4. Payloads.  Only instructions whose result can be other than TOP run in a
+ *      wave-uniform loop, in order; every payload rule gives TOP when one of
+ *      its inputs is TOP (and, except the move and select rules, when one is
+ *      uninitialised), so the others are TOP without evaluation.
+ *   5. Emission on every visit.  The lanes build the chunk's access and
+ *      built-in records and write them compacted (ballot prefix) into the
+ *      block's region of the sparse outputs; a block's last visit runs on its
+ *      fixpoint IN state, so the last write is the result and no extraction
+ *      walk is needed.  The last definition of each slot goes back to the block
+ *      state.
+ *   6. Joins.  The OUT state is joined lane-parallel into each successor's IN
+ *      state in the arena; a ballot detects change and marks the successor
  *      dirty in a bitmap over reverse-postorder positions.  Passes sweep that
  *      bitmap in order (the round-robin schedule).
  *
@@ -37,22 +43,43 @@
  * choices are selects: a store that only some lanes should make is a store by
  * every lane whose address is the real one or a per-lane scratch word.  A
  * lane-predicated branch around uniform code lets the optimiser thread the
- * predicate across a loop back edge and split the wave.
+ * predicate across a loop back edge and split the wave.  LDS accesses of one
+ * wavefront execute in order, which orders the lanes' table writes and reads;
+ * the wave barriers mark those points (they emit no instruction).
  */
 #include "dc_device.h"
 
 namespace dc {
 
 constexpr int32_t ST_OK_FIX = 0;
-constexpr uint32_t CX_NONE = 0x1FFu;       /* compact index of a non-register operand */
-constexpr uint32_t HTOP = 0xFFFFFF00u;     /* payload high word of TOP, type bits cleared */
-constexpr uint32_t ROW_DW = FIX_ROW_DWORDS;   /* arena dwords of one state row: 3 words x 64 lanes */
-constexpr int RMAX = (int)FIX_MAX_ROWS;       /* rows for any kernel: 6 x 64 >= NSLOT */
+constexpr uint32_t CX_NONE = 0x1FFu;          /* compact index of a non-register operand */
+constexpr uint32_t HTOP = 0xFFFFFF00u;        /* arena: payload high word of TOP, type bits cleared */
+constexpr uint32_t ROW_DW = FIX_ROW_DWORDS;   /* arena dwords of 64 slots: 3 words each */
+constexpr int RMAX = (int)FIX_MAX_ROWS;       /* 6 x 64 >= NSLOT */
 constexpr uint32_t USLOT_N = RMAX * 64;
-constexpr uint32_t MAIN_MAX_BLOCKS = 2048; /* register bitmap: 64 lanes x 32 bits */
+constexpr uint32_t MAIN_MAX_BLOCKS = 2048;    /* register bitmap: 64 lanes x 32 bits */
+
+/* LDS value tables: [0, 384) the block state by compact slot; [IX_DEF + 64 k
+ * + i) definition k of the chunk's instruction i (k < 4 the explicit dwords,
+ * k = 4 the implicit registers); IX_CONST an inline or literal source; IX_ZERO
+ * no source. */
+constexpr uint32_t IX_DEF = USLOT_N;
+constexpr uint32_t K_IMP = 4;
+constexpr uint32_t IX_CONST = IX_DEF + 5 * 64;
+constexpr uint32_t IX_ZERO = IX_CONST + 1;
+constexpr uint32_t IX_SCR = IX_ZERO + 1;      /* 64 per-lane scratch entries */
+constexpr uint32_t TBL_N = IX_SCR + 64 + 6;
+/* fpt entry: provenance bits | (type bits [4:0], T [5], N [6]) << 32, where T:
+ * the payload may be other than TOP, N: other than TOP and uninitialised */
+constexpr uint32_t FT_T = 1u << 5, FT_N = 1u << 6;
 
 /* per-wavefront LDS */
 struct WaveLds {
+    uint64_t fpt[TBL_N];
+    uint64_t fv[TBL_N];             /* payloads */
+    uint64_t dm[USLOT_N + 64];      /* per compact slot: the chunk's lanes that define it; tail scratch */
+    uint64_t junk[64];              /* per-lane scratch stores */
+    uint32_t lcd[64];               /* per lane: compact index of r0 | implicit definitions << 16 */
     uint16_t umap[USLOT_N];         /* slot -> compact index; entries >= NSLOT unused */
     uint16_t uslot[USLOT_N + 64];   /* compact index -> slot; 64-entry scratch tail */
     uint8_t umark[USLOT_N + 64];    /* slot marks; entries >= NSLOT are scratch */
@@ -190,10 +217,10 @@ __device__ __forceinline__ void arg_dword(const KCtx &K, uint32_t o, uint32_t &p
         return;
     }
     for (uint32_t k = 0; k < K.n_args; k++) {
-        const uint32_t off = rfl(K.args[k].offset), sz = rfl(K.args[k].size);
+        const uint32_t off = K.args[k].offset, sz = K.args[k].size;
         if (o >= off && (uint64_t)o < (uint64_t)off + sz) {
             prov = 1u << (PB_KARG + (k < 11 ? k : 11));
-            type = rfl(K.args[k].type);
+            type = K.args[k].type;
             if (sz == 4 && o == off) val = pv(T_KARG, IG_ENT, 0, 0, 0, k, 0);
             else if (sz == 8 && o == off) val = pv(T_KARG, IG_LO, 0, 0, 0, k, 0);
             else if (sz == 8 && o == off + 4) val = pv(T_KARG, IG_HI, 0, 0, 0, k, 0);
@@ -252,102 +279,6 @@ __device__ __forceinline__ uint4 entry_slot(uint32_t j, uint32_t dims) {
         val = VTOP;
     }
     return make_uint4(prov, type, (uint32_t)val, (uint32_t)(val >> 32));
-}
-
-/* in-register form of a payload: high word with the type bits in its low
- * byte (payload bits 39:32 are always zero; TOP's become HTOP) */
-__device__ __forceinline__ uint32_t pack_hi(uint64_t val, uint32_t type) {
-    return ((uint32_t)(val >> 32) & 0xFFFFFF00u) | type;
-}
-__device__ __forceinline__ uint64_t unpack_val(uint32_t lo, uint32_t hi) {
-    return hi >= HTOP ? VTOP : (((uint64_t)(hi & 0xFFFFFF00u) << 32) | lo);
-}
-
-/* ------------------------------------------------------------------ */
-/* register-resident state                                              */
-/* ------------------------------------------------------------------ */
-template <int R>
-struct St {
-    uint32_t p[R], lo[R], hi[R];
-};
-
-template <int R>
-__device__ __forceinline__ uint32_t rdc(const uint32_t (&a)[R], uint32_t c) {
-    const uint32_t ln = c & 63u, row = c >> 6;
-    uint32_t x = rdl(a[0], ln);
-#pragma unroll
-    for (int r = 1; r < R; r++) x = row == (uint32_t)r ? rdl(a[r], ln) : x;
-    return x;
-}
-template <int R>
-__device__ __forceinline__ SV get(const St<R> &S, uint32_t c) {
-    SV v;
-    v.prov = rdc(S.p, c);
-    const uint32_t lo = rdc(S.lo, c), hi = rdc(S.hi, c);
-    v.type = hi & 0xFFu;
-    v.val = unpack_val(lo, hi);
-    return v;
-}
-template <int R>
-__device__ __forceinline__ uint32_t get_prov(const St<R> &S, uint32_t c) { return rdc(S.p, c); }
-template <int R>
-__device__ __forceinline__ uint32_t get_type(const St<R> &S, uint32_t c) { return rdc(S.hi, c) & 0xFFu; }
-
-template <int R>
-__device__ __forceinline__ void put(St<R> &S, uint32_t c, uint32_t prov, uint32_t type, uint64_t val) {
-    const uint32_t lo = (uint32_t)val, hi = pack_hi(val, type);
-    const uint32_t row = c >> 6;
-    const bool me = lane_id() == (c & 63u);
-#pragma unroll
-    for (int r = 0; r < R; r++) {
-        const bool sel = me && row == (uint32_t)r;
-        S.p[r] = sel ? prov : S.p[r];
-        S.lo[r] = sel ? lo : S.lo[r];
-        S.hi[r] = sel ? hi : S.hi[r];
-    }
-}
-
-template <int R>
-__device__ __forceinline__ void st_load(St<R> &S, const uint32_t *a) {
-    const uint32_t l = lane_id();
-#pragma unroll
-    for (int r = 0; r < R; r++) {
-        S.p[r] = a[r * ROW_DW + l];
-        S.lo[r] = a[r * ROW_DW + 64 + l];
-        S.hi[r] = a[r * ROW_DW + 128 + l];
-    }
-}
-template <int R>
-__device__ __forceinline__ void st_store(const St<R> &S, uint32_t *a) {
-    const uint32_t l = lane_id();
-#pragma unroll
-    for (int r = 0; r < R; r++) {
-        a[r * ROW_DW + l] = S.p[r];
-        a[r * ROW_DW + 64 + l] = S.lo[r];
-        a[r * ROW_DW + 128 + l] = S.hi[r];
-    }
-}
-/* a := a join S (provenance and type bits unite; payloads that differ go to
- * TOP); true when a changed */
-template <int R>
-__device__ __forceinline__ bool st_join(const St<R> &S, uint32_t *a) {
-    const uint32_t l = lane_id();
-    St<R> J;
-    bool ch = false;
-#pragma unroll
-    for (int r = 0; r < R; r++) {
-        const uint32_t pa = a[r * ROW_DW + l], la = a[r * ROW_DW + 64 + l], ha = a[r * ROW_DW + 128 + l];
-        const uint32_t pb = S.p[r], lb = S.lo[r], hb = S.hi[r];
-        const bool same = la == lb && (ha & 0xFFFFFF00u) == (hb & 0xFFFFFF00u);
-        const uint32_t ty = (ha | hb) & 0xFFu;
-        J.p[r] = pa | pb;
-        J.lo[r] = same ? la : 0xFFFFFFFFu;
-        J.hi[r] = (same ? (ha & 0xFFFFFF00u) : HTOP) | ty;
-        ch = ch || J.p[r] != pa || J.lo[r] != la || J.hi[r] != ha;
-    }
-    const bool any = ballot(ch) != 0;
-    if (any) st_store(J, a);
-    return any;
 }
 
 /* ------------------------------------------------------------------ */
@@ -413,16 +344,97 @@ struct MemBits {
 };
 
 /* ------------------------------------------------------------------ */
+/* table entries                                                        */
+/* ------------------------------------------------------------------ */
+__device__ __forceinline__ uint64_t fpt_pack(uint32_t prov, uint32_t type, uint32_t live) {
+    return (uint64_t)prov | ((uint64_t)(type | live) << 32);
+}
+__device__ __forceinline__ uint32_t fpt_prov(uint64_t x) { return (uint32_t)x; }
+__device__ __forceinline__ uint32_t fpt_type(uint64_t x) { return (uint32_t)(x >> 32) & 31u; }
+__device__ __forceinline__ bool fpt_t(uint64_t x) { return ((x >> 32) & FT_T) != 0; }
+__device__ __forceinline__ bool fpt_n(uint64_t x) { return ((x >> 32) & FT_N) != 0; }
+/* liveness bits of a known payload */
+__device__ __forceinline__ uint32_t live_bits(uint64_t v) {
+    return v == VTOP ? 0u : (v_tag(v) == T_UNINIT ? FT_T : FT_T | FT_N);
+}
+
+/* the arena keeps three words per slot: provenance, payload low word, payload
+ * high word with the type bits in its low byte (payload bits 39:32 are always
+ * zero; TOP's high word becomes HTOP) */
+__device__ __forceinline__ uint32_t pack_hi(uint64_t val, uint32_t type) {
+    return ((uint32_t)(val >> 32) & 0xFFFFFF00u) | type;
+}
+__device__ __forceinline__ uint64_t unpack_val(uint32_t lo, uint32_t hi) {
+    return hi >= HTOP ? VTOP : (((uint64_t)(hi & 0xFFFFFF00u) << 32) | lo);
+}
+
+/* IN state of a block (arena, nu_pad slots per field) -> LDS state; all
+ * rows' loads are issued before the first LDS write */
+__device__ __forceinline__ void state_load(WaveLds &L, const uint32_t *a, uint32_t nu_pad) {
+    const uint32_t l = lane_id();
+    uint32_t p[RMAX], lo[RMAX], hi[RMAX];
+#pragma unroll
+    for (int r = 0; r < RMAX; r++) {
+        if ((uint32_t)r * 64 < nu_pad) {   /* uniform */
+            const uint32_t c = (uint32_t)r * 64 + l;
+            p[r] = a[c];
+            lo[r] = a[nu_pad + c];
+            hi[r] = a[2 * nu_pad + c];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RMAX; r++) {
+        if ((uint32_t)r * 64 < nu_pad) {
+            const uint32_t c = (uint32_t)r * 64 + l;
+            const uint64_t v = unpack_val(lo[r], hi[r]);
+            L.fpt[c] = fpt_pack(p[r], hi[r] & 0xFFu, live_bits(v));
+            L.fv[c] = v;
+        }
+    }
+}
+
+/* join of the OUT state into one arena IN state: a := a join OUT (provenance
+ * and type bits unite; payloads that differ go to TOP), or a := OUT when
+ * first; the words are stored unconditionally */
+__device__ __forceinline__ bool join_row(uint32_t *a, uint32_t nu_pad, uint32_t c, bool first, uint32_t pb, uint32_t lb,
+                                         uint32_t hb) {
+    uint32_t pn = pb, ln = lb, hn = hb;
+    bool ch = first;
+    if (!first) {   /* uniform */
+        const uint32_t pa = a[c], la = a[nu_pad + c], ha = a[2 * nu_pad + c];
+        const bool same = la == lb && (ha & 0xFFFFFF00u) == (hb & 0xFFFFFF00u);
+        pn = pa | pb;
+        ln = same ? la : 0xFFFFFFFFu;
+        hn = (same ? (ha & 0xFFFFFF00u) : HTOP) | ((ha | hb) & 0xFFu);
+        ch = pn != pa || ln != la || hn != ha;
+    }
+    a[c] = pn;
+    a[nu_pad + c] = ln;
+    a[2 * nu_pad + c] = hn;
+    return ch;
+}
+/* OUT state into the IN states of up to two successors (null when absent);
+ * returns the per-successor change bits (bit 0, bit 1) */
+__device__ __forceinline__ uint32_t state_join2(const WaveLds &L, uint32_t *a0, bool first0, uint32_t *a1, bool first1,
+                                                uint32_t nu_pad) {
+    const uint32_t l = lane_id();
+    bool ch0 = false, ch1 = false;
+#pragma unroll
+    for (int r = 0; r < RMAX; r++) {
+        if ((uint32_t)r * 64 < nu_pad) {   /* uniform */
+            const uint32_t c = (uint32_t)r * 64 + l;
+            const uint64_t x = L.fpt[c], v = L.fv[c];
+            const uint32_t pb = fpt_prov(x), lb = (uint32_t)v, hb = pack_hi(v, fpt_type(x));
+            if (a0) ch0 = join_row(a0, nu_pad, c, first0, pb, lb, hb) || ch0;
+            if (a1) ch1 = join_row(a1, nu_pad, c, first1, pb, lb, hb) || ch1;
+        }
+    }
+    return (ballot(ch0) != 0 ? 1u : 0u) | (ballot(ch1) != 0 ? 2u : 0u);
+}
+
+/* ------------------------------------------------------------------ */
 /* staged chunk: one instruction per lane                                */
 /* ------------------------------------------------------------------ */
-struct Stage {
-    uint32_t x, y, z;          /* record words: op | r0 << 16, r1 | r2 << 16, imm */
-    uint32_t elo, ehi;         /* opcode descriptor */
-    uint32_t cx;               /* compact indices: r0 [8:0], r1 [17:9], r2 [26:18] */
-    uint32_t cc;               /* compact index of the third source [8:0] */
-    uint32_t ka0, ka1, kb0, kb1, kc0;  /* dwords of non-register sources */
-};
-
 /* dword j of a non-register source id of width w (inline integer, inline
  * float, or the record's literal) */
 __device__ __forceinline__ uint32_t const_dword(uint32_t id, uint32_t j, uint32_t w, int32_t lit) {
@@ -443,313 +455,479 @@ __device__ __forceinline__ uint32_t cmap(const WaveLds &L, uint32_t id) {
     return id < (uint32_t)NSLOT ? (uint32_t)L.umap[id] : CX_NONE;
 }
 
-/* records of positions [g0, g0 + cnt) of the kernel starting at pos0 */
-__device__ __forceinline__ Stage stage_chunk(const Plan *__restrict__ P, const WaveLds &L, uint64_t rb, uint32_t pos0,
-                                             uint32_t g0, uint32_t cnt) {
+__device__ __forceinline__ bool imp_covers(uint32_t idf, uint32_t s, uint32_t cv) {
+    return ((idf & IM_VCC) && (s == cv || s == cv + 1)) || ((idf & IM_EXEC) && (s == cv + 2 || s == cv + 3)) ||
+           ((idf & IM_SCC) && s == cv + 4);
+}
+
+/* table index of compact slot s read by this lane's instruction: the latest
+ * earlier definition in the chunk, else the block state */
+__device__ __forceinline__ uint32_t src_ix(const WaveLds &L, uint32_t s, uint32_t cv) {
     const uint32_t l = lane_id();
-    const uint32_t li = l < cnt ? l : cnt - 1;   /* spare lanes repeat the last record */
-    const uint4 r = reinterpret_cast<const uint4 *>(P->instrs)[rb + (g0 + li - pos0)];
-    const uint64_t e = OPTAB[r.x & 0xFFFFu];
-    Stage T;
-    T.x = r.x;
-    T.y = r.y;
-    T.z = r.z;
-    T.elo = (uint32_t)e;
-    T.ehi = (uint32_t)(e >> 32);
-    const uint32_t r0 = r.x >> 16, r1 = r.y & 0xFFFFu, r2 = r.y >> 16;
-    const int32_t imm = (int32_t)r.z;
-    T.cx = cmap(L, r0) | cmap(L, r1) << 9 | cmap(L, r2) << 18;
-    const bool third = e_role(e, 3) != RO_NO;
-    T.cc = third ? cmap(L, (uint32_t)imm) : CX_NONE;
-    const uint32_t w1 = e_width(e, 1), w2 = e_width(e, 2), w3 = e_width(e, 3);
-    T.ka0 = const_dword(r1, 0, w1, imm);
-    T.ka1 = const_dword(r1, 1, w1, imm);
-    T.kb0 = const_dword(r2, 0, w2, imm);
-    T.kb1 = const_dword(r2, 1, w2, imm);
-    T.kc0 = const_dword((uint32_t)imm, 0, w3, 0);
-    return T;
+    const uint64_t m = L.dm[s < USLOT_N ? s : USLOT_N + l] & ((1ull << l) - 1ull);
+    const uint32_t p = 63u - (uint32_t)__builtin_clzll(m | 1ull);
+    const uint32_t lc = L.lcd[p];
+    const uint32_t k = imp_covers((lc >> 16) & 7u, s, cv) ? K_IMP : s - (lc & 0x1FFu);
+    return m ? IX_DEF + k * 64 + p : s;
+}
+
+/* per-lane staged instruction */
+struct Ins {
+    uint32_t x, y, imm;        /* record words: op | r0 << 16, r1 | r2 << 16, imm */
+    uint32_t elo, ehi;         /* descriptor; a no-op for lanes past the chunk */
+    uint32_t cd, ndef;         /* compact index of r0, explicit definition dwords */
+    uint32_t ia, ib, ic;       /* table indices A0 | A1 << 16, B0 | B1 << 16, C0 | C1 << 16 */
+    uint32_t iv, ie, isd;      /* VCC0 | VCC1 << 16, EXEC0 | EXEC1 << 16, SCC | D0 << 16 */
+    uint32_t id1;              /* D1 (second dword of store data) */
+    uint32_t ka0, ka1, kb0, kb1, kc0;   /* dwords of constant sources */
+};
+
+struct KCtx2 {
+    KCtx K;
+    uint32_t cv, dims;
+};
+
+/* ------------------------------------------------------------------ */
+/* payload rule of one instruction (wave-uniform)                        */
+/* ------------------------------------------------------------------ */
+__device__ __forceinline__ void eval_rule(const KCtx &K, uint32_t prule, bool val_is_r1, uint64_t a0, uint64_t a1,
+                                          uint64_t b0, uint64_t b1, uint64_t c0, uint64_t &v0, uint64_t &v1) {
+    v0 = VTOP;
+    v1 = VTOP;
+    switch (prule) {
+    case PR_MOV: v0 = a0; v1 = a1; break;
+    case PR_ADD: v0 = r_add(a0, b0); break;
+    case PR_ADDC: v0 = r_addc(a0, b0); break;
+    case PR_SUB: if (is_c(a0) && is_c(b0)) v0 = C32(v_c(a0) - v_c(b0)); break;
+    case PR_AND: if (is_c(a0) && is_c(b0)) v0 = C32(v_c(a0) & v_c(b0)); break;
+    case PR_OR: if (is_c(a0) && is_c(b0)) v0 = C32(v_c(a0) | v_c(b0)); break;
+    case PR_XOR: if (is_c(a0) && is_c(b0)) v0 = C32(v_c(a0) ^ v_c(b0)); break;
+    case PR_MUL: v0 = r_mul(K, a0, b0); break;
+    case PR_MUL24: v0 = r_mul(K, low24(a0), low24(b0)); break;
+    case PR_MAD24: v0 = r_add(r_mul(K, low24(a0), low24(b0)), c0); break;
+    case PR_SHL: v0 = val_is_r1 ? r_shl(K, a0, b0) : r_shl(K, b0, a0); break;
+    case PR_LSHR: v0 = val_is_r1 ? r_lshr(K, a0, b0) : r_lshr(K, b0, a0); break;
+    case PR_ASHR: v0 = val_is_r1 ? r_ashr(a0, b0) : r_ashr(b0, a0); break;
+    case PR_SEL: v0 = a0 == b0 ? a0 : VTOP; break;
+    case PR_AND64: case PR_OR64: case PR_XOR64: case PR_ANDN264:
+        if (is_c(a0) && is_c(a1) && is_c(b0) && is_c(b1)) {
+            const uint32_t x0 = v_c(a0), x1 = v_c(a1), y0 = v_c(b0), y1 = v_c(b1);
+            if (prule == PR_AND64) { v0 = C32(x0 & y0); v1 = C32(x1 & y1); }
+            else if (prule == PR_OR64) { v0 = C32(x0 | y0); v1 = C32(x1 | y1); }
+            else if (prule == PR_XOR64) { v0 = C32(x0 ^ y0); v1 = C32(x1 ^ y1); }
+            else { v0 = C32(x0 & ~y0); v1 = C32(x1 & ~y1); }
+        }
+        break;
+    case PR_SHL64: {
+        const uint64_t amt = a0, lo = b0, hi = b1;
+        if (!is_c(amt) || lo == VTOP || hi == VTOP) break;
+        const uint32_t s = v_c(amt) & 63u;
+        if (is_c(lo) && is_c(hi)) {
+            const uint64_t xx = (((uint64_t)v_c(hi) << 32) | v_c(lo)) << s;
+            v0 = C32((uint32_t)xx);
+            v1 = C32((uint32_t)(xx >> 32));
+        } else if (idx_lo(lo) && ((is_c(hi) && v_c(hi) == 0) ||
+                                  (v_tag(hi) == T_IDX && v_ig(hi) == IG_HI && v_dim(hi) == v_dim(lo) &&
+                                   v_aux(hi) == v_aux(lo)))) {
+            if (s == 0) { v0 = lo; v1 = hi; }
+            else if (s <= 15) {
+                v0 = pv(T_SHL, IG_LO, v_dim(lo), v_aux(lo), s, 0, v_c(lo) << s);
+                v1 = pv(T_SHL, IG_HI, v_dim(lo), v_aux(lo), s, 0, 0);
+            }
+        }
+        break;
+    }
+    default: break;
+    }
+}
+
+/* the SMEM loads of the argument area (Listing 3): provenance, type and
+ * payload of definition dword j (payload before the base-register check) */
+__device__ __forceinline__ void smem_dword(const KCtx &K, uint32_t w, uint32_t off, uint32_t j, uint32_t &pr,
+                                          uint32_t &ty, uint64_t &va) {
+    pr = 1u << PB_LOADG;
+    ty = 0;
+    va = VTOP;
+    arg_dword(K, off + 4u * j, pr, ty, va);
+    if (w == 2 && (off == 0u || off == 8u || off == 16u)) {
+        const uint32_t d = off >> 3;
+        pr = 1u << (PB_GOFF + d);
+        ty = TY_U;
+        va = j == 0 ? pv(T_IDX, IG_LO, d, M_GOFF, 0, 0, 0) : pv(T_SYS, IG_HI, d, K_GOFFHI, 0, 0, 0);
+    } else if (w == 1 && (off == 0xCu || off == 0x10u || off == 0x14u)) {
+        const uint32_t d = (off - 0xCu) >> 2;
+        pr = 1u << (PB_GSIZE + d);
+        ty = TY_U;
+        va = pv(T_SYS, IG_ENT, d, K_GSIZE, 0, 0, 0);
+    } else if (w == 1 && off == 0x20010u) {
+        pr = 1u << PB_WORKDIM;
+        ty = TY_U;
+        va = pv(T_SYS, IG_ENT, 0, K_WORKDIM, 0, 0, 0);
+    }
+}
+
+__device__ __forceinline__ uint64_t lds_val(const WaveLds &L, uint32_t ix) {
+    const uint64_t v = L.fv[ix];
+    return ((uint64_t)rfl((uint32_t)(v >> 32)) << 32) | rfl((uint32_t)v);
+}
+/* payload of source table index ix (k = the lane's constant dword) */
+__device__ __forceinline__ uint64_t src_val(const WaveLds &L, uint32_t ix, uint32_t k, uint32_t i) {
+    if (ix == IX_CONST) return C32(rdl(k, i));
+    return lds_val(L, ix);
+}
+/* lane 0 stores a uniform value; the other lanes store into scratch */
+__device__ __forceinline__ void lds_put_u64(WaveLds &L, uint64_t *dst, uint64_t v) {
+    const uint32_t l = lane_id();
+    *(l == 0 ? dst : &L.junk[l]) = v;
 }
 
 /* ------------------------------------------------------------------ */
-/* record buffers (one record per lane, flushed lane-parallel)          */
+/* record output                                                        */
 /* ------------------------------------------------------------------ */
 struct Emit {
-    uint32_t a0, a1, a2, a3;   /* access: instr, kind|space<<8|width<<16|dtype<<24, addr lo, hi */
-    uint32_t s0, s1;           /* built-in: instr, slot|kind<<16|dim<<24 */
-    uint32_t na, ns;           /* buffered counts (uniform) */
-    uint32_t ta, ts;           /* records already written for this visit (uniform) */
+    uint32_t ta, ts;   /* records written for this visit (uniform) */
 };
 
-__device__ __forceinline__ void flush_acc(const Plan *__restrict__ P, Emit &E, uint32_t g_lo, uint4 *dummy) {
-    if (E.na == 0) return;
+__device__ __forceinline__ uint32_t wave_excl_scan(uint32_t x, uint32_t &total) {
     const uint32_t l = lane_id();
-    uint4 *dst = l < E.na ? reinterpret_cast<uint4 *>(P->acc_sparse) + g_lo + E.ta + l : dummy + l;
-    *dst = make_uint4(E.a0, E.a1, E.a2, E.a3);
-    E.ta += E.na;
-    E.na = 0;
-}
-__device__ __forceinline__ void flush_sys(const Plan *__restrict__ P, Emit &E, uint32_t g_lo, uint4 *dummy) {
-    if (E.ns == 0) return;
-    const uint32_t l = lane_id();
-    uint2 *dst = l < E.ns ? reinterpret_cast<uint2 *>(P->sys_sparse) + 4ull * g_lo + E.ts + l
-                          : reinterpret_cast<uint2 *>(dummy + l);
-    *dst = make_uint2(E.s0, E.s1);
-    E.ts += E.ns;
-    E.ns = 0;
+    uint32_t inc = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(inc, d, 64);
+        inc += l >= (uint32_t)d ? y : 0u;
+    }
+    total = __shfl(inc, 63, 64);
+    return inc - x;
 }
 
 /* ------------------------------------------------------------------ */
-/* one instruction                                                      */
+/* one chunk                                                            */
 /* ------------------------------------------------------------------ */
-struct KConst {
-    uint32_t cv;      /* compact index of vcc (exec = cv + 2, scc = cv + 4) */
-};
+__device__ __forceinline__ void run_chunk(const Plan *__restrict__ P, WaveLds &L, const KCtx2 &KX, uint64_t rb,
+                                          uint32_t pos0, uint32_t g0, uint32_t cnt, uint32_t g_lo, Emit &E,
+                                          uint4 *dummy) {
+    const uint32_t l = lane_id();
+    const KCtx &K = KX.K;
+    const uint32_t cv = KX.cv;
+    const bool act = l < cnt;
+    const uint64_t bit = 1ull << l;
 
-template <int R>
-__device__ __forceinline__ SV src(const St<R> &S, uint32_t c, uint32_t j, uint32_t k) {
-    if (c != CX_NONE) return get(S, c + j);
-    SV v;
-    v.prov = 1u << PB_CONST;
-    v.type = 0;
-    v.val = C32(k);
-    return v;
-}
-
-/* the access record of a memory instruction from the pre-state */
-template <int R>
-__device__ __forceinline__ void emit_access(const St<R> &S, const KCtx &K, uint64_t e, uint32_t cx, uint32_t y,
-                                            int32_t imm, uint32_t instr, Emit &E) {
-    const uint32_t cls = e_cls(e), w0 = e_width(e, 0);
-    const uint32_t cd = cx & 0x1FFu, ca = (cx >> 9) & 0x1FFu;
-    uint32_t kind, space, width;
-    uint64_t addr = VTOP;
-    if (cls == C_GLD || cls == C_FLD || cls == C_GST || cls == C_FST) {
-        kind = (cls == C_GLD || cls == C_FLD) ? 0 : 1;
-        space = (cls == C_GLD || cls == C_GST) ? 0 : 1;
-        width = 4 * w0;
-        if ((y >> 16) == 0xFFFFu && ca != CX_NONE) {
-            const uint64_t lo = get(S, ca).val, hi = get(S, ca + 1).val;
-            if (lo != VTOP && hi != VTOP && v_ig(lo) == IG_LO && v_ig(hi) == IG_HI && v_arg(lo) == v_arg(hi)) {
-                if (v_tag(lo) == T_PTR && v_tag(hi) == T_PTR)
-                    addr = pv(T_PTR, IG_ENT, v_dim(lo), v_aux(lo), v_sh(lo), v_arg(lo), v_c(lo) + (uint32_t)imm);
-                else if (v_tag(lo) == T_KARG && v_tag(hi) == T_KARG)
-                    addr = pv(T_PTR, IG_ENT, 0, 0, 0, v_arg(lo), (uint32_t)imm);
-            }
-        }
-    } else {   /* C_DSR, C_DSW */
-        kind = cls == C_DSR ? 0 : 1;
-        space = 2;
-        width = 4;
-        if (ca != CX_NONE) {
-            const uint64_t v = get(S, ca).val;
-            if (v != VTOP) {
-                const uint32_t c = v_c(v) + (uint32_t)imm;
-                if (v_tag(v) == T_SHL && v_ig(v) == IG_ENT) addr = pv(T_SHL, IG_ENT, v_dim(v), v_aux(v), v_sh(v), 0, c);
-                else if (idx_lo(v)) addr = pv(T_IDX, IG_ENT, v_dim(v), v_aux(v), 0, 0, c);
-                else if (is_c(v)) addr = C32(c);
-            }
-        }
-    }
-    uint32_t dt = 0;
-    if (kind == 1) {
-        for (uint32_t j = 0; j < w0; j++) dt |= get_type(S, cd + j);
-    } else if (addr != VTOP && v_tag(addr) == T_PTR && v_arg(addr) < K.n_args) {
-        dt = rfl(K.args[v_arg(addr)].flags) & 31u;
-    }
-    const bool me = lane_id() == E.na;
-    E.a0 = me ? instr : E.a0;
-    E.a1 = me ? (kind | space << 8 | width << 16 | dt << 24) : E.a1;
-    E.a2 = me ? (uint32_t)addr : E.a2;
-    E.a3 = me ? (uint32_t)(addr >> 32) : E.a3;
-    E.na++;
-}
-
-__device__ __forceinline__ void emit_sysval(uint64_t v, uint32_t slot, uint32_t instr, Emit &E) {
-    uint32_t dim;
-    const int kind = builtin_kind(v, dim);
-    if (kind < 0) return;
-    const bool me = lane_id() == E.ns;
-    E.s0 = me ? instr : E.s0;
-    E.s1 = me ? (slot | (uint32_t)kind << 16 | dim << 24) : E.s1;
-    E.ns++;
-}
-
-/* transfer of instruction i of the staged chunk, with emission */
-template <int R>
-__device__ __forceinline__ void step(St<R> &S, const KCtx &K, const KConst &KC, const Stage &T, uint32_t i,
-                                     uint32_t instr, Emit &E) {
-    const uint32_t x = rdl(T.x, i), y = rdl(T.y, i);
-    const int32_t imm = (int32_t)rdl(T.z, i);
-    const uint64_t e = ((uint64_t)rdl(T.ehi, i) << 32) | rdl(T.elo, i);
-    const uint32_t cx = rdl(T.cx, i);
+    /* ---- stage ---- */
+    Ins I;
+    const uint32_t li = act ? l : cnt - 1;
+    const uint4 r = reinterpret_cast<const uint4 *>(P->instrs)[rb + (g0 + li - pos0)];
+    const uint64_t e = act ? OPTAB[r.x & 0xFFFFu] : (uint64_t)C_NOP;
+    I.x = r.x;
+    I.y = r.y;
+    I.imm = r.z;
+    I.elo = (uint32_t)e;
+    I.ehi = (uint32_t)(e >> 32);
     const uint32_t cls = e_cls(e);
-    const uint32_t cd = cx & 0x1FFu, ca = (cx >> 9) & 0x1FFu, cb = cx >> 18;
-    const uint32_t r0 = x >> 16;
-
-    if (cls >= C_GLD) emit_access(S, K, e, cx, y, imm, instr, E);
-
-    uint64_t dv[4] = {VTOP, VTOP, VTOP, VTOP};
-    uint32_t nd = 0;
-    if (cls == C_SMEM) {
-        const uint32_t w = e_width(e, 0);
-        const bool via = (y & 0xFFFFu) == 4u;
-        const bool ok = via && get(S, ca).val == pv(T_SYSPTR, IG_LO, 0, 0, 0, 0, 0) &&
-                        get(S, ca + 1).val == pv(T_SYSPTR, IG_HI, 0, 0, 0, 0, 0);
-        const uint32_t off = (uint32_t)imm;
-        uint32_t pr[4], ty[4];
-        uint64_t va[4];
+    const uint32_t r0 = r.x >> 16, r1 = r.y & 0xFFFFu, r2 = r.y >> 16;
+    const int32_t imm = (int32_t)r.z;
+    const uint32_t c0 = cmap(L, r0), c1 = cmap(L, r1), c2 = cmap(L, r2);
+    const uint32_t role0 = e_role(e, 0);
+    const uint32_t w0 = e_width(e, 0);
+    const bool alu = cls == C_SALU || cls == C_SCMP || cls == C_VALU || cls == C_VCMP;
+    I.cd = c0;
+    I.ndef = (role0 == RO_SD || role0 == RO_VD) ? w0 : 0u;
+    const uint32_t idf = alu ? e_idef(e) : 0u;
+    L.lcd[l] = c0 | idf << 16;
+    const uint32_t junk = USLOT_N + l;   /* def-mask scratch entry */
+    const uint32_t tscr = IX_SCR + l;     /* value-table scratch entry */
 #pragma unroll
-        for (uint32_t j = 0; j < 4; j++) {
-            pr[j] = 1u << PB_LOADG;
-            ty[j] = 0;
-            va[j] = VTOP;
-            if (via && j < w) arg_dword(K, off + 4u * j, pr[j], ty[j], va[j]);
-        }
-        if (via && w == 2 && (off == 0u || off == 8u || off == 16u)) {
-            const uint32_t d = off >> 3;
-            pr[0] = pr[1] = 1u << (PB_GOFF + d);
-            ty[0] = ty[1] = TY_U;
-            va[0] = pv(T_IDX, IG_LO, d, M_GOFF, 0, 0, 0);
-            va[1] = pv(T_SYS, IG_HI, d, K_GOFFHI, 0, 0, 0);
-        } else if (via && w == 1 && (off == 0xCu || off == 0x10u || off == 0x14u)) {
-            const uint32_t d = (off - 0xCu) >> 2;
-            pr[0] = 1u << (PB_GSIZE + d);
-            ty[0] = TY_U;
-            va[0] = pv(T_SYS, IG_ENT, d, K_GSIZE, 0, 0, 0);
-        } else if (via && w == 1 && off == 0x20010u) {
-            pr[0] = 1u << PB_WORKDIM;
-            ty[0] = TY_U;
-            va[0] = pv(T_SYS, IG_ENT, 0, K_WORKDIM, 0, 0, 0);
-        }
-#pragma unroll
-        for (uint32_t j = 0; j < 4; j++) {
-            dv[j] = ok ? va[j] : VTOP;
-            if (j < w) put(S, cd + j, pr[j], ty[j], dv[j]);
-        }
-        nd = w;
-    } else if (cls == C_GLD || cls == C_FLD || cls == C_DSR) {
-        const uint32_t w = e_width(e, 0);
-        const uint32_t pr = cls == C_DSR ? 1u << PB_LOADL : 1u << PB_LOADG;
-#pragma unroll
-        for (uint32_t j = 0; j < 4; j++)
-            if (j < w) put(S, cd + j, pr, 0, VTOP);
-        nd = w;
-    } else if (cls == C_SALU || cls == C_SCMP || cls == C_VALU || cls == C_VCMP) {
-        const uint32_t w1 = e_role(e, 1) != RO_NO ? e_width(e, 1) : 0;
-        const uint32_t w2 = e_role(e, 2) != RO_NO ? e_width(e, 2) : 0;
-        const uint32_t w3 = e_role(e, 3) != RO_NO ? e_width(e, 3) : 0;
-        SV a0 = {0, 0, VTOP}, a1 = {0, 0, VTOP}, b0 = {0, 0, VTOP}, b1 = {0, 0, VTOP}, c0 = {0, 0, VTOP};
-        uint32_t rp = 0;
-        if (w1) { a0 = src(S, ca, 0, rdl(T.ka0, i)); rp |= a0.prov; }
-        if (w1 == 2) { a1 = src(S, ca, 1, rdl(T.ka1, i)); rp |= a1.prov; }
-        if (w2) { b0 = src(S, cb, 0, rdl(T.kb0, i)); rp |= b0.prov; }
-        if (w2 == 2) { b1 = src(S, cb, 1, rdl(T.kb1, i)); rp |= b1.prov; }
-        if (w3) {
-            const uint32_t cc = rdl(T.cc, i);
-            c0 = src(S, cc, 0, rdl(T.kc0, i));
-            rp |= c0.prov;
-            if (w3 == 2) rp |= cc != CX_NONE ? get_prov(S, cc + 1) : (1u << PB_CONST);
-        }
-        const uint32_t iu = e_iuse(e);
-        if (iu & IM_VCC) rp |= get_prov(S, KC.cv) | get_prov(S, KC.cv + 1);
-        if (iu & IM_EXEC) rp |= get_prov(S, KC.cv + 2) | get_prov(S, KC.cv + 3);
-        if (iu & IM_SCC) rp |= get_prov(S, KC.cv + 4);
+    for (uint32_t j = 0; j < 4; j++) atomicOr((unsigned long long *)&L.dm[j < I.ndef ? c0 + j : junk], bit);
+    atomicOr((unsigned long long *)&L.dm[(idf & IM_VCC) ? cv : junk], bit);
+    atomicOr((unsigned long long *)&L.dm[(idf & IM_VCC) ? cv + 1 : junk], bit);
+    atomicOr((unsigned long long *)&L.dm[(idf & IM_EXEC) ? cv + 2 : junk], bit);
+    atomicOr((unsigned long long *)&L.dm[(idf & IM_EXEC) ? cv + 3 : junk], bit);
+    atomicOr((unsigned long long *)&L.dm[(idf & IM_SCC) ? cv + 4 : junk], bit);
+    __builtin_amdgcn_wave_barrier();
 
-        const uint32_t rrole = e_role(e, 0);
-        if (rrole == RO_SD || rrole == RO_VD) {
-            const uint32_t w0 = e_width(e, 0);
-            uint32_t ty0 = 0, ty1 = 0;
-            switch (e_trule(e)) {
-            case TR_SUF: ty0 = ty1 = e_suffix(e); break;
-            case TR_ADD: ty0 = ty1 = e_suffix(e) | ((a0.type | a1.type | b0.type | b1.type) & TY_P); break;
-            case TR_B: {
-                const uint32_t vs = e_vsrc(e);
-                uint32_t t = 0;
-                if (vs & 1u) t |= a0.type | a1.type;
-                if (vs & 2u) t |= b0.type | b1.type;
-                ty0 = ty1 = t;
-                break;
+    const uint32_t w1 = e_role(e, 1) != RO_NO ? e_width(e, 1) : 0;
+    const uint32_t w2 = e_role(e, 2) != RO_NO ? e_width(e, 2) : 0;
+    const uint32_t w3 = e_role(e, 3) != RO_NO ? e_width(e, 3) : 0;
+    const uint32_t c3 = w3 ? cmap(L, (uint32_t)imm) : CX_NONE;
+    /* source roles: A0 A1 B0 B1 C0 C1 (explicit operands), V0 V1 E0 E1 S
+     * (implicit vcc, exec, scc), D0 D1 (store data).  All lookups are issued
+     * together: def masks first, then the producers' descriptors. */
+    constexpr int NR = 13;
+    const uint32_t iu = alu ? e_iuse(e) : 0u;
+    const bool store = cls == C_GST || cls == C_FST || cls == C_DSW;
+    uint32_t rs[NR], rk[NR];   /* compact slot (CX_NONE if none); index used when it is not a register */
+    auto role = [&](int q, uint32_t c, uint32_t w, uint32_t j) {
+        rs[q] = j < w && c != CX_NONE ? c + j : CX_NONE;
+        rk[q] = j < w ? IX_CONST : IX_ZERO;
+    };
+    role(0, c1, w1, 0);
+    role(1, c1, w1, 1);
+    role(2, c2, w2, 0);
+    role(3, c2, w2, 1);
+    role(4, c3, w3, 0);
+    role(5, c3, w3, 1);
+#pragma unroll
+    for (int q = 0; q < 5; q++) {
+        const uint32_t m = q < 2 ? IM_VCC : (q < 4 ? IM_EXEC : IM_SCC);
+        rs[6 + q] = (iu & m) ? cv + (uint32_t)q : CX_NONE;
+        rk[6 + q] = IX_ZERO;
+    }
+    rs[11] = store && c0 != CX_NONE ? c0 : CX_NONE;
+    rs[12] = store && c0 != CX_NONE && w0 == 2 ? c0 + 1 : CX_NONE;
+    rk[11] = rk[12] = IX_ZERO;
+    uint64_t dmq[NR];
+    const uint64_t below = bit - 1ull;
+#pragma unroll
+    for (int q = 0; q < NR; q++) dmq[q] = L.dm[rs[q] != CX_NONE ? rs[q] : junk] & below;
+    uint32_t lcq[NR];
+#pragma unroll
+    for (int q = 0; q < NR; q++) lcq[q] = L.lcd[63u - (uint32_t)__builtin_clzll(dmq[q] | 1ull)];
+    uint32_t ix[NR];
+#pragma unroll
+    for (int q = 0; q < NR; q++) {
+        const uint32_t p = 63u - (uint32_t)__builtin_clzll(dmq[q] | 1ull);
+        const uint32_t k = imp_covers((lcq[q] >> 16) & 7u, rs[q], cv) ? K_IMP : rs[q] - (lcq[q] & 0x1FFu);
+        ix[q] = dmq[q] ? IX_DEF + k * 64 + p : (rs[q] != CX_NONE ? rs[q] : rk[q]);
+    }
+    I.ia = ix[0] | ix[1] << 16;
+    I.ib = ix[2] | ix[3] << 16;
+    I.ic = ix[4] | ix[5] << 16;
+    I.iv = ix[6] | ix[7] << 16;
+    I.ie = ix[8] | ix[9] << 16;
+    I.isd = ix[10] | ix[11] << 16;
+    I.id1 = ix[12];
+    I.ka0 = const_dword(r1, 0, w1, imm);
+    I.ka1 = const_dword(r1, 1, w1, imm);
+    I.kb0 = const_dword(r2, 0, w2, imm);
+    I.kb1 = const_dword(r2, 1, w2, imm);
+    I.kc0 = const_dword((uint32_t)imm, 0, w3, 0);
+
+    /* static definitions: SMEM (argument area), loads; payloads start as TOP */
+    const bool via = cls == C_SMEM && r1 == 4u;
+#pragma unroll
+    for (uint32_t k = 0; k < 5; k++) L.fv[IX_DEF + k * 64 + l] = VTOP;
+#pragma unroll
+    for (uint32_t k = 0; k < 4; k++) {
+        uint64_t x = fpt_pack(0, 0, FT_T | FT_N);
+        if (cls == C_SMEM) {
+            uint32_t pr = 1u << PB_LOADG, ty = 0;
+            uint64_t va = VTOP;
+            if (via) smem_dword(K, w0, (uint32_t)imm, k, pr, ty, va);
+            x = fpt_pack(pr, ty, via ? FT_T | FT_N : 0u);
+        } else if (cls == C_GLD || cls == C_FLD || cls == C_DSR) {
+            x = fpt_pack(cls == C_DSR ? 1u << PB_LOADL : 1u << PB_LOADG, 0, 0);
+        }
+        L.fpt[IX_DEF + k * 64 + l] = x;
+    }
+    L.fpt[IX_DEF + K_IMP * 64 + l] = fpt_pack(0, 0, 0);
+    /* constant and absent sources */
+    L.fpt[l == 0 ? IX_CONST : (l == 1 ? IX_ZERO : tscr)] =
+        l == 0 ? fpt_pack(1u << PB_CONST, 0, FT_T | FT_N) : fpt_pack(0, 0, FT_T | FT_N);
+    L.fv[l == 1 ? IX_ZERO : tscr] = VTOP;
+    __builtin_amdgcn_wave_barrier();
+
+    /* ---- provenance, types, liveness: passes to the solution ---- */
+    const uint32_t prule = alu && I.ndef ? e_prule(e) : PR_TOP;
+    const uint32_t trule = e_trule(e), suffix = e_suffix(e), vsrc = e_vsrc(e);
+    const uint32_t mbit = e_maskdef(e) ? 1u << PB_MASK : 0u;
+    uint64_t o0 = fpt_pack(0, 0, FT_T | FT_N), o1 = o0, o4 = fpt_pack(0, 0, 0);
+    for (;;) {
+        const uint64_t xa0 = L.fpt[I.ia & 0xFFFFu], xa1 = L.fpt[I.ia >> 16];
+        const uint64_t xb0 = L.fpt[I.ib & 0xFFFFu], xb1 = L.fpt[I.ib >> 16];
+        const uint64_t xc0 = L.fpt[I.ic & 0xFFFFu], xc1 = L.fpt[I.ic >> 16];
+        const uint64_t xv0 = L.fpt[I.iv & 0xFFFFu], xv1 = L.fpt[I.iv >> 16];
+        const uint64_t xe0 = L.fpt[I.ie & 0xFFFFu], xe1 = L.fpt[I.ie >> 16];
+        const uint64_t xs = L.fpt[I.isd & 0xFFFFu];
+        const uint32_t rp = fpt_prov(xa0) | fpt_prov(xa1) | fpt_prov(xb0) | fpt_prov(xb1) | fpt_prov(xc0) |
+                            fpt_prov(xc1) | fpt_prov(xv0) | fpt_prov(xv1) | fpt_prov(xe0) | fpt_prov(xe1) | fpt_prov(xs);
+        const uint32_t ta0 = fpt_type(xa0), ta1 = fpt_type(xa1), tb0 = fpt_type(xb0), tb1 = fpt_type(xb1);
+        uint32_t ty0 = 0, ty1 = 0;
+        switch (trule) {
+        case TR_SUF: ty0 = ty1 = suffix; break;
+        case TR_ADD: ty0 = ty1 = suffix | ((ta0 | ta1 | tb0 | tb1) & TY_P); break;
+        case TR_B: ty0 = ty1 = ((vsrc & 1u) ? ta0 | ta1 : 0u) | ((vsrc & 2u) ? tb0 | tb1 : 0u); break;
+        case TR_MOVE: ty0 = ta0; ty1 = ta1; break;
+        default: break;
+        }
+        /* liveness of the payload rule's result (TOP in, TOP out) */
+        uint32_t lv0 = 0, lv1 = 0;
+        const bool na0 = fpt_n(xa0), na1 = fpt_n(xa1), nb0 = fpt_n(xb0), nb1 = fpt_n(xb1), nc0 = fpt_n(xc0);
+        switch (prule) {
+        case PR_MOV:
+            lv0 = (fpt_t(xa0) ? FT_T : 0u) | (na0 ? FT_N : 0u);
+            lv1 = (fpt_t(xa1) ? FT_T : 0u) | (na1 ? FT_N : 0u);
+            break;
+        case PR_SEL: lv0 = fpt_t(xa0) && fpt_t(xb0) ? FT_T | FT_N : 0u; break;
+        case PR_ADD: case PR_ADDC: case PR_SUB: case PR_AND: case PR_OR: case PR_XOR: case PR_MUL: case PR_MUL24:
+        case PR_SHL: case PR_LSHR: case PR_ASHR:
+            lv0 = na0 && nb0 ? FT_T | FT_N : 0u;
+            break;
+        case PR_MAD24: lv0 = na0 && nb0 && nc0 ? FT_T | FT_N : 0u; break;
+        case PR_AND64: case PR_OR64: case PR_XOR64: case PR_ANDN264:
+            lv0 = lv1 = na0 && na1 && nb0 && nb1 ? FT_T | FT_N : 0u;
+            break;
+        case PR_SHL64: lv0 = lv1 = na0 && nb0 && nb1 ? FT_T | FT_N : 0u; break;
+        default: break;
+        }
+        const uint32_t pe = rp | mbit;
+        const uint64_t n0 = fpt_pack(pe, ty0, lv0), n1 = fpt_pack(pe, ty1, lv1), n4 = fpt_pack(rp | (1u << PB_MASK), 0, 0);
+        L.fpt[alu && I.ndef >= 1 ? IX_DEF + l : tscr] = n0;
+        L.fpt[alu && I.ndef >= 2 ? IX_DEF + 64 + l : tscr] = n1;
+        L.fpt[idf ? IX_DEF + K_IMP * 64 + l : tscr] = n4;
+        const bool ch = alu && (n0 != o0 || n1 != o1 || n4 != o4);
+        o0 = n0;
+        o1 = n1;
+        o4 = n4;
+        if (ballot(ch) == 0) break;
+    }
+    __builtin_amdgcn_wave_barrier();
+
+    /* ---- payloads of the instructions whose result may be other than TOP ---- */
+    const bool live = (alu && prule != PR_TOP && prule != PR_NONE && ((o0 >> 32) & FT_T)) ||
+                      (alu && prule != PR_TOP && prule != PR_NONE && I.ndef == 2 && ((o1 >> 32) & FT_T)) || via;
+    uint64_t lm = ballot(live);
+    while (lm) {
+        const uint32_t i = (uint32_t)__builtin_ctzll(lm);
+        lm &= lm - 1;
+        const uint64_t ei = ((uint64_t)rdl(I.ehi, i) << 32) | rdl(I.elo, i);
+        const uint32_t ci = e_cls(ei), wi = e_width(ei, 0);
+        if (ci == C_SMEM) {
+            const uint32_t ia = rdl(I.ia, i), off = rdl(I.imm, i);
+            const bool ok = lds_val(L, ia & 0xFFFFu) == pv(T_SYSPTR, IG_LO, 0, 0, 0, 0, 0) &&
+                            lds_val(L, ia >> 16) == pv(T_SYSPTR, IG_HI, 0, 0, 0, 0, 0);
+            for (uint32_t j = 0; j < wi; j++) {
+                uint32_t pr, ty;
+                uint64_t va;
+                smem_dword(K, wi, off, j, pr, ty, va);
+                lds_put_u64(L, &L.fv[IX_DEF + j * 64 + i], ok ? va : VTOP);
             }
-            case TR_MOVE: ty0 = a0.type; ty1 = a1.type; break;
-            default: break;
-            }
-            uint64_t v0 = VTOP, v1 = VTOP;
-            const bool val_is_r1 = e_vsrc(e) == 1u;   /* shift forms: which operand is shifted */
-            switch (e_prule(e)) {
-            case PR_MOV: v0 = a0.val; v1 = a1.val; break;
-            case PR_ADD: v0 = r_add(a0.val, b0.val); break;
-            case PR_ADDC: v0 = r_addc(a0.val, b0.val); break;
-            case PR_SUB: if (is_c(a0.val) && is_c(b0.val)) v0 = C32(v_c(a0.val) - v_c(b0.val)); break;
-            case PR_AND: if (is_c(a0.val) && is_c(b0.val)) v0 = C32(v_c(a0.val) & v_c(b0.val)); break;
-            case PR_OR: if (is_c(a0.val) && is_c(b0.val)) v0 = C32(v_c(a0.val) | v_c(b0.val)); break;
-            case PR_XOR: if (is_c(a0.val) && is_c(b0.val)) v0 = C32(v_c(a0.val) ^ v_c(b0.val)); break;
-            case PR_MUL: v0 = r_mul(K, a0.val, b0.val); break;
-            case PR_MUL24: v0 = r_mul(K, low24(a0.val), low24(b0.val)); break;
-            case PR_MAD24: v0 = r_add(r_mul(K, low24(a0.val), low24(b0.val)), c0.val); break;
-            case PR_SHL: v0 = val_is_r1 ? r_shl(K, a0.val, b0.val) : r_shl(K, b0.val, a0.val); break;
-            case PR_LSHR: v0 = val_is_r1 ? r_lshr(K, a0.val, b0.val) : r_lshr(K, b0.val, a0.val); break;
-            case PR_ASHR: v0 = val_is_r1 ? r_ashr(a0.val, b0.val) : r_ashr(b0.val, a0.val); break;
-            case PR_SEL: v0 = a0.val == b0.val ? a0.val : VTOP; break;
-            case PR_AND64: case PR_OR64: case PR_XOR64: case PR_ANDN264:
-                if (is_c(a0.val) && is_c(a1.val) && is_c(b0.val) && is_c(b1.val)) {
-                    const uint32_t pr = e_prule(e);
-                    const uint32_t x0 = v_c(a0.val), x1 = v_c(a1.val), y0 = v_c(b0.val), y1 = v_c(b1.val);
-                    if (pr == PR_AND64) { v0 = C32(x0 & y0); v1 = C32(x1 & y1); }
-                    else if (pr == PR_OR64) { v0 = C32(x0 | y0); v1 = C32(x1 | y1); }
-                    else if (pr == PR_XOR64) { v0 = C32(x0 ^ y0); v1 = C32(x1 ^ y1); }
-                    else { v0 = C32(x0 & ~y0); v1 = C32(x1 & ~y1); }
+            continue;
+        }
+        const uint32_t ia = rdl(I.ia, i), ib = rdl(I.ib, i), ic = rdl(I.ic, i);
+        const uint32_t xq[5] = {ia & 0xFFFFu, ia >> 16, ib & 0xFFFFu, ib >> 16, ic & 0xFFFFu};
+        uint64_t vq[5];
+#pragma unroll
+        for (int q = 0; q < 5; q++) vq[q] = L.fv[xq[q] == IX_CONST ? IX_ZERO : xq[q]];   /* all reads in flight */
+        const uint32_t kq[5] = {rdl(I.ka0, i), rdl(I.ka1, i), rdl(I.kb0, i), rdl(I.kb1, i), rdl(I.kc0, i)};
+#pragma unroll
+        for (int q = 0; q < 5; q++)
+            vq[q] = xq[q] == IX_CONST ? C32(kq[q]) : ((uint64_t)rfl((uint32_t)(vq[q] >> 32)) << 32) | rfl((uint32_t)vq[q]);
+        const uint64_t a0 = vq[0], a1 = vq[1], b0 = vq[2], b1 = vq[3], cc0 = vq[4];
+        uint64_t v0, v1;
+        eval_rule(K, e_prule(ei), e_vsrc(ei) == 1u, a0, a1, b0, b1, cc0, v0, v1);
+        lds_put_u64(L, &L.fv[IX_DEF + i], v0);
+        if (wi == 2) lds_put_u64(L, &L.fv[IX_DEF + 64 + i], v1);
+    }
+    __builtin_amdgcn_wave_barrier();
+
+    /* ---- records: accesses from the pre-state, built-ins among definitions ---- */
+    {
+        const bool mem = cls >= C_GLD;
+        /* address dwords and store-data types, read by every lane */
+        const uint32_t xa0 = I.ia & 0xFFFFu, xa1 = I.ia >> 16;
+        const uint64_t lo = L.fv[xa0 < IX_CONST ? xa0 : IX_ZERO], hi = L.fv[xa1 < IX_CONST ? xa1 : IX_ZERO];
+        const uint32_t tdat = fpt_type(L.fpt[I.isd >> 16]) | fpt_type(L.fpt[I.id1]);
+        uint32_t kind = 0, space = 0, width = 0, dt = 0;
+        uint64_t addr = VTOP;
+        if (cls == C_GLD || cls == C_FLD || cls == C_GST || cls == C_FST) {
+            kind = (cls == C_GLD || cls == C_FLD) ? 0 : 1;
+            space = (cls == C_GLD || cls == C_GST) ? 0 : 1;
+            width = 4 * w0;
+            if (r2 == 0xFFFFu && (I.ia & 0xFFFFu) < IX_CONST) {
+                if (lo != VTOP && hi != VTOP && v_ig(lo) == IG_LO && v_ig(hi) == IG_HI && v_arg(lo) == v_arg(hi)) {
+                    if (v_tag(lo) == T_PTR && v_tag(hi) == T_PTR)
+                        addr = pv(T_PTR, IG_ENT, v_dim(lo), v_aux(lo), v_sh(lo), v_arg(lo), v_c(lo) + (uint32_t)imm);
+                    else if (v_tag(lo) == T_KARG && v_tag(hi) == T_KARG)
+                        addr = pv(T_PTR, IG_ENT, 0, 0, 0, v_arg(lo), (uint32_t)imm);
                 }
-                break;
-            case PR_SHL64: {
-                const uint64_t amt = a0.val, lo = b0.val, hi = b1.val;
-                if (!is_c(amt) || lo == VTOP || hi == VTOP) break;
-                const uint32_t s = v_c(amt) & 63u;
-                if (is_c(lo) && is_c(hi)) {
-                    const uint64_t xx = (((uint64_t)v_c(hi) << 32) | v_c(lo)) << s;
-                    v0 = C32((uint32_t)xx);
-                    v1 = C32((uint32_t)(xx >> 32));
-                } else if (idx_lo(lo) && ((is_c(hi) && v_c(hi) == 0) ||
-                                          (v_tag(hi) == T_IDX && v_ig(hi) == IG_HI && v_dim(hi) == v_dim(lo) &&
-                                           v_aux(hi) == v_aux(lo)))) {
-                    if (s == 0) { v0 = lo; v1 = hi; }
-                    else if (s <= 15) {
-                        v0 = pv(T_SHL, IG_LO, v_dim(lo), v_aux(lo), s, 0, v_c(lo) << s);
-                        v1 = pv(T_SHL, IG_HI, v_dim(lo), v_aux(lo), s, 0, 0);
-                    }
+            }
+        } else if (cls == C_DSR || cls == C_DSW) {
+            kind = cls == C_DSR ? 0 : 1;
+            space = 2;
+            width = 4;
+            if ((I.ia & 0xFFFFu) < IX_CONST) {
+                const uint64_t v = lo;
+                if (v != VTOP) {
+                    const uint32_t c = v_c(v) + (uint32_t)imm;
+                    if (v_tag(v) == T_SHL && v_ig(v) == IG_ENT) addr = pv(T_SHL, IG_ENT, v_dim(v), v_aux(v), v_sh(v), 0, c);
+                    else if (idx_lo(v)) addr = pv(T_IDX, IG_ENT, v_dim(v), v_aux(v), 0, 0, c);
+                    else if (is_c(v)) addr = C32(c);
                 }
-                break;
             }
-            default: break;
-            }
-            const uint32_t prov = rp | (e_maskdef(e) ? 1u << PB_MASK : 0u);
-            dv[0] = v0;
-            dv[1] = v1;
-            put(S, cd, prov, ty0, v0);
-            if (w0 == 2) put(S, cd + 1, prov, ty1, v1);
-            nd = w0;
         }
-        const uint32_t idf = e_idef(e);
-        const uint32_t ip = rp | (1u << PB_MASK);
-        if (idf & IM_VCC) { put(S, KC.cv, ip, 0, VTOP); put(S, KC.cv + 1, ip, 0, VTOP); }
-        if (idf & IM_EXEC) { put(S, KC.cv + 2, ip, 0, VTOP); put(S, KC.cv + 3, ip, 0, VTOP); }
-        if (idf & IM_SCC) put(S, KC.cv + 4, ip, 0, VTOP);
-        /* built-ins among the explicit definitions (an implicit definition of
-         * the same slot overwrote the value with TOP) */
-#pragma unroll
-        for (uint32_t j = 0; j < 2; j++) {
+        if (kind == 1) {
+            dt = tdat;
+        } else if (mem && addr != VTOP && v_tag(addr) == T_PTR && v_arg(addr) < K.n_args) {
+            dt = K.args[v_arg(addr)].flags & 31u;
+        }
+        const uint64_t am = ballot(mem);
+        const uint32_t apos = E.ta + lanes_below(am);
+        uint4 *adst = mem ? reinterpret_cast<uint4 *>(P->acc_sparse) + g_lo + apos : dummy + l;
+        *adst = make_uint4(g0 + l - pos0, kind | space << 8 | width << 16 | dt << 24, (uint32_t)addr,
+                           (uint32_t)(addr >> 32));
+        E.ta += (uint32_t)__builtin_popcountll(am);
+
+        /* built-ins: explicit definitions not overwritten by an implicit one */
+        auto sys_kind = [&](uint32_t j, uint32_t &dim) -> int {
             const uint32_t slot = r0 + j;
             const bool covered = ((idf & IM_VCC) && (slot == 104u || slot == 105u)) ||
                                  ((idf & IM_EXEC) && (slot == 106u || slot == 107u)) ||
                                  ((idf & IM_SCC) && slot == 108u);
-            if (j < nd && !covered) emit_sysval(dv[j], slot, instr, E);
-        }
-        return;
-    }
+            return j < I.ndef && !covered ? builtin_kind(L.fv[IX_DEF + j * 64 + l], dim) : -1;
+        };
+        uint32_t ns = 0;
 #pragma unroll
-    for (uint32_t j = 0; j < 4; j++)
-        if (j < nd) emit_sysval(dv[j], r0 + j, instr, E);
-}
+        for (uint32_t j = 0; j < 4; j++) {
+            uint32_t dim;
+            ns += sys_kind(j, dim) >= 0 ? 1u : 0u;
+        }
+        uint32_t tot;
+        uint32_t spos = E.ts + wave_excl_scan(ns, tot);
+        for (uint32_t j = 0; j < 4; j++) {
+            uint32_t dim = 0;
+            const int kd = sys_kind(j, dim);
+            const bool has = kd >= 0;
+            uint2 *sdst = has ? reinterpret_cast<uint2 *>(P->sys_sparse) + 4ull * g_lo + spos
+                              : reinterpret_cast<uint2 *>(dummy + l);
+            *sdst = make_uint2(g0 + l - pos0, (r0 + j) | (uint32_t)(has ? kd : 0) << 16 | (has ? dim : 0u) << 24);
+            spos += has ? 1u : 0u;
+        }
+        E.ts += tot;
+    }
+    __builtin_amdgcn_wave_barrier();
 
+    /* ---- last definitions back to the block state; clear the def masks ---- */
+    /* definition j < 4: explicit dword j; j >= 4: implicit vcc, vcc hi, exec,
+     * exec hi, scc.  An explicit dword that an implicit definition of the same
+     * instruction covers is written back through the implicit entry. */
+    auto def_slot = [&](uint32_t j) -> uint32_t {
+        if (j < 4) return j < I.ndef && !imp_covers(idf, c0 + j, cv) ? c0 + j : junk;
+        const uint32_t m = j < 6 ? IM_VCC : (j < 8 ? IM_EXEC : IM_SCC);
+        return (idf & m) ? cv + (j - 4) : junk;
+    };
+    uint64_t wx[5], wv[5];
+#pragma unroll
+    for (uint32_t k = 0; k < 5; k++) {
+        wx[k] = L.fpt[IX_DEF + k * 64 + l];
+        wv[k] = L.fv[IX_DEF + k * 64 + l];
+    }
+    uint64_t wm[9];
+#pragma unroll
+    for (uint32_t j = 0; j < 9; j++) wm[j] = L.dm[def_slot(j)];
+#pragma unroll
+    for (uint32_t j = 0; j < 9; j++) {
+        const uint32_t s = def_slot(j);
+        const bool last = s != junk && (63u - (uint32_t)__builtin_clzll(wm[j] | 1ull)) == l;
+        const uint32_t dst = last ? s : tscr;
+        L.fpt[dst] = wx[j < 4 ? j : K_IMP];
+        L.fv[dst] = wv[j < 4 ? j : K_IMP];
+    }
+    __builtin_amdgcn_wave_barrier();
+    /* the explicit definitions' own slots, including those an implicit
+     * definition covers, leave the def masks too */
+    for (uint32_t j = 0; j < 4; j++) L.dm[j < I.ndef ? c0 + j : junk] = 0;
+    for (uint32_t j = 4; j < 9; j++) L.dm[def_slot(j)] = 0;
+    __builtin_amdgcn_wave_barrier();
+}
 /* ------------------------------------------------------------------ */
 /* one kernel                                                           */
 /* ------------------------------------------------------------------ */
@@ -758,8 +936,6 @@ __device__ __forceinline__ uint32_t build_compact(const Plan *__restrict__ P, Wa
     const uint32_t l = lane_id();
     uint32_t *mk = reinterpret_cast<uint32_t *>(L.umark);
     for (uint32_t j = 0; j < (USLOT_N + 64) / 4; j += 64) mk[(j + l) < (USLOT_N + 64) / 4 ? j + l : l] = 0;
-    /* LDS is in order within a wavefront; the barriers only order the lanes
-     * of emulated builds and keep the compiler from moving code across */
     __builtin_amdgcn_wave_barrier();
     const uint4 *recs = reinterpret_cast<const uint4 *>(P->instrs) + rb;
     const uint32_t junk = USLOT_N + l;
@@ -796,46 +972,42 @@ __device__ __forceinline__ uint32_t build_compact(const Plan *__restrict__ P, Wa
     return base;
 }
 
-/* per-wave arena, bitmaps and scratch */
+/* per-wave arena and scratch */
 struct WaveMem {
     uint32_t *arena;
     uint4 *dummy;
 };
 
-template <int R, class Bits>
+template <class Bits>
 __device__ __forceinline__ void analyze(const Plan *__restrict__ P, uint32_t k, WaveLds &L, Bits &reached,
                                         Bits &dirty, const WaveMem &M, uint32_t nu) {
     const uint32_t l = lane_id();
     const dc_kernel_t *D = &P->kernels[k];
     const uint32_t nb = rfl(P->n_blocks[k]), fb = rfl(P->first_block[k]), nr = rfl(P->n_reach[k]);
     const uint32_t pos0 = rfl(P->pos_begin[k]);
-    KCtx K;
-    K.cws0 = rfl(D->cws[0]);
-    K.cws1 = rfl(D->cws[1]);
-    K.cws2 = rfl(D->cws[2]);
-    K.n_args = rfl(D->n_args);
-    K.args = P->args + rfl(D->arg_begin);
+    KCtx2 KX;
+    KX.K.cws0 = rfl(D->cws[0]);
+    KX.K.cws1 = rfl(D->cws[1]);
+    KX.K.cws2 = rfl(D->cws[2]);
+    KX.K.n_args = rfl(D->n_args);
+    KX.K.args = P->args + rfl(D->arg_begin);
     const uint64_t rb = ((uint64_t)rfl((uint32_t)(D->instr_begin >> 32)) << 32) | rfl((uint32_t)D->instr_begin);
     const uint32_t dims = rfl(D->dims);
-    KConst KC;
-    KC.cv = L.umap[104];
-    KC.cv = rfl(KC.cv);
-    const uint32_t blk_dw = (uint32_t)R * ROW_DW;
+    KX.dims = dims;
+    KX.cv = rfl(L.umap[104]);
+    const uint32_t nu_pad = (nu + 63u) & ~63u;
+    const uint32_t bs = 3 * nu_pad;   /* arena dwords per block */
 
     reached.init(nb);
     dirty.init(nr);
+    for (uint32_t c0 = 0; c0 < USLOT_N + 64; c0 += 64) L.dm[c0 + l] = 0;
     /* IN[0] = the ABI entry state on the compact slots */
-    {
-        St<R> S;
-#pragma unroll
-        for (int r = 0; r < R; r++) {
-            const uint32_t c = (uint32_t)r * 64 + l;
-            const uint4 v = c < nu ? entry_slot(L.uslot[c], dims) : make_uint4(0, 0, 0, 0);
-            S.p[r] = v.x;
-            S.lo[r] = v.z;
-            S.hi[r] = (v.w & 0xFFFFFF00u) | v.y;
-        }
-        st_store(S, M.arena);
+    for (uint32_t c0 = 0; c0 < nu_pad; c0 += 64) {
+        const uint32_t c = c0 + l;
+        const uint4 v = c < nu ? entry_slot(L.uslot[c], dims) : make_uint4(0, 0, 0, 0);
+        M.arena[c] = v.x;
+        M.arena[nu_pad + c] = v.z;
+        M.arena[2 * nu_pad + c] = (v.w & 0xFFFFFF00u) | v.y;
     }
     reached.set(0);
     dirty.set(0);   /* block 0 is first in reverse postorder */
@@ -855,38 +1027,24 @@ __device__ __forceinline__ void analyze(const Plan *__restrict__ P, uint32_t k, 
         dirty.clr(p);
         pos = p + 1;
         const uint32_t b = rfl(P->rpo[fb + p]);
-        St<R> S;
-        st_load(S, M.arena + (uint64_t)b * blk_dw);
+        state_load(L, M.arena + (uint64_t)b * bs, nu_pad);
+        __builtin_amdgcn_wave_barrier();
         const uint32_t g_lo = rfl(P->block_start[fb + b]), g_hi = rfl(P->block_start[fb + b + 1]);
         Emit E;
-        E.a0 = E.a1 = E.a2 = E.a3 = E.s0 = E.s1 = 0;
-        E.na = E.ns = E.ta = E.ts = 0;
-        for (uint32_t g0 = g_lo; g0 < g_hi; g0 += 64) {
-            const uint32_t cnt = min(64u, g_hi - g0);
-            const Stage T = stage_chunk(P, L, rb, pos0, g0, cnt);
-            for (uint32_t i = 0; i < cnt; i++) {
-                if (E.ns > 60) flush_sys(P, E, g_lo, M.dummy);
-                step(S, K, KC, T, i, g0 + i - pos0, E);
-            }
-            flush_acc(P, E, g_lo, M.dummy);
-        }
-        flush_sys(P, E, g_lo, M.dummy);
+        E.ta = E.ts = 0;
+        for (uint32_t g0 = g_lo; g0 < g_hi; g0 += 64) run_chunk(P, L, KX, rb, pos0, g0, min(64u, g_hi - g0), g_lo, E, M.dummy);
         P->blk_acc[fb + b] = E.ta;
         P->blk_sys[fb + b] = E.ts;
-        for (int ed = 0; ed < 2; ed++) {
-            const int32_t s = (int32_t)rfl((uint32_t)P->succ[2 * (uint64_t)(fb + b) + ed]);
-            if (s < 0) continue;
-            uint32_t *dst = M.arena + (uint64_t)s * blk_dw;
-            bool changed;
-            if (!reached.get((uint32_t)s)) {
-                st_store(S, dst);
-                reached.set((uint32_t)s);
-                changed = true;
-            } else {
-                changed = st_join(S, dst);
-            }
-            if (changed) dirty.set(rfl((uint32_t)P->rpo_pos[fb + (uint32_t)s]));
-        }
+        const int32_t s0 = (int32_t)rfl((uint32_t)P->succ[2 * (uint64_t)(fb + b)]);
+        const int32_t s1 = (int32_t)rfl((uint32_t)P->succ[2 * (uint64_t)(fb + b) + 1]);
+        const bool first0 = s0 >= 0 && !reached.get((uint32_t)s0);
+        const bool first1 = s1 >= 0 && !reached.get((uint32_t)s1);
+        const uint32_t chg = state_join2(L, s0 >= 0 ? M.arena + (uint64_t)s0 * bs : nullptr, first0,
+                                         s1 >= 0 ? M.arena + (uint64_t)s1 * bs : nullptr, first1, nu_pad);
+        if (first0) reached.set((uint32_t)s0);
+        if (first1) reached.set((uint32_t)s1);
+        if (chg & 1u) dirty.set(rfl((uint32_t)P->rpo_pos[fb + (uint32_t)s0]));
+        if (chg & 2u) dirty.set(rfl((uint32_t)P->rpo_pos[fb + (uint32_t)s1]));
     }
 
     /* counts of blocks without a valid last visit are zero */
@@ -911,7 +1069,7 @@ __device__ __forceinline__ void analyze(const Plan *__restrict__ P, uint32_t k, 
             __builtin_amdgcn_wave_barrier();
             for (uint32_t b = 0; b < nb; b++) {
                 const bool rb_ = reached.get(b);
-                const uint32_t *a = M.arena + (uint64_t)b * blk_dw;
+                const uint32_t *a = M.arena + (uint64_t)b * bs;
                 uint64_t h = 0;
                 for (uint32_t j0 = 0; j0 < USLOT_N; j0 += 64) {
                     const uint32_t j = j0 + l;
@@ -919,9 +1077,8 @@ __device__ __forceinline__ void analyze(const Plan *__restrict__ P, uint32_t k, 
                     uint32_t prov, type;
                     uint64_t val;
                     if (c != CX_NONE) {
-                        const uint32_t o = (c >> 6) * ROW_DW + (c & 63u);
-                        prov = a[o];
-                        const uint32_t lo = a[o + 64], hi = a[o + 128];
+                        prov = a[c];
+                        const uint32_t lo = a[nu_pad + c], hi = a[2 * nu_pad + c];
                         type = hi & 0xFFu;
                         val = unpack_val(lo, hi);
                     } else {
@@ -993,9 +1150,6 @@ __device__ __forceinline__ void fail_kernel(const Plan *__restrict__ P, uint32_t
     P->results[k] = res;
 }
 
-/* rows of state for U compact slots */
-__device__ __forceinline__ uint32_t rows_for(uint32_t nu) { return nu <= 128u ? 2u : (uint32_t)RMAX; }
-
 /* Persistent grid.  Main pass: kernels whose blocks fit the register bitmap
  * and whose IN states fit the wave's arena; the others are queued for the
  * overflow pass, which keeps its bitmaps in HBM and has a larger arena. */
@@ -1031,29 +1185,29 @@ __global__ __launch_bounds__(256) void k_fixpoint(const Plan *__restrict__ P, ui
         const dc_kernel_t *D = &P->kernels[k];
         const uint64_t rb = ((uint64_t)rfl((uint32_t)(D->instr_begin >> 32)) << 32) | rfl((uint32_t)D->instr_begin);
         const uint32_t nu = rfl(build_compact(P, L, rb, n));
-        const uint32_t R = rows_for(nu);
+        const uint64_t rows = (uint64_t)nb * ((nu + 63u) >> 6);
         if (!OVF) {
-            if (nb > MAIN_MAX_BLOCKS || (uint64_t)nb * R > cap_rows) {
+            if (nb > MAIN_MAX_BLOCKS || rows > cap_rows) {
                 const uint32_t slot = rfl(atomicAdd(&P->counters[1], l == 0 ? 1u : 0u));
                 *(l == 0 ? &P->ovf_list[slot] : reinterpret_cast<uint32_t *>(M.dummy + l)) = k;
                 continue;
             }
             RegBits reached, dirty;
-            if (R == 2) analyze<2>(P, k, L, reached, dirty, M, nu);
-            else analyze<RMAX>(P, k, L, reached, dirty, M, nu);
+            analyze(P, k, L, reached, dirty, M, nu);
         } else {
-            if ((uint64_t)nb * R > cap_rows) {
+            if (rows > cap_rows) {
                 fail_kernel(P, k, DC_E_UNSUPPORTED, M);
                 continue;
             }
             const uint32_t words = (P->ovf_block_cap + 31) >> 5;
             uint32_t *bm = P->ovf_bitmaps + (uint64_t)gw * (2 * words + 64);
             MemBits reached{bm, bm + 2 * words}, dirty{bm + words, bm + 2 * words};
-            if (R == 2) analyze<2>(P, k, L, reached, dirty, M, nu);
-            else analyze<RMAX>(P, k, L, reached, dirty, M, nu);
+            analyze(P, k, L, reached, dirty, M, nu);
         }
     }
 }
+
+size_t fixpoint_lds_per_wave() { return sizeof(WaveLds); }
 
 uint32_t fixpoint_groups_per_cu(uint32_t wpg) {
     int n = 0;

@@ -97,6 +97,7 @@ hipError_t launch_fixpoint(const Plan &P, const Plan *dP, const FixCfg &c, hipSt
                            hipEvent_t after);
 hipError_t launch_compact(const Plan &P, hipStream_t s);                /* dense outputs */
 uint32_t fixpoint_groups_per_cu(uint32_t waves_per_group);              /* resident fixpoint groups per CU */
+size_t fixpoint_lds_per_wave();                                         /* LDS bytes per fixpoint wavefront */
 constexpr uint32_t FIX_ROW_DWORDS = 192;                                /* arena dwords per state row */
 constexpr uint32_t FIX_MAX_ROWS = 6;                                    /* state rows of the largest kernel */
 uint64_t scan_tmp_words_needed(uint64_t n);
