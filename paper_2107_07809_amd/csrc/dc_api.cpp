@@ -266,6 +266,7 @@ static dc_status_t plan_batch(dc_batch *B, dc_ctx *ctx, const dc_kernel_t *kerne
         P.counters = M.alloc<uint32_t>(4);
         P.sweep_cap = B->opts.sweep_cap;
         P.flags = B->opts.flags;
+        P.binfo = M.alloc<uint4>(2 * N);
         P.acc_sparse = M.alloc<dc_access_t>(N);
         P.sys_sparse = M.alloc<dc_sysval_t>(4 * N);
         P.blk_acc = M.alloc<uint32_t>(N);

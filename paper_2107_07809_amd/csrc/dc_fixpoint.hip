@@ -80,10 +80,12 @@ struct WaveLds {
     uint64_t dm[USLOT_N + 64];      /* per compact slot: the chunk's lanes that define it; tail scratch */
     uint64_t junk[64];              /* per-lane scratch stores */
     uint32_t lcd[64];               /* per lane: compact index of r0 | implicit definitions << 16 */
+    uint64_t optab[80];             /* opcode descriptors */
     uint16_t umap[USLOT_N];         /* slot -> compact index; entries >= NSLOT unused */
     uint16_t uslot[USLOT_N + 64];   /* compact index -> slot; 64-entry scratch tail */
     uint8_t umark[USLOT_N + 64];    /* slot marks; entries >= NSLOT are scratch */
     uint32_t tail[64];              /* scratch words for single-lane bitmap stores */
+    uint8_t argf[64];               /* pointee type bits of the kernel's first 64 arguments */
 };
 static_assert(sizeof(WaveLds) % 16 == 0, "LDS layout");
 
@@ -393,15 +395,34 @@ __device__ __forceinline__ void state_load(WaveLds &L, const uint32_t *a, uint32
     }
 }
 
-/* join of the OUT state into one arena IN state: a := a join OUT (provenance
- * and type bits unite; payloads that differ go to TOP), or a := OUT when
- * first; the words are stored unconditionally */
-__device__ __forceinline__ bool join_row(uint32_t *a, uint32_t nu_pad, uint32_t c, bool first, uint32_t pb, uint32_t lb,
-                                         uint32_t hb) {
+/* The IN states of a block's successors are read when the visit starts (the
+ * first PRE_ROWS rows into registers), so the reads are not queued behind the
+ * visit's record stores. */
+constexpr int PRE_ROWS = 1;
+struct PreIn {
+    uint32_t p[PRE_ROWS], lo[PRE_ROWS], hi[PRE_ROWS];
+};
+__device__ __forceinline__ void prefetch_in(PreIn &Q, const uint32_t *a, uint32_t nu_pad) {
+    const uint32_t l = lane_id();
+#pragma unroll
+    for (int r = 0; r < PRE_ROWS; r++) {
+        if (a && (uint32_t)r * 64 < nu_pad) {   /* uniform */
+            const uint32_t c = (uint32_t)r * 64 + l;
+            Q.p[r] = a[c];
+            Q.lo[r] = a[nu_pad + c];
+            Q.hi[r] = a[2 * nu_pad + c];
+        }
+    }
+}
+
+/* a := a join OUT for one slot per lane (provenance and type bits unite;
+ * payloads that differ go to TOP), or a := OUT when first; the words are
+ * stored unconditionally; (pa, la, ha) is a's current value */
+__device__ __forceinline__ bool join_slot(uint32_t *a, uint32_t nu_pad, uint32_t c, bool first, uint32_t pa, uint32_t la,
+                                          uint32_t ha, uint32_t pb, uint32_t lb, uint32_t hb) {
     uint32_t pn = pb, ln = lb, hn = hb;
     bool ch = first;
     if (!first) {   /* uniform */
-        const uint32_t pa = a[c], la = a[nu_pad + c], ha = a[2 * nu_pad + c];
         const bool same = la == lb && (ha & 0xFFFFFF00u) == (hb & 0xFFFFFF00u);
         pn = pa | pb;
         ln = same ? la : 0xFFFFFFFFu;
@@ -413,10 +434,11 @@ __device__ __forceinline__ bool join_row(uint32_t *a, uint32_t nu_pad, uint32_t 
     a[2 * nu_pad + c] = hn;
     return ch;
 }
-/* OUT state into the IN states of up to two successors (null when absent);
- * returns the per-successor change bits (bit 0, bit 1) */
-__device__ __forceinline__ uint32_t state_join2(const WaveLds &L, uint32_t *a0, bool first0, uint32_t *a1, bool first1,
-                                                uint32_t nu_pad) {
+/* OUT state into the IN states of up to two successors (null when absent),
+ * rows below PRE_ROWS from the prefetched values; returns the per-successor
+ * change bits (bit 0, bit 1) */
+__device__ __forceinline__ uint32_t state_join2(const WaveLds &L, uint32_t *a0, bool first0, const PreIn &Q0, uint32_t *a1,
+                                                bool first1, const PreIn &Q1, uint32_t nu_pad) {
     const uint32_t l = lane_id();
     bool ch0 = false, ch1 = false;
 #pragma unroll
@@ -425,8 +447,20 @@ __device__ __forceinline__ uint32_t state_join2(const WaveLds &L, uint32_t *a0, 
             const uint32_t c = (uint32_t)r * 64 + l;
             const uint64_t x = L.fpt[c], v = L.fv[c];
             const uint32_t pb = fpt_prov(x), lb = (uint32_t)v, hb = pack_hi(v, fpt_type(x));
-            if (a0) ch0 = join_row(a0, nu_pad, c, first0, pb, lb, hb) || ch0;
-            if (a1) ch1 = join_row(a1, nu_pad, c, first1, pb, lb, hb) || ch1;
+            if (a0) {
+                uint32_t pa, la, ha;
+                if (r < PRE_ROWS) { pa = Q0.p[r < PRE_ROWS ? r : 0]; la = Q0.lo[r < PRE_ROWS ? r : 0]; ha = Q0.hi[r < PRE_ROWS ? r : 0]; }
+                else if (!first0) { pa = a0[c]; la = a0[nu_pad + c]; ha = a0[2 * nu_pad + c]; }
+                else { pa = la = ha = 0; }
+                ch0 = join_slot(a0, nu_pad, c, first0, pa, la, ha, pb, lb, hb) || ch0;
+            }
+            if (a1) {
+                uint32_t pa, la, ha;
+                if (r < PRE_ROWS) { pa = Q1.p[r < PRE_ROWS ? r : 0]; la = Q1.lo[r < PRE_ROWS ? r : 0]; ha = Q1.hi[r < PRE_ROWS ? r : 0]; }
+                else if (!first1) { pa = a1[c]; la = a1[nu_pad + c]; ha = a1[2 * nu_pad + c]; }
+                else { pa = la = ha = 0; }
+                ch1 = join_slot(a1, nu_pad, c, first1, pa, la, ha, pb, lb, hb) || ch1;
+            }
         }
     }
     return (ballot(ch0) != 0 ? 1u : 0u) | (ballot(ch1) != 0 ? 2u : 0u);
@@ -570,11 +604,6 @@ __device__ __forceinline__ uint64_t lds_val(const WaveLds &L, uint32_t ix) {
     const uint64_t v = L.fv[ix];
     return ((uint64_t)rfl((uint32_t)(v >> 32)) << 32) | rfl((uint32_t)v);
 }
-/* payload of source table index ix (k = the lane's constant dword) */
-__device__ __forceinline__ uint64_t src_val(const WaveLds &L, uint32_t ix, uint32_t k, uint32_t i) {
-    if (ix == IX_CONST) return C32(rdl(k, i));
-    return lds_val(L, ix);
-}
 /* lane 0 stores a uniform value; the other lanes store into scratch */
 __device__ __forceinline__ void lds_put_u64(WaveLds &L, uint64_t *dst, uint64_t v) {
     const uint32_t l = lane_id();
@@ -603,7 +632,16 @@ __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t x, uint32_t &total) 
 /* ------------------------------------------------------------------ */
 /* one chunk                                                            */
 /* ------------------------------------------------------------------ */
-__device__ __forceinline__ void run_chunk(const Plan *__restrict__ P, WaveLds &L, const KCtx2 &KX, uint64_t rb,
+/* records of positions [g0, g0 + cnt) of the kernel starting at pos0, one per
+ * lane (spare lanes repeat the last one) */
+__device__ __forceinline__ uint4 load_chunk(const Plan *__restrict__ P, uint64_t rb, uint32_t pos0, uint32_t g0,
+                                            uint32_t cnt) {
+    const uint32_t l = lane_id();
+    const uint32_t li = l < cnt ? l : cnt - 1;
+    return reinterpret_cast<const uint4 *>(P->instrs)[rb + (g0 + li - pos0)];
+}
+
+__device__ __forceinline__ void run_chunk(const Plan *__restrict__ P, WaveLds &L, const KCtx2 &KX, uint4 r,
                                           uint32_t pos0, uint32_t g0, uint32_t cnt, uint32_t g_lo, Emit &E,
                                           uint4 *dummy) {
     const uint32_t l = lane_id();
@@ -614,9 +652,8 @@ __device__ __forceinline__ void run_chunk(const Plan *__restrict__ P, WaveLds &L
 
     /* ---- stage ---- */
     Ins I;
-    const uint32_t li = act ? l : cnt - 1;
-    const uint4 r = reinterpret_cast<const uint4 *>(P->instrs)[rb + (g0 + li - pos0)];
-    const uint64_t e = act ? OPTAB[r.x & 0xFFFFu] : (uint64_t)C_NOP;
+    const uint32_t opc = r.x & 0xFFFFu;
+    const uint64_t e = act ? L.optab[opc < (uint32_t)N_OPS ? opc : 0] : (uint64_t)C_NOP;
     I.x = r.x;
     I.y = r.y;
     I.imm = r.z;
@@ -782,40 +819,75 @@ __device__ __forceinline__ void run_chunk(const Plan *__restrict__ P, WaveLds &L
     __builtin_amdgcn_wave_barrier();
 
     /* ---- payloads of the instructions whose result may be other than TOP ---- */
+    /* Payload sources A0 A1 B0 B1 C0 of each lane: a definition dword 0 or 1
+     * of an earlier lane is read from that lane's registers (dv0, dv1) as the
+     * loop produces it; dwords 2 and 3 (wide SMEM) from LDS; anything else
+     * (block state, constant, TOP) is gathered before the loop into sv. */
     const bool live = (alu && prule != PR_TOP && prule != PR_NONE && ((o0 >> 32) & FT_T)) ||
                       (alu && prule != PR_TOP && prule != PR_NONE && I.ndef == 2 && ((o1 >> 32) & FT_T)) || via;
+    uint32_t dv0lo = 0xFFFFFFFFu, dv0hi = 0xFFFFFFFFu, dv1lo = 0xFFFFFFFFu, dv1hi = 0xFFFFFFFFu;
     uint64_t lm = ballot(live);
-    while (lm) {
-        const uint32_t i = (uint32_t)__builtin_ctzll(lm);
-        lm &= lm - 1;
-        const uint64_t ei = ((uint64_t)rdl(I.ehi, i) << 32) | rdl(I.elo, i);
-        const uint32_t ci = e_cls(ei), wi = e_width(ei, 0);
-        if (ci == C_SMEM) {
-            const uint32_t ia = rdl(I.ia, i), off = rdl(I.imm, i);
-            const bool ok = lds_val(L, ia & 0xFFFFu) == pv(T_SYSPTR, IG_LO, 0, 0, 0, 0, 0) &&
-                            lds_val(L, ia >> 16) == pv(T_SYSPTR, IG_HI, 0, 0, 0, 0, 0);
-            for (uint32_t j = 0; j < wi; j++) {
-                uint32_t pr, ty;
-                uint64_t va;
-                smem_dword(K, wi, off, j, pr, ty, va);
-                lds_put_u64(L, &L.fv[IX_DEF + j * 64 + i], ok ? va : VTOP);
-            }
-            continue;
+    if (lm) {
+        const uint32_t xq[5] = {I.ia & 0xFFFFu, I.ia >> 16, I.ib & 0xFFFFu, I.ib >> 16, I.ic & 0xFFFFu};
+        const uint32_t kq[5] = {I.ka0, I.ka1, I.kb0, I.kb1, I.kc0};
+        uint32_t svlo[5], svhi[5], sd[5];
+#pragma unroll
+        for (int q = 0; q < 5; q++) {
+            const uint32_t x = xq[q];
+            const uint64_t v = L.fv[x < IX_DEF ? x : IX_ZERO];
+            const bool def = x >= IX_DEF && x < IX_CONST;
+            const uint32_t k = (x - IX_DEF) >> 6, pl = (x - IX_DEF) & 63u;
+            const uint64_t sv = x == IX_CONST ? C32(kq[q]) : (x < IX_DEF ? v : VTOP);
+            svlo[q] = (uint32_t)sv;
+            svhi[q] = (uint32_t)(sv >> 32);
+            /* source mode: 0 sv, 1 register of lane pl (k = 0 / 1 in bit 7), 2 LDS entry x */
+            sd[q] = def && k < 2 ? (1u << 16) | pl | k << 7 : (def && k < 4 ? (2u << 16) | x : 0u);
         }
-        const uint32_t ia = rdl(I.ia, i), ib = rdl(I.ib, i), ic = rdl(I.ic, i);
-        const uint32_t xq[5] = {ia & 0xFFFFu, ia >> 16, ib & 0xFFFFu, ib >> 16, ic & 0xFFFFu};
-        uint64_t vq[5];
+        __builtin_amdgcn_wave_barrier();
+        while (lm) {
+            const uint32_t i = (uint32_t)__builtin_ctzll(lm);
+            lm &= lm - 1;
+            const uint64_t ei = ((uint64_t)rdl(I.ehi, i) << 32) | rdl(I.elo, i);
+            const uint32_t ci = e_cls(ei), wi = e_width(ei, 0);
+            uint64_t vq[5];
 #pragma unroll
-        for (int q = 0; q < 5; q++) vq[q] = L.fv[xq[q] == IX_CONST ? IX_ZERO : xq[q]];   /* all reads in flight */
-        const uint32_t kq[5] = {rdl(I.ka0, i), rdl(I.ka1, i), rdl(I.kb0, i), rdl(I.kb1, i), rdl(I.kc0, i)};
-#pragma unroll
-        for (int q = 0; q < 5; q++)
-            vq[q] = xq[q] == IX_CONST ? C32(kq[q]) : ((uint64_t)rfl((uint32_t)(vq[q] >> 32)) << 32) | rfl((uint32_t)vq[q]);
-        const uint64_t a0 = vq[0], a1 = vq[1], b0 = vq[2], b1 = vq[3], cc0 = vq[4];
-        uint64_t v0, v1;
-        eval_rule(K, e_prule(ei), e_vsrc(ei) == 1u, a0, a1, b0, b1, cc0, v0, v1);
-        lds_put_u64(L, &L.fv[IX_DEF + i], v0);
-        if (wi == 2) lds_put_u64(L, &L.fv[IX_DEF + 64 + i], v1);
+            for (int q = 0; q < 5; q++) {
+                const uint32_t d = rdl(sd[q], i);
+                const uint32_t mode = d >> 16;
+                if (mode == 1) {
+                    const uint32_t pl = d & 63u;
+                    vq[q] = (d & 128u) ? ((uint64_t)rdl(dv1hi, pl) << 32) | rdl(dv1lo, pl)
+                                       : ((uint64_t)rdl(dv0hi, pl) << 32) | rdl(dv0lo, pl);
+                } else if (mode == 2) {
+                    vq[q] = lds_val(L, d & 0xFFFFu);
+                } else {
+                    vq[q] = ((uint64_t)rdl(svhi[q], i) << 32) | rdl(svlo[q], i);
+                }
+            }
+            uint64_t v0 = VTOP, v1 = VTOP;
+            const bool me = l == i;
+            if (ci == C_SMEM) {
+                const uint32_t off = rdl(I.imm, i);
+                const bool ok = vq[0] == pv(T_SYSPTR, IG_LO, 0, 0, 0, 0, 0) && vq[1] == pv(T_SYSPTR, IG_HI, 0, 0, 0, 0, 0);
+                for (uint32_t j = 0; j < wi; j++) {
+                    uint32_t pr, ty;
+                    uint64_t va;
+                    smem_dword(K, wi, off, j, pr, ty, va);
+                    va = ok ? va : VTOP;
+                    if (j == 0) v0 = va;
+                    else if (j == 1) v1 = va;
+                    else lds_put_u64(L, &L.fv[IX_DEF + j * 64 + i], va);
+                }
+            } else {
+                eval_rule(K, e_prule(ei), e_vsrc(ei) == 1u, vq[0], vq[1], vq[2], vq[3], vq[4], v0, v1);
+            }
+            dv0lo = me ? (uint32_t)v0 : dv0lo;
+            dv0hi = me ? (uint32_t)(v0 >> 32) : dv0hi;
+            dv1lo = me && wi >= 2 ? (uint32_t)v1 : dv1lo;
+            dv1hi = me && wi >= 2 ? (uint32_t)(v1 >> 32) : dv1hi;
+        }
+        L.fv[IX_DEF + l] = ((uint64_t)dv0hi << 32) | dv0lo;
+        L.fv[IX_DEF + 64 + l] = ((uint64_t)dv1hi << 32) | dv1lo;
     }
     __builtin_amdgcn_wave_barrier();
 
@@ -857,7 +929,7 @@ __device__ __forceinline__ void run_chunk(const Plan *__restrict__ P, WaveLds &L
         if (kind == 1) {
             dt = tdat;
         } else if (mem && addr != VTOP && v_tag(addr) == T_PTR && v_arg(addr) < K.n_args) {
-            dt = K.args[v_arg(addr)].flags & 31u;
+            dt = (v_arg(addr) < 64 ? L.argf[v_arg(addr)] : K.args[v_arg(addr)].flags) & 31u;
         }
         const uint64_t am = ballot(mem);
         const uint32_t apos = E.ta + lanes_below(am);
@@ -942,7 +1014,8 @@ __device__ __forceinline__ uint32_t build_compact(const Plan *__restrict__ P, Wa
     for (uint32_t g0 = 0; g0 < n; g0 += 64) {
         const uint32_t gi = g0 + l < n ? g0 + l : n - 1;
         const uint4 r = recs[gi];
-        const uint64_t e = OPTAB[r.x & 0xFFFFu];
+        const uint32_t opc = r.x & 0xFFFFu;
+        const uint64_t e = L.optab[opc < (uint32_t)N_OPS ? opc : 0];
         const uint32_t id[4] = {r.x >> 16, r.y & 0xFFFFu, r.y >> 16, r.z};
 #pragma unroll
         for (int o = 0; o < 4; o++) {
@@ -998,8 +1071,12 @@ __device__ __forceinline__ void analyze(const Plan *__restrict__ P, uint32_t k, 
     const uint32_t nu_pad = (nu + 63u) & ~63u;
     const uint32_t bs = 3 * nu_pad;   /* arena dwords per block */
 
-    reached.init(nb);
+    reached.init(nr);   /* both bitmaps are indexed by reverse-postorder position */
     dirty.init(nr);
+    {
+        const uint32_t na = KX.K.n_args;
+        L.argf[l] = l < na ? KX.K.args[l < na ? l : 0].flags : 0;
+    }
     for (uint32_t c0 = 0; c0 < USLOT_N + 64; c0 += 64) L.dm[c0 + l] = 0;
     /* IN[0] = the ABI entry state on the compact slots */
     for (uint32_t c0 = 0; c0 < nu_pad; c0 += 64) {
@@ -1026,32 +1103,45 @@ __device__ __forceinline__ void analyze(const Plan *__restrict__ P, uint32_t k, 
         }
         dirty.clr(p);
         pos = p + 1;
-        const uint32_t b = rfl(P->rpo[fb + p]);
-        state_load(L, M.arena + (uint64_t)b * bs, nu_pad);
+        /* the block record and the IN state (arena slot = RPO position) load together */
+        const uint4 *bi = P->binfo + 2 * ((uint64_t)fb + p);
+        const uint4 i0 = bi[0], i1 = bi[1];
+        state_load(L, M.arena + (uint64_t)p * bs, nu_pad);
+        const uint32_t b = rfl(i0.x), g_lo = rfl(i0.y), g_hi = rfl(i0.z);
+        const int32_t ps0 = (int32_t)rfl(i1.x), ps1 = (int32_t)rfl(i1.y);
+        /* successors' IN states (a first visit joins nothing, so it reads nothing) */
+        const bool first0 = ps0 >= 0 && !reached.get((uint32_t)(ps0 >= 0 ? ps0 : 0));
+        const bool first1 = ps1 >= 0 && !reached.get((uint32_t)(ps1 >= 0 ? ps1 : 0));
+        uint32_t *const a0 = ps0 >= 0 ? M.arena + (uint64_t)ps0 * bs : nullptr;
+        uint32_t *const a1 = ps1 >= 0 ? M.arena + (uint64_t)ps1 * bs : nullptr;
+        PreIn Q0, Q1;
+        prefetch_in(Q0, first0 ? nullptr : a0, nu_pad);
+        prefetch_in(Q1, first1 ? nullptr : a1, nu_pad);
         __builtin_amdgcn_wave_barrier();
-        const uint32_t g_lo = rfl(P->block_start[fb + b]), g_hi = rfl(P->block_start[fb + b + 1]);
         Emit E;
         E.ta = E.ts = 0;
-        for (uint32_t g0 = g_lo; g0 < g_hi; g0 += 64) run_chunk(P, L, KX, rb, pos0, g0, min(64u, g_hi - g0), g_lo, E, M.dummy);
+        /* records of the next chunk are in flight while a chunk runs */
+        uint4 rnext = load_chunk(P, rb, pos0, g_lo, min(64u, g_hi - g_lo));
+        for (uint32_t g0 = g_lo; g0 < g_hi; g0 += 64) {
+            const uint4 r = rnext;
+            if (g0 + 64 < g_hi) rnext = load_chunk(P, rb, pos0, g0 + 64, min(64u, g_hi - g0 - 64));
+            run_chunk(P, L, KX, r, pos0, g0, min(64u, g_hi - g0), g_lo, E, M.dummy);
+        }
         P->blk_acc[fb + b] = E.ta;
         P->blk_sys[fb + b] = E.ts;
-        const int32_t s0 = (int32_t)rfl((uint32_t)P->succ[2 * (uint64_t)(fb + b)]);
-        const int32_t s1 = (int32_t)rfl((uint32_t)P->succ[2 * (uint64_t)(fb + b) + 1]);
-        const bool first0 = s0 >= 0 && !reached.get((uint32_t)s0);
-        const bool first1 = s1 >= 0 && !reached.get((uint32_t)s1);
-        const uint32_t chg = state_join2(L, s0 >= 0 ? M.arena + (uint64_t)s0 * bs : nullptr, first0,
-                                         s1 >= 0 ? M.arena + (uint64_t)s1 * bs : nullptr, first1, nu_pad);
-        if (first0) reached.set((uint32_t)s0);
-        if (first1) reached.set((uint32_t)s1);
-        if (chg & 1u) dirty.set(rfl((uint32_t)P->rpo_pos[fb + (uint32_t)s0]));
-        if (chg & 2u) dirty.set(rfl((uint32_t)P->rpo_pos[fb + (uint32_t)s1]));
+        const uint32_t chg = state_join2(L, a0, first0, Q0, a1, first1, Q1, nu_pad);
+        if (first0) reached.set((uint32_t)ps0);
+        if (first1) reached.set((uint32_t)ps1);
+        if (chg & 1u) dirty.set((uint32_t)ps0);
+        if (chg & 2u) dirty.set((uint32_t)ps1);
     }
 
     /* counts of blocks without a valid last visit are zero */
     const bool ok = status == ST_OK_FIX;
     for (uint32_t b0 = 0; b0 < nb; b0 += 64) {
         const uint32_t b = b0 + l;
-        const bool rch = reached.get_lane(b < nb ? b : 0);   /* every lane takes part in the exchange */
+        const int32_t pb = b < nb ? P->rpo_pos[fb + b] : -1;
+        const bool rch = reached.get_lane(pb >= 0 ? (uint32_t)pb : 0u) && pb >= 0;   /* every lane takes part */
         const bool keep = ok && b < nb && rch;
         uint32_t *pa = keep || b >= nb ? reinterpret_cast<uint32_t *>(M.dummy + l) : P->blk_acc + fb + b;
         uint32_t *ps = keep || b >= nb ? reinterpret_cast<uint32_t *>(M.dummy + l) + 1 : P->blk_sys + fb + b;
@@ -1068,8 +1158,9 @@ __device__ __forceinline__ void analyze(const Plan *__restrict__ P, uint32_t k, 
             __threadfence_block();
             __builtin_amdgcn_wave_barrier();
             for (uint32_t b = 0; b < nb; b++) {
-                const bool rb_ = reached.get(b);
-                const uint32_t *a = M.arena + (uint64_t)b * bs;
+                const int32_t pb = (int32_t)rfl((uint32_t)P->rpo_pos[fb + b]);
+                const bool rb_ = reached.get(pb >= 0 ? (uint32_t)pb : 0u) && pb >= 0;
+                const uint32_t *a = M.arena + (uint64_t)(pb >= 0 ? pb : 0) * bs;
                 uint64_t h = 0;
                 for (uint32_t j0 = 0; j0 < USLOT_N; j0 += 64) {
                     const uint32_t j = j0 + l;
@@ -1170,6 +1261,9 @@ __global__ __launch_bounds__(256) void k_fixpoint(const Plan *__restrict__ P, ui
         M.arena = P->ovf_arena + (uint64_t)gw * cap_rows * ROW_DW;
         M.dummy = P->dummy + ((uint64_t)P->main_waves + gw) * 64;
     }
+    L.optab[l] = OPTAB[l < (uint32_t)N_OPS ? l : 0];
+    L.optab[l < 16 ? 64 + l : l] = OPTAB[l < 16 && 64 + l < (uint32_t)N_OPS ? 64 + l : (l < (uint32_t)N_OPS ? l : 0)];
+    __builtin_amdgcn_wave_barrier();
     for (;;) {
         /* branch-free: every lane takes part, only lane 0 adds 1 */
         const uint32_t idx = rfl(atomicAdd(&P->counters[OVF ? 2 : 0], l == 0 ? 1u : 0u));

@@ -481,6 +481,26 @@ __global__ void k_order(Plan P) {
     P.n_reach[k] = np;
 }
 
+/* one thread per global block: the fixpoint's per-visit block record, stored
+ * at the block's reverse-postorder position (local id, instruction range,
+ * RPO positions of the successors, -1 when absent) */
+__global__ void k_blockinfo(Plan P) {
+    const uint32_t total = *P.total_blocks;
+    for (uint32_t gb = blockIdx.x * blockDim.x + threadIdx.x; gb < total; gb += gridDim.x * blockDim.x) {
+        const uint32_t k = P.block_kernel[gb];
+        if (P.status[k] != ST_OK) continue;
+        const int32_t p = P.rpo_pos[gb];
+        if (p < 0) continue;
+        const uint32_t fb = P.first_block[k];
+        const int32_t s0 = P.succ[2 * (uint64_t)gb], s1 = P.succ[2 * (uint64_t)gb + 1];
+        const int32_t ps0 = s0 >= 0 ? P.rpo_pos[fb + (uint32_t)s0] : -1;
+        const int32_t ps1 = s1 >= 0 ? P.rpo_pos[fb + (uint32_t)s1] : -1;
+        uint4 *dst = P.binfo + 2 * ((uint64_t)fb + (uint32_t)p);
+        dst[0] = make_uint4(gb - fb, P.block_start[gb], P.block_start[gb + 1], 0u);
+        dst[1] = make_uint4((uint32_t)ps0, (uint32_t)ps1, 0u, 0u);
+    }
+}
+
 hipError_t launch_edges(const Plan &P, hipStream_t s) {
     const uint32_t K = P.n_kernels;
     if (K) hipLaunchKernelGGL(k_kernel_info, dim3((K + 255) / 256), dim3(256), 0, s, P);
@@ -494,6 +514,7 @@ hipError_t launch_edges(const Plan &P, hipStream_t s) {
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_pred_scatter, dim3(grid), dim3(256), 0, s, P);
     if (K) hipLaunchKernelGGL(k_order, dim3((K + 63) / 64), dim3(64), 0, s, P);
+    if (P.binfo) hipLaunchKernelGGL(k_blockinfo, dim3(grid), dim3(256), 0, s, P);
     return hipGetLastError();
 }
 
