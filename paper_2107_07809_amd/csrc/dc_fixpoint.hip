@@ -395,34 +395,15 @@ __device__ __forceinline__ void state_load(WaveLds &L, const uint32_t *a, uint32
     }
 }
 
-/* The IN states of a block's successors are read when the visit starts (the
- * first PRE_ROWS rows into registers), so the reads are not queued behind the
- * visit's record stores. */
-constexpr int PRE_ROWS = 1;
-struct PreIn {
-    uint32_t p[PRE_ROWS], lo[PRE_ROWS], hi[PRE_ROWS];
-};
-__device__ __forceinline__ void prefetch_in(PreIn &Q, const uint32_t *a, uint32_t nu_pad) {
-    const uint32_t l = lane_id();
-#pragma unroll
-    for (int r = 0; r < PRE_ROWS; r++) {
-        if (a && (uint32_t)r * 64 < nu_pad) {   /* uniform */
-            const uint32_t c = (uint32_t)r * 64 + l;
-            Q.p[r] = a[c];
-            Q.lo[r] = a[nu_pad + c];
-            Q.hi[r] = a[2 * nu_pad + c];
-        }
-    }
-}
-
 /* a := a join OUT for one slot per lane (provenance and type bits unite;
  * payloads that differ go to TOP), or a := OUT when first; the words are
- * stored unconditionally; (pa, la, ha) is a's current value */
-__device__ __forceinline__ bool join_slot(uint32_t *a, uint32_t nu_pad, uint32_t c, bool first, uint32_t pa, uint32_t la,
-                                          uint32_t ha, uint32_t pb, uint32_t lb, uint32_t hb) {
+ * stored unconditionally */
+__device__ __forceinline__ bool join_slot(uint32_t *a, uint32_t nu_pad, uint32_t c, bool first, uint32_t pb, uint32_t lb,
+                                          uint32_t hb) {
     uint32_t pn = pb, ln = lb, hn = hb;
     bool ch = first;
     if (!first) {   /* uniform */
+        const uint32_t pa = a[c], la = a[nu_pad + c], ha = a[2 * nu_pad + c];
         const bool same = la == lb && (ha & 0xFFFFFF00u) == (hb & 0xFFFFFF00u);
         pn = pa | pb;
         ln = same ? la : 0xFFFFFFFFu;
@@ -434,11 +415,10 @@ __device__ __forceinline__ bool join_slot(uint32_t *a, uint32_t nu_pad, uint32_t
     a[2 * nu_pad + c] = hn;
     return ch;
 }
-/* OUT state into the IN states of up to two successors (null when absent),
- * rows below PRE_ROWS from the prefetched values; returns the per-successor
- * change bits (bit 0, bit 1) */
-__device__ __forceinline__ uint32_t state_join2(const WaveLds &L, uint32_t *a0, bool first0, const PreIn &Q0, uint32_t *a1,
-                                                bool first1, const PreIn &Q1, uint32_t nu_pad) {
+/* OUT state into the IN states of up to two successors (null when absent);
+ * returns the per-successor change bits (bit 0, bit 1) */
+__device__ __forceinline__ uint32_t state_join2(const WaveLds &L, uint32_t *a0, bool first0, uint32_t *a1, bool first1,
+                                                uint32_t nu_pad) {
     const uint32_t l = lane_id();
     bool ch0 = false, ch1 = false;
 #pragma unroll
@@ -447,20 +427,8 @@ __device__ __forceinline__ uint32_t state_join2(const WaveLds &L, uint32_t *a0, 
             const uint32_t c = (uint32_t)r * 64 + l;
             const uint64_t x = L.fpt[c], v = L.fv[c];
             const uint32_t pb = fpt_prov(x), lb = (uint32_t)v, hb = pack_hi(v, fpt_type(x));
-            if (a0) {
-                uint32_t pa, la, ha;
-                if (r < PRE_ROWS) { pa = Q0.p[r < PRE_ROWS ? r : 0]; la = Q0.lo[r < PRE_ROWS ? r : 0]; ha = Q0.hi[r < PRE_ROWS ? r : 0]; }
-                else if (!first0) { pa = a0[c]; la = a0[nu_pad + c]; ha = a0[2 * nu_pad + c]; }
-                else { pa = la = ha = 0; }
-                ch0 = join_slot(a0, nu_pad, c, first0, pa, la, ha, pb, lb, hb) || ch0;
-            }
-            if (a1) {
-                uint32_t pa, la, ha;
-                if (r < PRE_ROWS) { pa = Q1.p[r < PRE_ROWS ? r : 0]; la = Q1.lo[r < PRE_ROWS ? r : 0]; ha = Q1.hi[r < PRE_ROWS ? r : 0]; }
-                else if (!first1) { pa = a1[c]; la = a1[nu_pad + c]; ha = a1[2 * nu_pad + c]; }
-                else { pa = la = ha = 0; }
-                ch1 = join_slot(a1, nu_pad, c, first1, pa, la, ha, pb, lb, hb) || ch1;
-            }
+            if (a0) ch0 = join_slot(a0, nu_pad, c, first0, pb, lb, hb) || ch0;
+            if (a1) ch1 = join_slot(a1, nu_pad, c, first1, pb, lb, hb) || ch1;
         }
     }
     return (ballot(ch0) != 0 ? 1u : 0u) | (ballot(ch1) != 0 ? 2u : 0u);
@@ -1070,6 +1038,7 @@ __device__ __forceinline__ void analyze(const Plan *__restrict__ P, uint32_t k, 
     KX.cv = rfl(L.umap[104]);
     const uint32_t nu_pad = (nu + 63u) & ~63u;
     const uint32_t bs = 3 * nu_pad;   /* arena dwords per block */
+    const bool keep_states = (P->flags & (DC_OPT_DIGEST | DC_OPT_EXPORT_STATES)) != 0;
 
     reached.init(nr);   /* both bitmaps are indexed by reverse-postorder position */
     dirty.init(nr);
@@ -1105,35 +1074,53 @@ __device__ __forceinline__ void analyze(const Plan *__restrict__ P, uint32_t k, 
         pos = p + 1;
         /* the block record and the IN state (arena slot = RPO position) load together */
         const uint4 *bi = P->binfo + 2 * ((uint64_t)fb + p);
-        const uint4 i0 = bi[0], i1 = bi[1];
+        uint4 i0 = bi[0], i1 = bi[1];
         state_load(L, M.arena + (uint64_t)p * bs, nu_pad);
-        const uint32_t b = rfl(i0.x), g_lo = rfl(i0.y), g_hi = rfl(i0.z);
-        const int32_t ps0 = (int32_t)rfl(i1.x), ps1 = (int32_t)rfl(i1.y);
-        /* successors' IN states (a first visit joins nothing, so it reads nothing) */
-        const bool first0 = ps0 >= 0 && !reached.get((uint32_t)(ps0 >= 0 ? ps0 : 0));
-        const bool first1 = ps1 >= 0 && !reached.get((uint32_t)(ps1 >= 0 ? ps1 : 0));
-        uint32_t *const a0 = ps0 >= 0 ? M.arena + (uint64_t)ps0 * bs : nullptr;
-        uint32_t *const a1 = ps1 >= 0 ? M.arena + (uint64_t)ps1 * bs : nullptr;
-        PreIn Q0, Q1;
-        prefetch_in(Q0, first0 ? nullptr : a0, nu_pad);
-        prefetch_in(Q1, first1 ? nullptr : a1, nu_pad);
-        __builtin_amdgcn_wave_barrier();
-        Emit E;
-        E.ta = E.ts = 0;
-        /* records of the next chunk are in flight while a chunk runs */
-        uint4 rnext = load_chunk(P, rb, pos0, g_lo, min(64u, g_hi - g_lo));
-        for (uint32_t g0 = g_lo; g0 < g_hi; g0 += 64) {
-            const uint4 r = rnext;
-            if (g0 + 64 < g_hi) rnext = load_chunk(P, rb, pos0, g0 + 64, min(64u, g_hi - g0 - 64));
-            run_chunk(P, L, KX, r, pos0, g0, min(64u, g_hi - g0), g_lo, E, M.dummy);
+        /* the block, then the chain of successors whose only predecessor is the
+         * block before them: their IN state is that block's OUT state, already
+         * in LDS.  Running a chained block right after its predecessor instead
+         * of at its own RPO position changes no pass's result: nothing between
+         * the two positions feeds it or is fed by it. */
+        for (;;) {
+            const uint32_t b = rfl(i0.x), g_lo = rfl(i0.y), g_hi = rfl(i0.z);
+            const int32_t ps0 = (int32_t)rfl(i1.x), ps1 = (int32_t)rfl(i1.y);
+            const uint32_t chain = rfl(i1.z);
+            const int32_t pc = chain == 0 ? ps0 : (chain == 1 ? ps1 : -1);
+            /* a chained successor's IN state is stored only when states are
+             * exported or digested */
+            const bool join0 = ps0 >= 0 && (ps0 != pc || keep_states);
+            const bool join1 = ps1 >= 0 && (ps1 != pc || keep_states);
+            const bool first0 = ps0 >= 0 && !reached.get((uint32_t)(ps0 >= 0 ? ps0 : 0));
+            const bool first1 = ps1 >= 0 && !reached.get((uint32_t)(ps1 >= 0 ? ps1 : 0));
+            uint32_t *const a0 = join0 ? M.arena + (uint64_t)ps0 * bs : nullptr;
+            uint32_t *const a1 = join1 ? M.arena + (uint64_t)ps1 * bs : nullptr;
+            uint4 n0 = i0, n1 = i1;
+            if (pc >= 0) {
+                const uint4 *bn = P->binfo + 2 * ((uint64_t)fb + (uint32_t)pc);
+                n0 = bn[0];
+                n1 = bn[1];
+            }
+            __builtin_amdgcn_wave_barrier();
+            Emit E;
+            E.ta = E.ts = 0;
+            /* records of the next chunk are in flight while a chunk runs */
+            uint4 rnext = load_chunk(P, rb, pos0, g_lo, min(64u, g_hi - g_lo));
+            for (uint32_t g0 = g_lo; g0 < g_hi; g0 += 64) {
+                const uint4 r = rnext;
+                if (g0 + 64 < g_hi) rnext = load_chunk(P, rb, pos0, g0 + 64, min(64u, g_hi - g0 - 64));
+                run_chunk(P, L, KX, r, pos0, g0, min(64u, g_hi - g0), g_lo, E, M.dummy);
+            }
+            P->blk_acc[fb + b] = E.ta;
+            P->blk_sys[fb + b] = E.ts;
+            const uint32_t chg = state_join2(L, a0, first0, a1, first1, nu_pad);
+            if (first0) reached.set((uint32_t)ps0);
+            if (first1) reached.set((uint32_t)ps1);
+            if ((chg & 1u) && ps0 != pc) dirty.set((uint32_t)ps0);
+            if ((chg & 2u) && ps1 != pc) dirty.set((uint32_t)ps1);
+            if (pc < 0) break;
+            i0 = n0;
+            i1 = n1;
         }
-        P->blk_acc[fb + b] = E.ta;
-        P->blk_sys[fb + b] = E.ts;
-        const uint32_t chg = state_join2(L, a0, first0, Q0, a1, first1, Q1, nu_pad);
-        if (first0) reached.set((uint32_t)ps0);
-        if (first1) reached.set((uint32_t)ps1);
-        if (chg & 1u) dirty.set((uint32_t)ps0);
-        if (chg & 2u) dirty.set((uint32_t)ps1);
     }
 
     /* counts of blocks without a valid last visit are zero */

@@ -46,7 +46,8 @@ struct Plan {
     uint32_t *total_blocks;         /* 1 */
     uint4 *binfo;                   /* 2 * n_pos, per kernel at first_block, by RPO position: {local id, first
                                        position, end position, 0}, {RPO position of successor 0, of successor 1,
-                                       0, 0} (-1 when absent); null for CFG-only batches */
+                                       chained successor (0, 1; 2 = none), 0} (-1 when absent); null for
+                                       CFG-only batches */
 
     /* fixpoint + extraction */
     uint32_t *arena;                /* per main-pass wave: arena_rows state rows of 192 dwords */

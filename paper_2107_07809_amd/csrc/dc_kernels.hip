@@ -483,7 +483,8 @@ __global__ void k_order(Plan P) {
 
 /* one thread per global block: the fixpoint's per-visit block record, stored
  * at the block's reverse-postorder position (local id, instruction range,
- * RPO positions of the successors, -1 when absent) */
+ * RPO positions of the successors, -1 when absent, and which successor, if
+ * any, has this block as its only predecessor) */
 __global__ void k_blockinfo(Plan P) {
     const uint32_t total = *P.total_blocks;
     for (uint32_t gb = blockIdx.x * blockDim.x + threadIdx.x; gb < total; gb += gridDim.x * blockDim.x) {
@@ -495,9 +496,13 @@ __global__ void k_blockinfo(Plan P) {
         const int32_t s0 = P.succ[2 * (uint64_t)gb], s1 = P.succ[2 * (uint64_t)gb + 1];
         const int32_t ps0 = s0 >= 0 ? P.rpo_pos[fb + (uint32_t)s0] : -1;
         const int32_t ps1 = s1 >= 0 ? P.rpo_pos[fb + (uint32_t)s1] : -1;
+        /* a successor whose only predecessor is this block continues this
+         * block's visit (its IN state is this block's OUT state) */
+        auto single = [&](int32_t sb) { return sb >= 0 && P.pred_cnt[fb + (uint32_t)sb + 1] - P.pred_cnt[fb + (uint32_t)sb] == 1; };
+        const uint32_t chain = single(s0) ? 0u : (single(s1) ? 1u : 2u);
         uint4 *dst = P.binfo + 2 * ((uint64_t)fb + (uint32_t)p);
         dst[0] = make_uint4(gb - fb, P.block_start[gb], P.block_start[gb + 1], 0u);
-        dst[1] = make_uint4((uint32_t)ps0, (uint32_t)ps1, 0u, 0u);
+        dst[1] = make_uint4((uint32_t)ps0, (uint32_t)ps1, chain, 0u);
     }
 }
 

@@ -28,12 +28,14 @@ def oracle_config(cfg: int, n: int, procs: int = 0):
     return summ, acc, sys
 
 
-def compare_summaries(gpu_res, summ):
-    """Per-kernel status, block count, sweeps, counts and state digest."""
+def compare_summaries(gpu_res, summ, digest: bool = True):
+    """Per-kernel status, block count, sweeps, counts and (unless the run did
+    not ask for it) the state digest."""
     assert len(gpu_res) == len(summ)
     for f_gpu, f_or in [("status", "status"), ("n_blocks", "n_blocks"), ("sweeps", "sweeps"),
                         ("n_access", "n_acc"), ("n_sysval", "n_sys")]:
         bad = np.nonzero(gpu_res[f_gpu] != summ[f_or])[0]
         assert len(bad) == 0, (f_gpu, bad[:10], gpu_res[f_gpu][bad[:10]], summ[f_or][bad[:10]])
-    bad = np.nonzero(gpu_res["digest"] != summ["digest"])[0]
-    assert len(bad) == 0, ("digest", bad[:10])
+    if digest:
+        bad = np.nonzero(gpu_res["digest"] != summ["digest"])[0]
+        assert len(bad) == 0, ("digest", bad[:10])

@@ -111,21 +111,28 @@ def test_c3_and_c5_shapes(ctx):
 
 def test_c2_full_digest(ctx):
     """All 65,536 kernels of the 51.2M-instruction workload in the bench's
-    launch configuration: every record and every kernel's state digest."""
+    launch configuration: every record and every kernel's state digest; then
+    the run exactly as the bench makes it (no digest, no exported states, so
+    the IN states of chained blocks are never stored), again every record,
+    status, block count and sweep count."""
     n = 65536
     b = dcgen.generate(2, n)
     say("c2 full: generated", b.n_instr)
-    batch, dev = run(ctx, b, flags=dc.OPT_DIGEST)
-    res = batch.results()
-    acc, _ = batch.all_accesses()
-    sysv, _ = batch.all_sysvals()
-    say("c2 full: gpu done; running the oracle")
+    dev = dc.to_device(b.instrs)
+    say("c2 full: oracle")
     summ, oacc, osys = oracle_config(2, n)
     say("c2 full: oracle done")
-    compare_summaries(res, summ)
-    assert acc.tobytes() == oacc.tobytes()
-    assert sysv.tobytes() == osys.tobytes()
-    batch.free()
+    for flags, digest in ((dc.OPT_DIGEST, True), (dc.OPT_TIMING, False)):
+        batch = ctx.analyze(b.kernels, dev, b.n_instr, b.args, flags=flags)
+        batch.run()
+        res = batch.results()
+        acc, _ = batch.all_accesses()
+        sysv, _ = batch.all_sysvals()
+        say(f"c2 full: gpu done (flags {flags})")
+        compare_summaries(res, summ, digest=digest)
+        assert acc.tobytes() == oacc.tobytes()
+        assert sysv.tobytes() == osys.tobytes()
+        batch.free()
 
 
 def test_cfg_parity(ctx):
