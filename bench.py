@@ -21,6 +21,25 @@ sys.path.insert(0, ROOT)
 
 METRIC = "instructions analysed/sec to fixpoint (bit-exact) + HBM GB/s fraction; p99 latency"
 HBM_PEAK_GBS = 8000.0
+PROFILE = os.path.join(ROOT, "profiles", "k_fixpoint_c2_65536_kernels.md")
+FIXPOINT_SRC = os.path.join(ROOT, "paper_2107_07809_amd", "csrc", "dc_fixpoint.hip")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the fixpoint kernel from the committed rocprofv3
+    summary (FETCH_SIZE + WRITE_SIZE, calibrated by a 1 GiB copy), or None when
+    the kernel source has changed since the counters were taken."""
+    import hashlib
+    try:
+        text = open(PROFILE).read()
+        src = hashlib.sha256(open(FIXPOINT_SRC, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    fields = dict(line.split(": ", 1) for line in text.splitlines()
+                  if line.startswith(("traffic_bytes_per_launch: ", "measured_source_sha256: ")))
+    if fields.get("measured_source_sha256", "").strip() != src:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
 
 
 def log(msg):
@@ -122,6 +141,8 @@ def main():
     # once, descriptors, the access/system-value records and results written
     alg_bytes = 16 * b.n_instr + 32 * b.n_kernels + 16 * n_acc + 8 * n_sys + 32 * b.n_kernels
     achieved = alg_bytes / (fix_ms * 1e-3) / 1e9
+    traffic_bytes = measured_traffic()
+    traffic = traffic_bytes / (fix_ms * 1e-3) / 1e9 if traffic_bytes else None
     # per-run latencies from a second, short pass with one sync per step
     lat = []
     for _ in range(min(args.steps, 20)):
@@ -147,8 +168,9 @@ def main():
                    "kernels": b.n_kernels, "instructions": b.n_instr, "record_bytes": 16 * b.n_instr,
                    "form": "batched persistent (one wavefront per kernel)"},
         "roofline": {"bound": "hbm", "kernel": "k_fixpoint", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": fix_ms},
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "alg_bytes_per_launch": alg_bytes, "traffic_bytes_per_launch": traffic_bytes,
+                     "avg_launch_ms": fix_ms},
         "stages_ms": {"total": total_ms, "decode": tm["ms_decode"] / max(1, tm["runs"]),
                       "cfg": tm["ms_cfg"] / max(1, tm["runs"]), "fixpoint": fix_ms,
                       "compact": tm["ms_compact"] / max(1, tm["runs"])},
