@@ -141,7 +141,8 @@ def sizes(cfg: int, i0: int, n: int):
 
 
 def generate(cfg: int, n: int, i0: int = 0, threads: int | None = None) -> Batch:
-    """Kernels [i0, i0+n) of config `cfg` (1..5), packed densely in index order."""
+    """Kernels [i0, i0+n) of config `cfg` (1..5; 6 is a dense-control-flow test
+    shape), packed densely in index order."""
     ln, na = sizes(cfg, i0, n)
     ioff = np.zeros(n, np.uint64)
     aoff = np.zeros(n, np.uint32)

@@ -159,6 +159,7 @@ static void make_header(int cfg, uint64_t index, header *h) {
         h->len = (uint32_t)l;
         break;
     }
+    case 6: h->len = 6000 + below(r, 6001); break;   /* dense control flow (test shape) */
     default: h->len = 64; break;
     }
     h->dims = 1 + (int)below(r, 3);
@@ -506,9 +507,9 @@ static void gen_one(int cfg, uint64_t index, gen_instr *out) {
     g.out = out;
     g.s_lo = 34; g.s_hi = g.h.full_range ? 103 : 63;
     g.v_lo = 8; g.v_hi = g.h.full_range ? 255 : 63;
-    g.if_depth_max = cfg == 1 ? 1 : cfg == 4 ? 5 : 3;
-    g.loop_depth_max = cfg == 1 ? 0 : cfg == 4 ? 5 : 3;
-    g.p_struct = cfg == 4 ? 0.0025 : 0.012;
+    g.if_depth_max = cfg == 1 ? 1 : (cfg == 4 || cfg == 6) ? 5 : 3;
+    g.loop_depth_max = cfg == 1 ? 0 : (cfg == 4 || cfg == 6) ? 5 : 3;
+    g.p_struct = cfg == 4 ? 0.0025 : cfg == 6 ? 0.3 : 0.012;
     gen_body(&g);
 }
 

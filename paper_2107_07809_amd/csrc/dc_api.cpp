@@ -90,6 +90,7 @@ struct dc_batch {
     bool have_events = false;
     uint64_t runs = 0, runs_at_reset = 0;   /* enqueued runs; ring slot = run % TIMING_RING */
     uint64_t export_blocks = 0;
+    bool ovf_planned = false;   /* the overflow pass is sized from the first run's block counts */
     /* host copies, filled on first use after a run */
     bool host_valid = false;
     std::vector<dc_kernel_result_t> results;
@@ -184,7 +185,7 @@ static dc_status_t plan_batch(dc_batch *B, dc_ctx *ctx, const dc_kernel_t *kerne
     B->kernels.assign(kernels, kernels + n_kernels);
     B->pos_begin.resize((size_t)n_kernels + 1);
     std::vector<int32_t> dstat(n_kernels);
-    uint64_t pos = 0, max_len = 0;
+    uint64_t pos = 0;
     for (uint32_t k = 0; k < n_kernels; k++) {
         const dc_kernel_t &d = kernels[k];
         if (d.instr_begin > n_records || d.n_instr > n_records - d.instr_begin) return DC_E_INVAL;
@@ -192,7 +193,6 @@ static dc_status_t plan_batch(dc_batch *B, dc_ctx *ctx, const dc_kernel_t *kerne
         if (dstat[k] == DC_OK && ((uint64_t)d.arg_begin + d.n_args > n_args_total)) return DC_E_INVAL;
         B->pos_begin[k] = (uint32_t)pos;
         pos += d.n_instr;
-        max_len = std::max<uint64_t>(max_len, d.n_instr);
         if (pos >= 0xFFFFFFF0ull) return DC_E_INVAL;   /* positions are 32-bit */
     }
     B->pos_begin[n_kernels] = (uint32_t)pos;
@@ -247,21 +247,15 @@ static dc_status_t plan_batch(dc_batch *B, dc_ctx *ctx, const dc_kernel_t *kerne
         P.arena_rows = 2 * B->opts.block_cap;
         P.main_waves = (uint32_t)waves;
         P.arena = M.alloc<uint32_t>(waves * P.arena_rows * FIX_ROW_DWORDS);
-        /* overflow pass: kernels with more than 2048 blocks or whose states do
-         * not fit the main arena; a kernel has at most as many blocks as
-         * instructions */
-        const uint64_t main_blocks = std::min<uint64_t>(2048, P.arena_rows / FIX_MAX_ROWS);
-        uint64_t ovf_cap = std::max<uint64_t>(max_len, 1);
-        uint64_t ovf_waves = 64;
-        const uint64_t budget = 8ull << 30;
-        while (ovf_waves > 1 && ovf_waves * ovf_cap * FIX_MAX_ROWS * FIX_ROW_DWORDS * 4 > budget) ovf_waves /= 2;
-        if (max_len <= main_blocks) { ovf_cap = 1; ovf_waves = 1; }
-        P.ovf_block_cap = (uint32_t)ovf_cap;
-        P.ovf_rows = (uint32_t)(ovf_cap * FIX_MAX_ROWS);
-        P.ovf_waves = (uint32_t)ovf_waves;
-        P.ovf_arena = M.alloc<uint32_t>(ovf_waves * P.ovf_rows * FIX_ROW_DWORDS);
-        P.ovf_bitmaps = M.alloc<uint32_t>(ovf_waves * (2 * ((ovf_cap + 31) / 32) + 64));
-        P.dummy = M.alloc<uint4>((waves + ovf_waves) * 64);
+        /* overflow pass (kernels with more than 2048 blocks or states beyond
+         * the main arena): sized after the first run's CFG stage, from the
+         * real block counts (plan_overflow) */
+        P.ovf_block_cap = 0;
+        P.ovf_rows = 0;
+        P.ovf_waves = 0;
+        P.ovf_arena = nullptr;
+        P.ovf_bitmaps = nullptr;
+        P.dummy = M.alloc<uint4>((waves + OVF_MAX_WAVES) * 64);
         P.ovf_list = M.alloc<uint32_t>(K);
         P.counters = M.alloc<uint32_t>(4);
         P.sweep_cap = B->opts.sweep_cap;
@@ -304,6 +298,38 @@ static dc_status_t plan_batch(dc_batch *B, dc_ctx *ctx, const dc_kernel_t *kerne
     return DC_OK;
 }
 
+/* Overflow pass sizing from the block counts of the CFG stage just enqueued
+ * (waits for the stream).  A kernel whose state width is not known yet may
+ * need up to FIX_MAX_ROWS rows per block; the pass gets up to OVF_MAX_WAVES
+ * waves within an 8 GB arena budget.  A later run whose kernels have more
+ * blocks than planned reports DC_E_UNSUPPORTED for those kernels. */
+static hipError_t plan_overflow(dc_batch *B, hipStream_t s) {
+    Plan &P = B->P;
+    std::vector<uint32_t> nb(B->K);
+    hipError_t e = hipSuccess;
+    if (B->K) e = hipMemcpyAsync(nb.data(), P.n_blocks, B->K * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    uint64_t cap = 1, n_ovf = 0;
+    for (uint32_t x : nb) {
+        if (x > 2048 || (uint64_t)x * FIX_MAX_ROWS > P.arena_rows) {
+            n_ovf++;
+            cap = std::max<uint64_t>(cap, x);
+        }
+    }
+    uint64_t waves = std::max<uint64_t>(1, std::min<uint64_t>(OVF_MAX_WAVES, n_ovf));
+    const uint64_t row_bytes = FIX_ROW_DWORDS * 4ull, budget = 8ull << 30;
+    while (waves > 1 && waves * cap * FIX_MAX_ROWS * row_bytes > budget) waves--;
+    P.ovf_block_cap = (uint32_t)cap;
+    P.ovf_rows = (uint32_t)(cap * FIX_MAX_ROWS);
+    P.ovf_waves = (uint32_t)waves;
+    P.ovf_arena = B->mem.alloc<uint32_t>(waves * P.ovf_rows * FIX_ROW_DWORDS);
+    P.ovf_bitmaps = B->mem.alloc<uint32_t>(waves * (2 * ((cap + 31) / 32) + 64));
+    if (B->mem.failed) return hipErrorOutOfMemory;
+    B->ovf_planned = true;
+    return hipSuccess;
+}
+
 static dc_status_t enqueue(dc_batch *B) {
     Plan &P = B->P;
     hipStream_t s = B->stream;
@@ -332,6 +358,13 @@ static dc_status_t enqueue(dc_batch *B) {
         B->runs++;
         return DC_OK;
     }
+    bool plan_changed = false;
+    if (!B->ovf_planned) {
+        e = plan_overflow(B, s);
+        if (e == hipErrorOutOfMemory) return DC_E_OOM;
+        if (e != hipSuccess) return hip_fail(e);
+        plan_changed = true;
+    }
     if (B->opts.flags & DC_OPT_EXPORT_STATES) {
         /* size the state export from the block count */
         uint32_t total = 0;
@@ -345,6 +378,9 @@ static dc_status_t enqueue(dc_batch *B) {
             if (B->mem.failed) return DC_E_OOM;
             B->export_blocks = total;
         }
+        plan_changed = true;
+    }
+    if (plan_changed) {
         TRY(hipMemcpyAsync(B->dP, &P, sizeof(Plan), hipMemcpyHostToDevice, s));
         TRY(hipStreamSynchronize(s));
     }

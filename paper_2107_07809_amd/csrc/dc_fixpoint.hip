@@ -1276,7 +1276,7 @@ __global__ __launch_bounds__(256) void k_fixpoint(const Plan *__restrict__ P, ui
             RegBits reached, dirty;
             analyze(P, k, L, reached, dirty, M, nu);
         } else {
-            if (rows > cap_rows) {
+            if (nb > P->ovf_block_cap || rows > cap_rows) {   /* more blocks than the pass was planned for */
                 fail_kernel(P, k, DC_E_UNSUPPORTED, M);
                 continue;
             }

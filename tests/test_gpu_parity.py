@@ -109,6 +109,16 @@ def test_c3_and_c5_shapes(ctx):
     full_compare(ctx, dcgen.generate(5, 100))
 
 
+def test_dense_cfg_main_and_overflow(ctx):
+    """Kernels of 6,000-12,000 instructions with 1,300-2,400 blocks: states
+    byte-exact through the overflow pass (default block cap), then with the
+    largest block cap, where kernels up to 2,048 blocks take the main pass and
+    the rest the overflow pass."""
+    b = dcgen.generate(6, 12)
+    full_compare(ctx, b)
+    full_compare(ctx, b, block_cap=2048)
+
+
 def test_c2_full_digest(ctx):
     """All 65,536 kernels of the 51.2M-instruction workload in the bench's
     launch configuration: every record and every kernel's state digest; then
@@ -133,6 +143,53 @@ def test_c2_full_digest(ctx):
         assert acc.tobytes() == oacc.tobytes()
         assert sysv.tobytes() == osys.tobytes()
         batch.free()
+
+
+def _records_and_summaries(ctx, b, summ, oacc, osys, flags, digest, tag):
+    dev = dc.to_device(b.instrs)
+    batch = ctx.analyze(b.kernels, dev, b.n_instr, b.args, flags=flags)
+    batch.run()
+    res = batch.results()
+    acc, _ = batch.all_accesses()
+    sysv, _ = batch.all_sysvals()
+    say(f"{tag}: gpu done (flags {flags})")
+    compare_summaries(res, summ, digest=digest)
+    assert acc.tobytes() == oacc.tobytes()
+    assert sysv.tobytes() == osys.tobytes()
+    batch.free()
+    return res
+
+
+def test_c3_zipf_65536(ctx):
+    """The first 65,536 kernels of the Zipf(1.2) 20-20,000 workload (about
+    109M instructions): every record, status, sweep count and digest, then
+    again without the digest."""
+    n = 65536
+    b = dcgen.generate(3, n)
+    say("c3 65536: generated", b.n_instr)
+    summ, oacc, osys = oracle_config(3, n)
+    say("c3 65536: oracle done")
+    for flags, digest in ((dc.OPT_DIGEST, True), (0, False)):
+        _records_and_summaries(ctx, b, summ, oacc, osys, flags, digest, "c3 65536")
+
+
+def test_c4_very_large(ctx):
+    """All 16 kernels of 1-4M instructions (up to ~17k blocks, which take
+    the overflow pass with global-memory bitmaps), alone and interleaved with
+    short kernels that take the main pass, in one batch."""
+    b4 = dcgen.generate(4, 16)
+    say("c4: generated", b4.n_instr)
+    summ, oacc, osys = oracle_config(4, 16)
+    say("c4: oracle done", int(summ["n_blocks"].max()))
+    res = _records_and_summaries(ctx, b4, summ, oacc, osys, dc.OPT_DIGEST, True, "c4")
+    assert (res["n_blocks"] > 2048).any()
+    b2 = dcgen.generate(2, 48, i0=5000)
+    order = [(4, k) for k in range(16)] + [(2, k) for k in range(48)]
+    rng = np.random.default_rng(11)
+    rng.shuffle(order)
+    mix = dcgen.concat([(b4 if c == 4 else b2).kernel(k) for c, k in order])
+    ms, ma, my = oracle.analyze_batch(mix)
+    _records_and_summaries(ctx, mix, ms, ma, my, dc.OPT_DIGEST, True, "c4 mix")
 
 
 def test_cfg_parity(ctx):
