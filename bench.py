@@ -6,7 +6,11 @@ extraction and dense compaction, on 65,536 seeded synthetic GCN kernels with
 lengths log-uniform on [200, 2000] (51.2M instructions, 820 MB of records)
 already resident in HBM.  Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--copy-calibration]
+Beside the headline figure it reports the plain form (each kernel analysed
+by its own launch sequence) on a sample, and the request server at Poisson
+arrivals (latency percentiles, served rate, the same requests offline).
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-serving] [--copy-calibration]
 """
 import argparse
 import json
@@ -77,6 +81,114 @@ def cpu_baseline(cfg, n_kernels, target_core_seconds=15.0):
             "seconds": dt}
 
 
+def plain_per_kernel(ctx, b, dev, stream, n_sample):
+    """The plain form for comparison: every kernel analysed by its own
+    sequence of launches (its own batch of one), one after another, on the
+    first n_sample kernels of the same workload.  Planning and allocation
+    happen before the timed region, as for the batched form."""
+    import torch
+    from paper_2107_07809_amd import dc
+    batches = []
+    n_instr = 0
+    for k in range(n_sample):
+        d = b.kernels[k:k + 1].copy()
+        ab, na = int(d["arg_begin"][0]), int(d["n_args"][0])
+        d["arg_begin"] = 0
+        batches.append(ctx.analyze(d, dev, b.n_instr, b.args[ab:ab + na], stream=stream))
+        n_instr += int(d["n_instr"][0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for bt in batches:
+        bt.run(stream=stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    for bt in batches:
+        bt.free()
+    return {"value": n_instr / dt, "unit": "instructions/s", "sample": f"first {n_sample} kernels of the same "
+            f"workload ({n_instr} instructions), one launch sequence per kernel", "seconds": dt}
+
+
+def serving(ctx, rate, seconds, warm_seconds=0.3, offline=True, **server_opts):
+    """The request server at Poisson arrivals (log-normal lengths, median
+    1,000 instructions, sigma 1, cap 100k): offered and served rates, latency
+    from submission to result on the host, and the same requests analysed
+    as one offline batch."""
+    import dcgen
+    from paper_2107_07809_amd import dc
+    n_warm = int(rate * warm_seconds)
+    n = int(rate * seconds)
+    b = dcgen.generate(5, n_warm + n)
+    reqs = dc.requests(b.kernels, b.instrs, b.args)
+    due = np.cumsum(np.random.default_rng(0xD1C5A11E).exponential(1.0 / rate, n_warm + n))
+    srv = dc.Server(ctx, **(server_opts or {"lanes": 4}))
+    stride = dc.REQUEST_DTYPE.itemsize
+    base = reqs.ctypes.data
+    done = []
+    t0 = time.perf_counter()
+    i = 0
+    while i < n_warm + n:
+        now = time.perf_counter() - t0
+        while i < n_warm + n and due[i] <= now:
+            srv.submit_raw(base + i * stride)
+            i += 1
+        res, _ = srv.poll(8192, records=False)
+        if len(res):
+            done.append(res)
+    deadline = time.perf_counter() + 60
+    while sum(len(x) for x in done) < n_warm + n and time.perf_counter() < deadline:
+        res, _ = srv.poll(8192, records=False)
+        if len(res):
+            done.append(res)
+        else:
+            time.sleep(0.0002)
+    st = srv.stats()
+    srv.close()
+    res = np.concatenate(done)
+    res = res[res["tag"] >= n_warm]           # measured window: after the warm-up arrivals
+    lat = (res["t_done_ns"] - res["t_submit_ns"]) / 1e6
+    instr = int(b.kernels["n_instr"][n_warm:].sum())
+    span = (res["t_done_ns"].max() - res["t_submit_ns"].min()) / 1e9
+    offered = len(res) / ((res["t_submit_ns"].max() - res["t_submit_ns"].min()) / 1e9)
+    failed = int((res["summary"]["status"] != 0).sum())
+
+    def med(x):
+        return float(np.percentile(x.astype(np.float64), 50) / 1e6)
+    out = {}
+    if offline:
+        out["offline_batch_instructions_per_s"] = offline_rate(ctx, b.subset(np.arange(n_warm, n_warm + n)))
+    return {"requests": int(len(res)), "completed_all": bool(len(res) == n), "failed": failed,
+            "offered_per_s": offered, "offered_target_per_s": rate,
+            "instructions": instr, "served_instructions_per_s": instr / span,
+            "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                           "max": float(lat.max())},
+            "stage_ms_p50": {"wait": med(res["t_admit_ns"] - res["t_submit_ns"]),
+                             "pack": med(res["t_enqueued_ns"] - res["t_admit_ns"]),
+                             "device": med(res["t_device_ns"] - res["t_enqueued_ns"]),
+                             "copy_back": med(res["t_done_ns"] - res["t_device_ns"])},
+            "batches": int(len(np.unique(res["batch"]))), "mean_batch": float(res["batch_kernels"].mean()),
+            "lanes": st["lanes"], **out,
+            "workload": f"{n} log-normal requests (median 1,000 instructions, sigma 1, cap 100k) at Poisson "
+                        f"arrivals after {n_warm} warm-up arrivals"}
+
+
+def offline_rate(ctx, off):
+    """Instructions/s of one dc_analyze_batch run over the same requests."""
+    import torch
+    from paper_2107_07809_amd import dc
+    dev = dc.to_device(off.instrs)
+    stream = torch.cuda.current_stream()
+    bt = ctx.analyze(off.kernels, dev, off.n_instr, off.args, stream=stream)
+    bt.wait()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    bt.run(stream=stream)
+    torch.cuda.synchronize()
+    off_rate = off.n_instr / (time.perf_counter() - t)
+    bt.free()
+    del dev
+    return off_rate
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,6 +200,10 @@ def main():
                     help="run one 1 GiB device copy first (a known-size reference for HBM counters)")
     ap.add_argument("--waves-per-group", type=int, default=0)
     ap.add_argument("--groups-per-cu", type=int, default=0)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-rate", type=float, default=50000.0)
+    ap.add_argument("--serve-seconds", type=float, default=2.0)
+    ap.add_argument("--plain-sample", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -179,8 +295,15 @@ def main():
         "failed_kernels": n_failed,
     }
     batch.free()
-    ctx.close()
+    if args.plain_sample:
+        log(f"plain form: {args.plain_sample} kernels, one launch sequence each")
+        out["plain_per_kernel"] = plain_per_kernel(ctx, b, dev, stream, args.plain_sample)
+        out["plain_per_kernel"]["batched_speedup"] = value / out["plain_per_kernel"]["value"]
     del dev
+    if not args.no_serving:
+        log(f"serving: {args.serve_rate:.0f} requests/s for {args.serve_seconds} s")
+        out["serving"] = serving(ctx, args.serve_rate, args.serve_seconds)
+    ctx.close()
     if not args.no_cpu:
         log("timing the CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(cfg, args.kernels)

@@ -151,7 +151,7 @@ typedef struct dc_batch dc_batch_t;
 dc_status_t dc_ctx_create(int hip_device, dc_ctx_t **out);
 void dc_ctx_destroy(dc_ctx_t *ctx);
 
-/* Steps a1-a4 only (decode and validate, leaders, block numbering, edges,
+/* The graph part only (decode and validate, leaders, block numbering, edges,
  * predecessor CSR, reverse postorder) for n_kernels kernels whose records
  * are in `instrs` (device, n_records entries).  Section "Search for control
  * structures": the control flow graph is built first.  Synchronous w.r.t.
@@ -162,7 +162,7 @@ dc_status_t dc_build_cfg(dc_ctx_t *ctx, const dc_kernel_t *kernels, uint32_t n_k
 dc_status_t dc_cfg_view(dc_cfg_t *cfg, uint32_t k, dc_cfg_view_t *view);
 void dc_cfg_free(dc_cfg_t *cfg);
 
-/* The whole analysis (steps a1-a9) for a batch.  kernels and args are host
+/* The whole analysis (graph, fixpoint, accesses and built-ins) for a batch.  kernels and args are host
  * arrays (copied before return); instrs is device memory.  opts may be NULL.
  * Enqueues on `stream` and returns; results are ready after dc_batch_wait.
  * With DC_OPT_EXPORT_STATES the call synchronises the stream once to size
@@ -201,6 +201,91 @@ typedef struct { uint32_t runs, pad; float ms_total, ms_decode, ms_cfg, ms_fixpo
 dc_status_t dc_get_timing(const dc_batch_t *batch, dc_timing_t *out);
 dc_status_t dc_timing_reset(dc_batch_t *batch);
 void dc_batch_free(dc_batch_t *batch);
+
+/* ------------------------------------------------------------------ */
+/* Request server: continuous batching of single-kernel analyses.       */
+/* ------------------------------------------------------------------ */
+/* The server takes analysis requests one kernel at a time as they arrive
+ * and returns each one's result on its own; the analysis is the same as
+ * dc_analyze_batch's, so a request's result does not depend
+ * on what it was batched with.
+ *
+ * A service thread admits waiting requests into lanes.  A lane is a
+ * preallocated slice of device memory (the arrays of a batch of up to
+ * `lane_instr` instructions and `max_batch_kernels` kernels, the fixpoint
+ * arenas) with pinned host staging and its own HIP stream.  Whenever a lane
+ * is free and requests wait, it takes as many of them as fit it, oldest
+ * first, from one length class, and enqueues the whole analysis.  A batch
+ * is done when its longest kernel is, so requests are batched with others of
+ * similar length: four classes with upper bounds long_instr/16, long_instr/4
+ * and long_instr, the two longer classes holding at most half and a quarter
+ * of the lanes (at least one).  Lanes run concurrently on the device, so requests
+ * that arrive while others are being analysed start as soon as a lane and
+ * its memory free up, and their work overlaps with what is already on the
+ * GPU.  Admission is therefore by device memory: the lanes are carved from
+ * `pool_bytes` when the server is created and nothing is allocated per
+ * request on the device. */
+typedef struct dc_server dc_server_t;
+
+typedef struct {
+    uint64_t pool_bytes;         /* device memory for the lanes; 0 = what `lanes` lanes of the largest size need */
+    uint32_t lanes;              /* concurrent batches in flight (0 = 4; at most 16) */
+    uint32_t max_request_instr;  /* longest request accepted (0 = 100,000 instructions) */
+    uint32_t max_batch_kernels;  /* requests per batch (0 = 2048) */
+    uint32_t long_instr;         /* length class bounds long_instr/16, /4, /1 (0 = 16384) */
+    uint32_t flags;              /* DC_OPT_DIGEST or 0 */
+    uint32_t reserved[3];
+} dc_server_opts_t;
+
+/* One request: a kernel descriptor (instr_begin and arg_begin are ignored),
+ * its n_instr records and n_args argument entries (host memory, copied by
+ * dc_server_submit), and a caller value returned with the result. */
+typedef struct {
+    dc_kernel_t kernel;
+    const dc_instr_t *instrs;
+    const dc_arg_t *args;
+    uint64_t tag;
+} dc_request_t;
+
+/* One completed request.  accesses/sysvals point at summary.n_access and
+ * summary.n_sysval records owned by the server, valid until the next
+ * dc_server_poll or dc_server_destroy.  Times are CLOCK_MONOTONIC
+ * nanoseconds: submission, admission into a lane, its batch's work enqueued
+ * (records packed), the batch's analysis seen complete on the device,
+ * results on the host.
+ * status is the request's per-kernel status, or DC_E_HIP when the device
+ * failed while it was in flight. */
+typedef struct {
+    uint64_t ticket, tag;
+    dc_kernel_result_t summary;
+    const dc_access_t *accesses;
+    const dc_sysval_t *sysvals;
+    uint64_t t_submit_ns, t_admit_ns, t_enqueued_ns, t_device_ns, t_done_ns;
+    uint64_t batch;              /* batch id (admission order) */
+    uint32_t batch_kernels;      /* requests in that batch */
+    uint32_t lane;
+} dc_result_t;
+
+typedef struct {
+    uint64_t submitted, completed, waiting, batches, max_batch_kernels, device_bytes, lane_instr;
+    uint32_t lanes, pad;
+} dc_server_stats_t;
+
+/* Create a server on the context's device and start its service thread.
+ * DC_E_INVAL when an option is out of range or pool_bytes cannot hold the
+ * lanes for max_request_instr; DC_E_OOM when the allocation fails. */
+dc_status_t dc_server_create(dc_ctx_t *ctx, const dc_server_opts_t *opts, dc_server_t **out);
+/* Queue a request (copies it; non-blocking).  *ticket identifies it in the
+ * results.  DC_E_INVAL for a request longer than max_request_instr or null
+ * buffers; DC_E_HIP once the device has failed. */
+dc_status_t dc_server_submit(dc_server_t *srv, const dc_request_t *req, uint64_t *ticket);
+/* Move up to `max` completed results into out[]; *n = how many.  Never
+ * blocks.  Invalidates the record pointers of the previous call. */
+dc_status_t dc_server_poll(dc_server_t *srv, dc_result_t *out, uint32_t max, uint32_t *n);
+dc_status_t dc_server_get_stats(dc_server_t *srv, dc_server_stats_t *out);
+/* Stop admitting, wait for the batches in flight, free everything.
+ * Requests still waiting are dropped. */
+void dc_server_destroy(dc_server_t *srv);
 
 const char *dc_status_str(dc_status_t st);
 int dc_opcode_count(void);

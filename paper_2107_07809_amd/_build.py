@@ -6,9 +6,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdc.so")
-SOURCES = [os.path.join(CSRC, "dc_kernels.hip"), os.path.join(CSRC, "dc_fixpoint.hip"), os.path.join(CSRC, "dc_api.cpp")]
-HEADERS = [os.path.join(CSRC, "dc_internal.h"), os.path.join(CSRC, "dc_isa.h"), os.path.join(CSRC, "dc_device.h"),
-           os.path.join(ROOT, "include", "dc.h")]
+SOURCES = [os.path.join(CSRC, "dc_kernels.hip"), os.path.join(CSRC, "dc_fixpoint.hip"),
+           os.path.join(CSRC, "dc_api.cpp"), os.path.join(CSRC, "dc_server.cpp")]
+HEADERS = [os.path.join(CSRC, "dc_internal.h"), os.path.join(CSRC, "dc_host.h"), os.path.join(CSRC, "dc_isa.h"),
+           os.path.join(CSRC, "dc_device.h"), os.path.join(ROOT, "include", "dc.h")]
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          # no packed fp32 instructions anywhere in the library
@@ -19,7 +20,7 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
 def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = LIB + ".tmp"
-    cmd = [hipcc, *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-o", tmp, *SOURCES]
+    cmd = [hipcc, *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-o", tmp, *SOURCES, "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed:\n" + r.stderr[-4000:])

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "dc.h"
+#include "dc_host.h"
 #include "dc_internal.h"
 
 using namespace dc;
@@ -31,43 +32,7 @@ static const char *const OPCODE_NAMES[N_OPS] = {
     "flat_store_dword", "ds_read_b32", "ds_write_b32",
 };
 
-struct dc_ctx {
-    int device;
-    int n_cu;
-    size_t lds_per_cu;
-    size_t lds_per_group;
-};
-
-/* one device allocation list per object, freed together */
-struct DevMem {
-    std::vector<void *> ptrs;
-    bool failed = false;
-    template <typename T>
-    T *alloc(uint64_t count) {
-        void *p = nullptr;
-        uint64_t bytes = count * sizeof(T);
-        if (bytes == 0) bytes = 16;
-        bytes = (bytes + 255) & ~255ull;
-        if (hipMalloc(&p, bytes) != hipSuccess) {
-            failed = true;
-            return nullptr;
-        }
-        ptrs.push_back(p);
-        return static_cast<T *>(p);
-    }
-    void release(void *p) {
-        auto it = std::find(ptrs.begin(), ptrs.end(), p);
-        if (it != ptrs.end()) {
-            hipFree(p);
-            ptrs.erase(it);
-        }
-    }
-    ~DevMem() {
-        for (void *p : ptrs) hipFree(p);
-    }
-};
-
-/* HIP events per run: start, after a1-a2, after a3-a4, right before and
+/* HIP events per run: start, after decoding, after the graph, right before and
  * right after the main fixpoint launch, end */
 enum { EV_START, EV_DECODE, EV_CFG, EV_FIXB, EV_FIX, EV_END, N_EV };
 constexpr int TIMING_RING = 64;
@@ -152,14 +117,64 @@ extern "C" dc_status_t dc_ctx_create(int hip_device, dc_ctx_t **out) {
 
 extern "C" void dc_ctx_destroy(dc_ctx_t *ctx) { delete ctx; }
 
-/* descriptor checks that need no records (per kernel) */
-static int32_t descriptor_status(const dc_kernel_t &k) {
-    if (k.useargs != 1) return DC_E_UNSUPPORTED;
-    if (k.dims < 1 || k.dims > 3) return DC_E_UNSUPPORTED;
-    for (int d = 0; d < k.dims; d++)
-        if (k.cws[d] == 0) return DC_E_UNSUPPORTED;
-    if (k.n_args > 255) return DC_E_UNSUPPORTED;
-    return DC_OK;
+PlanInputs dc::alloc_plan(DevMem &M, Plan &P, const PlanDims &d) {
+    const uint64_t N = d.N, K = d.K;
+    PlanInputs in;
+    in.kernels = M.alloc<dc_kernel_t>(K);
+    in.args = M.alloc<dc_arg_t>(d.A);
+    in.pos_begin = M.alloc<uint32_t>(K + 1);
+    in.desc_status = M.alloc<int32_t>(K);
+    P.kernels = in.kernels;
+    P.args = in.args;
+    P.pos_begin = in.pos_begin;
+    P.desc_status = in.desc_status;
+    P.leader = M.alloc<uint8_t>(N + 16);
+    P.block_id = M.alloc<uint32_t>(N);
+    P.block_start = M.alloc<uint32_t>(N + 1);
+    P.block_kernel = M.alloc<uint32_t>(N);
+    P.succ = M.alloc<int32_t>(2 * N);
+    P.pred_cnt = M.alloc<uint32_t>(N + 1);
+    P.pred_fill = M.alloc<uint32_t>(N);
+    P.pred = M.alloc<uint32_t>(2 * N);
+    P.rpo = M.alloc<uint32_t>(N);
+    P.rpo_pos = M.alloc<int32_t>(N);
+    P.dfs_stack = M.alloc<uint32_t>(N);
+    P.dfs_seen = M.alloc<uint8_t>(N);
+    P.kbad = M.alloc<uint32_t>(K);
+    P.status = M.alloc<int32_t>(K);
+    P.first_block = M.alloc<uint32_t>(K);
+    P.n_blocks = M.alloc<uint32_t>(K);
+    P.n_reach = M.alloc<uint32_t>(K);
+    P.total_blocks = M.alloc<uint32_t>(4);
+    P.scan_tmp_words = scan_tmp_words_needed(std::max<uint64_t>(N + 1, K + 1));
+    P.scan_tmp = M.alloc<uint32_t>(P.scan_tmp_words);
+    if (d.cfg_only) return in;
+    P.arena_rows = d.arena_rows;
+    P.main_waves = (uint32_t)d.waves;
+    P.arena = M.alloc<uint32_t>(d.waves * d.arena_rows * FIX_ROW_DWORDS);
+    P.ovf_block_cap = 0;
+    P.ovf_rows = 0;
+    P.ovf_waves = 0;
+    P.ovf_arena = nullptr;
+    P.ovf_bitmaps = nullptr;
+    P.dummy = M.alloc<uint4>((d.waves + OVF_MAX_WAVES) * 64);
+    P.ovf_list = M.alloc<uint32_t>(K);
+    P.counters = M.alloc<uint32_t>(4);
+    P.binfo = M.alloc<uint4>(2 * N);
+    P.acc_sparse = M.alloc<dc_access_t>(N);
+    P.sys_sparse = M.alloc<dc_sysval_t>(4 * N);
+    P.blk_acc = M.alloc<uint32_t>(N);
+    P.blk_sys = M.alloc<uint32_t>(N);
+    P.blk_acc_off = M.alloc<uint32_t>(N);
+    P.blk_sys_off = M.alloc<uint32_t>(N);
+    P.results = M.alloc<dc_kernel_result_t>(K);
+    P.acc_count = M.alloc<uint32_t>(K + 1);
+    P.sys_count = M.alloc<uint32_t>(K + 1);
+    P.acc_dense = M.alloc<dc_access_t>(N);
+    P.sys_dense = M.alloc<dc_sysval_t>(4 * N);
+    P.export_states = nullptr;
+    P.export_reached = nullptr;
+    return in;
 }
 
 static dc_status_t plan_batch(dc_batch *B, dc_ctx *ctx, const dc_kernel_t *kernels, uint32_t n_kernels,
@@ -205,34 +220,7 @@ static dc_status_t plan_batch(dc_batch *B, dc_ctx *ctx, const dc_kernel_t *kerne
     P.n_pos = (uint32_t)N;
     P.n_records = n_records;
     P.n_args = n_args_total;
-    dc_kernel_t *d_k = M.alloc<dc_kernel_t>(K);
-    dc_arg_t *d_a = M.alloc<dc_arg_t>(n_args_total);
-    uint32_t *d_pb = M.alloc<uint32_t>(K + 1);
-    int32_t *d_ds = M.alloc<int32_t>(K);
-    P.kernels = d_k;
-    P.args = d_a;
-    P.pos_begin = d_pb;
-    P.desc_status = d_ds;
-    P.leader = M.alloc<uint8_t>(N + 16);
-    P.block_id = M.alloc<uint32_t>(N);
-    P.block_start = M.alloc<uint32_t>(N + 1);
-    P.block_kernel = M.alloc<uint32_t>(N);
-    P.succ = M.alloc<int32_t>(2 * N);
-    P.pred_cnt = M.alloc<uint32_t>(N + 1);
-    P.pred_fill = M.alloc<uint32_t>(N);
-    P.pred = M.alloc<uint32_t>(2 * N);
-    P.rpo = M.alloc<uint32_t>(N);
-    P.rpo_pos = M.alloc<int32_t>(N);
-    P.dfs_stack = M.alloc<uint32_t>(N);
-    P.dfs_seen = M.alloc<uint8_t>(N);
-    P.kbad = M.alloc<uint32_t>(K);
-    P.status = M.alloc<int32_t>(K);
-    P.first_block = M.alloc<uint32_t>(K);
-    P.n_blocks = M.alloc<uint32_t>(K);
-    P.n_reach = M.alloc<uint32_t>(K);
-    P.total_blocks = M.alloc<uint32_t>(4);
-    P.scan_tmp_words = scan_tmp_words_needed(std::max<uint64_t>(N + 1, K + 1));
-    P.scan_tmp = M.alloc<uint32_t>(P.scan_tmp_words);
+    PlanDims dims{N, K, n_args_total, cfg_only, 0, 0};
     if (!cfg_only) {
         const uint32_t wpg = B->opts.waves_per_group;
         /* persistent grid: as many groups per CU as the fixpoint kernel's
@@ -241,39 +229,19 @@ static dc_status_t plan_batch(dc_batch *B, dc_ctx *ctx, const dc_kernel_t *kerne
         if (per_cu == 0) per_cu = fixpoint_groups_per_cu(wpg);
         B->fc.waves_per_group = (int)wpg;
         B->fc.groups = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)ctx->n_cu * per_cu, (K + wpg - 1) / wpg));
-        const uint64_t waves = (uint64_t)B->fc.groups * wpg;
+        dims.waves = (uint64_t)B->fc.groups * wpg;
         /* main pass arena: block_cap blocks of two state rows (kernels with up
          * to 128 named register slots), or fewer blocks of six rows */
-        P.arena_rows = 2 * B->opts.block_cap;
-        P.main_waves = (uint32_t)waves;
-        P.arena = M.alloc<uint32_t>(waves * P.arena_rows * FIX_ROW_DWORDS);
-        /* overflow pass (kernels with more than 2048 blocks or states beyond
-         * the main arena): sized after the first run's CFG stage, from the
-         * real block counts (plan_overflow) */
-        P.ovf_block_cap = 0;
-        P.ovf_rows = 0;
-        P.ovf_waves = 0;
-        P.ovf_arena = nullptr;
-        P.ovf_bitmaps = nullptr;
-        P.dummy = M.alloc<uint4>((waves + OVF_MAX_WAVES) * 64);
-        P.ovf_list = M.alloc<uint32_t>(K);
-        P.counters = M.alloc<uint32_t>(4);
+        dims.arena_rows = 2 * B->opts.block_cap;
+    }
+    const PlanInputs in = alloc_plan(M, P, dims);
+    dc_kernel_t *d_k = in.kernels;
+    dc_arg_t *d_a = in.args;
+    uint32_t *d_pb = in.pos_begin;
+    int32_t *d_ds = in.desc_status;
+    if (!cfg_only) {
         P.sweep_cap = B->opts.sweep_cap;
         P.flags = B->opts.flags;
-        P.binfo = M.alloc<uint4>(2 * N);
-        P.acc_sparse = M.alloc<dc_access_t>(N);
-        P.sys_sparse = M.alloc<dc_sysval_t>(4 * N);
-        P.blk_acc = M.alloc<uint32_t>(N);
-        P.blk_sys = M.alloc<uint32_t>(N);
-        P.blk_acc_off = M.alloc<uint32_t>(N);
-        P.blk_sys_off = M.alloc<uint32_t>(N);
-        P.results = M.alloc<dc_kernel_result_t>(K);
-        P.acc_count = M.alloc<uint32_t>(K + 1);
-        P.sys_count = M.alloc<uint32_t>(K + 1);
-        P.acc_dense = M.alloc<dc_access_t>(N);
-        P.sys_dense = M.alloc<dc_sysval_t>(4 * N);
-        P.export_states = nullptr;
-        P.export_reached = nullptr;
     }
     B->dP = M.alloc<Plan>(1);
     if (M.failed) return DC_E_OOM;

@@ -1,5 +1,5 @@
 /*
- * dc_fixpoint.hip -- steps a5-a9 on gfx950: the register-state fixpoint of
+ * dc_fixpoint.hip -- the analysis proper on gfx950: the register-state fixpoint of
  * every kernel of a batch (Section "Register state analysis" of the paper:
  * a forward pass over the control flow graph that tracks, per register, where
  * its value came from and what type it carries), and the extraction of memory

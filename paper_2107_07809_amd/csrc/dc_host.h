@@ -1,0 +1,90 @@
+/* dc_host.h -- host-side pieces shared by the batch API (dc_api.cpp) and the
+ * request server (dc_server.cpp): the context, device allocation lists, the
+ * descriptor checks and the allocation of a plan's device arrays. */
+#pragma once
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "dc.h"
+#include "dc_internal.h"
+
+struct dc_ctx {
+    int device;
+    int n_cu;
+    size_t lds_per_cu;
+    size_t lds_per_group;
+};
+
+namespace dc {
+
+/* one device allocation list per object, freed together */
+struct DevMem {
+    std::vector<void *> ptrs;
+    bool failed = false;
+    uint64_t bytes_total = 0;
+    template <typename T>
+    T *alloc(uint64_t count) {
+        void *p = nullptr;
+        uint64_t bytes = count * sizeof(T);
+        if (bytes == 0) bytes = 16;
+        bytes = (bytes + 255) & ~255ull;
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            failed = true;
+            return nullptr;
+        }
+        ptrs.push_back(p);
+        bytes_total += bytes;
+        return static_cast<T *>(p);
+    }
+    void release(void *p) {
+        auto it = std::find(ptrs.begin(), ptrs.end(), p);
+        if (it != ptrs.end()) {
+            hipFree(p);
+            ptrs.erase(it);
+        }
+    }
+    DevMem() = default;
+    DevMem(const DevMem &) = delete;
+    DevMem &operator=(const DevMem &) = delete;
+    ~DevMem() {
+        for (void *p : ptrs) hipFree(p);
+    }
+};
+
+/* descriptor checks that need no records (per kernel) */
+inline int32_t descriptor_status(const dc_kernel_t &k) {
+    if (k.useargs != 1) return DC_E_UNSUPPORTED;
+    if (k.dims < 1 || k.dims > 3) return DC_E_UNSUPPORTED;
+    for (int d = 0; d < k.dims; d++)
+        if (k.cws[d] == 0) return DC_E_UNSUPPORTED;
+    if (k.n_args > 255) return DC_E_UNSUPPORTED;
+    return DC_OK;
+}
+
+/* Sizes a plan's device arrays are allocated for: positions, kernels,
+ * argument entries; for an analysis (not CFG-only) also the main-pass waves
+ * and their arena rows. */
+struct PlanDims {
+    uint64_t N, K, A;
+    bool cfg_only;
+    uint64_t waves;
+    uint32_t arena_rows;
+};
+
+/* Device input tables of a plan (the Plan holds them as const pointers). */
+struct PlanInputs {
+    dc_kernel_t *kernels;
+    dc_arg_t *args;
+    uint32_t *pos_begin;
+    int32_t *desc_status;
+};
+
+/* Allocate every device array of P for dims d from M (M.failed on error).
+ * The overflow arena, the state export and the counts in P are left to the
+ * caller. */
+PlanInputs alloc_plan(DevMem &M, Plan &P, const PlanDims &d);
+
+}  // namespace dc

@@ -93,10 +93,10 @@ struct FixCfg {
 /* stage launchers (enqueue only; return hipSuccess or the launch error) */
 hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t *p, uint64_t n, uint8_t v, hipStream_t s);
-hipError_t launch_decode(const Plan &P, hipStream_t s);                 /* a1 + a2 */
-hipError_t launch_number_blocks(const Plan &P, hipStream_t s);          /* a3 */
-hipError_t launch_edges(const Plan &P, hipStream_t s);                  /* a4 (+ statuses) */
-/* a5-a9; dP = device copy of P; optional events bracket the main launch */
+hipError_t launch_decode(const Plan &P, hipStream_t s);                 /* decode, checks, leaders */
+hipError_t launch_number_blocks(const Plan &P, hipStream_t s);          /* block numbering */
+hipError_t launch_edges(const Plan &P, hipStream_t s);                  /* edges, predecessors, RPO, statuses */
+/* entry state, fixpoint, extraction; dP = device copy of P; optional events bracket the main launch */
 hipError_t launch_fixpoint(const Plan &P, const Plan *dP, const FixCfg &c, hipStream_t s, hipEvent_t before,
                            hipEvent_t after);
 hipError_t launch_compact(const Plan &P, hipStream_t s);                /* dense outputs */

@@ -3,16 +3,16 @@
  * dataflow analysis.
  *
  * Stages (all integer work; no MFMA):
- *   a1+a2  k_decode       one thread per instruction: coalesced 16-byte
+ *   decode   k_decode     one thread per instruction: coalesced 16-byte
  *                         record loads, opcode-table lookup, record checks,
  *                         leader flags (textbook basic-block leaders)
- *   a3     k_scan_*       reduce-then-scan of the leader flags over the whole
+ *   number   k_scan_*     reduce-then-scan of the leader flags over the whole
  *                         batch: global block ids, block_start
- *   a4     k_kernel_info, k_edges, k_pred_*, k_order
+ *   graph    k_kernel_info, k_edges, k_pred_*, k_order
  *                         successors, predecessor CSR (count, scan, scatter,
  *                         sort), reverse postorder, per-kernel status
- *   a5-a9  k_fixpoint     in dc_fixpoint.hip
- *   out    k_blk_*, k_finish, k_compact
+ *   fixpoint k_fixpoint   in dc_fixpoint.hip
+ *   out      k_blk_*, k_finish, k_compact
  *                         scans of the per-block record counts, per-kernel
  *                         totals, dense output records in instruction order
  */
@@ -163,7 +163,7 @@ __device__ __forceinline__ uint32_t lookup(const uint32_t *pos_begin, uint32_t K
 }
 
 /* ------------------------------------------------------------------ */
-/* a1 + a2: decode, check, leader flags                                  */
+/* decode, check, leader flags                                          */
 /* ------------------------------------------------------------------ */
 __global__ __launch_bounds__(256) void k_decode(Plan P) {
     __shared__ uint32_t lk[LK_CAP];
@@ -317,7 +317,7 @@ hipError_t scan_excl(const T *in, uint64_t n, uint32_t *out, uint32_t *total_out
 }
 
 /* ------------------------------------------------------------------ */
-/* a3: block numbering                                                   */
+/* block numbering                                                       */
 /* ------------------------------------------------------------------ */
 /* block_id[g] = (exclusive leader count at g) + leader[g] - 1, and for every
  * leader g: block_start[id] = g, block_kernel[id] = kernel of g */
@@ -356,7 +356,7 @@ hipError_t launch_number_blocks(const Plan &P, hipStream_t s) {
 }
 
 /* ------------------------------------------------------------------ */
-/* a4: per-kernel info, edges, predecessors, reverse postorder          */
+/* per-kernel info, edges, predecessors, reverse postorder              */
 /* ------------------------------------------------------------------ */
 constexpr int32_t ST_OK = 0;
 

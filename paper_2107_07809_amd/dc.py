@@ -33,6 +33,11 @@ ACCESS_DTYPE = np.dtype([("instr", "<u4"), ("kind", "u1"), ("space", "u1"), ("wi
 SYSVAL_DTYPE = np.dtype([("instr", "<u4"), ("slot", "<u2"), ("kind", "u1"), ("dim", "u1")])
 RESULT_DTYPE = np.dtype([("status", "<i4"), ("n_blocks", "<u4"), ("sweeps", "<u4"), ("n_access", "<u4"),
                          ("n_sysval", "<u4"), ("pad", "<u4"), ("digest", "<u8")])
+# dc_request_t and dc_result_t of the request server
+REQUEST_DTYPE = np.dtype([("kernel", KERNEL_DTYPE), ("instrs", "<u8"), ("args", "<u8"), ("tag", "<u8")])
+SERVER_RESULT_DTYPE = np.dtype([("ticket", "<u8"), ("tag", "<u8"), ("summary", RESULT_DTYPE), ("accesses", "<u8"),
+                                ("sysvals", "<u8"), ("t_submit_ns", "<u8"), ("t_admit_ns", "<u8"),
+                                ("t_enqueued_ns", "<u8"), ("t_device_ns", "<u8"), ("t_done_ns", "<u8"), ("batch", "<u8"), ("batch_kernels", "<u4"), ("lane", "<u4")])
 
 
 class Options(ctypes.Structure):
@@ -51,6 +56,19 @@ class Stats(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k not in ("pad", "ms_pad")}
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("pool_bytes", ctypes.c_uint64), ("lanes", ctypes.c_uint32), ("max_request_instr", ctypes.c_uint32),
+                ("max_batch_kernels", ctypes.c_uint32), ("long_instr", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 3)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("waiting", ctypes.c_uint64),
+                ("batches", ctypes.c_uint64), ("max_batch_kernels", ctypes.c_uint64),
+                ("device_bytes", ctypes.c_uint64), ("lane_instr", ctypes.c_uint64), ("lanes", ctypes.c_uint32),
+                ("pad", ctypes.c_uint32)]
 
 
 class Timing(ctypes.Structure):
@@ -91,6 +109,11 @@ SIGNATURES = [
     ("dc_get_timing", I32, [VP, ctypes.POINTER(Timing)]),
     ("dc_timing_reset", I32, [VP]),
     ("dc_batch_free", None, [VP]),
+    ("dc_server_create", I32, [VP, ctypes.POINTER(ServerOpts), ctypes.POINTER(VP)]),
+    ("dc_server_submit", I32, [VP, VP, ctypes.POINTER(U64)]),
+    ("dc_server_poll", I32, [VP, VP, U32, ctypes.POINTER(U32)]),
+    ("dc_server_get_stats", I32, [VP, ctypes.POINTER(ServerStats)]),
+    ("dc_server_destroy", None, [VP]),
     ("dc_status_str", ctypes.c_char_p, [I32]),
     ("dc_opcode_count", ctypes.c_int, []),
     ("dc_opcode_name", ctypes.c_char_p, [ctypes.c_int]),
@@ -308,5 +331,81 @@ class Cfg:
     def __del__(self):
         try:
             self.free()
+        except Exception:
+            pass
+
+
+def requests(kernels, instrs, args=None, tags=None) -> np.ndarray:
+    """dc_request_t array for kernels[k] of a packed batch: pointers into
+    `instrs` and `args`, which must stay alive until the requests are
+    submitted (dc_server_submit copies them)."""
+    kernels = np.asarray(kernels, KERNEL_DTYPE)
+    out = np.zeros(len(kernels), REQUEST_DTYPE)
+    out["kernel"] = kernels
+    out["kernel"]["instr_begin"] = 0
+    out["kernel"]["arg_begin"] = 0
+    ib = instrs.ctypes.data if instrs.size else 0
+    ab = args.ctypes.data if args is not None and args.size else 0
+    out["instrs"] = ib + kernels["instr_begin"].astype(np.uint64) * np.uint64(INSTR_DTYPE.itemsize)
+    out["args"] = ab + kernels["arg_begin"].astype(np.uint64) * np.uint64(ARG_DTYPE.itemsize)
+    out["tag"] = np.arange(len(kernels), dtype=np.uint64) if tags is None else tags
+    return out
+
+
+class Server:
+    """dc_server_*: continuous batching of single-kernel requests."""
+
+    def __init__(self, ctx: Context, pool_bytes=0, lanes=0, max_request_instr=0, max_batch_kernels=0,
+                 long_instr=0, flags=0):
+        o = ServerOpts(pool_bytes, lanes, max_request_instr, max_batch_kernels, long_instr, flags)
+        h = VP()
+        check("dc_server_create", lib().dc_server_create(ctx.h, ctypes.byref(o), ctypes.byref(h)))
+        self.h = h
+        self._ticket = U64()
+        self._buf = np.zeros(0, SERVER_RESULT_DTYPE)
+
+    def submit_raw(self, req_addr: int) -> int:
+        """Submit the dc_request_t at host address req_addr; returns its ticket."""
+        check("dc_server_submit", lib().dc_server_submit(self.h, req_addr, ctypes.byref(self._ticket)))
+        return self._ticket.value
+
+    def submit(self, reqs: np.ndarray, i: int) -> int:
+        return self.submit_raw(reqs.ctypes.data + i * REQUEST_DTYPE.itemsize)
+
+    def poll(self, max_results: int = 4096, records: bool = True):
+        """Completed results as a SERVER_RESULT_DTYPE array and, with
+        records=True, a list of (accesses, sysvals) copies per result."""
+        if len(self._buf) < max_results:
+            self._buf = np.zeros(max_results, SERVER_RESULT_DTYPE)
+        n = U32()
+        check("dc_server_poll", lib().dc_server_poll(self.h, self._buf.ctypes.data, max_results, ctypes.byref(n)))
+        res = self._buf[:n.value].copy()
+        if not records:
+            return res, None
+        recs = []
+        for r in res:
+            na, ns = int(r["summary"]["n_access"]), int(r["summary"]["n_sysval"])
+            acc = np.zeros(na, ACCESS_DTYPE)
+            sysv = np.zeros(ns, SYSVAL_DTYPE)
+            if na:
+                ctypes.memmove(acc.ctypes.data, int(r["accesses"]), na * ACCESS_DTYPE.itemsize)
+            if ns:
+                ctypes.memmove(sysv.ctypes.data, int(r["sysvals"]), ns * SYSVAL_DTYPE.itemsize)
+            recs.append((acc, sysv))
+        return res, recs
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        check("dc_server_get_stats", lib().dc_server_get_stats(self.h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in st._fields_ if k != "pad"}
+
+    def close(self):
+        if self.h:
+            lib().dc_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
         except Exception:
             pass

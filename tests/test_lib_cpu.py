@@ -70,6 +70,13 @@ def test_null_arguments(dc):
     L.dc_batch_free(None)
     L.dc_cfg_free(None)
     L.dc_ctx_destroy(None)
+    assert L.dc_server_create(None, None, ctypes.byref(h)) == -1
+    t = ctypes.c_uint64()
+    n = ctypes.c_uint32()
+    assert L.dc_server_submit(None, None, ctypes.byref(t)) == -1
+    assert L.dc_server_poll(None, None, 0, ctypes.byref(n)) == -1
+    assert L.dc_server_get_stats(None, None) == -1
+    L.dc_server_destroy(None)
 
 
 def test_struct_sizes(dc):
@@ -77,3 +84,18 @@ def test_struct_sizes(dc):
     assert dc.REG_DTYPE.itemsize == 16 and dc.ACCESS_DTYPE.itemsize == 16 and dc.SYSVAL_DTYPE.itemsize == 8
     assert dc.RESULT_DTYPE.itemsize == 32 and ctypes.sizeof(dc.Options) == 32
     assert dc.INSTR_DTYPE == dcgen.INSTR_DTYPE and dc.KERNEL_DTYPE == dcgen.KERNEL_DTYPE
+    assert dc.REQUEST_DTYPE.itemsize == 56 and dc.SERVER_RESULT_DTYPE.itemsize == 120
+    assert ctypes.sizeof(dc.ServerOpts) == 40 and ctypes.sizeof(dc.ServerStats) == 64
+
+
+def test_request_pointers(dc):
+    """dc_request_t entries point at each kernel's own records and arguments."""
+    import numpy as np
+    b = dcgen.generate(1, 5)
+    reqs = dc.requests(b.kernels, b.instrs, b.args)
+    for k in range(5):
+        d = b.kernels[k]
+        assert reqs["instrs"][k] == b.instrs.ctypes.data + 16 * int(d["instr_begin"])
+        assert reqs["args"][k] == b.args.ctypes.data + 8 * int(d["arg_begin"])
+        assert reqs["kernel"][k]["instr_begin"] == 0 and reqs["kernel"][k]["n_instr"] == d["n_instr"]
+    assert (reqs["tag"] == np.arange(5)).all()
