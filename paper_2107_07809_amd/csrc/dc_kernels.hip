@@ -497,8 +497,12 @@ __global__ void k_blockinfo(Plan P) {
         const int32_t ps0 = s0 >= 0 ? P.rpo_pos[fb + (uint32_t)s0] : -1;
         const int32_t ps1 = s1 >= 0 ? P.rpo_pos[fb + (uint32_t)s1] : -1;
         /* a successor whose only predecessor is this block continues this
-         * block's visit (its IN state is this block's OUT state) */
-        auto single = [&](int32_t sb) { return sb >= 0 && P.pred_cnt[fb + (uint32_t)sb + 1] - P.pred_cnt[fb + (uint32_t)sb] == 1; };
+         * block's visit (its IN state is this block's OUT state).  The entry
+         * block never does: its IN state also holds the entry state, and a
+         * jump back to it would chain forever. */
+        auto single = [&](int32_t sb) {
+            return sb > 0 && P.pred_cnt[fb + (uint32_t)sb + 1] - P.pred_cnt[fb + (uint32_t)sb] == 1;
+        };
         const uint32_t chain = single(s0) ? 0u : (single(s1) ? 1u : 2u);
         uint4 *dst = P.binfo + 2 * ((uint64_t)fb + (uint32_t)p);
         dst[0] = make_uint4(gb - fb, P.block_start[gb], P.block_start[gb + 1], 0u);

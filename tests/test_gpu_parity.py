@@ -212,6 +212,55 @@ def _rec(name, r0=0xFFFF, r1=0xFFFF, r2=0xFFFF, imm=0, target=-1):
     return x
 
 
+ENTRY_LOOPS = [
+    # the entry block jumps to itself
+    """
+    L0:
+      s_add_u32 s20, s20, 1
+      s_branch L0
+      s_endpgm
+    """,
+    # a cycle through the entry block of blocks with one predecessor each
+    """
+    L0:
+      s_add_u32 s20, s20, 1
+      s_branch L2
+      s_endpgm
+    L2:
+      s_add_u32 s21, s21, s20
+      s_branch L0
+      s_endpgm
+    """,
+    # the taken edge returns to the entry, the fall-through has two predecessors
+    """
+    L0:
+      s_add_u32 s20, s20, 1
+      s_cmp_lt_u32 s20, 10
+      s_cbranch_scc0 L0
+    L1:
+      s_add_u32 s22, s22, s20
+      s_cmp_lt_u32 s22, 5
+      s_cbranch_scc1 L3
+      s_endpgm
+    L3:
+      s_branch L1
+    """,
+]
+
+
+def test_entry_block_loops(ctx):
+    """Kernels whose entry block is its own or a chain's only predecessor: the
+    entry block's IN state joins the entry state with the back edge, so it is
+    never run as a continuation of another block's visit."""
+    ks = []
+    for src in ENTRY_LOOPS:
+        recs = asmtext.assemble(src)
+        ks.append((recs, dcgen.descriptor(len(recs)), np.zeros(0, dcgen.ARG_DTYPE)))
+    b = dcgen.concat(ks + [dcgen.generate(2, 3).kernel(k) for k in range(3)])
+    res = full_compare(ctx, b)
+    assert (res["status"] == 0).all()
+
+
 def test_errors_do_not_poison_batch(ctx):
     """Bad records, bad descriptors and empty kernels mixed with good ones:
     each kernel gets its own status and the good ones are unaffected."""
