@@ -22,6 +22,10 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+# the request server runs one lane per HIP hardware queue (one queue per
+# lane keeps a long batch from holding up another lane's); must be set before
+# the HIP runtime starts
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
 
 METRIC = "instructions analysed/sec to fixpoint (bit-exact) + HBM GB/s fraction; p99 latency"
 HBM_PEAK_GBS = 8000.0
@@ -120,7 +124,7 @@ def serving(ctx, rate, seconds, warm_seconds=0.3, offline=True, **server_opts):
     b = dcgen.generate(5, n_warm + n)
     reqs = dc.requests(b.kernels, b.instrs, b.args)
     due = np.cumsum(np.random.default_rng(0xD1C5A11E).exponential(1.0 / rate, n_warm + n))
-    srv = dc.Server(ctx, **(server_opts or {"lanes": 4}))
+    srv = dc.Server(ctx, **server_opts)
     stride = dc.REQUEST_DTYPE.itemsize
     base = reqs.ctypes.data
     done = []

@@ -229,7 +229,9 @@ typedef struct dc_server dc_server_t;
 
 typedef struct {
     uint64_t pool_bytes;         /* device memory for the lanes; 0 = what `lanes` lanes of the largest size need */
-    uint32_t lanes;              /* concurrent batches in flight (0 = 4; at most 16) */
+    uint32_t lanes;              /* concurrent batches in flight, at most 16; 0 = one less than the process's HIP
+                                    hardware queues (GPU_MAX_HW_QUEUES, HIP's default 4), at most 8: lanes that
+                                    share a hardware queue run in order, so a long batch holds up the other */
     uint32_t max_request_instr;  /* longest request accepted (0 = 100,000 instructions) */
     uint32_t max_batch_kernels;  /* requests per batch (0 = 2048) */
     uint32_t long_instr;         /* length class bounds long_instr/16, /4, /1 (0 = 16384) */

@@ -20,6 +20,7 @@
  * overlaps with them.  Nothing is allocated per request on the device.
  */
 #include <hip/hip_runtime_api.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -412,7 +413,13 @@ extern "C" dc_status_t dc_server_create(dc_ctx_t *ctx, const dc_server_opts_t *o
     *out = nullptr;
     dc_server_opts_t o{};
     if (opts) o = *opts;
-    if (o.lanes == 0) o.lanes = 4;
+    if (o.lanes == 0) {
+        /* lanes that share a hardware queue run in order, so one lane per
+         * queue of the process, leaving one for the caller's own stream */
+        const char *q = getenv("GPU_MAX_HW_QUEUES");
+        const int hwq = std::max(2, q ? atoi(q) : 4);
+        o.lanes = (uint32_t)std::min(8, hwq - 1);
+    }
     if (o.max_request_instr == 0) o.max_request_instr = 100000;
     if (o.max_batch_kernels == 0) o.max_batch_kernels = 2048;
     if (o.long_instr == 0) o.long_instr = 16384;
