@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 # the request server runs one lane per HIP hardware queue (one queue per
 # lane keeps a long batch from holding up another lane's); must be set before
 # the HIP runtime starts
-os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
+os.environ["GPU_MAX_HW_QUEUES"] = "16"
 
 METRIC = "instructions analysed/sec to fixpoint (bit-exact) + HBM GB/s fraction; p99 latency"
 HBM_PEAK_GBS = 8000.0

@@ -794,8 +794,7 @@ __device__ __forceinline__ void run_chunk(const Plan *__restrict__ P, WaveLds &L
     const bool live = (alu && prule != PR_TOP && prule != PR_NONE && ((o0 >> 32) & FT_T)) ||
                       (alu && prule != PR_TOP && prule != PR_NONE && I.ndef == 2 && ((o1 >> 32) & FT_T)) || via;
     uint32_t dv0lo = 0xFFFFFFFFu, dv0hi = 0xFFFFFFFFu, dv1lo = 0xFFFFFFFFu, dv1hi = 0xFFFFFFFFu;
-    uint64_t lm = ballot(live);
-    if (lm) {
+    if (ballot(live)) {
         const uint32_t xq[5] = {I.ia & 0xFFFFu, I.ia >> 16, I.ib & 0xFFFFu, I.ib >> 16, I.ic & 0xFFFFu};
         const uint32_t kq[5] = {I.ka0, I.ka1, I.kb0, I.kb1, I.kc0};
         uint32_t svlo[5], svhi[5], sd[5];
@@ -811,17 +810,38 @@ __device__ __forceinline__ void run_chunk(const Plan *__restrict__ P, WaveLds &L
             /* source mode: 0 sv, 1 register of lane pl (k = 0 / 1 in bit 7), 2 LDS entry x */
             sd[q] = def && k < 2 ? (1u << 16) | pl | k << 7 : (def && k < 4 ? (2u << 16) | x : 0u);
         }
+        /* A move whose source dwords are not definitions of this chunk
+         * (block state, constant) takes its payload now, outside the loop.
+         * Each lane also records which sources its rule reads (bit q of the
+         * mask for source q), so the loop fetches only those. */
+        const uint32_t m0 = sd[0] >> 16, m1 = sd[1] >> 16;
+        const bool wide = I.ndef >= 2;
+        const bool mv = live && prule == PR_MOV && m0 == 0u && (!wide || m1 == 0u);
+        dv0lo = mv ? svlo[0] : dv0lo;
+        dv0hi = mv ? svhi[0] : dv0hi;
+        dv1lo = mv && wide ? svlo[1] : dv1lo;
+        dv1hi = mv && wide ? svhi[1] : dv1hi;
+        const uint32_t rr = cls == C_SMEM ? PR_SMEM : prule;
+        const uint32_t need = rr == PR_MOV || rr == PR_SMEM ? 0x03u
+                              : rr == PR_MAD24 ? 0x15u
+                              : (rr == PR_AND64 || rr == PR_OR64 || rr == PR_XOR64 || rr == PR_ANDN264) ? 0x0Fu
+                              : rr == PR_SHL64 ? 0x0Du : 0x05u;
+        sd[0] |= need << 18;
         __builtin_amdgcn_wave_barrier();
+        uint64_t lm = ballot(live && !mv);
         while (lm) {
             const uint32_t i = (uint32_t)__builtin_ctzll(lm);
             lm &= lm - 1;
             const uint64_t ei = ((uint64_t)rdl(I.ehi, i) << 32) | rdl(I.elo, i);
             const uint32_t ci = e_cls(ei), wi = e_width(ei, 0);
             uint64_t vq[5];
+            const uint32_t nd = rdl(sd[0], i) >> 18;
 #pragma unroll
             for (int q = 0; q < 5; q++) {
+                vq[q] = VTOP;
+                if (!((nd >> q) & 1u)) continue;
                 const uint32_t d = rdl(sd[q], i);
-                const uint32_t mode = d >> 16;
+                const uint32_t mode = (d >> 16) & 3u;
                 if (mode == 1) {
                     const uint32_t pl = d & 63u;
                     vq[q] = (d & 128u) ? ((uint64_t)rdl(dv1hi, pl) << 32) | rdl(dv1lo, pl)
@@ -856,6 +876,7 @@ __device__ __forceinline__ void run_chunk(const Plan *__restrict__ P, WaveLds &L
         }
         L.fv[IX_DEF + l] = ((uint64_t)dv0hi << 32) | dv0lo;
         L.fv[IX_DEF + 64 + l] = ((uint64_t)dv1hi << 32) | dv1lo;
+        __builtin_amdgcn_wave_barrier();
     }
     __builtin_amdgcn_wave_barrier();
 
@@ -1232,7 +1253,7 @@ __device__ __forceinline__ void fail_kernel(const Plan *__restrict__ P, uint32_t
  * and whose IN states fit the wave's arena; the others are queued for the
  * overflow pass, which keeps its bitmaps in HBM and has a larger arena. */
 template <bool OVF>
-__global__ __launch_bounds__(256) void k_fixpoint(const Plan *__restrict__ P, uint32_t wpg) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_fixpoint(const Plan *__restrict__ P, uint32_t wpg) {
     extern __shared__ uint4 smem[];
     const uint32_t w = rfl(threadIdx.x >> 6), l = lane_id();
     WaveLds &L = reinterpret_cast<WaveLds *>(smem)[w];

@@ -261,6 +261,64 @@ def test_entry_block_loops(ctx):
     assert (res["status"] == 0).all()
 
 
+MOVE_CHAINS = """
+  s_load_dwordx4 s[8:11], s[4:5], 0x30
+  s_load_dwordx2 s[2:3], s[4:5], 0x0
+  s_mul_i32 s0, s6, 64
+  v_add_co_u32 v1, vcc, s0, v0
+  s_mov_b64 s[20:21], s[8:9]
+  s_mov_b64 s[22:23], s[20:21]
+  s_mov_b32 s24, s23
+  s_mov_b32 s25, s22
+  s_mov_b64 s[26:27], s[24:25]
+  s_mov_b64 s[28:29], s[10:11]
+  s_mov_b32 s30, 5
+  s_mov_b32 s31, s30
+  v_mov_b32 v2, v1
+  v_mov_b32 v3, v2
+  v_mov_b32 v4, 0
+  v_mov_b32 v5, v4
+  v_lshlrev_b64 v[6:7], 2, v[3:4]
+  v_mov_b32 v8, v6
+  v_mov_b32 v9, v7
+  v_add_co_u32 v10, vcc, s22, v8
+  v_mov_b32 v20, s26
+  v_mov_b32 v12, v20
+  v_addc_co_u32 v11, vcc, v12, v9, vcc
+  global_load_dword v14, v[10:11], off
+  v_mov_b32 v15, v10
+  v_mov_b32 v16, v11
+  global_store_dword v[15:16], v14, off
+  s_mov_b64 s[32:33], s[2:3]
+  s_mov_b32 s34, s32
+  v_mov_b32 v17, s34
+  v_add_co_u32 v18, vcc, v17, v1
+  v_mov_b32 v19, v18
+  s_endpgm
+"""
+
+
+def test_move_chains(ctx):
+    """Chains of moves: of pairs whose halves come from different
+    definitions, of wide SMEM dwords, of constants, of moves of moves, and
+    the same chains split across 64-instruction chunks."""
+    recs = asmtext.assemble(MOVE_CHAINS)
+    pad = asmtext.assemble("\n".join(["  s_nop"] * 40 + ["  s_endpgm"]))[:-1]
+    ks = [(recs, dcgen.descriptor(len(recs), n_args=2), None)]
+    for cut in (5, 13, 17, 25):
+        r2 = np.concatenate([recs[:cut], pad, recs[cut:]])
+        ks.append((r2, dcgen.descriptor(len(r2), n_args=2), None))
+    args = np.zeros(2, dcgen.ARG_DTYPE)
+    args["offset"] = [0x30, 0x38]
+    args["size"] = 8
+    args["type"] = 16
+    args["flags"] = [4, 2]
+    b = dcgen.concat([(r, d, args) for r, d, _ in ks])
+    res = full_compare(ctx, b)
+    assert (res["status"] == 0).all()
+    assert (res["n_access"] == 2).all()
+
+
 def test_errors_do_not_poison_batch(ctx):
     """Bad records, bad descriptors and empty kernels mixed with good ones:
     each kernel gets its own status and the good ones are unaffected."""
