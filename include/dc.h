@@ -123,7 +123,9 @@ typedef struct {
     uint32_t waves_per_group;    /* fixpoint kernel: waves per workgroup, at most 4 and within the device's LDS
                                     per workgroup (0 = the most that fit, up to 4) */
     uint32_t groups_per_cu;      /* fixpoint kernel: resident workgroups per CU in the persistent grid (0 = auto) */
-    uint32_t block_cap;          /* blocks a kernel may have in the main pass (0 = 256); larger go to the overflow pass */
+    uint32_t block_cap;          /* blocks (of two state rows) a kernel may have in the main pass; larger go to the
+                                    overflow pass.  0 = sized on the first run to the largest kernel of at most 2048
+                                    blocks, within 8 GB and a quarter of the free device memory */
     uint32_t reserved[3];
 } dc_options_t;
 

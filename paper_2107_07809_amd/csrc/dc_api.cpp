@@ -56,6 +56,7 @@ struct dc_batch {
     uint64_t runs = 0, runs_at_reset = 0;   /* enqueued runs; ring slot = run % TIMING_RING */
     uint64_t export_blocks = 0;
     bool ovf_planned = false;   /* the overflow pass is sized from the first run's block counts */
+    bool auto_arena = false;    /* no block cap given: the main arena grows to the largest kernel */
     /* host copies, filled on first use after a run */
     bool host_valid = false;
     std::vector<dc_kernel_result_t> results;
@@ -192,6 +193,7 @@ static dc_status_t plan_batch(dc_batch *B, dc_ctx *ctx, const dc_kernel_t *kerne
     if (B->opts.waves_per_group == 0)
         B->opts.waves_per_group = (uint32_t)std::max<size_t>(1, std::min<size_t>(4, ctx->lds_per_group / lds_wave));
     if (B->opts.waves_per_group > 4 || B->opts.waves_per_group * lds_wave > ctx->lds_per_group) return DC_E_INVAL;
+    B->auto_arena = B->opts.block_cap == 0;
     if (B->opts.block_cap == 0) B->opts.block_cap = 256;
     if (B->opts.block_cap > 2048) return DC_E_INVAL;   /* the main pass keeps its bitmaps in one VGPR */
     B->K = n_kernels;
@@ -266,11 +268,14 @@ static dc_status_t plan_batch(dc_batch *B, dc_ctx *ctx, const dc_kernel_t *kerne
     return DC_OK;
 }
 
-/* Overflow pass sizing from the block counts of the CFG stage just enqueued
- * (waits for the stream).  A kernel whose state width is not known yet may
- * need up to FIX_MAX_ROWS rows per block; the pass gets up to OVF_MAX_WAVES
- * waves within an 8 GB arena budget.  A later run whose kernels have more
- * blocks than planned reports DC_E_UNSUPPORTED for those kernels. */
+/* Arena sizing from the block counts of the CFG stage just enqueued (waits
+ * for the stream).  A kernel whose state width is not known yet may need up
+ * to FIX_MAX_ROWS rows per block.  Without an explicit block cap the main
+ * pass's arenas grow to hold the largest kernel it can take (at most 2048
+ * blocks), within ARENA_BUDGET and a quarter of the free device memory; the
+ * kernels that still do not fit go to the overflow pass, which gets up to
+ * OVF_MAX_WAVES waves within the same budget.  A later run whose kernels
+ * have more blocks than planned reports DC_E_UNSUPPORTED for those kernels. */
 static hipError_t plan_overflow(dc_batch *B, hipStream_t s) {
     Plan &P = B->P;
     std::vector<uint32_t> nb(B->K);
@@ -278,6 +283,22 @@ static hipError_t plan_overflow(dc_batch *B, hipStream_t s) {
     if (B->K) e = hipMemcpyAsync(nb.data(), P.n_blocks, B->K * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return e;
+    const uint64_t row_bytes = FIX_ROW_DWORDS * 4ull;
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = 0;
+    const uint64_t budget = std::min<uint64_t>(ARENA_BUDGET, free_b / 4);
+    if (B->auto_arena) {
+        uint64_t need = 0;
+        for (uint32_t x : nb)
+            if (x <= 2048) need = std::max<uint64_t>(need, (uint64_t)x * FIX_MAX_ROWS);
+        const uint64_t rows = std::min<uint64_t>(need, budget / ((uint64_t)P.main_waves * row_bytes));
+        if (rows > P.arena_rows) {
+            B->mem.release(P.arena);
+            P.arena = B->mem.alloc<uint32_t>((uint64_t)P.main_waves * rows * FIX_ROW_DWORDS);
+            if (B->mem.failed) return hipErrorOutOfMemory;
+            P.arena_rows = (uint32_t)rows;
+        }
+    }
     uint64_t cap = 1, n_ovf = 0;
     for (uint32_t x : nb) {
         if (x > 2048 || (uint64_t)x * FIX_MAX_ROWS > P.arena_rows) {
@@ -285,9 +306,8 @@ static hipError_t plan_overflow(dc_batch *B, hipStream_t s) {
             cap = std::max<uint64_t>(cap, x);
         }
     }
-    uint64_t waves = std::max<uint64_t>(1, std::min<uint64_t>(OVF_MAX_WAVES, n_ovf));
-    const uint64_t row_bytes = FIX_ROW_DWORDS * 4ull, budget = 8ull << 30;
-    while (waves > 1 && waves * cap * FIX_MAX_ROWS * row_bytes > budget) waves--;
+    const uint64_t fit = budget / (cap * FIX_MAX_ROWS * row_bytes);
+    const uint64_t waves = std::max<uint64_t>(1, std::min<uint64_t>({(uint64_t)OVF_MAX_WAVES, n_ovf, fit}));
     P.ovf_block_cap = (uint32_t)cap;
     P.ovf_rows = (uint32_t)(cap * FIX_MAX_ROWS);
     P.ovf_waves = (uint32_t)waves;

@@ -104,7 +104,8 @@ uint32_t fixpoint_groups_per_cu(uint32_t waves_per_group);              /* resid
 size_t fixpoint_lds_per_wave();                                         /* LDS bytes per fixpoint wavefront */
 constexpr uint32_t FIX_ROW_DWORDS = 192;                                /* arena dwords per state row */
 constexpr uint32_t FIX_MAX_ROWS = 6;                                    /* state rows of the largest kernel */
-constexpr uint32_t OVF_MAX_WAVES = 64;                                  /* waves of the overflow pass */
+constexpr uint32_t OVF_MAX_WAVES = 512;                                 /* waves of the overflow pass */
+constexpr uint64_t ARENA_BUDGET = 8ull << 30;                           /* arena bytes of either pass */
 uint64_t scan_tmp_words_needed(uint64_t n);
 
 }  // namespace dc
