@@ -193,6 +193,69 @@ def offline_rate(ctx, off):
     return off_rate
 
 
+def timed_batch(ctx, b, stream, reps=1):
+    """Plan once (untimed, with its first run), then time `reps` whole runs
+    with the records resident in HBM."""
+    import torch
+    from paper_2107_07809_amd import dc
+    dev = dc.to_device(b.instrs)
+    bt = ctx.analyze(b.kernels, dev, b.n_instr, b.args, flags=dc.OPT_TIMING, stream=stream)
+    bt.wait()
+    res = bt.results()
+    st = bt.stats()
+    bt.timing_reset()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        bt.run(stream=stream)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / reps
+    tm = bt.timing()
+    bt.free()
+    del dev
+    torch.cuda.empty_cache()
+    return dt, tm["ms_fixpoint"] / max(1, tm["runs"]), res, st
+
+
+def other_workloads(ctx, stream, c3_slices=8):
+    """The other configurations, each timed as whole-path runs with its
+    records in HBM: the 16 kernels of 1-4M instructions; the 1,048,576-kernel
+    Zipf workload in slices of 131,072 kernels (one plan per slice, the
+    slices' run times summed); the 32-kernel workload batched and as one
+    launch sequence per kernel."""
+    import dcgen
+    out = {}
+    b = dcgen.generate(4, 16)
+    dt, fix, res, st = timed_batch(ctx, b, stream)
+    out["c4_16_kernels_1M_to_4M"] = {"instructions": int(b.n_instr), "seconds": dt, "instructions_per_s": b.n_instr / dt,
+                                     "sweeps_max": st["sweeps_max"], "blocks_max": int(res["n_blocks"].max()),
+                                     "failed": int((res["status"] != 0).sum()),
+                                     "form": "one wavefront per kernel (overflow pass)"}
+    log("workloads: 16 huge kernels done")
+    per = 1048576 // c3_slices
+    tot_s = tot_i = fail = 0
+    for k in range(c3_slices):
+        b = dcgen.generate(3, per, i0=k * per)
+        dt, fix, res, st = timed_batch(ctx, b, stream)
+        tot_s += dt
+        tot_i += int(b.n_instr)
+        fail += int((res["status"] != 0).sum())
+        log(f"workloads: Zipf slice {k + 1}/{c3_slices}: {b.n_instr} instructions in {dt * 1e3:.1f} ms")
+    out["c3_zipf_1048576_kernels"] = {"instructions": tot_i, "seconds": tot_s, "instructions_per_s": tot_i / tot_s,
+                                      "failed": fail, "form": f"{c3_slices} slices of {per} kernels, batched persistent"}
+    b = dcgen.generate(1, 32)
+    dt, fix, res, st = timed_batch(ctx, b, stream, reps=20)
+    plain = plain_per_kernel(ctx, b, dc_dev(b), stream, 32)
+    out["c1_32_kernels"] = {"instructions": int(b.n_instr), "batched_instructions_per_s": b.n_instr / dt,
+                            "plain_instructions_per_s": plain["value"], "batched_ms": dt * 1e3}
+    return out
+
+
+def dc_dev(b):
+    from paper_2107_07809_amd import dc
+    return dc.to_device(b.instrs)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -208,6 +271,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=50000.0)
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--plain-sample", type=int, default=256)
+    ap.add_argument("--workloads", action="store_true",
+                    help="also time the 16 huge kernels, the 1,048,576-kernel Zipf workload and the 32-kernel one")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -304,6 +369,8 @@ def main():
         out["plain_per_kernel"] = plain_per_kernel(ctx, b, dev, stream, args.plain_sample)
         out["plain_per_kernel"]["batched_speedup"] = value / out["plain_per_kernel"]["value"]
     del dev
+    if args.workloads:
+        out["workloads"] = other_workloads(ctx, stream)
     if not args.no_serving:
         log(f"serving: {args.serve_rate:.0f} requests/s for {args.serve_seconds} s")
         out["serving"] = serving(ctx, args.serve_rate, args.serve_seconds)
