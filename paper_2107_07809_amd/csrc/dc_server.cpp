@@ -376,6 +376,9 @@ void service(dc_server *S) {
                 S->max_batch = std::max<uint64_t>(S->max_batch, L->reqs.size());
             }
             if (launch(S, *L) != hipSuccess) {
+                /* the lane's requests fail with the rest */
+                hipStreamSynchronize(L->s);
+                publish(S, *L, true);
                 fail_all(S);
                 break;
             }

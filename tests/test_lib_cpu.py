@@ -99,3 +99,14 @@ def test_request_pointers(dc):
         assert reqs["args"][k] == b.args.ctypes.data + 8 * int(d["arg_begin"])
         assert reqs["kernel"][k]["instr_begin"] == 0 and reqs["kernel"][k]["n_instr"] == d["n_instr"]
     assert (reqs["tag"] == np.arange(5)).all()
+
+
+def test_bench_refuses_several_gpus():
+    """The bench measures one GPU; asking for more prints why and exits 2."""
+    import json
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
