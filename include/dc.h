@@ -117,6 +117,9 @@ typedef struct {
 #define DC_OPT_EXPORT_STATES 1u  /* keep every block's fixpoint IN state for dc_get_block_state */
 #define DC_OPT_DIGEST 2u         /* compute the per-kernel digest of the fixpoint states */
 #define DC_OPT_TIMING 4u         /* record HIP events around the stages (dc_get_stats ms_*) */
+#define DC_OPT_GRAPH 8u          /* dc_batch_run replays the stages as one captured HIP graph (from the second run
+                                    on; not with DC_OPT_EXPORT_STATES or DC_OPT_TIMING, nor on the NULL stream,
+                                    where runs stay eager) */
 typedef struct {
     uint32_t flags;
     uint32_t sweep_cap;          /* 0 = 64 + 2 * n_blocks per kernel */

@@ -57,6 +57,7 @@ struct dc_batch {
     uint64_t export_blocks = 0;
     bool ovf_planned = false;   /* the overflow pass is sized from the first run's block counts */
     bool auto_arena = false;    /* no block cap given: the main arena grows to the largest kernel */
+    hipGraphExec_t graph = nullptr;   /* DC_OPT_GRAPH: the stages captured on the second run */
     /* host copies, filled on first use after a run */
     bool host_valid = false;
     std::vector<dc_kernel_result_t> results;
@@ -187,7 +188,8 @@ static dc_status_t plan_batch(dc_batch *B, dc_ctx *ctx, const dc_kernel_t *kerne
     B->stream = (hipStream_t)stream;
     B->cfg_only = cfg_only;
     if (opts) B->opts = *opts;
-    if (B->opts.flags & ~(DC_OPT_EXPORT_STATES | DC_OPT_DIGEST | DC_OPT_TIMING)) return DC_E_INVAL;
+    if (B->opts.flags & ~(DC_OPT_EXPORT_STATES | DC_OPT_DIGEST | DC_OPT_TIMING | DC_OPT_GRAPH)) return DC_E_INVAL;
+    if ((B->opts.flags & DC_OPT_GRAPH) && (B->opts.flags & (DC_OPT_EXPORT_STATES | DC_OPT_TIMING))) return DC_E_INVAL;
     /* waves per group: the fixpoint kernel's LDS per wave must fit a group */
     const size_t lds_wave = fixpoint_lds_per_wave();
     if (B->opts.waves_per_group == 0)
@@ -318,11 +320,51 @@ static hipError_t plan_overflow(dc_batch *B, hipStream_t s) {
     return hipSuccess;
 }
 
+/* every stage of an analysis run, enqueued on s (no host synchronisation) */
+static hipError_t enqueue_stages(dc_batch *B, hipStream_t s) {
+    const Plan &P = B->P;
+    hipError_t e = launch_fill_u8(P.leader, B->N, 0, s);
+    if (e == hipSuccess) e = launch_fill_u32(P.kbad, B->K, 0xFFFFFFFFu, s);
+    if (e == hipSuccess) e = launch_decode(P, s);
+    if (e == hipSuccess) e = launch_number_blocks(P, s);
+    if (e == hipSuccess) e = launch_edges(P, s);
+    if (e == hipSuccess) e = launch_fixpoint(P, B->dP, B->fc, s, nullptr, nullptr);
+    if (e == hipSuccess) e = launch_compact(P, s);
+    return e;
+}
+
+/* DC_OPT_GRAPH runs after the first: capture the stages once, replay */
+static dc_status_t enqueue_graph(dc_batch *B) {
+    hipStream_t s = B->stream;
+    if (!B->graph) {
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e);
+        const hipError_t es = enqueue_stages(B, s);
+        e = hipStreamEndCapture(s, &g);
+        if (es != hipSuccess || e != hipSuccess) {
+            if (g) hipGraphDestroy(g);
+            return hip_fail(es != hipSuccess ? es : e);
+        }
+        e = hipGraphInstantiate(&B->graph, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            B->graph = nullptr;
+            return hip_fail(e);
+        }
+    }
+    const hipError_t e = hipGraphLaunch(B->graph, s);
+    if (e != hipSuccess) return hip_fail(e);
+    B->runs++;
+    return DC_OK;
+}
+
 static dc_status_t enqueue(dc_batch *B) {
     Plan &P = B->P;
     hipStream_t s = B->stream;
     hipError_t e = hipSuccess;
     B->host_valid = false;
+    if ((B->opts.flags & DC_OPT_GRAPH) && B->ovf_planned && !B->cfg_only && s) return enqueue_graph(B);
     hipEvent_t *ev = B->ev[B->runs % TIMING_RING];
 #define TRY(x)                                  \
     do {                                        \
@@ -406,6 +448,11 @@ extern "C" dc_status_t dc_batch_run(dc_batch_t *B, const dc_instr_t *instrs, voi
     B->stream = (hipStream_t)stream;
     if (instrs && instrs != B->P.instrs) {
         B->P.instrs = instrs;
+        if (B->graph) {   /* the captured launches hold the old plan */
+            if (hipStreamSynchronize(B->stream) != hipSuccess) return DC_E_HIP;
+            hipGraphExecDestroy(B->graph);
+            B->graph = nullptr;
+        }
         if (hipMemcpyAsync(B->dP, &B->P, sizeof(Plan), hipMemcpyHostToDevice, B->stream) != hipSuccess) return DC_E_HIP;
         if (hipStreamSynchronize(B->stream) != hipSuccess) return DC_E_HIP;
     }
@@ -632,6 +679,7 @@ extern "C" void dc_batch_free(dc_batch_t *B) {
     if (B->have_events)
         for (int r = 0; r < TIMING_RING; r++)
             for (int i = 0; i < N_EV; i++) hipEventDestroy(B->ev[r][i]);
+    if (B->graph) hipGraphExecDestroy(B->graph);
     delete B;
 }
 

@@ -7,6 +7,7 @@ records and the fixpoint IN state of every block must match byte for byte
 import glob
 import os
 import sys
+import time
 
 import numpy as np
 import pytest
@@ -412,3 +413,43 @@ def test_single_and_alone_vs_batch(ctx):
         assert b1.accesses(0).tobytes() == batch.accesses(k).tobytes()
         b1.free()
     batch.free()
+
+
+def test_graph_replays_match_eager(ctx):
+    """DC_OPT_GRAPH: the stages captured once and replayed give the eager
+    results on every replay, with eager work on the same stream between the
+    replays (a second batch's runs and a torch operation)."""
+    b = dcgen.generate(2, 1500, i0=3000)
+    dev = dc.to_device(b.instrs)
+    stream = torch.cuda.Stream()
+    eager = ctx.analyze(b.kernels, dev, b.n_instr, b.args, flags=dc.OPT_DIGEST, stream=stream)
+    ref = (eager.results(), eager.all_accesses()[0], eager.all_sysvals()[0])
+    g = ctx.analyze(b.kernels, dev, b.n_instr, b.args, flags=dc.OPT_DIGEST | dc.OPT_GRAPH, stream=stream)
+    x = torch.ones(1 << 20, device="cuda")
+    for rep in range(5):
+        g.run(stream=stream)
+        got = (g.results(), g.all_accesses()[0], g.all_sysvals()[0])
+        assert got[0].tobytes() == ref[0].tobytes(), rep
+        assert got[1].tobytes() == ref[1].tobytes(), rep
+        assert got[2].tobytes() == ref[2].tobytes(), rep
+        eager.run(stream=stream)
+        with torch.cuda.stream(stream):
+            x.mul_(1.0001)
+        eager.wait()
+    # small batches are launch-bound: replaying the graph saves the launches
+    s1 = dcgen.generate(1, 32)
+    dev1 = dc.to_device(s1.instrs)
+    times = {}
+    for name, fl in (("eager", 0), ("graph", dc.OPT_GRAPH)):
+        bt = ctx.analyze(s1.kernels, dev1, s1.n_instr, s1.args, flags=fl, stream=stream)
+        bt.run(stream=stream)
+        bt.wait()
+        t = time.perf_counter()
+        for _ in range(50):
+            bt.run(stream=stream)
+        bt.wait()
+        times[name] = (time.perf_counter() - t) / 50 * 1e3
+        bt.free()
+    say(f"32-kernel batch: eager {times['eager']:.3f} ms, graph {times['graph']:.3f} ms per run")
+    g.free()
+    eager.free()
