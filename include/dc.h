@@ -84,8 +84,12 @@ typedef struct { uint32_t offset; uint16_t size; uint8_t type, flags; } dc_arg_t
 #define DC_TY_DOUBLE 8
 #define DC_TY_PTR 16
 
-/* Abstract value of one register slot (16 bytes): provenance bits, type
- * bits, payload (see the design doc for the bit layouts). */
+/* Abstract value of one register slot (16 bytes): provenance bits (where
+ * the value came from: local, group and global-offset ids per dimension,
+ * sizes, the argument pointer, constants, loads, kernel arguments), type
+ * bits (DC_TY_*), and the payload: bits 63:60 tag, 59:58 dword of a 64-bit
+ * value, 57:56 dimension, 55:52 id-term mask or built-in kind, 51:48 shift,
+ * 47:40 argument slot, 31:0 constant; all ones = unknown (TOP). */
 typedef struct { uint32_t prov; uint8_t type, flags, pad0, pad1; uint64_t val; } dc_reg_state_t;
 
 /* A memory access (16 bytes): instruction index, kind (0 load, 1 store),

@@ -8,8 +8,10 @@ wrapper.
 
 Parity: pinned by tests/test_oracle_*.py (the paper's worked statements,
 textbook basic blocks, meet-over-all-paths for the distributive tiers,
-schedule independence, lattice laws).  The payload tier beyond those pins is
-"parity unpinned" except for the invariants listed in the design doc.
+schedule independence, lattice laws).  The payload tier beyond the paper's
+printed cases is "parity unpinned": only invariants pin it (monotone rules,
+meet over all paths below the fixpoint, schedule independence, constant
+folding in closed form), since the paper prints no further values.
 """
 from __future__ import annotations
 

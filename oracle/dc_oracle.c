@@ -22,8 +22,10 @@
  *   - at a block with several predecessors a register whose incoming values
  *     differ becomes ambiguous (Section "Search for control structures",
  *     paragraph on vertices with several ancestors): the payload joins to TOP.
- * The rule tables that make these passages exact are this build's reading
- * of the paper and are listed in the design doc.
+ * The rule tables below make these passages exact.  Where the paper leaves a
+ * choice open (record format, argument-area offsets, the order of id terms,
+ * carries, float results) they take one reading throughout; the tests under
+ * tests/ pin each one.
  *
  * Everything here is deliberately simple: full 368-slot states, plain loops,
  * no blocking.  The reference schedule is round-robin in reverse postorder
