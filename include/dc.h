@@ -179,6 +179,16 @@ void dc_cfg_free(dc_cfg_t *cfg);
 dc_status_t dc_analyze_batch(dc_ctx_t *ctx, const dc_kernel_t *kernels, uint32_t n_kernels, const dc_instr_t *instrs,
                              uint64_t n_records, const dc_arg_t *args, uint64_t n_args_total,
                              const dc_options_t *opts, void *stream, dc_batch_t **out);
+/* Launch-shape autotuner.  Times whole runs of a sample of the batch
+ * (every stride-th kernel, at most `sample` kernels; 0 = 8192) under a few
+ * fixpoint launch shapes -- waves per workgroup 1, 2 and the most that fit,
+ * each with the most resident groups per CU and three quarters of that --
+ * and writes the fastest shape into *best (the other fields are copied from
+ * base, which may be NULL) and its time per run into *best_ms.  Synchronous;
+ * allocates and frees its own trial batches. */
+dc_status_t dc_autotune(dc_ctx_t *ctx, const dc_kernel_t *kernels, uint32_t n_kernels, const dc_instr_t *instrs,
+                        uint64_t n_records, const dc_arg_t *args, uint64_t n_args_total, const dc_options_t *base,
+                        uint32_t sample, void *stream, dc_options_t *best, float *best_ms);
 /* Run the same batch again on `instrs` (same layout; NULL = the previous
  * pointer).  Results are overwritten.  Allocates nothing. */
 dc_status_t dc_batch_run(dc_batch_t *batch, const dc_instr_t *instrs, void *stream);

@@ -442,6 +442,56 @@ extern "C" dc_status_t dc_analyze_batch(dc_ctx_t *ctx, const dc_kernel_t *kernel
     return DC_OK;
 }
 
+extern "C" dc_status_t dc_autotune(dc_ctx_t *ctx, const dc_kernel_t *kernels, uint32_t n_kernels,
+                                   const dc_instr_t *instrs, uint64_t n_records, const dc_arg_t *args,
+                                   uint64_t n_args_total, const dc_options_t *base, uint32_t sample, void *stream,
+                                   dc_options_t *best, float *best_ms) {
+    if (!ctx || !best || !best_ms || (n_kernels && !kernels)) return DC_E_INVAL;
+    if (base && (base->flags & DC_OPT_GRAPH)) return DC_E_INVAL;
+    if (sample == 0) sample = 8192;
+    const uint32_t stride = std::max<uint32_t>(1, (n_kernels + sample - 1) / sample);
+    std::vector<dc_kernel_t> ks;
+    for (uint32_t k = 0; k < n_kernels; k += stride) ks.push_back(kernels[k]);
+    const size_t lds_wave = fixpoint_lds_per_wave();
+    const uint32_t wmax = (uint32_t)std::max<size_t>(1, std::min<size_t>(4, ctx->lds_per_group / lds_wave));
+    std::vector<std::pair<uint32_t, uint32_t>> shapes;
+    for (uint32_t w : {1u, 2u, wmax}) {
+        if (w > wmax || std::find_if(shapes.begin(), shapes.end(), [&](auto &x) { return x.first == w; }) != shapes.end())
+            continue;
+        const uint32_t pc = fixpoint_groups_per_cu(w);
+        shapes.push_back({w, pc});
+        if ((pc * 3 + 3) / 4 != pc) shapes.push_back({w, (pc * 3 + 3) / 4});
+    }
+    dc_options_t o{};
+    if (base) o = *base;
+    o.flags = (o.flags & ~DC_OPT_EXPORT_STATES) | DC_OPT_TIMING;
+    float best_t = -1.0f;
+    for (auto [w, pc] : shapes) {
+        o.waves_per_group = w;
+        o.groups_per_cu = pc;
+        dc_batch_t *B = nullptr;
+        dc_status_t st = dc_analyze_batch(ctx, ks.data(), (uint32_t)ks.size(), instrs, n_records, args, n_args_total,
+                                          &o, stream, &B);
+        if (st != DC_OK) return st;
+        dc_timing_t t{};
+        st = dc_batch_wait(B);
+        if (st == DC_OK) st = dc_timing_reset(B);
+        for (int r = 0; r < 3 && st == DC_OK; r++) st = dc_batch_run(B, nullptr, stream);
+        if (st == DC_OK) st = dc_get_timing(B, &t);
+        dc_batch_free(B);
+        if (st != DC_OK) return st;
+        const float ms = t.runs ? t.ms_total / t.runs : 0.0f;
+        if (best_t < 0.0f || ms < best_t) {
+            best_t = ms;
+            *best = base ? *base : dc_options_t{};
+            best->waves_per_group = w;
+            best->groups_per_cu = pc;
+        }
+    }
+    *best_ms = best_t;
+    return DC_OK;
+}
+
 extern "C" dc_status_t dc_batch_run(dc_batch_t *B, const dc_instr_t *instrs, void *stream) {
     if (!B || B->cfg_only) return DC_E_INVAL;
     if (hipSetDevice(B->ctx->device) != hipSuccess) return DC_E_HIP;

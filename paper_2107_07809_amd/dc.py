@@ -96,6 +96,8 @@ SIGNATURES = [
     ("dc_cfg_free", None, [VP]),
     ("dc_analyze_batch", I32, [VP, VP, U32, VP, U64, VP, U64, ctypes.POINTER(Options), VP, ctypes.POINTER(VP)]),
     ("dc_batch_run", I32, [VP, VP, VP]),
+    ("dc_autotune", I32, [VP, VP, U32, VP, U64, VP, U64, ctypes.POINTER(Options), U32, VP, ctypes.POINTER(Options),
+                          ctypes.POINTER(ctypes.c_float)]),
     ("dc_batch_wait", I32, [VP]),
     ("dc_get_kernel_status", I32, [VP, U32, ctypes.POINTER(I32)]),
     ("dc_get_kernel_result", I32, [VP, U32, VP]),
@@ -206,6 +208,19 @@ class Context:
                                                          n_records, _np_ptr(args), len(args), ctypes.byref(o),
                                                          _stream_ptr(stream), ctypes.byref(h)))
         return Batch(h, len(kernels), instrs_dev, stream)
+
+    def autotune(self, kernels, instrs_dev, n_records, args=None, flags=0, sample=0, stream=None):
+        """Fastest fixpoint launch shape on a sample of the batch:
+        (dict of options for analyze(), ms per run of the sample)."""
+        kernels = np.ascontiguousarray(np.asarray(kernels, KERNEL_DTYPE))
+        args = np.ascontiguousarray(np.asarray(args if args is not None else np.zeros(0, ARG_DTYPE), ARG_DTYPE))
+        base = Options(flags, 0, 0, 0, 0)
+        best = Options()
+        ms = ctypes.c_float()
+        check("dc_autotune", lib().dc_autotune(self.h, _np_ptr(kernels), len(kernels), _dev_ptr(instrs_dev), n_records,
+                                               _np_ptr(args), len(args), ctypes.byref(base), sample,
+                                               _stream_ptr(stream), ctypes.byref(best), ctypes.byref(ms)))
+        return {"waves_per_group": best.waves_per_group, "groups_per_cu": best.groups_per_cu}, ms.value
 
     def build_cfg(self, kernels, instrs_dev, n_records, stream=None) -> "Cfg":
         kernels = np.ascontiguousarray(np.asarray(kernels, KERNEL_DTYPE))

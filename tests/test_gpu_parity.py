@@ -453,3 +453,20 @@ def test_graph_replays_match_eager(ctx):
     say(f"32-kernel batch: eager {times['eager']:.3f} ms, graph {times['graph']:.3f} ms per run")
     g.free()
     eager.free()
+
+
+def test_autotune_shape_gives_same_results(ctx):
+    """The autotuner's launch shape for a Zipf sample is a valid shape and
+    gives byte-identical results to the default shape."""
+    b = dcgen.generate(3, 20000, i0=7000)
+    dev = dc.to_device(b.instrs)
+    shape, ms = ctx.autotune(b.kernels, dev, b.n_instr, b.args, flags=dc.OPT_DIGEST, sample=4096)
+    say(f"autotune: {shape}, {ms:.3f} ms per run of the sample")
+    assert 1 <= shape["waves_per_group"] <= 4 and shape["groups_per_cu"] >= 1 and ms > 0
+    ref = ctx.analyze(b.kernels, dev, b.n_instr, b.args, flags=dc.OPT_DIGEST)
+    tuned = ctx.analyze(b.kernels, dev, b.n_instr, b.args, flags=dc.OPT_DIGEST, **shape)
+    assert tuned.results().tobytes() == ref.results().tobytes()
+    assert tuned.all_accesses()[0].tobytes() == ref.all_accesses()[0].tobytes()
+    assert tuned.all_sysvals()[0].tobytes() == ref.all_sysvals()[0].tobytes()
+    tuned.free()
+    ref.free()
