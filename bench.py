@@ -267,6 +267,8 @@ def main():
                     help="run one 1 GiB device copy first (a known-size reference for HBM counters)")
     ap.add_argument("--waves-per-group", type=int, default=0)
     ap.add_argument("--groups-per-cu", type=int, default=0)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the library's default launch shape instead of dc_autotune's (also when a shape is given)")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-rate", type=float, default=50000.0)
     ap.add_argument("--serve-seconds", type=float, default=2.0)
@@ -295,8 +297,14 @@ def main():
         del src, dst
         log("copy calibration: 1 GiB device-to-device copy done")
     ctx = dc.Context(0)
-    batch = ctx.analyze(b.kernels, dev, b.n_instr, b.args, flags=dc.OPT_TIMING,
-                        waves_per_group=args.waves_per_group, groups_per_cu=args.groups_per_cu, stream=stream)
+    shape = {"waves_per_group": args.waves_per_group, "groups_per_cu": args.groups_per_cu}
+    tuned = False
+    if not args.no_autotune and not (args.waves_per_group or args.groups_per_cu):
+        # launch shape from the autotuner on a sample (outside the timed region)
+        shape, tune_ms = ctx.autotune(b.kernels, dev, b.n_instr, b.args, sample=8192, stream=stream)
+        tuned = True
+        log(f"autotune: {shape} ({tune_ms:.2f} ms per run of the sample)")
+    batch = ctx.analyze(b.kernels, dev, b.n_instr, b.args, flags=dc.OPT_TIMING, stream=stream, **shape)
     for _ in range(max(0, args.warmup - 1)):
         batch.run(stream=stream)
     batch.wait()
@@ -351,7 +359,8 @@ def main():
         "config": {"workload": "65,536 seeded synthetic GCN kernels, lengths log-uniform on [200, 2000], nested "
                                "exec-mask if/else and counted loops to depth 3, ~18% float ALU",
                    "kernels": b.n_kernels, "instructions": b.n_instr, "record_bytes": 16 * b.n_instr,
-                   "form": "batched persistent (one wavefront per kernel)"},
+                   "form": "batched persistent (one wavefront per kernel)",
+                   "launch": {**shape, "autotuned": tuned}},
         "roofline": {"bound": "hbm", "kernel": "k_fixpoint", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "alg_bytes_per_launch": alg_bytes, "traffic_bytes_per_launch": traffic_bytes,
