@@ -174,6 +174,19 @@ def test_c3_zipf_65536(ctx):
         _records_and_summaries(ctx, b, summ, oacc, osys, flags, digest, "c3 65536")
 
 
+def test_c5_lognormal_65536(ctx):
+    """The first 65,536 kernels of the log-normal workload (median 1,000
+    instructions, cap 100k; about 108M instructions), with the main-pass
+    arenas sized on the first run: every record, status, sweep count and
+    digest."""
+    n = 65536
+    b = dcgen.generate(5, n)
+    say("c5 65536: generated", b.n_instr)
+    summ, oacc, osys = oracle_config(5, n)
+    say("c5 65536: oracle done")
+    _records_and_summaries(ctx, b, summ, oacc, osys, dc.OPT_DIGEST, True, "c5 65536")
+
+
 def test_c4_very_large(ctx):
     """All 16 kernels of 1-4M instructions (up to ~17k blocks, which take
     the overflow pass with global-memory bitmaps), alone and interleaved with
