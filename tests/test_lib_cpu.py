@@ -77,6 +77,10 @@ def test_null_arguments(dc):
     assert L.dc_server_poll(None, None, 0, ctypes.byref(n)) == -1
     assert L.dc_server_get_stats(None, None) == -1
     L.dc_server_destroy(None)
+    best = dc.Options()
+    ms = ctypes.c_float()
+    assert L.dc_autotune(None, None, 0, None, 0, None, 0, None, 0, None, ctypes.byref(best), ctypes.byref(ms)) == -1
+    assert L.dc_autotune(None, None, 0, None, 0, None, 0, None, 0, None, None, None) == -1
 
 
 def test_struct_sizes(dc):
