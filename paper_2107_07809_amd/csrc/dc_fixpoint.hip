@@ -734,6 +734,31 @@ __device__ __forceinline__ void run_chunk(const Plan *__restrict__ P, WaveLds &L
     const uint32_t prule = alu && I.ndef ? e_prule(e) : PR_TOP;
     const uint32_t trule = e_trule(e), suffix = e_suffix(e), vsrc = e_vsrc(e);
     const uint32_t mbit = e_maskdef(e) ? 1u << PB_MASK : 0u;
+    /* Each lane's type and liveness rules as masks, so that the passes are
+     * straight-line code.  Types: the union of the A and/or B source types,
+     * masked, plus the suffix type (a move copies each dword's type).
+     * Liveness: the result may be other than TOP (T) and other than TOP and
+     * uninitialised (N) when the sources in needT carry T and those in needN
+     * carry N (bits: A0 1, A1 2, B0 4, B1 8, C0 16; 32 = never); a move copies
+     * its source's bits; `both` gives dword 1 the same liveness. */
+    const bool tadd = trule == TR_ADD, tbu = trule == TR_B, tmove = trule == TR_MOVE;
+    const bool selA = tadd || (tbu && (vsrc & 1u)), selB = tadd || (tbu && (vsrc & 2u));
+    const uint32_t tmask = tadd ? TY_P : (tbu ? 31u : 0u);
+    const uint32_t tsuf = (trule == TR_SUF || tadd) ? suffix : 0u;
+    uint32_t needT = 32u, needN = 0u;
+    bool both = false;
+    switch (prule) {
+    case PR_SEL: needT = 5u; break;
+    case PR_ADD: case PR_ADDC: case PR_SUB: case PR_AND: case PR_OR: case PR_XOR: case PR_MUL: case PR_MUL24:
+    case PR_SHL: case PR_LSHR: case PR_ASHR:
+        needT = 0u; needN = 5u;
+        break;
+    case PR_MAD24: needT = 0u; needN = 21u; break;
+    case PR_AND64: case PR_OR64: case PR_XOR64: case PR_ANDN264: needT = 0u; needN = 15u; both = true; break;
+    case PR_SHL64: needT = 0u; needN = 13u; both = true; break;
+    default: break;
+    }
+    const bool lmov = prule == PR_MOV;
     uint64_t o0 = fpt_pack(0, 0, FT_T | FT_N), o1 = o0, o4 = fpt_pack(0, 0, 0);
     for (;;) {
         const uint64_t xa0 = L.fpt[I.ia & 0xFFFFu], xa1 = L.fpt[I.ia >> 16];
@@ -744,35 +769,20 @@ __device__ __forceinline__ void run_chunk(const Plan *__restrict__ P, WaveLds &L
         const uint64_t xs = L.fpt[I.isd & 0xFFFFu];
         const uint32_t rp = fpt_prov(xa0) | fpt_prov(xa1) | fpt_prov(xb0) | fpt_prov(xb1) | fpt_prov(xc0) |
                             fpt_prov(xc1) | fpt_prov(xv0) | fpt_prov(xv1) | fpt_prov(xe0) | fpt_prov(xe1) | fpt_prov(xs);
-        const uint32_t ta0 = fpt_type(xa0), ta1 = fpt_type(xa1), tb0 = fpt_type(xb0), tb1 = fpt_type(xb1);
-        uint32_t ty0 = 0, ty1 = 0;
-        switch (trule) {
-        case TR_SUF: ty0 = ty1 = suffix; break;
-        case TR_ADD: ty0 = ty1 = suffix | ((ta0 | ta1 | tb0 | tb1) & TY_P); break;
-        case TR_B: ty0 = ty1 = ((vsrc & 1u) ? ta0 | ta1 : 0u) | ((vsrc & 2u) ? tb0 | tb1 : 0u); break;
-        case TR_MOVE: ty0 = ta0; ty1 = ta1; break;
-        default: break;
-        }
+        const uint32_t ha0 = (uint32_t)(xa0 >> 32), ha1 = (uint32_t)(xa1 >> 32);
+        const uint32_t hb0 = (uint32_t)(xb0 >> 32), hb1 = (uint32_t)(xb1 >> 32), hc0 = (uint32_t)(xc0 >> 32);
+        const uint32_t ta0 = ha0 & 31u, ta1 = ha1 & 31u, tb0 = hb0 & 31u, tb1 = hb1 & 31u;
+        const uint32_t un = (selA ? ta0 | ta1 : 0u) | (selB ? tb0 | tb1 : 0u);
+        const uint32_t tyc = tsuf | (un & tmask);
+        const uint32_t ty0 = tmove ? ta0 : tyc, ty1 = tmove ? ta1 : tyc;
         /* liveness of the payload rule's result (TOP in, TOP out) */
-        uint32_t lv0 = 0, lv1 = 0;
-        const bool na0 = fpt_n(xa0), na1 = fpt_n(xa1), nb0 = fpt_n(xb0), nb1 = fpt_n(xb1), nc0 = fpt_n(xc0);
-        switch (prule) {
-        case PR_MOV:
-            lv0 = (fpt_t(xa0) ? FT_T : 0u) | (na0 ? FT_N : 0u);
-            lv1 = (fpt_t(xa1) ? FT_T : 0u) | (na1 ? FT_N : 0u);
-            break;
-        case PR_SEL: lv0 = fpt_t(xa0) && fpt_t(xb0) ? FT_T | FT_N : 0u; break;
-        case PR_ADD: case PR_ADDC: case PR_SUB: case PR_AND: case PR_OR: case PR_XOR: case PR_MUL: case PR_MUL24:
-        case PR_SHL: case PR_LSHR: case PR_ASHR:
-            lv0 = na0 && nb0 ? FT_T | FT_N : 0u;
-            break;
-        case PR_MAD24: lv0 = na0 && nb0 && nc0 ? FT_T | FT_N : 0u; break;
-        case PR_AND64: case PR_OR64: case PR_XOR64: case PR_ANDN264:
-            lv0 = lv1 = na0 && na1 && nb0 && nb1 ? FT_T | FT_N : 0u;
-            break;
-        case PR_SHL64: lv0 = lv1 = na0 && nb0 && nb1 ? FT_T | FT_N : 0u; break;
-        default: break;
-        }
+        const uint32_t tbits = ((ha0 & FT_T) >> 5) | ((ha1 & FT_T) >> 4) | ((hb0 & FT_T) >> 3) | ((hb1 & FT_T) >> 2) |
+                               ((hc0 & FT_T) >> 1);
+        const uint32_t nbits = ((ha0 & FT_N) >> 6) | ((ha1 & FT_N) >> 5) | ((hb0 & FT_N) >> 4) | ((hb1 & FT_N) >> 3) |
+                               ((hc0 & FT_N) >> 2);
+        const uint32_t lvx = ((tbits & needT) == needT && (nbits & needN) == needN) ? FT_T | FT_N : 0u;
+        const uint32_t lv0 = lmov ? (ha0 & (FT_T | FT_N)) : lvx;
+        const uint32_t lv1 = lmov ? (ha1 & (FT_T | FT_N)) : (both ? lvx : 0u);
         const uint32_t pe = rp | mbit;
         const uint64_t n0 = fpt_pack(pe, ty0, lv0), n1 = fpt_pack(pe, ty1, lv1), n4 = fpt_pack(rp | (1u << PB_MASK), 0, 0);
         L.fpt[alu && I.ndef >= 1 ? IX_DEF + l : tscr] = n0;
