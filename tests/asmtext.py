@@ -96,11 +96,11 @@ def assemble(text: str):
         elif name.startswith("v_cmp"):
             r1, r2 = src(ops[1]), src(ops[2])       # first operand is vcc
         elif name.startswith(("global_load", "flat_load")):
-            r0, r1 = reg(ops[0]), reg(ops[1])
+            r0, r1 = reg(ops[0]), reg(ops[1].split()[0])
             r2 = dcgen.NONE if len(ops) < 3 or ops[2].split()[0] == "off" else reg(ops[2].split()[0])
             imm = _offset(s)
         elif name.startswith(("global_store", "flat_store")):
-            r1, r0 = reg(ops[0]), reg(ops[1])
+            r1, r0 = reg(ops[0]), reg(ops[1].split()[0])
             r2 = dcgen.NONE if len(ops) < 3 or ops[2].split()[0] == "off" else reg(ops[2].split()[0])
             imm = _offset(s)
         elif name == "ds_read_b32":
