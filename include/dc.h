@@ -171,11 +171,24 @@ dc_status_t dc_build_cfg(dc_ctx_t *ctx, const dc_kernel_t *kernels, uint32_t n_k
 dc_status_t dc_cfg_view(dc_cfg_t *cfg, uint32_t k, dc_cfg_view_t *view);
 void dc_cfg_free(dc_cfg_t *cfg);
 
-/* The whole analysis (graph, fixpoint, accesses and built-ins) for a batch.  kernels and args are host
- * arrays (copied before return); instrs is device memory.  opts may be NULL.
- * Enqueues on `stream` and returns; results are ready after dc_batch_wait.
- * With DC_OPT_EXPORT_STATES the call synchronises the stream once to size
- * the state export. */
+/* The whole analysis for a batch: steps 2 and 3 of Section "Statement of
+ * the problem" (registers and kernel parameters initialised from the ABI,
+ * then instruction processing that builds the control flow graph and
+ * determines what every register holds) solved to the least fixpoint over
+ * the graph, with the searches of Section "Search for memory accesses"
+ * (array accesses, work-item built-ins) and the types of Section "Data type
+ * recovery" (.arg lines of Listing 3, instruction suffixes).
+ * kernels (n_kernels descriptors) and args (n_args_total entries) are host
+ * arrays, copied before return; instrs is device memory holding n_records
+ * records, which must stay alive and unchanged until the batch is freed.
+ * opts may be NULL (defaults).  Plans the batch (allocates its device
+ * memory), enqueues the first run on `stream` and returns; the first run
+ * synchronises the stream once, after the graph stage, to size the
+ * block-indexed arrays and the fixpoint arenas from the real block counts.
+ * Results are ready after dc_batch_wait.  Errors: DC_E_INVAL (null pointer,
+ * a descriptor's records or arguments outside the arrays, more than 2^32-16
+ * instructions), DC_E_OOM, DC_E_HIP; per-kernel problems are per-kernel
+ * statuses. */
 dc_status_t dc_analyze_batch(dc_ctx_t *ctx, const dc_kernel_t *kernels, uint32_t n_kernels, const dc_instr_t *instrs,
                              uint64_t n_records, const dc_arg_t *args, uint64_t n_args_total,
                              const dc_options_t *opts, void *stream, dc_batch_t **out);
@@ -198,8 +211,20 @@ dc_status_t dc_get_kernel_status(const dc_batch_t *batch, uint32_t k, dc_status_
 dc_status_t dc_get_kernel_result(const dc_batch_t *batch, uint32_t k, dc_kernel_result_t *out);
 /* All n_kernels summaries into out[cap]. */
 dc_status_t dc_get_results(const dc_batch_t *batch, dc_kernel_result_t *out, uint32_t cap);
-/* Two-call idiom: always sets *n_total, copies min(cap, n_total) records. */
+/* Memory accesses of kernel k (Section "Search for memory accesses": array
+ * element accesses recognised from the address arithmetic), one record per
+ * reachable global/flat/LDS instruction in instruction order, the address
+ * resolved from the fixpoint state before it.  Two-call idiom: always sets
+ * *n_total, copies min(cap, n_total) records into buf (host).  Waits for the
+ * batch.  DC_E_INVAL for k out of range or a null n_total (or a null buf
+ * with cap > 0).  A failed kernel has no records. */
 dc_status_t dc_get_accesses(const dc_batch_t *batch, uint32_t k, dc_access_t *buf, uint32_t cap, uint32_t *n_total);
+/* Work-item built-ins of kernel k (Section "Search for memory accesses":
+ * get_global_id and its idx0 form, get_global_offset, get_global_size,
+ * get_num_groups, get_work_dim, get_local_id, get_group_id and the
+ * group-id-times-size term), one record per register definition whose value
+ * is one of them, ordered by (instruction, register).  Same conventions as
+ * dc_get_accesses. */
 dc_status_t dc_get_sysvals(const dc_batch_t *batch, uint32_t k, dc_sysval_t *buf, uint32_t cap, uint32_t *n_total);
 /* Every kernel's records packed in kernel order; offsets (n_kernels + 1
  * entries, may be NULL) give each kernel's range. */
@@ -207,7 +232,14 @@ dc_status_t dc_get_all_accesses(const dc_batch_t *batch, dc_access_t *buf, uint6
                                 uint64_t *offsets);
 dc_status_t dc_get_all_sysvals(const dc_batch_t *batch, dc_sysval_t *buf, uint64_t cap, uint64_t *n_total,
                                uint64_t *offsets);
-/* Fixpoint IN state of one block (needs DC_OPT_EXPORT_STATES). */
+/* Fixpoint IN state of one block: for each of the 368 register slots the
+ * paper's Register record (Section "Search for memory accesses": type and
+ * integrity, here with the value's provenance and payload) and its type bits
+ * (Section "Data type recovery").  out368 (host) receives DC_NSLOT entries;
+ * *reached (may be NULL) = 1 when the block is reachable (an unreachable
+ * block's state is all zero).  Needs DC_OPT_EXPORT_STATES (else
+ * DC_E_NOTREADY); DC_E_INVAL for k or block out of range or a failed
+ * kernel. */
 dc_status_t dc_get_block_state(const dc_batch_t *batch, uint32_t k, uint32_t block, dc_reg_state_t *out368,
                                uint8_t *reached);
 dc_status_t dc_get_stats(const dc_batch_t *batch, dc_stats_t *out);

@@ -1,10 +1,11 @@
 /*
  * dc_fixpoint.hip -- the analysis proper on gfx950: the register-state fixpoint of
- * every kernel of a batch (Section "Register state analysis" of the paper:
- * a forward pass over the control flow graph that tracks, per register, where
- * its value came from and what type it carries), and the extraction of memory
- * accesses (Section "The body extraction") and work-item built-ins (Section
- * "Work-item built-in functions").
+ * every kernel of a batch (Section "Statement of the problem", steps 2 and 3:
+ * registers initialised from the ABI, then instruction processing over the
+ * control flow graph that determines, per register, where its value came from
+ * and what type it carries), and the extraction of memory accesses and
+ * work-item built-ins (Section "Search for memory accesses") with the types of
+ * Section "Data type recovery".
  *
  * Layout of the work.  A persistent grid; one wavefront takes one kernel at a
  * time from an atomic counter.  Per kernel:
@@ -111,8 +112,9 @@ __device__ __forceinline__ int lg2(uint32_t x) {
     return (x != 0 && (x & (x - 1)) == 0) ? (int)__builtin_ctz(x) : -1;
 }
 
-/* ---- payload rules (Section "Register state analysis": index arithmetic,
- *      pointer formation from an argument base plus a scaled index) ---- */
+/* ---- payload rules (Section "Search for memory accesses": the global id
+ *      composed from group id, work-group size, local id and offset; array
+ *      accesses as an argument base plus a scaled index) ---- */
 __device__ uint64_t r_add1(uint64_t a, uint64_t b) {
     const uint32_t ta = v_tag(a), tb = v_tag(b);
     if (is_c(a) && is_c(b)) return C32(v_c(a) + v_c(b));
@@ -235,7 +237,8 @@ __device__ __forceinline__ void arg_dword(const KCtx &K, uint32_t o, uint32_t &p
     val = VTOP;
 }
 
-/* recognised work-item built-ins (Section "Work-item built-in functions");
+/* recognised work-item built-ins (the list in Section "Search for memory
+ * accesses");
  * returns the DC_SV_* kind or -1 */
 __device__ __forceinline__ int builtin_kind(uint64_t v, uint32_t &dim) {
     if (v == VTOP) return -1;
@@ -259,7 +262,7 @@ __device__ __forceinline__ int builtin_kind(uint64_t v, uint32_t &dim) {
     return -1;
 }
 
-/* ABI entry state of slot j (Section "Register state analysis": s[4:5] the
+/* ABI entry state of slot j (Section "Search for memory accesses": s[4:5] the
  * argument pointer, s6.. group ids, v0.. local ids, exec the launch mask,
  * every other register uninitialised), as (prov, type, payload lo, hi) */
 __device__ __forceinline__ uint4 entry_slot(uint32_t j, uint32_t dims) {

@@ -96,6 +96,21 @@ def test_golden_fixtures(ctx):
     batch.free()
 
 
+
+def test_hand_written_kernels(ctx):
+    """Every hand-written rule kernel of the oracle's CPU pins (folding with
+    edge and random constants, 64-bit shifts up to 63, inline floats, the
+    argument-area table with hidden slots, mid-argument and spanning loads
+    and a clobbered s4, index and pointer rules, uninitialised sources, the
+    second dimension, loops and an entry-block back edge), in one batch:
+    every state byte, record and digest against the oracle."""
+    import hand_kernels as hk
+    ks = hk.all_kernels()
+    say(f"hand-written kernels: {len(ks)}")
+    b = dcgen.concat([k for _, k in ks])
+    res = full_compare(ctx, b)
+    assert (res["status"] == 0).all(), [ks[i][0] for i in np.nonzero(res["status"])[0]]
+
 def test_c2_subset_states(ctx):
     """Ragged lengths 200-2000 with loops: 600 kernels, states byte-exact
     (including kernels that use the full register range)."""

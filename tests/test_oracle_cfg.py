@@ -112,15 +112,8 @@ def test_c1_shape():
 def test_branch_to_entry_and_unreachable():
     """A back edge into block 0 and code after s_endpgm that nothing targets."""
     import asmtext
-    recs = asmtext.assemble("""
-    L0:
-      s_add_u32 s20, s20, 1
-      s_cmp_lt_u32 s20, 10
-      s_cbranch_scc1 L0
-      s_endpgm
-      v_mov_b32 v3, 1
-      s_endpgm
-    """)
+    import hand_kernels as hk
+    recs = asmtext.assemble(hk.ENTRY_AND_UNREACHABLE)
     d = dcgen.descriptor(len(recs))
     res = oracle.analyze(recs, d, np.zeros(0, dcgen.ARG_DTYPE))
     assert res["status"] == 0

@@ -18,6 +18,7 @@ import numpy as np
 import pytest
 
 import asmtext
+import hand_kernels as hk
 import dcgen
 import oracle
 
@@ -78,50 +79,7 @@ def test_mop_acyclic_c1():
         check_mop(res, mop)
 
 
-LOOPS = [
-    # a loop around a diamond; values flow around the back edge
-    """
-      s_mov_b32 s20, 0
-      v_mov_b32 v5, 0
-    HEAD:
-      v_cmp_gt_u32 vcc, v0, s20
-      s_and_saveexec_b64 s[24:25], vcc
-      s_cbranch_execz ELSE
-      v_add_co_u32 v5, vcc, v5, v0
-      v_mov_b32 v7, s6
-      s_branch END
-    ELSE:
-      v_mov_b32 v6, v5
-      s_load_dword s12, s[4:5], 0xc
-    END:
-      s_or_b64 exec, exec, s[24:25]
-      v_mov_b32 v8, v6
-      s_add_u32 s20, s20, 1
-      s_cmp_lt_u32 s20, 16
-      s_cbranch_scc1 HEAD
-      global_store_dword v[2:3], v8, off
-      s_endpgm
-    """,
-    # nested loops with a rotating chain of copies (bits need several trips)
-    """
-      s_mov_b32 s21, 0
-    OUTER:
-      s_mov_b32 s20, 0
-    INNER:
-      v_mov_b32 v9, v8
-      v_mov_b32 v8, v7
-      v_mov_b32 v7, v6
-      v_mov_b32 v6, v0
-      s_add_u32 s20, s20, 1
-      s_cmp_lt_u32 s20, 4
-      s_cbranch_scc1 INNER
-      s_mov_b32 s13, s7
-      s_add_u32 s21, s21, 1
-      s_cmp_lt_u32 s21, 4
-      s_cbranch_scc1 OUTER
-      s_endpgm
-    """,
-]
+LOOPS = hk.LOOPS
 
 
 @pytest.mark.parametrize("src", LOOPS)
@@ -187,14 +145,7 @@ def test_acyclic_converges_in_one_sweep():
 def test_straight_line_is_sequential():
     """One block: IN[0] is the entry state and the extraction walks the
     records in order (sequential evaluation)."""
-    recs = asmtext.assemble("""
-      s_load_dwordx2 s[2:3], s[4:5], 0x0
-      s_mul_i32 s0, s6, 64
-      v_add_co_u32 v1, vcc, s0, v0
-      v_add_co_u32 v1, vcc, s2, v1
-      v_mov_b32 v9, v1
-      s_endpgm
-    """)
+    recs = asmtext.assemble(hk.STRAIGHT_GLOBAL_ID)
     d = dcgen.descriptor(len(recs))
     res = oracle.analyze(recs, d, np.zeros(0, dcgen.ARG_DTYPE))
     assert res["n_blocks"] == 1

@@ -10,6 +10,7 @@ from hypothesis import given, settings, strategies as st
 
 import asmtext
 import dcgen
+import hand_kernels as hk
 import oracle
 
 TOP = oracle.TOP
@@ -35,25 +36,7 @@ U32 = st.integers(0, 2 ** 32 - 1)
 @settings(max_examples=60, deadline=None)
 @given(U32, U32)
 def test_fold_scalar(x, y):
-    src = f"""
-      s_mov_b32 s1, {x:#x}
-      s_mov_b32 s2, {y:#x}
-      s_add_u32 s3, s1, s2
-      s_sub_u32 s10, s1, s2
-      s_mul_i32 s11, s1, s2
-      s_and_b32 s12, s1, s2
-      s_or_b32 s13, s1, s2
-      s_lshl_b32 s14, s1, s2
-      s_lshr_b32 s15, s1, s2
-      v_xor_b32 v3, s1, s2
-      v_mul_u32_u24 v4, s1, s2
-      v_lshlrev_b32 v5, s2, s1
-      v_lshrrev_b32 v6, s2, s1
-      v_ashrrev_i32 v7, s2, s1
-      v_mad_u32_u24 v8, s1, s2, s1
-      s_endpgm
-    """
-    s = run_after(src)
+    s = run_after(hk.fold_scalar_src(x, y))
     X, Y = np.uint64(x), np.uint64(y)
     m = np.uint64(0xFFFFFFFF)
     sh = int(y) & 31
@@ -72,20 +55,7 @@ def test_fold_scalar(x, y):
 @settings(max_examples=40, deadline=None)
 @given(U32, U32, U32, U32, st.integers(0, 63))
 def test_fold_64(a, b, c, d, sh):
-    s = run_after(f"""
-      s_mov_b32 s10, {a:#x}
-      s_mov_b32 s11, {b:#x}
-      s_mov_b32 s12, {c:#x}
-      s_mov_b32 s13, {d:#x}
-      s_and_b64 s[20:21], s[10:11], s[12:13]
-      s_or_b64 s[22:23], s[10:11], s[12:13]
-      s_xor_b64 s[24:25], s[10:11], s[12:13]
-      s_andn2_b64 s[26:27], s[10:11], s[12:13]
-      v_mov_b32 v10, s10
-      v_mov_b32 v11, s11
-      v_lshlrev_b64 v[20:21], {sh}, v[10:11]
-      s_endpgm
-    """)
+    s = run_after(hk.fold_64_src(a, b, c, d, sh))
     A = (b << 32) | a
     C = (d << 32) | c
     M = 2 ** 64 - 1
@@ -98,17 +68,7 @@ def test_fold_64(a, b, c, d, sh):
 
 
 def test_inline_constants():
-    s = run_after("""
-      s_mov_b32 s1, 0.5
-      s_mov_b32 s2, -4.0
-      v_mov_b32 v1, 1.0
-      s_mov_b64 s[10:11], 2.0
-      s_mov_b64 s[12:13], -16
-      s_mov_b64 s[14:15], 64
-      s_mov_b64 s[16:17], -70000
-      s_mov_b32 s18, 100000
-      s_endpgm
-    """)
+    s = run_after(hk.INLINE_CONSTANTS)
     f32 = lambda x: int(np.float32(x).view(np.uint32))
     f64 = lambda x: int(np.float64(x).view(np.uint64))
     assert int(s[1]["val"]) == cval(f32(0.5))
@@ -123,17 +83,7 @@ def test_inline_constants():
 
 
 def test_float_ops_are_typed_not_folded():
-    s = run_after("""
-      v_mov_b32 v1, 1.0
-      v_add_f32 v2, v1, v1
-      v_mad_f32 v3, v1, v1, v1
-      v_cvt_f32_u32 v4, v0
-      v_cvt_u32_f32 v5, v1
-      v_cvt_f64_f32 v[6:7], v1
-      v_add_f64 v[8:9], v[6:7], v[6:7]
-      v_mul_hi_u32 v10, v0, 7
-      s_endpgm
-    """)
+    s = run_after(hk.FLOAT_OPS)
     for slot, ty in [(114, 4), (115, 4), (116, 4), (117, 2), (118, 8), (119, 8), (120, 8), (121, 8), (122, 2)]:
         assert int(s[slot]["val"]) == TOP and int(s[slot]["type"]) == ty, slot
 
@@ -144,17 +94,7 @@ def test_smem_table():
     args = np.zeros(2, dcgen.ARG_DTYPE)
     args[0] = (0x30, 8, dcgen.T_PTR, dcgen.T_FLOAT)
     args[1] = (0x38, 4, dcgen.T_UINT, 0)
-    s = run_after("""
-      s_load_dwordx2 s[10:11], s[4:5], 0x8
-      s_load_dwordx2 s[12:13], s[4:5], 0x10
-      s_load_dwordx4 s[16:19], s[4:5], 0x0
-      s_load_dword s20, s[4:5], 0x3c
-      s_load_dword s21, s[4:5], 0x34
-      s_load_dwordx2 s[22:23], s[4:5], 0x34
-      s_load_dword s24, s[2:3], 0x30
-      s_load_dword s25, s[4:5], 0x2c
-      s_endpgm
-    """, dims=3, cws=(8, 8, 2), args=args)
+    s = run_after(hk.SMEM_TABLE, dims=3, cws=(8, 8, 2), args=args)
     v = oracle.val
     IDX, SYS, KARG = 4, 7, 2
     assert int(s[10]["val"]) == v(IDX, 1, 1, 4) and int(s[11]["val"]) == v(SYS, 2, 1, 0)
@@ -172,33 +112,40 @@ def test_smem_table():
     # hidden slot, high half of the aqlwrap pointer
     assert int(s[25]["val"]) == v(SYS, 2, 2, 4) and int(s[25]["prov"]) == 1 << 19
     # a clobbered s4 keeps the syntactic type/provenance but loses the payload
-    t = run_after("""
-      s_mov_b32 s4, 0
-      s_load_dword s10, s[4:5], 0xc
-      s_endpgm
-    """)
+    t = run_after(hk.SMEM_CLOBBERED)
     assert int(t[10]["val"]) == TOP and int(t[10]["prov"]) == 1 << 9 and int(t[10]["type"]) == dcgen.T_UINT
 
 
+
+def test_smem_hidden_slots_and_mid_argument():
+    """Listing 3's argument area dword by dword: the three hidden 8-byte
+    pointer slots after the global offsets (printf buffer, vqueue, aqlwrap;
+    low then high dword), an x2 and an x4 load starting in the last hidden
+    slot (the x4 runs into the first user argument), a load in the middle of
+    an 8-byte argument (its provenance and type, no payload), the work
+    dimension at its printed offset, and the high dword of the first global
+    offset read on its own."""
+    s = run_after(hk.SMEM_HIDDEN, dims=2, cws=(64, 2, 1), args=hk.smem_hidden_args())
+    v = oracle.val
+    KARG, SYS = 2, 7
+    HIDDEN, GOFF_HI, WORKDIM = 4, 0, 3
+    P_HIDDEN = 1 << 19
+    for slot, q, hi in [(10, 0, 0), (11, 0, 1), (12, 1, 0), (13, 1, 1), (14, 2, 0)]:
+        assert int(s[slot]["val"]) == v(SYS, 2 if hi else 1, q, HIDDEN), slot
+        assert int(s[slot]["prov"]) == P_HIDDEN and int(s[slot]["type"]) == 0, slot
+    assert int(s[16]["val"]) == v(SYS, 1, 2, HIDDEN) and int(s[17]["val"]) == v(SYS, 2, 2, HIDDEN)
+    assert [int(s[20 + j]["val"]) for j in range(4)] == [v(SYS, 1, 2, HIDDEN), v(SYS, 2, 2, HIDDEN),
+                                                       v(KARG, 1, arg=0), v(KARG, 2, arg=0)]
+    assert [int(s[20 + j]["prov"]) for j in range(4)] == [P_HIDDEN, P_HIDDEN, 1 << 20, 1 << 20]
+    assert [int(s[20 + j]["type"]) for j in range(4)] == [0, 0, dcgen.T_PTR, dcgen.T_PTR]
+    assert int(s[24]["val"]) == TOP and int(s[24]["prov"]) == 1 << 21 and int(s[24]["type"]) == dcgen.T_PTR
+    assert int(s[25]["val"]) == v(SYS, 0, 0, WORKDIM) and int(s[25]["prov"]) == 1 << 12
+    assert int(s[25]["type"]) == dcgen.T_UINT
+    assert int(s[26]["val"]) == v(SYS, 2, 0, GOFF_HI) and int(s[26]["prov"]) == 1 << 6
+    assert int(s[26]["type"]) == dcgen.T_UINT
+
 def test_index_rules():
-    s = run_after("""
-      s_lshl_b32 s0, s6, 6
-      s_lshl_b32 s1, s6, 5
-      s_mul_i32 s2, 64, s6
-      v_add_co_u32 v1, vcc, s0, v0
-      v_add_u32 v2, v1, 12
-      v_mul_lo_u32 v3, v1, 8
-      v_lshlrev_b32 v4, 0, v1
-      v_lshlrev_b32 v5, 16, v1
-      v_add_co_u32 v6, vcc, v3, 5
-      v_ashrrev_i32 v7, 31, v1
-      v_add_co_u32 v8, vcc, v1, v1
-      v_mad_u32_u24 v9, v1, 4, 3
-      v_mul_lo_u32 v10, v1, 12
-      v_add_co_u32 v11, vcc, v3, v3
-      v_add_co_u32 v12, vcc, v0, v7
-      s_endpgm
-    """)
+    s = run_after(hk.INDEX_RULES)
     v = oracle.val
     IDX, SHL = 4, 5
     assert int(s[0]["val"]) == v(IDX, 0, 0, 1)                 # WGID << log2(cws) -> group base
@@ -219,11 +166,7 @@ def test_index_rules():
 
 
 def test_mad_is_add_of_mul():
-    s = run_after("""
-      v_mad_u32_u24 v9, v0, 4, 3
-      v_mad_u32_u24 v10, s6, 64, v0
-      s_endpgm
-    """)
+    s = run_after(hk.MAD_RULES)
     v = oracle.val
     assert int(s[121]["val"]) == v(5, 0, 0, 2, 2, c=3)
     assert int(s[122]["val"]) == v(4, 0, 0, 3)
@@ -232,23 +175,7 @@ def test_mad_is_add_of_mul():
 def test_pointer_rules():
     args = np.zeros(1, dcgen.ARG_DTYPE)
     args[0] = (0x30, 8, dcgen.T_PTR, dcgen.T_INT)
-    s = run_after("""
-      s_load_dwordx2 s[8:9], s[4:5], 0x30
-      s_add_u32 s10, s8, 16
-      s_addc_u32 s11, s9, 0
-      s_add_u32 s12, s10, 4
-      v_mov_b32 v2, v0
-      v_ashrrev_i32 v3, 31, v2
-      v_lshlrev_b64 v[2:3], 3, v[2:3]
-      v_add_co_u32 v4, vcc, s10, v2
-      v_addc_co_u32 v5, vcc, s11, v3, vcc
-      v_add_co_u32 v6, vcc, s12, v2
-      s_addc_u32 s13, s9, 1
-      s_addc_u32 s14, 3, 4
-      global_load_dword v7, v[4:5], off offset:8
-      ds_read_b32 v8, v2 offset:4
-      s_endpgm
-    """, args=args)
+    s = run_after(hk.POINTER_RULES, args=args)
     v = oracle.val
     PTR, SHL = 6, 5
     assert int(s[10]["val"]) == v(PTR, 1, arg=0, c=16)
@@ -263,12 +190,7 @@ def test_pointer_rules():
 
 
 def test_uninit_and_top():
-    s = run_after("""
-      v_mov_b32 v3, v9
-      v_add_u32 v4, v9, 1
-      s_mov_b32 s30, exec_lo
-      s_endpgm
-    """)
+    s = run_after(hk.UNINIT_TOP)
     assert int(s[115]["val"]) == oracle.val(8) and int(s[115]["prov"]) == 1 << 17
     assert int(s[116]["val"]) == TOP and int(s[116]["prov"]) == (1 << 17) | (1 << 14)
     assert int(s[30]["val"]) == TOP and int(s[30]["prov"]) == 1 << 18
@@ -419,18 +341,19 @@ def test_transfer_monotone(seed):
 def test_second_dimension_uses_its_own_size():
     """get_num_groups(1) and the group-base term of dimension 1 divide or
     multiply by the second .cws entry, not the first."""
-    s = run_after("""
-      s_load_dword s10, s[4:5], 0x10
-      s_lshr_b32 s11, s10, 2
-      s_lshr_b32 s12, s10, 6
-      s_mul_i32 s13, s7, 4
-      s_mul_i32 s14, s7, 64
-      v_add_co_u32 v3, vcc, s13, v1
-      s_endpgm
-    """, dims=2, cws=(64, 4, 1))
+    s = run_after(hk.SECOND_DIM, dims=2, cws=(64, 4, 1))
     v = oracle.val
     assert int(s[11]["val"]) == v(7, 0, 1, 2)
     assert int(s[12]["val"]) == TOP
     assert int(s[13]["val"]) == v(4, 0, 1, 1)
     assert int(s[14]["val"]) == TOP
     assert int(s[115]["val"]) == v(4, 0, 1, 3)
+
+
+def test_hand_kernels_valid():
+    """The shared hand-written kernels are well formed (the GPU parity test
+    runs the same list)."""
+    for name, (recs, d, a) in hk.all_kernels():
+        assert oracle.kernel_status(recs, d) == 0, name
+        r = oracle.analyze(recs, d, a)
+        assert r["status"] == 0 and r["n_blocks"] >= 2, name
