@@ -1,18 +1,24 @@
 """Throughput bench of the register-state dataflow analysis on one MI355X.
 
 One step = the whole hot path over one batch: decode and checks, leaders,
-block numbering, edges and predecessor lists, reverse postorder, fixpoint,
-extraction and dense compaction, on 65,536 seeded synthetic GCN kernels with
-lengths log-uniform on [200, 2000] (51.2M instructions, 820 MB of records)
-already resident in HBM.  Prints one JSON line.
+block numbering, record regions, edges and predecessor lists, reverse
+postorder, fixpoint, extraction and dense compaction.  The headline workload
+is 1,048,576 seeded synthetic GCN kernels with Zipf(1.2) lengths on
+[20, 20000] (1.74e9 instructions, 27.8 GB of records) in one persistent
+launch, records resident in HBM.  Prints one JSON line.
 
-Beside the headline figure it reports the plain form (each kernel analysed
-by its own launch sequence) on a sample, and the request server at Poisson
-arrivals (latency percentiles, served rate, the same requests offline).
+Beside the headline figure it reports: the 65,536-kernel log-uniform
+workload; the 16 kernels of 1-4M instructions (sweeps and GB/s); the
+32-kernel workload batched and in the plain form (each kernel analysed by its
+own launch sequence); the request server at Poisson arrivals (latency
+percentiles, served rate, the same requests offline); and the CPU oracle on
+a length-stratified sample of the headline workload, whose results also
+check the timed run's results for the sampled kernels.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-serving] [--copy-calibration]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-serving] [--no-extra] [--copy-calibration]
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -22,76 +28,189 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
-# the request server runs one lane per HIP hardware queue (one queue per
-# lane keeps a long batch from holding up another lane's); must be set before
-# the HIP runtime starts
-os.environ["GPU_MAX_HW_QUEUES"] = "16"
 
 METRIC = "instructions analysed/sec to fixpoint (bit-exact) + HBM GB/s fraction; p99 latency"
 HBM_PEAK_GBS = 8000.0
-PROFILE = os.path.join(ROOT, "profiles", "k_fixpoint_c2_65536_kernels.md")
+N_CU = 256
+CLOCK_GHZ = 2.4
+PROFILE = os.path.join(ROOT, "profiles", "k_fixpoint_zipf_1048576_kernels.md")
 FIXPOINT_SRC = os.path.join(ROOT, "paper_2107_07809_amd", "csrc", "dc_fixpoint.hip")
-
-
-def measured_traffic():
-    """HBM bytes per launch of the fixpoint kernel from the committed rocprofv3
-    summary (FETCH_SIZE + WRITE_SIZE, calibrated by a 1 GiB copy), or None when
-    the kernel source has changed since the counters were taken."""
-    import hashlib
-    try:
-        text = open(PROFILE).read()
-        src = hashlib.sha256(open(FIXPOINT_SRC, "rb").read()).hexdigest()
-    except OSError:
-        return None
-    fields = dict(line.split(": ", 1) for line in text.splitlines()
-                  if line.startswith(("traffic_bytes_per_launch: ", "measured_source_sha256: ")))
-    if fields.get("measured_source_sha256", "").strip() != src:
-        return None
-    return float(fields["traffic_bytes_per_launch"])
+WORKLOADS = {
+    3: ("1,048,576 seeded synthetic GCN kernels, Zipf(s=1.2) lengths on [20, 20000], nested exec-mask if/else "
+        "and counted loops to depth 3, ~18% float ALU", 1048576),
+    2: ("65,536 seeded synthetic GCN kernels, lengths log-uniform on [200, 2000], nested exec-mask if/else and "
+        "counted loops to depth 3, ~18% float ALU", 65536),
+}
 
 
 def log(msg):
     print("bench: " + msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(cfg, n_kernels, target_core_seconds=15.0):
-    """The oracle as it stands, one worker process per available core, on a
-    bounded sample (a prefix of the same workload)."""
+def profile_fields():
+    """Per-launch counter figures of the fixpoint kernel from the committed
+    rocprofv3 summary, or {} when the kernel source has changed since the
+    counters were taken."""
+    try:
+        text = open(PROFILE).read()
+        src = hashlib.sha256(open(FIXPOINT_SRC, "rb").read()).hexdigest()
+    except OSError:
+        return {}
+    fields = dict(line.split(": ", 1) for line in text.splitlines() if ": " in line and line[:1].islower())
+    if fields.get("measured_source_sha256", "").strip() != src:
+        return {}
+    out = {}
+    for k, v in fields.items():
+        try:
+            out[k] = float(v)
+        except ValueError:
+            pass
+    return out
+
+
+# ---------------------------------------------------------------- CPU leg
+
+def _oracle_job(job):
+    """One worker's share of the sample: generate its kernels (untimed), then
+    time the oracle over them."""
     import dcgen
-    from concurrent.futures import ProcessPoolExecutor
-    sys.path.insert(0, os.path.join(ROOT, "tests"))
-    from gpu_common import _oracle_chunk
-    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
-    cores = max(1, min(cores, 16))
-    # size the sample from a quick single-core probe
-    probe = dcgen.generate(cfg, 256, threads=1)
+    import oracle
+    cfg, idx = job
+    b = dcgen.concat([dcgen.generate(cfg, 1, i0=int(i), threads=1).kernel(0) for i in idx])
     t = time.perf_counter()
-    _oracle_chunk((cfg, 0, 256))
-    rate1 = probe.n_instr / (time.perf_counter() - t)
-    mean_len = probe.n_instr / 256
-    n = int(min(n_kernels, max(256, target_core_seconds * rate1 / mean_len)))
-    step = max(1, n // (cores * 8))
-    jobs = [(cfg, i, min(step, n - i)) for i in range(0, n, step)]
-    lens, _ = dcgen.sizes(cfg, 0, n)
-    n_instr = int(lens.sum())
+    summ, acc, sysv = oracle.analyze_batch(b)
+    dt = time.perf_counter() - t
+    return dt, int(b.n_instr), summ, acc, sysv
+
+
+def stratified_sample(cfg, n_kernels, fraction):
+    """Every (1/fraction)-th kernel in order of length: a length-stratified
+    sample of the workload's kernel indices, ascending."""
+    import dcgen
+    lens, _ = dcgen.sizes(cfg, 0, n_kernels)
+    order = np.argsort(lens, kind="stable")
+    step = max(1, int(round(1.0 / fraction)))
+    return np.sort(order[step // 2::step]), lens
+
+
+def cpu_baseline(cfg, n_kernels, idx, lens):
+    """The oracle as it stands, one single-threaded worker process per core of
+    this process's CPU share, on the sampled kernels; every worker gets an
+    equal share of each length stratum and is timed on the oracle alone."""
+    from concurrent.futures import ProcessPoolExecutor
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    # one GPU's CPU share on the GPU boxes is 16 cores, whatever the host shows
+    cores = max(1, min(avail, 16))
+    jobs = [(cfg, idx[w::cores]) for w in range(cores)]
     with ProcessPoolExecutor(cores) as ex:
-        list(ex.map(_oracle_chunk, [(cfg, 0, 16)] * cores))   # start the workers
-        t = time.perf_counter()
-        list(ex.map(_oracle_chunk, jobs))
-        dt = time.perf_counter() - t
-    return {"value": n_instr / dt, "unit": "instructions/s", "cores": cores, "kind": "oracle",
-            "sample": f"first {n} of the {n_kernels} kernels ({n_instr} instructions, regenerated per worker "
-                      f"shard, generation inside the timed span); single-core rate {rate1:.4g} instructions/s",
-            "seconds": dt}
+        parts = list(ex.map(_oracle_job, jobs))
+    secs = [p[0] for p in parts]
+    n_instr = sum(p[1] for p in parts)
+    total_instr = int(lens.sum(dtype=np.uint64))
+    value = n_instr / max(secs)
+    per_core = n_instr / sum(secs)
+    # results back in sample order (worker w holds idx[w::cores])
+    by_kernel = {}
+    for w, p in enumerate(parts):
+        summ, acc, sysv = p[2], p[3], p[4]
+        ia = isy = 0
+        for j, k in enumerate(idx[w::cores]):
+            na, ns = int(summ[j]["n_acc"]), int(summ[j]["n_sys"])
+            by_kernel[int(k)] = (summ[j], acc[ia:ia + na], sysv[isy:isy + ns])
+            ia += na
+            isy += ns
+    out = {"value": value, "unit": "instructions/s", "cores": cores, "kind": "oracle",
+           "sample": f"{len(idx)} of the {n_kernels} kernels, every {n_kernels // max(1, len(idx))}th in order of "
+                     f"length ({n_instr} instructions, {100.0 * n_instr / total_instr:.2f}% of the workload's "
+                     f"{total_instr}); value = sample instructions / the longest worker's oracle seconds "
+                     f"(generation untimed); the whole workload would take {total_instr / value:.0f} s",
+           "per_core_value": per_core, "seconds": max(secs), "host_cpus": os.cpu_count(), "cpu_share": avail}
+    return out, by_kernel
 
 
-def plain_per_kernel(ctx, b, dev, stream, n_sample):
-    """The plain form for comparison: every kernel analysed by its own
-    sequence of launches (its own batch of one), one after another, on the
-    first n_sample kernels of the same workload.  Planning and allocation
-    happen before the timed region, as for the batched form."""
+def verify_sample(gpu, by_kernel):
+    """The timed run's results of the sampled kernels against the oracle:
+    status, blocks, sweeps, record counts and every record byte."""
+    bad = 0
+    for k, (s, acc, sysv) in by_kernel.items():
+        r = gpu["results"][k]
+        ok = (int(r["status"]), int(r["n_blocks"]), int(r["sweeps"]), int(r["n_access"]), int(r["n_sysval"])) == \
+            (int(s["status"]), int(s["n_blocks"]), int(s["sweeps"]), int(s["n_acc"]), int(s["n_sys"]))
+        ga, gs = gpu["records"][k]
+        ok = ok and ga.tobytes() == acc.tobytes() and gs.tobytes() == sysv.tobytes()
+        bad += 0 if ok else 1
+    return {"kernels": len(by_kernel), "mismatches": bad}
+
+
+# ---------------------------------------------------------------- GPU legs
+
+def timed_run(ctx, b, stream, steps, warmup, shape, sample_idx=None, lat_steps=5, what="batch"):
+    """Plan once (with its first run, untimed), `warmup` more runs, then time
+    `steps` whole-path runs with the records resident in HBM.  Returns the
+    figures, the per-kernel results and, for sample_idx, those kernels'
+    records."""
     import torch
     from paper_2107_07809_amd import dc
+    t = time.perf_counter()
+    dev = dc.to_device(b.instrs)
+    torch.cuda.synchronize()
+    log(f"{what}: records uploaded in {time.perf_counter() - t:.1f}s")
+    t = time.perf_counter()
+    bt = ctx.analyze(b.kernels, dev, b.n_instr, b.args, flags=dc.OPT_TIMING, stream=stream, **shape)
+    bt.wait()
+    log(f"{what}: planned and first run in {time.perf_counter() - t:.1f}s")
+    for _ in range(warmup):
+        bt.run(stream=stream)
+    bt.wait()
+    res = bt.results()
+    st = bt.stats()
+    bt.timing_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        bt.run(stream=stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    tm = bt.timing()
+    runs = max(1, tm["runs"])
+    lat = []
+    for _ in range(lat_steps):
+        t = time.perf_counter()
+        bt.run(stream=stream)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - t) * 1e3)
+    res_after = bt.results()
+    records = {}
+    if sample_idx is not None:
+        for k in sample_idx:
+            records[int(k)] = (bt.accesses(int(k)), bt.sysvals(int(k)))
+    bt.free()
+    del dev
+    torch.cuda.empty_cache()
+    n_failed = int((res["status"] != 0).sum())
+    n_acc, n_sys = int(res["n_access"].sum()), int(res["n_sysval"].sum())
+    fix_ms = tm["ms_fixpoint"] / runs
+    alg_bytes = 16 * b.n_instr + 32 * b.n_kernels + 16 * n_acc + 8 * n_sys + 32 * b.n_kernels
+    return {
+        "elapsed": elapsed, "value": b.n_instr * steps / elapsed, "ms_per_step": elapsed * 1e3 / steps,
+        "fix_ms": fix_ms, "alg_bytes": alg_bytes,
+        "stages_ms": {"total": tm["ms_total"] / runs, "decode": tm["ms_decode"] / runs, "cfg": tm["ms_cfg"] / runs,
+                      "fixpoint": fix_ms, "compact": tm["ms_compact"] / runs},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))} if lat else None,
+        "sweeps": {"max": st["sweeps_max"], "mean": st["sweeps_sum"] / max(1, b.n_kernels - n_failed)},
+        "failed": n_failed, "overflow_kernels": st["n_overflow"],
+        "rerun_identical": bool(res_after.tobytes() == res.tobytes()),
+        "results": res, "records": records,
+    }
+
+
+def plain_per_kernel(ctx, b, stream, n_sample):
+    """The plain form for comparison: every kernel analysed by its own
+    sequence of launches (its own batch of one), one after another, on the
+    first n_sample kernels.  Planning happens before the timed region."""
+    import torch
+    from paper_2107_07809_amd import dc
+    dev = dc.to_device(b.instrs)
     batches = []
     n_instr = 0
     for k in range(n_sample):
@@ -108,11 +227,37 @@ def plain_per_kernel(ctx, b, dev, stream, n_sample):
     dt = time.perf_counter() - t0
     for bt in batches:
         bt.free()
-    return {"value": n_instr / dt, "unit": "instructions/s", "sample": f"first {n_sample} kernels of the same "
-            f"workload ({n_instr} instructions), one launch sequence per kernel", "seconds": dt}
+    return {"value": n_instr / dt, "unit": "instructions/s", "kernels": n_sample, "instructions": n_instr,
+            "seconds": dt}
 
 
-def serving(ctx, rate, seconds, warm_seconds=0.3, offline=True, **server_opts):
+def extra_workloads(ctx, stream):
+    """The other configurations, each timed as whole-path runs with its
+    records in HBM."""
+    import dcgen
+    out = {}
+    b = dcgen.generate(2, 65536)
+    r = timed_run(ctx, b, stream, steps=10, warmup=2, shape={}, lat_steps=0, what="65,536 kernels")
+    out["loguniform_65536_kernels"] = {"instructions": int(b.n_instr), "instructions_per_s": r["value"],
+                                       "ms_per_step": r["ms_per_step"], "fixpoint_ms": r["fix_ms"],
+                                       "sweeps_max": r["sweeps"]["max"], "failed": r["failed"]}
+    b = dcgen.generate(4, 16)
+    r = timed_run(ctx, b, stream, steps=2, warmup=0, shape={}, lat_steps=0, what="16 huge kernels")
+    out["huge_16_kernels_1M_to_4M"] = {
+        "instructions": int(b.n_instr), "instructions_per_s": r["value"], "ms_per_step": r["ms_per_step"],
+        "sweeps_max": r["sweeps"]["max"], "blocks_max": int(r["results"]["n_blocks"].max()),
+        "alg_GBps": r["alg_bytes"] / (r["fix_ms"] * 1e-3) / 1e9, "failed": r["failed"]}
+    b = dcgen.generate(1, 32)
+    r = timed_run(ctx, b, stream, steps=50, warmup=2, shape={}, lat_steps=0, what="32 kernels")
+    plain = plain_per_kernel(ctx, b, stream, 32)
+    out["small_32_kernels"] = {"instructions": int(b.n_instr), "batched_instructions_per_s": r["value"],
+                               "batched_ms": r["ms_per_step"], "plain_instructions_per_s": plain["value"],
+                               "plain_ms_per_kernel": plain["seconds"] * 1e3 / 32,
+                               "batched_speedup": r["value"] / plain["value"]}
+    return out
+
+
+def serving(ctx, rate, seconds, warm_seconds=1.0, offline=True, **server_opts):
     """The request server at Poisson arrivals (log-normal lengths, median
     1,000 instructions, sigma 1, cap 100k): offered and served rates, latency
     from submission to result on the host, and the same requests analysed
@@ -170,9 +315,9 @@ def serving(ctx, rate, seconds, warm_seconds=0.3, offline=True, **server_opts):
                              "device": med(res["t_device_ns"] - res["t_enqueued_ns"]),
                              "copy_back": med(res["t_done_ns"] - res["t_device_ns"])},
             "batches": int(len(np.unique(res["batch"]))), "mean_batch": float(res["batch_kernels"].mean()),
-            "lanes": st["lanes"], **out,
+            "lanes": st["lanes"], "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES", "HIP default"), **out,
             "workload": f"{n} log-normal requests (median 1,000 instructions, sigma 1, cap 100k) at Poisson "
-                        f"arrivals after {n_warm} warm-up arrivals"}
+                        f"arrivals in {seconds:g} s after {n_warm} warm-up arrivals ({warm_seconds:g} s)"}
 
 
 def offline_rate(ctx, off):
@@ -193,88 +338,55 @@ def offline_rate(ctx, off):
     return off_rate
 
 
-def timed_batch(ctx, b, stream, reps=1):
-    """Plan once (untimed, with its first run), then time `reps` whole runs
-    with the records resident in HBM."""
-    import torch
-    from paper_2107_07809_amd import dc
-    dev = dc.to_device(b.instrs)
-    bt = ctx.analyze(b.kernels, dev, b.n_instr, b.args, flags=dc.OPT_TIMING, stream=stream)
-    bt.wait()
-    res = bt.results()
-    st = bt.stats()
-    bt.timing_reset()
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    for _ in range(reps):
-        bt.run(stream=stream)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t) / reps
-    tm = bt.timing()
-    bt.free()
-    del dev
-    torch.cuda.empty_cache()
-    return dt, tm["ms_fixpoint"] / max(1, tm["runs"]), res, st
-
-
-def other_workloads(ctx, stream, c3_slices=8):
-    """The other configurations, each timed as whole-path runs with its
-    records in HBM: the 16 kernels of 1-4M instructions; the 1,048,576-kernel
-    Zipf workload in slices of 131,072 kernels (one plan per slice, the
-    slices' run times summed); the 32-kernel workload batched and as one
-    launch sequence per kernel."""
-    import dcgen
-    out = {}
-    b = dcgen.generate(4, 16)
-    dt, fix, res, st = timed_batch(ctx, b, stream)
-    out["c4_16_kernels_1M_to_4M"] = {"instructions": int(b.n_instr), "seconds": dt, "instructions_per_s": b.n_instr / dt,
-                                     "sweeps_max": st["sweeps_max"], "blocks_max": int(res["n_blocks"].max()),
-                                     "failed": int((res["status"] != 0).sum()),
-                                     "form": "one wavefront per kernel (overflow pass)"}
-    log("workloads: 16 huge kernels done")
-    per = 1048576 // c3_slices
-    tot_s = tot_i = fail = 0
-    for k in range(c3_slices):
-        b = dcgen.generate(3, per, i0=k * per)
-        dt, fix, res, st = timed_batch(ctx, b, stream)
-        tot_s += dt
-        tot_i += int(b.n_instr)
-        fail += int((res["status"] != 0).sum())
-        log(f"workloads: Zipf slice {k + 1}/{c3_slices}: {b.n_instr} instructions in {dt * 1e3:.1f} ms")
-    out["c3_zipf_1048576_kernels"] = {"instructions": tot_i, "seconds": tot_s, "instructions_per_s": tot_i / tot_s,
-                                      "failed": fail, "form": f"{c3_slices} slices of {per} kernels, batched persistent"}
-    b = dcgen.generate(1, 32)
-    dt, fix, res, st = timed_batch(ctx, b, stream, reps=20)
-    plain = plain_per_kernel(ctx, b, dc_dev(b), stream, 32)
-    out["c1_32_kernels"] = {"instructions": int(b.n_instr), "batched_instructions_per_s": b.n_instr / dt,
-                            "plain_instructions_per_s": plain["value"], "batched_ms": dt * 1e3}
+def roofline(r, prof):
+    """HBM roofline of the fixpoint kernel (algorithmic bytes per launch over
+    its HIP-event launch time) and, from the committed counters of the same
+    source, the measured HBM traffic and the issue rate against the chip's
+    instruction-issue limits."""
+    achieved = r["alg_bytes"] / (r["fix_ms"] * 1e-3) / 1e9
+    tb = prof.get("traffic_bytes_per_launch")
+    out = {"bound": "hbm", "kernel": "k_fixpoint", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": achieved / HBM_PEAK_GBS, "traffic": tb / (r["fix_ms"] * 1e-3) / 1e9 if tb else None,
+           "alg_bytes_per_launch": r["alg_bytes"], "traffic_bytes_per_launch": tb, "avg_launch_ms": r["fix_ms"]}
+    if "wave_instructions_per_launch" in prof:
+        # one instruction of each kind per cycle per CU at most for wave64
+        # work (four SIMDs, each issuing to a unit every fourth cycle): the
+        # kernel's busiest kind is compared with that
+        cyc = r["fix_ms"] * 1e-3 * CLOCK_GHZ * 1e9 * N_CU
+        kinds = {k: prof[k + "_per_launch"] for k in ("valu", "salu", "lds", "smem", "branch", "vmem")
+                 if k + "_per_launch" in prof}
+        busiest = max(kinds, key=kinds.get)
+        out["issue"] = {"bound": "issue", "kind": busiest, "achieved": kinds[busiest] / cyc,
+                        "peak": 1.0, "unit": "wave-instructions/cycle/CU", "frac": kinds[busiest] / cyc,
+                        "all_kinds_per_cycle_per_cu": prof["wave_instructions_per_launch"] / cyc,
+                        "all_kinds_peak": 5.0,
+                        "lds_bank_conflict_cycles_per_lds_cycle": prof.get("lds_conflict_frac")}
     return out
-
-
-def dc_dev(b):
-    from paper_2107_07809_amd import dc
-    return dc.to_device(b.instrs)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--kernels", type=int, default=65536)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", type=int, default=3, choices=sorted(WORKLOADS),
+                    help="3: 1,048,576 Zipf kernels (the headline); 2: 65,536 log-uniform kernels")
+    ap.add_argument("--kernels", type=int, default=0, help="first N kernels of the workload (0 = all)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-fraction", type=float, default=0.01)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy first (a known-size reference for HBM counters)")
     ap.add_argument("--waves-per-group", type=int, default=0)
     ap.add_argument("--groups-per-cu", type=int, default=0)
     ap.add_argument("--no-autotune", action="store_true",
-                    help="keep the library's default launch shape instead of dc_autotune's (also when a shape is given)")
+                    help="keep the library's default launch shape instead of dc_autotune's")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-rate", type=float, default=50000.0)
-    ap.add_argument("--serve-seconds", type=float, default=2.0)
-    ap.add_argument("--plain-sample", type=int, default=256)
-    ap.add_argument("--workloads", action="store_true",
-                    help="also time the 16 huge kernels, the 1,048,576-kernel Zipf workload and the 32-kernel one")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--no-extra", action="store_true", help="skip the other workloads")
+    ap.add_argument("--lat-steps", type=int, default=5, help="runs timed one by one for the latency percentiles")
+    ap.add_argument("--tune-sample", type=int, default=65536,
+                    help="kernels in the autotuner's sample (every stride-th kernel; enough work to fill the GPU)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -283,11 +395,12 @@ def main():
     import dcgen
     from paper_2107_07809_amd import dc
 
-    cfg = 2
+    cfg = args.workload
+    desc, n_all = WORKLOADS[cfg]
+    n_k = args.kernels or n_all
     t = time.perf_counter()
-    b = dcgen.generate(cfg, args.kernels)
-    log(f"generated {b.n_kernels} kernels, {b.n_instr} instructions in {time.perf_counter() - t:.2f}s")
-    dev = dc.to_device(b.instrs)
+    b = dcgen.generate(cfg, n_k)
+    log(f"generated {b.n_kernels} kernels, {b.n_instr} instructions in {time.perf_counter() - t:.1f}s")
     stream = torch.cuda.current_stream()
     if args.copy_calibration:
         src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
@@ -300,93 +413,58 @@ def main():
     shape = {"waves_per_group": args.waves_per_group, "groups_per_cu": args.groups_per_cu}
     tuned = False
     if not args.no_autotune and not (args.waves_per_group or args.groups_per_cu):
-        # launch shape from the autotuner on a sample (outside the timed region)
-        shape, tune_ms = ctx.autotune(b.kernels, dev, b.n_instr, b.args, sample=8192, stream=stream)
+        # launch shape from the autotuner on a sample of every stride-th
+        # kernel (outside the timed region)
+        sub = b.subset(np.arange(0, b.n_kernels, max(1, b.n_kernels // args.tune_sample)))
+        dev = dc.to_device(sub.instrs)
+        shape, tune_ms = ctx.autotune(sub.kernels, dev, sub.n_instr, sub.args, sample=sub.n_kernels, stream=stream)
+        del dev, sub
+        torch.cuda.empty_cache()
         tuned = True
         log(f"autotune: {shape} ({tune_ms:.2f} ms per run of the sample)")
-    batch = ctx.analyze(b.kernels, dev, b.n_instr, b.args, flags=dc.OPT_TIMING, stream=stream, **shape)
-    for _ in range(max(0, args.warmup - 1)):
-        batch.run(stream=stream)
-    batch.wait()
-    res = batch.results()
-    n_failed = int((res["status"] != 0).sum())
-    n_acc, n_sys = int(res["n_access"].sum()), int(res["n_sysval"].sum())
-    st = batch.stats()
-    log(f"warmup done: failed={n_failed} sweeps max={st['sweeps_max']} overflow={st['n_overflow']}")
-
-    # timed region: K steps, each one whole pass of the hot path
-    batch.timing_reset()
-    step_ms = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        batch.run(stream=stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    tm = batch.timing()
-    elapsed = t1 - t0
-    # per-step device time from the events of each run (for latency percentiles)
-    ms_per_step = elapsed * 1e3 / args.steps
-    value = b.n_instr * args.steps / elapsed
-    fix_ms = tm["ms_fixpoint"] / max(1, tm["runs"])
-    total_ms = tm["ms_total"] / max(1, tm["runs"])
-    # algorithmic bytes of the fixpoint kernel per launch: every record read
-    # once, descriptors, the access/system-value records and results written
-    alg_bytes = 16 * b.n_instr + 32 * b.n_kernels + 16 * n_acc + 8 * n_sys + 32 * b.n_kernels
-    achieved = alg_bytes / (fix_ms * 1e-3) / 1e9
-    traffic_bytes = measured_traffic()
-    traffic = traffic_bytes / (fix_ms * 1e-3) / 1e9 if traffic_bytes else None
-    # per-run latencies from a second, short pass with one sync per step
-    lat = []
-    for _ in range(min(args.steps, 20)):
-        t = time.perf_counter()
-        batch.run(stream=stream)
-        torch.cuda.synchronize()
-        lat.append((time.perf_counter() - t) * 1e3)
+    sample_idx = lens = None
+    if not args.no_cpu:
+        sample_idx, lens = stratified_sample(cfg, n_k, args.cpu_fraction)
+    r = timed_run(ctx, b, stream, args.steps, args.warmup, shape, sample_idx=sample_idx, lat_steps=args.lat_steps,
+                  what="headline")
+    log(f"headline: {r['value']:.4g} instructions/s, {r['ms_per_step']:.1f} ms per step, failed {r['failed']}")
+    prof = profile_fields()
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": r["value"],
         "unit": "instructions/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": r["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": "65,536 seeded synthetic GCN kernels, lengths log-uniform on [200, 2000], nested "
-                               "exec-mask if/else and counted loops to depth 3, ~18% float ALU",
+        "config": {"workload": desc if n_k == n_all else f"first {n_k} of: {desc}",
                    "kernels": b.n_kernels, "instructions": b.n_instr, "record_bytes": 16 * b.n_instr,
-                   "form": "batched persistent (one wavefront per kernel)",
+                   "form": "batched persistent (one wavefront per kernel), one plan for the whole batch",
                    "launch": {**shape, "autotuned": tuned}},
-        "roofline": {"bound": "hbm", "kernel": "k_fixpoint", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "alg_bytes_per_launch": alg_bytes, "traffic_bytes_per_launch": traffic_bytes,
-                     "avg_launch_ms": fix_ms},
-        "stages_ms": {"total": total_ms, "decode": tm["ms_decode"] / max(1, tm["runs"]),
-                      "cfg": tm["ms_cfg"] / max(1, tm["runs"]), "fixpoint": fix_ms,
-                      "compact": tm["ms_compact"] / max(1, tm["runs"])},
-        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
-        "sweeps": {"max": st["sweeps_max"], "mean": st["sweeps_sum"] / max(1, b.n_kernels - n_failed)},
-        "failed_kernels": n_failed,
+        "roofline": roofline(r, prof),
+        "stages_ms": r["stages_ms"],
+        "latency_ms": r["latency_ms"],
+        "sweeps": r["sweeps"],
+        "failed_kernels": r["failed"],
+        "overflow_kernels": r["overflow_kernels"],
+        "rerun_identical": r["rerun_identical"],
     }
-    batch.free()
-    if args.plain_sample:
-        log(f"plain form: {args.plain_sample} kernels, one launch sequence each")
-        out["plain_per_kernel"] = plain_per_kernel(ctx, b, dev, stream, args.plain_sample)
-        out["plain_per_kernel"]["batched_speedup"] = value / out["plain_per_kernel"]["value"]
-    del dev
-    if args.workloads:
-        out["workloads"] = other_workloads(ctx, stream)
+    del b
+    if not args.no_extra:
+        out["workloads"] = extra_workloads(ctx, stream)
     if not args.no_serving:
         log(f"serving: {args.serve_rate:.0f} requests/s for {args.serve_seconds} s")
         out["serving"] = serving(ctx, args.serve_rate, args.serve_seconds)
     ctx.close()
     if not args.no_cpu:
-        log("timing the CPU oracle baseline")
-        out["cpu_baseline"] = cpu_baseline(cfg, args.kernels)
+        log("timing the CPU oracle baseline on the stratified sample")
+        out["cpu_baseline"], by_kernel = cpu_baseline(cfg, n_k, sample_idx, lens)
+        out["verified_sample"] = verify_sample(r, by_kernel)
     print(json.dumps(out), flush=True)
 
 

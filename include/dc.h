@@ -50,6 +50,8 @@ typedef int32_t dc_status_t;
 #define DC_E_NOEND (-13)       /* per kernel: control can fall off the end (last record not s_endpgm/s_branch) */
 #define DC_E_UNSUPPORTED (-14) /* per kernel: descriptor outside the described ABI (useargs=0, dims, cws, args) */
 #define DC_E_NOFIX (-15)       /* per kernel: no fixpoint within the sweep cap */
+#define DC_E_CAPACITY (-16)    /* per kernel: the records have more blocks or records than the batch was planned
+                                  for (they changed in place after planning); analyse them in a new batch */
 
 #define DC_NSLOT 368           /* s0..s103, vcc, exec, scc, m0, 2 reserved, v0..v255 */
 
@@ -202,8 +204,14 @@ dc_status_t dc_analyze_batch(dc_ctx_t *ctx, const dc_kernel_t *kernels, uint32_t
 dc_status_t dc_autotune(dc_ctx_t *ctx, const dc_kernel_t *kernels, uint32_t n_kernels, const dc_instr_t *instrs,
                         uint64_t n_records, const dc_arg_t *args, uint64_t n_args_total, const dc_options_t *base,
                         uint32_t sample, void *stream, dc_options_t *best, float *best_ms);
-/* Run the same batch again on `instrs` (same layout; NULL = the previous
- * pointer).  Results are overwritten.  Allocates nothing. */
+/* Run the same batch again on `instrs` (device; the same descriptors and
+ * layout; NULL = the previous pointer).  Results are overwritten.  On the
+ * planned records it allocates nothing and does not synchronise.  A new
+ * pointer holds other records, whose block counts and record capacities may
+ * differ: the run then plans the batch again for them (it synchronises the
+ * stream and may allocate), as its first run did.  Records changed in place
+ * after planning are the caller's error: kernels whose records no longer fit
+ * the plan report DC_E_CAPACITY. */
 dc_status_t dc_batch_run(dc_batch_t *batch, const dc_instr_t *instrs, void *stream);
 dc_status_t dc_batch_wait(dc_batch_t *batch);
 

@@ -45,7 +45,8 @@ struct dc_batch {
     uint32_t K = 0;
     uint64_t N = 0;
     uint64_t n_records = 0, n_args_total = 0;
-    DevMem mem;
+    DevMem mem;    /* arrays sized by kernels and positions, the arenas */
+    DevMem bmem;   /* block-indexed arrays and record regions, sized from the records' totals */
     Plan P{};
     Plan *dP = nullptr;
     FixCfg fc{};
@@ -55,6 +56,7 @@ struct dc_batch {
     bool have_events = false;
     uint64_t runs = 0, runs_at_reset = 0;   /* enqueued runs; ring slot = run % TIMING_RING */
     uint64_t export_blocks = 0;
+    bool blocks_planned = false;   /* bmem sized from the totals of the first run on these records */
     bool ovf_planned = false;   /* the overflow pass is sized from the first run's block counts */
     bool auto_arena = false;    /* no block cap given: the main arena grows to the largest kernel */
     hipGraphExec_t graph = nullptr;   /* DC_OPT_GRAPH: the stages captured on the second run */
@@ -92,6 +94,7 @@ extern "C" const char *dc_status_str(dc_status_t st) {
     case DC_E_NOEND: return "control falls off the end";
     case DC_E_UNSUPPORTED: return "unsupported kernel descriptor";
     case DC_E_NOFIX: return "no fixpoint within the sweep cap";
+    case DC_E_CAPACITY: return "records changed after planning: more blocks or records than planned";
     }
     return "unknown status";
 }
@@ -131,26 +134,22 @@ PlanInputs dc::alloc_plan(DevMem &M, Plan &P, const PlanDims &d) {
     P.pos_begin = in.pos_begin;
     P.desc_status = in.desc_status;
     P.leader = M.alloc<uint8_t>(N + 16);
+    P.pcap = M.alloc<uint8_t>(N + 16);
     P.block_id = M.alloc<uint32_t>(N);
-    P.block_start = M.alloc<uint32_t>(N + 1);
-    P.block_kernel = M.alloc<uint32_t>(N);
-    P.succ = M.alloc<int32_t>(2 * N);
-    P.pred_cnt = M.alloc<uint32_t>(N + 1);
-    P.pred_fill = M.alloc<uint32_t>(N);
-    P.pred = M.alloc<uint32_t>(2 * N);
-    P.rpo = M.alloc<uint32_t>(N);
-    P.rpo_pos = M.alloc<int32_t>(N);
-    P.dfs_stack = M.alloc<uint32_t>(N);
-    P.dfs_seen = M.alloc<uint8_t>(N);
+    P.totals = M.alloc<uint32_t>(4);
     P.kbad = M.alloc<uint32_t>(K);
     P.status = M.alloc<int32_t>(K);
     P.first_block = M.alloc<uint32_t>(K);
     P.n_blocks = M.alloc<uint32_t>(K);
     P.n_reach = M.alloc<uint32_t>(K);
-    P.total_blocks = M.alloc<uint32_t>(4);
     P.scan_tmp_words = scan_tmp_words_needed(std::max<uint64_t>(N + 1, K + 1));
-    P.scan_tmp = M.alloc<uint32_t>(P.scan_tmp_words);
+    P.scan_tmp = M.alloc<uint32_t>(P.scan_tmp_words + (d.cfg_only ? 0 : cap_scan_words(N)));
+    P.blk_cap = 0;
+    in.work_order = nullptr;
+    P.work_order = nullptr;
     if (d.cfg_only) return in;
+    in.work_order = M.alloc<uint32_t>(K);
+    P.work_order = in.work_order;
     P.arena_rows = d.arena_rows;
     P.main_waves = (uint32_t)d.waves;
     P.arena = M.alloc<uint32_t>(d.waves * d.arena_rows * FIX_ROW_DWORDS);
@@ -162,21 +161,45 @@ PlanInputs dc::alloc_plan(DevMem &M, Plan &P, const PlanDims &d) {
     P.dummy = M.alloc<uint4>((d.waves + OVF_MAX_WAVES) * 64);
     P.ovf_list = M.alloc<uint32_t>(K);
     P.counters = M.alloc<uint32_t>(4);
-    P.binfo = M.alloc<uint4>(2 * N);
-    P.acc_sparse = M.alloc<dc_access_t>(N);
-    P.sys_sparse = M.alloc<dc_sysval_t>(4 * N);
-    P.blk_acc = M.alloc<uint32_t>(N);
-    P.blk_sys = M.alloc<uint32_t>(N);
-    P.blk_acc_off = M.alloc<uint32_t>(N);
-    P.blk_sys_off = M.alloc<uint32_t>(N);
     P.results = M.alloc<dc_kernel_result_t>(K);
     P.acc_count = M.alloc<uint32_t>(K + 1);
     P.sys_count = M.alloc<uint32_t>(K + 1);
-    P.acc_dense = M.alloc<dc_access_t>(N);
-    P.sys_dense = M.alloc<dc_sysval_t>(4 * N);
     P.export_states = nullptr;
     P.export_reached = nullptr;
     return in;
+}
+
+void dc::alloc_blocks(DevMem &M, Plan &P, uint64_t blocks, uint64_t acc, uint64_t sys, bool cfg_only) {
+    const uint64_t B = blocks;
+    P.blk_cap = (uint32_t)B;
+    P.block_start = M.alloc<uint32_t>(B + 1);
+    P.block_kernel = M.alloc<uint32_t>(B);
+    P.succ = M.alloc<int32_t>(2 * B);
+    P.pred_cnt = M.alloc<uint32_t>(B + 1);
+    P.pred_fill = M.alloc<uint32_t>(B);
+    P.pred = M.alloc<uint32_t>(2 * B);
+    P.rpo = M.alloc<uint32_t>(B);
+    P.rpo_pos = M.alloc<int32_t>(B);
+    P.dfs_stack = M.alloc<uint32_t>(B);
+    P.dfs_seen = M.alloc<uint8_t>(B);
+    if (cfg_only) {
+        P.binfo = nullptr;
+        P.blk_acc_base = P.blk_sys_base = nullptr;
+        return;
+    }
+    P.binfo = M.alloc<uint4>(2 * B);
+    P.blk_acc_base = M.alloc<uint32_t>(B + 1);
+    P.blk_sys_base = M.alloc<uint32_t>(B + 1);
+    P.blk_acc = M.alloc<uint32_t>(B);
+    P.blk_sys = M.alloc<uint32_t>(B);
+    P.blk_acc_off = M.alloc<uint32_t>(B);
+    P.blk_sys_off = M.alloc<uint32_t>(B);
+    P.acc_cap = (uint32_t)acc;
+    P.sys_cap = (uint32_t)sys;
+    P.acc_sparse = M.alloc<dc_access_t>(acc);
+    P.acc_dense = M.alloc<dc_access_t>(acc);
+    P.sys_sparse = M.alloc<dc_sysval_t>(sys);
+    P.sys_dense = M.alloc<dc_sysval_t>(sys);
 }
 
 static dc_status_t plan_batch(dc_batch *B, dc_ctx *ctx, const dc_kernel_t *kernels, uint32_t n_kernels,
@@ -257,6 +280,17 @@ static dc_status_t plan_batch(dc_batch *B, dc_ctx *ctx, const dc_kernel_t *kerne
     if (e == hipSuccess)
         e = hipMemcpyAsync(d_pb, B->pos_begin.data(), (K + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, s);
     if (e == hipSuccess && K) e = hipMemcpyAsync(d_ds, dstat.data(), K * sizeof(int32_t), hipMemcpyHostToDevice, s);
+    /* the fixpoint takes the longest kernels first, so that no long kernel
+     * starts last and holds up the end of the launch */
+    std::vector<uint32_t> order;
+    if (!cfg_only && K) {
+        order.resize(K);
+        for (uint32_t k = 0; k < K; k++) order[k] = k;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](uint32_t a, uint32_t b) { return kernels[a].n_instr > kernels[b].n_instr; });
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(in.work_order, order.data(), K * sizeof(uint32_t), hipMemcpyHostToDevice, s);
+    }
     if (e == hipSuccess) e = hipMemcpyAsync(B->dP, &P, sizeof(Plan), hipMemcpyHostToDevice, s);
     /* the host vectors above are stack/batch owned: make the copies complete */
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -276,8 +310,8 @@ static dc_status_t plan_batch(dc_batch *B, dc_ctx *ctx, const dc_kernel_t *kerne
  * pass's arenas grow to hold the largest kernel it can take (at most 2048
  * blocks), within ARENA_BUDGET and a quarter of the free device memory; the
  * kernels that still do not fit go to the overflow pass, which gets up to
- * OVF_MAX_WAVES waves within the same budget.  A later run whose kernels
- * have more blocks than planned reports DC_E_UNSUPPORTED for those kernels. */
+ * OVF_MAX_WAVES waves within the same budget.  A later run on the same
+ * records has the same block counts; a run on other records plans again. */
 static hipError_t plan_overflow(dc_batch *B, hipStream_t s) {
     Plan &P = B->P;
     std::vector<uint32_t> nb(B->K);
@@ -313,10 +347,28 @@ static hipError_t plan_overflow(dc_batch *B, hipStream_t s) {
     P.ovf_block_cap = (uint32_t)cap;
     P.ovf_rows = (uint32_t)(cap * FIX_MAX_ROWS);
     P.ovf_waves = (uint32_t)waves;
+    if (P.ovf_arena) B->mem.release(P.ovf_arena);
+    if (P.ovf_bitmaps) B->mem.release(P.ovf_bitmaps);
     P.ovf_arena = B->mem.alloc<uint32_t>(waves * P.ovf_rows * FIX_ROW_DWORDS);
     P.ovf_bitmaps = B->mem.alloc<uint32_t>(waves * (2 * ((cap + 31) / 32) + 64));
     if (B->mem.failed) return hipErrorOutOfMemory;
     B->ovf_planned = true;
+    return hipSuccess;
+}
+
+/* Size the block-indexed arrays and the record regions from the totals of
+ * the decode and leader-scan stages just enqueued (waits for the stream):
+ * the block count, the access and the built-in record capacity. */
+static hipError_t plan_blocks(dc_batch *B, hipStream_t s) {
+    Plan &P = B->P;
+    uint32_t t[4] = {0, 0, 0, 0};
+    hipError_t e = hipMemcpyAsync(t, P.totals, sizeof(t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    B->bmem.reset();
+    alloc_blocks(B->bmem, P, t[0], t[1], t[2], B->cfg_only);
+    if (B->bmem.failed) return hipErrorOutOfMemory;
+    B->blocks_planned = true;
     return hipSuccess;
 }
 
@@ -326,6 +378,7 @@ static hipError_t enqueue_stages(dc_batch *B, hipStream_t s) {
     hipError_t e = launch_fill_u8(P.leader, B->N, 0, s);
     if (e == hipSuccess) e = launch_fill_u32(P.kbad, B->K, 0xFFFFFFFFu, s);
     if (e == hipSuccess) e = launch_decode(P, s);
+    if (e == hipSuccess) e = launch_leader_scan(P, s);
     if (e == hipSuccess) e = launch_number_blocks(P, s);
     if (e == hipSuccess) e = launch_edges(P, s);
     if (e == hipSuccess) e = launch_fixpoint(P, B->dP, B->fc, s, nullptr, nullptr);
@@ -376,6 +429,14 @@ static dc_status_t enqueue(dc_batch *B) {
     TRY(launch_fill_u32(P.kbad, B->K, 0xFFFFFFFFu, s));
     TRY(launch_decode(P, s));
     if (B->have_events) TRY(hipEventRecord(ev[EV_DECODE], s));
+    TRY(launch_leader_scan(P, s));
+    bool plan_changed = false;
+    if (!B->blocks_planned) {
+        e = plan_blocks(B, s);
+        if (e == hipErrorOutOfMemory) return DC_E_OOM;
+        if (e != hipSuccess) return hip_fail(e);
+        plan_changed = true;
+    }
     TRY(launch_number_blocks(P, s));
     TRY(launch_edges(P, s));
     if (B->have_events) TRY(hipEventRecord(ev[EV_CFG], s));
@@ -388,7 +449,6 @@ static dc_status_t enqueue(dc_batch *B) {
         B->runs++;
         return DC_OK;
     }
-    bool plan_changed = false;
     if (!B->ovf_planned) {
         e = plan_overflow(B, s);
         if (e == hipErrorOutOfMemory) return DC_E_OOM;
@@ -398,7 +458,7 @@ static dc_status_t enqueue(dc_batch *B) {
     if (B->opts.flags & DC_OPT_EXPORT_STATES) {
         /* size the state export from the block count */
         uint32_t total = 0;
-        TRY(hipMemcpyAsync(&total, P.total_blocks, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        TRY(hipMemcpyAsync(&total, P.totals, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         TRY(hipStreamSynchronize(s));
         if (total > B->export_blocks || !P.export_states) {
             if (P.export_states) B->mem.release(P.export_states);
@@ -497,14 +557,17 @@ extern "C" dc_status_t dc_batch_run(dc_batch_t *B, const dc_instr_t *instrs, voi
     if (hipSetDevice(B->ctx->device) != hipSuccess) return DC_E_HIP;
     B->stream = (hipStream_t)stream;
     if (instrs && instrs != B->P.instrs) {
+        /* other records: their block counts and record capacities may differ,
+         * so the block-indexed arrays, the regions and the arenas are planned
+         * again on this run */
+        if (hipStreamSynchronize(B->stream) != hipSuccess) return DC_E_HIP;
         B->P.instrs = instrs;
         if (B->graph) {   /* the captured launches hold the old plan */
-            if (hipStreamSynchronize(B->stream) != hipSuccess) return DC_E_HIP;
             hipGraphExecDestroy(B->graph);
             B->graph = nullptr;
         }
-        if (hipMemcpyAsync(B->dP, &B->P, sizeof(Plan), hipMemcpyHostToDevice, B->stream) != hipSuccess) return DC_E_HIP;
-        if (hipStreamSynchronize(B->stream) != hipSuccess) return DC_E_HIP;
+        B->blocks_planned = false;
+        B->ovf_planned = false;
     }
     return enqueue(B);
 }
@@ -773,7 +836,7 @@ static dc_status_t fetch_cfg(dc_batch *B) {
     const Plan &P = B->P;
     const uint32_t K = B->K;
     uint32_t total = 0;
-    hipError_t e = hipMemcpy(&total, P.total_blocks, sizeof(uint32_t), hipMemcpyDeviceToHost);
+    hipError_t e = hipMemcpy(&total, P.totals, sizeof(uint32_t), hipMemcpyDeviceToHost);
     B->k_status.resize(K);
     B->k_nblocks.resize(K);
     B->k_nreach.resize(K);

@@ -585,7 +585,9 @@ __device__ __forceinline__ void lds_put_u64(WaveLds &L, uint64_t *dst, uint64_t 
 /* record output                                                        */
 /* ------------------------------------------------------------------ */
 struct Emit {
-    uint32_t ta, ts;   /* records written for this visit (uniform) */
+    uint32_t ta, ts;       /* records emitted in this visit (uniform) */
+    uint32_t ab, acap;     /* the block's access-record region: first slot, capacity */
+    uint32_t sb, scap;     /* its built-in-record region */
 };
 
 __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t x, uint32_t &total) {
@@ -613,7 +615,7 @@ __device__ __forceinline__ uint4 load_chunk(const Plan *__restrict__ P, uint64_t
 }
 
 __device__ __forceinline__ void run_chunk(const Plan *__restrict__ P, WaveLds &L, const KCtx2 &KX, uint4 r,
-                                          uint32_t pos0, uint32_t g0, uint32_t cnt, uint32_t g_lo, Emit &E,
+                                          uint32_t pos0, uint32_t g0, uint32_t cnt, Emit &E,
                                           uint4 *dummy) {
     const uint32_t l = lane_id();
     const KCtx &K = KX.K;
@@ -935,7 +937,9 @@ __device__ __forceinline__ void run_chunk(const Plan *__restrict__ P, WaveLds &L
         }
         const uint64_t am = ballot(mem);
         const uint32_t apos = E.ta + lanes_below(am);
-        uint4 *adst = mem ? reinterpret_cast<uint4 *>(P->acc_sparse) + g_lo + apos : dummy + l;
+        /* a region holds every record its block can emit; the bound only
+         * keeps a wrong capacity from writing outside it */
+        uint4 *adst = mem && apos < E.acap ? reinterpret_cast<uint4 *>(P->acc_sparse) + E.ab + apos : dummy + l;
         *adst = make_uint4(g0 + l - pos0, kind | space << 8 | width << 16 | dt << 24, (uint32_t)addr,
                            (uint32_t)(addr >> 32));
         E.ta += (uint32_t)__builtin_popcountll(am);
@@ -960,7 +964,7 @@ __device__ __forceinline__ void run_chunk(const Plan *__restrict__ P, WaveLds &L
             uint32_t dim = 0;
             const int kd = sys_kind(j, dim);
             const bool has = kd >= 0;
-            uint2 *sdst = has ? reinterpret_cast<uint2 *>(P->sys_sparse) + 4ull * g_lo + spos
+            uint2 *sdst = has && spos < E.scap ? reinterpret_cast<uint2 *>(P->sys_sparse) + E.sb + spos
                               : reinterpret_cast<uint2 *>(dummy + l);
             *sdst = make_uint2(g0 + l - pos0, (r0 + j) | (uint32_t)(has ? kd : 0) << 16 | (has ? dim : 0u) << 24);
             spos += has ? 1u : 0u;
@@ -1137,15 +1141,19 @@ __device__ __forceinline__ void analyze(const Plan *__restrict__ P, uint32_t k, 
             __builtin_amdgcn_wave_barrier();
             Emit E;
             E.ta = E.ts = 0;
+            E.ab = rfl(P->blk_acc_base[fb + b]);
+            E.acap = rfl(P->blk_acc_base[fb + b + 1]) - E.ab;
+            E.sb = rfl(P->blk_sys_base[fb + b]);
+            E.scap = rfl(P->blk_sys_base[fb + b + 1]) - E.sb;
             /* records of the next chunk are in flight while a chunk runs */
             uint4 rnext = load_chunk(P, rb, pos0, g_lo, min(64u, g_hi - g_lo));
             for (uint32_t g0 = g_lo; g0 < g_hi; g0 += 64) {
                 const uint4 r = rnext;
                 if (g0 + 64 < g_hi) rnext = load_chunk(P, rb, pos0, g0 + 64, min(64u, g_hi - g0 - 64));
-                run_chunk(P, L, KX, r, pos0, g0, min(64u, g_hi - g0), g_lo, E, M.dummy);
+                run_chunk(P, L, KX, r, pos0, g0, min(64u, g_hi - g0), E, M.dummy);
             }
-            P->blk_acc[fb + b] = E.ta;
-            P->blk_sys[fb + b] = E.ts;
+            P->blk_acc[fb + b] = min(E.ta, E.acap);
+            P->blk_sys[fb + b] = min(E.ts, E.scap);
             const uint32_t chg = state_join2(L, a0, first0, a1, first1, nu_pad);
             if (first0) reached.set((uint32_t)ps0);
             if (first1) reached.set((uint32_t)ps1);
@@ -1290,7 +1298,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         const uint32_t idx = rfl(atomicAdd(&P->counters[OVF ? 2 : 0], l == 0 ? 1u : 0u));
         const uint32_t limit = OVF ? rfl(P->counters[1]) : P->n_kernels;
         if (idx >= limit) break;
-        const uint32_t k = OVF ? rfl(P->ovf_list[idx]) : idx;
+        const uint32_t k = OVF ? rfl(P->ovf_list[idx]) : (P->work_order ? rfl(P->work_order[idx]) : idx);
         const int32_t status = (int32_t)rfl((uint32_t)P->status[k]);
         if (status != ST_OK_FIX) {
             fail_kernel(P, k, status, M);
@@ -1311,7 +1319,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             analyze(P, k, L, reached, dirty, M, nu);
         } else {
             if (nb > P->ovf_block_cap || rows > cap_rows) {   /* more blocks than the pass was planned for */
-                fail_kernel(P, k, DC_E_UNSUPPORTED, M);
+                fail_kernel(P, k, DC_E_CAPACITY, M);
                 continue;
             }
             const uint32_t words = (P->ovf_block_cap + 31) >> 5;

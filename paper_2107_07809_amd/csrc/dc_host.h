@@ -39,6 +39,12 @@ struct DevMem {
         bytes_total += bytes;
         return static_cast<T *>(p);
     }
+    void reset() {
+        for (void *p : ptrs) hipFree(p);
+        ptrs.clear();
+        failed = false;
+        bytes_total = 0;
+    }
     void release(void *p) {
         auto it = std::find(ptrs.begin(), ptrs.end(), p);
         if (it != ptrs.end()) {
@@ -74,17 +80,28 @@ struct PlanDims {
     uint32_t arena_rows;
 };
 
+/* device bytes per block and per record slot of alloc_blocks */
+constexpr uint64_t BLOCK_BYTES_CFG = 4 + 4 + 8 + 4 + 4 + 8 + 4 + 4 + 4 + 1;
+constexpr uint64_t BLOCK_BYTES = BLOCK_BYTES_CFG + 32 + 4 * 2 + 4 * 4;
+constexpr uint64_t ACC_SLOT_BYTES = 2 * 16, SYS_SLOT_BYTES = 2 * 8;
+
 /* Device input tables of a plan (the Plan holds them as const pointers). */
 struct PlanInputs {
     dc_kernel_t *kernels;
     dc_arg_t *args;
     uint32_t *pos_begin;
     int32_t *desc_status;
+    uint32_t *work_order;   /* analysis plans only */
 };
 
-/* Allocate every device array of P for dims d from M (M.failed on error).
- * The overflow arena, the state export and the counts in P are left to the
- * caller. */
+/* Allocate the per-kernel and per-position device arrays of P for dims d
+ * (and, for an analysis, the main-pass arena) from M (M.failed on error).
+ * The block-indexed arrays, the overflow arena, the state export and the
+ * counts in P are left to the caller. */
 PlanInputs alloc_plan(DevMem &M, Plan &P, const PlanDims &d);
+/* Allocate the block-indexed arrays of P for `blocks` global blocks and,
+ * for an analysis, the record regions for `acc` access and `sys` built-in
+ * record slots. */
+void alloc_blocks(DevMem &M, Plan &P, uint64_t blocks, uint64_t acc, uint64_t sys, bool cfg_only);
 
 }  // namespace dc

@@ -12,7 +12,9 @@ constexpr int NSLOT = DC_NSLOT;
 constexpr int N_OPS = 77;
 
 /* Device-side view of one planned batch.  Positions are this batch's own
- * dense numbering of instructions: kernel k owns [pos_begin[k], pos_begin[k+1]). */
+ * dense numbering of instructions: kernel k owns [pos_begin[k], pos_begin[k+1]).
+ * Arrays are indexed by position (sized n_pos), by global block (sized by
+ * blk_cap, the block count the plan was made for) or by record capacity. */
 struct Plan {
     /* inputs (device) */
     const dc_instr_t *instrs;
@@ -20,31 +22,41 @@ struct Plan {
     const dc_arg_t *args;
     const uint32_t *pos_begin;      /* K + 1 */
     const int32_t *desc_status;     /* K: descriptor check done on the host */
+    const uint32_t *work_order;     /* K: the order in which the fixpoint takes kernels (longest first); null =
+                                       index order */
     uint32_t n_kernels;
     uint32_t n_pos;                 /* total instructions */
     uint64_t n_records;
     uint64_t n_args;
 
-    /* CFG stage (device, sized by n_pos as the block-count bound) */
-    uint8_t *leader;                /* n_pos */
+    /* per position */
+    uint8_t *leader;                /* n_pos: leader flag */
+    uint8_t *pcap;                  /* n_pos: record capacity of the instruction: bit 0 one access record,
+                                       bits 3:1 built-in records (explicit definition dwords of a rule that can
+                                       yield a built-in) */
     uint32_t *block_id;             /* n_pos: global block id of each position */
-    uint32_t *block_start;          /* n_pos + 1: first position of each global block; [total] = n_pos */
-    uint32_t *block_kernel;         /* n_pos */
-    int32_t *succ;                  /* 2 * n_pos: local ids */
-    uint32_t *pred_cnt;             /* n_pos + 1 (count, then exclusive offsets) */
-    uint32_t *pred_fill;            /* n_pos */
-    uint32_t *pred;                 /* 2 * n_pos: local ids */
-    uint32_t *rpo;                  /* n_pos: local ids, per kernel at first_block */
-    int32_t *rpo_pos;               /* n_pos: position of each block in its kernel's RPO, -1 unreachable */
-    uint32_t *dfs_stack;            /* n_pos */
-    uint8_t *dfs_seen;              /* n_pos */
+    uint32_t *totals;               /* [0] blocks, [1] access capacity, [2] built-in capacity of the batch */
+    /* per global block (blk_cap entries, +1 where noted) */
+    uint32_t blk_cap;
+    uint32_t *block_start;          /* +1: first position of each global block; [total] = n_pos */
+    uint32_t *block_kernel;
+    int32_t *succ;                  /* 2 per block: local ids */
+    uint32_t *pred_cnt;             /* +1 (count, then exclusive offsets) */
+    uint32_t *pred_fill;
+    uint32_t *pred;                 /* 2 per block: local ids */
+    uint32_t *rpo;                  /* local ids, per kernel at first_block */
+    int32_t *rpo_pos;               /* position of each block in its kernel's RPO, -1 unreachable */
+    uint32_t *dfs_stack;
+    uint8_t *dfs_seen;
+    uint32_t *blk_acc_base;         /* +1: first access-record slot of the block's region (exclusive scan of the
+                                       access capacity of its instructions); [total] = access capacity */
+    uint32_t *blk_sys_base;         /* +1: the same for built-in records */
     uint32_t *kbad;                 /* K: first bad record, (index << 2) | code */
     int32_t *status;                /* K */
     uint32_t *first_block;          /* K */
     uint32_t *n_blocks;             /* K */
     uint32_t *n_reach;              /* K */
-    uint32_t *total_blocks;         /* 1 */
-    uint4 *binfo;                   /* 2 * n_pos, per kernel at first_block, by RPO position: {local id, first
+    uint4 *binfo;                   /* 2 per block, per kernel at first_block, by RPO position: {local id, first
                                        position, end position, 0}, {RPO position of successor 0, of successor 1,
                                        chained successor (0, 1; 2 = none), 0} (-1 when absent); null for
                                        CFG-only batches */
@@ -63,21 +75,22 @@ struct Plan {
     uint32_t *counters;             /* [0] work counter, [1] overflow count, [2] overflow work counter */
     uint32_t sweep_cap;
     uint32_t flags;
-    dc_access_t *acc_sparse;        /* n_pos: a block's records from its first position */
-    dc_sysval_t *sys_sparse;        /* 4 * n_pos: a block's records from 4 x its first position */
-    uint32_t *blk_acc;              /* n_pos (per global block): access records of the last visit */
-    uint32_t *blk_sys;              /* n_pos: built-in records of the last visit */
+    uint32_t acc_cap, sys_cap;      /* record slots allocated (acc_sparse/acc_dense, sys_sparse/sys_dense) */
+    dc_access_t *acc_sparse;        /* acc_cap: a block's records in its region */
+    dc_sysval_t *sys_sparse;        /* sys_cap */
+    uint32_t *blk_acc;              /* per block: access records of the last visit */
+    uint32_t *blk_sys;              /* per block: built-in records of the last visit */
     dc_kernel_result_t *results;    /* K */
     dc_reg_state_t *export_states;  /* total_blocks * NSLOT (DC_OPT_EXPORT_STATES) */
     uint8_t *export_reached;        /* total_blocks */
 
     /* compaction */
-    uint32_t *blk_acc_off;          /* n_pos: exclusive scan of blk_acc over the blocks */
-    uint32_t *blk_sys_off;          /* n_pos */
+    uint32_t *blk_acc_off;          /* per block: exclusive scan of blk_acc over the blocks */
+    uint32_t *blk_sys_off;          /* per block */
     uint32_t *acc_count;            /* K + 1 -> exclusive offsets */
     uint32_t *sys_count;            /* K + 1 */
-    dc_access_t *acc_dense;         /* n_pos */
-    dc_sysval_t *sys_dense;         /* 4 * n_pos */
+    dc_access_t *acc_dense;         /* acc_cap */
+    dc_sysval_t *sys_dense;         /* sys_cap */
 
     /* scan scratch */
     uint32_t *scan_tmp;             /* scan_tmp_words */
@@ -93,8 +106,9 @@ struct FixCfg {
 /* stage launchers (enqueue only; return hipSuccess or the launch error) */
 hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t *p, uint64_t n, uint8_t v, hipStream_t s);
-hipError_t launch_decode(const Plan &P, hipStream_t s);                 /* decode, checks, leaders */
-hipError_t launch_number_blocks(const Plan &P, hipStream_t s);          /* block numbering */
+hipError_t launch_decode(const Plan &P, hipStream_t s);                 /* decode, checks, leaders, capacities */
+hipError_t launch_leader_scan(const Plan &P, hipStream_t s);            /* block count (totals[0]) */
+hipError_t launch_number_blocks(const Plan &P, hipStream_t s);          /* block numbering, record regions */
 hipError_t launch_edges(const Plan &P, hipStream_t s);                  /* edges, predecessors, RPO, statuses */
 /* entry state, fixpoint, extraction; dP = device copy of P; optional events bracket the main launch */
 hipError_t launch_fixpoint(const Plan &P, const Plan *dP, const FixCfg &c, hipStream_t s, hipEvent_t before,
@@ -107,5 +121,6 @@ constexpr uint32_t FIX_MAX_ROWS = 6;                                    /* state
 constexpr uint32_t OVF_MAX_WAVES = 512;                                 /* waves of the overflow pass */
 constexpr uint64_t ARENA_BUDGET = 8ull << 30;                           /* arena bytes of either pass */
 uint64_t scan_tmp_words_needed(uint64_t n);
+uint64_t cap_scan_words(uint64_t n);   /* extra scan words of the capacity scan of n positions */
 
 }  // namespace dc

@@ -5,16 +5,24 @@
  * Stages (all integer work; no MFMA):
  *   decode   k_decode     one thread per instruction: coalesced 16-byte
  *                         record loads, opcode-table lookup, record checks,
- *                         leader flags (textbook basic-block leaders)
+ *                         leader flags (textbook basic-block leaders), record
+ *                         capacities (access and built-in records the
+ *                         instruction can emit)
  *   number   k_scan_*     reduce-then-scan of the leader flags over the whole
  *                         batch: global block ids, block_start
+ *            k_cap_*      scan of the capacities: each block's record region
  *   graph    k_kernel_info, k_edges, k_pred_*, k_order
  *                         successors, predecessor CSR (count, scan, scatter,
  *                         sort), reverse postorder, per-kernel status
  *   fixpoint k_fixpoint   in dc_fixpoint.hip
- *   out      k_blk_*, k_finish, k_compact
+ *   out      k_finish, k_compact
  *                         scans of the per-block record counts, per-kernel
  *                         totals, dense output records in instruction order
+ *
+ * Block-indexed arrays hold P.blk_cap blocks (the count the batch was planned
+ * for); every kernel bounds its block indices by it, and a batch whose
+ * records have more blocks or record capacity than planned fails every kernel
+ * with DC_E_CAPACITY instead of writing past an array.
  */
 #include "dc_device.h"
 
@@ -165,6 +173,29 @@ __device__ __forceinline__ uint32_t lookup(const uint32_t *pos_begin, uint32_t K
 /* ------------------------------------------------------------------ */
 /* decode, check, leader flags                                          */
 /* ------------------------------------------------------------------ */
+/* Record capacity of one instruction: one access record for a memory
+ * instruction; one built-in record per explicit definition dword of a rule
+ * that can yield a work-item built-in (moves, selects, adds, multiplies,
+ * shifts, argument loads).  The other rules yield only constants, pointer
+ * halves, sign words or unknowns, none of which is a built-in.  Packed as
+ * bit 0 (access) and bits 3:1 (built-ins). */
+__device__ __forceinline__ uint32_t rec_cap(uint64_t e) {
+    const uint32_t cls = e_cls(e), pr = e_prule(e), r0 = e_role(e, 0);
+    const uint32_t acc = cls >= C_GLD ? 1u : 0u;
+    const bool alu = cls == C_SALU || cls == C_VALU;
+    const bool can = cls == C_SMEM || (alu && (pr == PR_MOV || pr == PR_SEL || pr == PR_ADD || pr == PR_MUL ||
+                                               pr == PR_MUL24 || pr == PR_MAD24 || pr == PR_SHL || pr == PR_LSHR ||
+                                               pr == PR_SHL64));
+    const uint32_t sys = can && (r0 == RO_SD || r0 == RO_VD) ? e_width(e, 0) : 0u;
+    return acc | sys << 1;
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t x) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+    return x;
+}
+
 __global__ __launch_bounds__(256) void k_decode(Plan P) {
     __shared__ uint32_t lk[LK_CAP];
     const uint32_t t0 = blockIdx.x * TILE_LK;
@@ -172,6 +203,7 @@ __global__ __launch_bounds__(256) void k_decode(Plan P) {
     const uint32_t t1 = min(P.n_pos, t0 + TILE_LK);
     uint32_t k0, cnt;
     lookup_setup(P.pos_begin, P.n_kernels, t0, t1, lk, &k0, &cnt);
+    uint32_t sum_a = 0, sum_s = 0;
     for (uint32_t g = t0 + threadIdx.x; g < t1; g += blockDim.x) {
         const uint32_t k = lookup(P.pos_begin, P.n_kernels, lk, k0, cnt, g);
         const uint32_t pb = P.pos_begin[k];
@@ -184,16 +216,30 @@ __global__ __launch_bounds__(256) void k_decode(Plan P) {
         const uint32_t bad = check_record(op, r0, r1, r2, imm, target, n);
         if (i == 0) P.leader[g] = 1;
         if (bad) {
+            P.pcap[g] = 0;
             atomicMin(&P.kbad[k], (i << 2) | bad);
             continue;
         }
-        const uint32_t cls = e_cls(OPTAB[op]);
+        const uint64_t e = OPTAB[op];
+        const uint32_t cls = e_cls(e);
+        const uint32_t c = rec_cap(e);
+        P.pcap[g] = (uint8_t)c;
+        sum_a += c & 1u;
+        sum_s += c >> 1;
         if (ends_block(cls) && i + 1 < n) P.leader[g + 1] = 1;
         if (cls == C_BR || cls == C_CBR) P.leader[pb + (uint32_t)target] = 1;
     }
+    /* batch totals of the capacities: one atomic per wavefront */
+    sum_a = wave_sum(sum_a);
+    sum_s = wave_sum(sum_s);
+    if (lane_id() == 0) {
+        atomicAdd(&P.totals[1], sum_a);
+        atomicAdd(&P.totals[2], sum_s);
+    }
 }
 hipError_t launch_decode(const Plan &P, hipStream_t s) {
-    if (!P.n_pos) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, P.totals, (uint64_t)4, 0u);
+    if (!P.n_pos) return hipGetLastError();
     uint32_t tiles = (P.n_pos + TILE_LK - 1) / TILE_LK;
     hipLaunchKernelGGL(k_decode, dim3(tiles), dim3(256), 0, s, P);
     return hipGetLastError();
@@ -280,6 +326,10 @@ __global__ __launch_bounds__(256) void k_scan_apply(const T *in, uint64_t n, con
     if (total_out && blockIdx.x == gridDim.x - 1 && threadIdx.x == 255) *total_out = tile_offs[blockIdx.x] + tot;
 }
 
+/* words after scan_tmp_words_needed(n) that the capacity scan of n positions
+ * uses for its two tile-sum arrays */
+uint64_t cap_scan_words(uint64_t n) { return 2 * ((n + SCAN_TILE - 1) / SCAN_TILE + 1) + 16; }
+
 uint64_t scan_tmp_words_needed(uint64_t n) {
     uint64_t words = 0;
     while (true) {
@@ -332,26 +382,94 @@ __global__ __launch_bounds__(256) void k_number(Plan P, const uint32_t *excl) {
         const uint32_t l = P.leader[g];
         const uint32_t id = excl[g] + l - 1;
         P.block_id[g] = id;
-        if (l) {
+        if (l && id < P.blk_cap) {
             P.block_start[id] = g;
             P.block_kernel[id] = lookup(P.pos_begin, P.n_kernels, lk, k0, cnt, g);
         }
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) P.block_start[*P.total_blocks] = P.n_pos;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && P.totals[0] <= P.blk_cap) P.block_start[P.totals[0]] = P.n_pos;
+}
+
+/* Record regions.  Each block's access (built-in) records go to a region of
+ * the sparse output as long as the access (built-in) capacity of its
+ * instructions; the region starts at the exclusive prefix sum of the
+ * capacities at the block's first position.  The two capacity fields of a
+ * tile are summed as one word (access count in bits 15:0, built-ins in
+ * 31:16: a tile of 4096 positions holds at most 4096 and 16384). */
+__device__ __forceinline__ uint32_t cap_pack(uint32_t c) { return (c & 1u) | (c >> 1) << 16; }
+
+__global__ __launch_bounds__(256) void k_cap_reduce(Plan P, uint32_t *sums_a, uint32_t *sums_s) {
+    const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE + (uint64_t)threadIdx.x * SCAN_ITEMS;
+    uint32_t x = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; j++) x += base + j < P.n_pos ? cap_pack(P.pcap[base + j]) : 0u;
+    uint32_t excl;
+    const uint32_t tot = block_excl_scan(x, &excl);
+    if (threadIdx.x == 0) {
+        sums_a[blockIdx.x] = tot & 0xFFFFu;
+        sums_s[blockIdx.x] = tot >> 16;
+    }
+}
+
+/* offs_a/offs_s: exclusive tile offsets */
+__global__ __launch_bounds__(256) void k_cap_apply(Plan P, const uint32_t *offs_a, const uint32_t *offs_s) {
+    const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE + (uint64_t)threadIdx.x * SCAN_ITEMS;
+    uint32_t c[SCAN_ITEMS];
+    uint32_t x = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; j++) {
+        c[j] = base + j < P.n_pos ? cap_pack(P.pcap[base + j]) : 0u;
+        x += c[j];
+    }
+    uint32_t excl;
+    block_excl_scan(x, &excl);
+    uint32_t ra = offs_a[blockIdx.x] + (excl & 0xFFFFu), rs = offs_s[blockIdx.x] + (excl >> 16);
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; j++) {
+        if (base + j < P.n_pos && P.leader[base + j]) {
+            const uint32_t id = P.block_id[base + j];
+            if (id < P.blk_cap) {
+                P.blk_acc_base[id] = ra;
+                P.blk_sys_base[id] = rs;
+            }
+        }
+        ra += c[j] & 0xFFFFu;
+        rs += c[j] >> 16;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && P.totals[0] <= P.blk_cap) {
+        P.blk_acc_base[P.totals[0]] = P.totals[1];
+        P.blk_sys_base[P.totals[0]] = P.totals[2];
+    }
+}
+
+hipError_t launch_leader_scan(const Plan &P, hipStream_t s) {
+    if (!P.n_pos) return hipSuccess;   /* totals[0] = 0 from the decode stage */
+    /* the exclusive leader counts go to block_id first; k_number rewrites
+     * block_id in place (each position reads its own entry before writing) */
+    return scan_excl<uint8_t>(P.leader, P.n_pos, P.block_id, P.totals, P.scan_tmp, s);
 }
 
 hipError_t launch_number_blocks(const Plan &P, hipStream_t s) {
     if (!P.n_pos) {
-        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, P.total_blocks, (uint64_t)1, 0u);
-        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, P.block_start, (uint64_t)1, 0u);
+        if (P.blk_cap) {
+            hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, P.block_start, (uint64_t)1, 0u);
+            if (P.blk_acc_base) {
+                hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, P.blk_acc_base, (uint64_t)1, 0u);
+                hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, P.blk_sys_base, (uint64_t)1, 0u);
+            }
+        }
         return hipGetLastError();
     }
-    /* the exclusive leader counts go to block_id first, then k_number rewrites
-     * block_id in place (each position reads its own entry before writing) */
-    hipError_t e = scan_excl<uint8_t>(P.leader, P.n_pos, P.block_id, P.total_blocks, P.scan_tmp, s);
-    if (e != hipSuccess) return e;
-    uint32_t tiles = (P.n_pos + TILE_LK - 1) / TILE_LK;
+    const uint32_t tiles = (P.n_pos + TILE_LK - 1) / TILE_LK;
     hipLaunchKernelGGL(k_number, dim3(tiles), dim3(256), 0, s, P, P.block_id);
+    if (!P.blk_acc_base) return hipGetLastError();   /* graph only: no record regions */
+    const uint64_t ct = ((uint64_t)P.n_pos + SCAN_TILE - 1) / SCAN_TILE;
+    uint32_t *sums_a = P.scan_tmp + P.scan_tmp_words, *sums_s = sums_a + ct + 1;
+    hipLaunchKernelGGL(k_cap_reduce, dim3((uint32_t)ct), dim3(256), 0, s, P, sums_a, sums_s);
+    hipError_t e = scan_excl<uint32_t>(sums_a, ct, sums_a, nullptr, P.scan_tmp, s);
+    if (e == hipSuccess) e = scan_excl<uint32_t>(sums_s, ct, sums_s, nullptr, P.scan_tmp, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cap_apply, dim3((uint32_t)ct), dim3(256), 0, s, P, sums_a, sums_s);
     return hipGetLastError();
 }
 
@@ -379,18 +497,26 @@ __global__ void k_kernel_info(Plan P) {
             if (!(cls == C_BR || cls == C_END)) st = DC_E_NOEND;
         }
     }
-    P.status[k] = st;
     uint32_t fb = 0, nb = 0;
     if (n) {
         fb = P.block_id[pb];
         nb = P.block_id[pb + n - 1] - fb + 1;
     }
+    /* records changed since the batch was planned: more blocks or record
+     * capacity than its arrays hold */
+    const bool over = P.totals[0] > P.blk_cap ||
+                      (P.acc_sparse && (P.totals[1] > P.acc_cap || P.totals[2] > P.sys_cap));
+    if (over) {
+        st = DC_E_CAPACITY;
+        nb = 0;
+    }
+    P.status[k] = st;
     P.first_block[k] = fb;
     P.n_blocks[k] = nb;
 }
 
 __global__ void k_edges(Plan P) {
-    const uint32_t total = *P.total_blocks;
+    const uint32_t total = min(P.totals[0], P.blk_cap);
     for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < total; b += gridDim.x * blockDim.x) {
         const uint32_t k = P.block_kernel[b];
         int32_t s0 = -1, s1 = -1;
@@ -412,7 +538,7 @@ __global__ void k_edges(Plan P) {
 }
 
 __global__ void k_pred_scatter(Plan P) {
-    const uint32_t total = *P.total_blocks;
+    const uint32_t total = min(P.totals[0], P.blk_cap);
     for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < total; b += gridDim.x * blockDim.x) {
         const uint32_t k = P.block_kernel[b];
         const uint32_t fb = P.first_block[k];
@@ -486,7 +612,7 @@ __global__ void k_order(Plan P) {
  * RPO positions of the successors, -1 when absent, and which successor, if
  * any, has this block as its only predecessor) */
 __global__ void k_blockinfo(Plan P) {
-    const uint32_t total = *P.total_blocks;
+    const uint32_t total = min(P.totals[0], P.blk_cap);
     for (uint32_t gb = blockIdx.x * blockDim.x + threadIdx.x; gb < total; gb += gridDim.x * blockDim.x) {
         const uint32_t k = P.block_kernel[gb];
         if (P.status[k] != ST_OK) continue;
@@ -513,13 +639,13 @@ __global__ void k_blockinfo(Plan P) {
 hipError_t launch_edges(const Plan &P, hipStream_t s) {
     const uint32_t K = P.n_kernels;
     if (K) hipLaunchKernelGGL(k_kernel_info, dim3((K + 255) / 256), dim3(256), 0, s, P);
-    hipError_t e = launch_fill_u32(P.pred_cnt, (uint64_t)P.n_pos + 1, 0u, s);
+    hipError_t e = launch_fill_u32(P.pred_cnt, (uint64_t)P.blk_cap + 1, 0u, s);
     if (e != hipSuccess) return e;
-    e = launch_fill_u32(P.pred_fill, (uint64_t)P.n_pos, 0u, s);
+    e = launch_fill_u32(P.pred_fill, (uint64_t)P.blk_cap, 0u, s);
     if (e != hipSuccess) return e;
-    const uint32_t grid = grid_for(P.n_pos ? P.n_pos : 1, 256 * 4);
+    const uint32_t grid = grid_for(P.blk_cap ? P.blk_cap : 1, 256 * 4);
     hipLaunchKernelGGL(k_edges, dim3(grid), dim3(256), 0, s, P);
-    e = scan_excl<uint32_t>(P.pred_cnt, (uint64_t)P.n_pos + 1, P.pred_cnt, nullptr, P.scan_tmp, s);
+    e = scan_excl<uint32_t>(P.pred_cnt, (uint64_t)P.blk_cap + 1, P.pred_cnt, nullptr, P.scan_tmp, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_pred_scatter, dim3(grid), dim3(256), 0, s, P);
     if (K) hipLaunchKernelGGL(k_order, dim3((K + 63) / 64), dim3(64), 0, s, P);
@@ -533,7 +659,7 @@ hipError_t launch_edges(const Plan &P, hipStream_t s) {
 /* ------------------------------------------------------------------ */
 /* The fixpoint leaves, per global block, the number of access and built-in
  * records of the block's last visit (zero for unreached blocks and failed
- * kernels) and the records themselves at the block's positions.  Blocks are
+ * kernels) and the records themselves in the block's regions.  Blocks are
  * numbered in position order, so exclusive scans of the counts are the dense
  * offsets directly. */
 __global__ void k_finish(Plan P) {
@@ -541,7 +667,7 @@ __global__ void k_finish(Plan P) {
     if (k >= P.n_kernels) return;
     const uint32_t fb = P.first_block[k], nb = P.n_blocks[k];
     uint32_t na = 0, ns = 0;
-    if (nb) {
+    if (nb && fb + nb <= P.blk_cap) {
         const uint32_t lb = fb + nb - 1;
         na = P.blk_acc_off[lb] + P.blk_acc[lb] - P.blk_acc_off[fb];
         ns = P.blk_sys_off[lb] + P.blk_sys[lb] - P.blk_sys_off[fb];
@@ -557,27 +683,35 @@ __global__ void k_count_tail(Plan P) {
         P.sys_count[P.n_kernels] = 0;
     }
 }
-/* one thread per position: copy the position's access record and its four
- * built-in slots when they lie within the block's final counts */
+/* one thread per global block: its records, from its regions of the sparse
+ * outputs to its dense offsets */
 __global__ __launch_bounds__(256) void k_compact(Plan P) {
-    const uint32_t total = *P.total_blocks;
-    for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < P.n_pos; g += gridDim.x * blockDim.x) {
-        const uint32_t gb = P.block_id[g];
-        if (gb >= total) continue;
-        const uint32_t o = g - P.block_start[gb];
-        if (o < P.blk_acc[gb]) P.acc_dense[P.blk_acc_off[gb] + o] = P.acc_sparse[g];
-        const uint32_t ns = P.blk_sys[gb];
-#pragma unroll
-        for (uint32_t q = 0; q < 4; q++)
-            if (4 * o + q < ns) P.sys_dense[P.blk_sys_off[gb] + 4 * o + q] = P.sys_sparse[4ull * g + q];
+    /* records that outgrew the plan: every kernel failed, nothing to copy
+     * (the counts of the blocks are stale) */
+    if (P.totals[0] > P.blk_cap || P.totals[1] > P.acc_cap || P.totals[2] > P.sys_cap) return;
+    const uint32_t total = P.totals[0];
+    for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < total; b += gridDim.x * blockDim.x) {
+        uint32_t na = P.blk_acc[b], ns = P.blk_sys[b];
+        na = P.blk_acc_base[b] + na <= P.acc_cap && P.blk_acc_off[b] + na <= P.acc_cap ? na : 0u;
+        ns = P.blk_sys_base[b] + ns <= P.sys_cap && P.blk_sys_off[b] + ns <= P.sys_cap ? ns : 0u;
+        if (na) {
+            const uint4 *src = reinterpret_cast<const uint4 *>(P.acc_sparse) + P.blk_acc_base[b];
+            uint4 *dst = reinterpret_cast<uint4 *>(P.acc_dense) + P.blk_acc_off[b];
+            for (uint32_t i = 0; i < na; i++) dst[i] = src[i];
+        }
+        if (ns) {
+            const uint2 *src = reinterpret_cast<const uint2 *>(P.sys_sparse) + P.blk_sys_base[b];
+            uint2 *dst = reinterpret_cast<uint2 *>(P.sys_dense) + P.blk_sys_off[b];
+            for (uint32_t i = 0; i < ns; i++) dst[i] = src[i];
+        }
     }
 }
 hipError_t launch_compact(const Plan &P, hipStream_t s) {
     const uint32_t K = P.n_kernels;
-    hipError_t e = scan_excl<uint32_t>(P.blk_acc, (uint64_t)P.n_pos, P.blk_acc_off, nullptr, P.scan_tmp, s,
-                                       P.total_blocks);
+    hipError_t e = scan_excl<uint32_t>(P.blk_acc, (uint64_t)P.blk_cap, P.blk_acc_off, nullptr, P.scan_tmp, s,
+                                       P.totals);
     if (e != hipSuccess) return e;
-    e = scan_excl<uint32_t>(P.blk_sys, (uint64_t)P.n_pos, P.blk_sys_off, nullptr, P.scan_tmp, s, P.total_blocks);
+    e = scan_excl<uint32_t>(P.blk_sys, (uint64_t)P.blk_cap, P.blk_sys_off, nullptr, P.scan_tmp, s, P.totals);
     if (e != hipSuccess) return e;
     if (K) hipLaunchKernelGGL(k_finish, dim3((K + 255) / 256), dim3(256), 0, s, P);
     hipLaunchKernelGGL(k_count_tail, dim3(1), dim3(64), 0, s, P);
@@ -585,7 +719,7 @@ hipError_t launch_compact(const Plan &P, hipStream_t s) {
     if (e != hipSuccess) return e;
     e = scan_excl<uint32_t>(P.sys_count, (uint64_t)K + 1, P.sys_count, nullptr, P.scan_tmp, s);
     if (e != hipSuccess) return e;
-    if (P.n_pos) hipLaunchKernelGGL(k_compact, dim3(grid_for(P.n_pos, 256 * 4)), dim3(256), 0, s, P);
+    if (P.blk_cap) hipLaunchKernelGGL(k_compact, dim3(grid_for(P.blk_cap, 256 * 2)), dim3(256), 0, s, P);
     return hipGetLastError();
 }
 

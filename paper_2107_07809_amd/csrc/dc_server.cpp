@@ -101,6 +101,7 @@ struct Lane {
     Pinned<dc_arg_t> h_a;
     Pinned<uint32_t> h_pb;
     Pinned<int32_t> h_ds;
+    Pinned<uint32_t> h_order;
     Pinned<Plan> h_plan;
     Pinned<dc_kernel_result_t> h_res;
     Pinned<uint32_t> h_acc_off, h_sys_off;
@@ -119,10 +120,11 @@ constexpr uint32_t LANE_ARENA_ROWS = 512;            /* main-pass rows per wave 
 constexpr uint64_t LANE_INSTR_MAX = 4ull << 20;      /* largest lane, in instructions */
 constexpr uint64_t OVF_BUDGET_BYTES = 1ull << 30;    /* overflow arenas per lane */
 constexpr uint64_t ROW_BYTES = FIX_ROW_DWORDS * 4ull;
-/* device bytes per instruction of a lane's arrays (records, CFG, records
- * out, compaction; see alloc_plan) and per kernel */
-constexpr uint64_t BYTES_PER_INSTR = 16 + 1 + 4 + 4 + 4 + 8 + 4 + 4 + 8 + 4 + 4 + 4 + 1 + 32 + 16 + 32 + 4 + 4 + 4 + 4 +
-                                     16 + 32 + 8;
+/* device bytes per instruction of a lane's arrays: records, the
+ * per-position arrays (leader, capacity, block id), the block-indexed arrays
+ * for one block per instruction, one access and four built-in record slots
+ * per instruction (alloc_plan, alloc_blocks), the capacity scan */
+constexpr uint64_t BYTES_PER_INSTR = 16 + 1 + 1 + 4 + BLOCK_BYTES + ACC_SLOT_BYTES + 4 * SYS_SLOT_BYTES + 8;
 constexpr uint64_t BYTES_PER_KERNEL = 32 + 255 * 8 + 4 + 4 + 4 + 4 + 4 + 4 + 4 + 4 + 32 + 4 + 4 + 8;
 
 static_assert(sizeof(dc_request_t) == 56 && sizeof(dc_result_t) == 120, "server ABI layout");
@@ -216,6 +218,10 @@ hipError_t launch(dc_server *S, Lane &L) {
         maxlen = std::max<uint32_t>(maxlen, d.n_instr);
     }
     L.h_pb.p[K] = (uint32_t)N;
+    /* the fixpoint takes the longest requests first */
+    for (uint32_t k = 0; k < K; k++) L.h_order.p[k] = k;
+    std::stable_sort(L.h_order.p, L.h_order.p + K,
+                     [&](uint32_t a, uint32_t b) { return L.h_k.p[a].n_instr > L.h_k.p[b].n_instr; });
     Plan &P = L.P;
     P.n_kernels = K;
     P.n_pos = (uint32_t)N;
@@ -236,10 +242,12 @@ hipError_t launch(dc_server *S, Lane &L) {
     if (A) TRYH(hipMemcpyAsync(L.in.args, L.h_a.p, A * sizeof(dc_arg_t), hipMemcpyHostToDevice, s));
     TRYH(hipMemcpyAsync(L.in.pos_begin, L.h_pb.p, (K + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, s));
     TRYH(hipMemcpyAsync(L.in.desc_status, L.h_ds.p, K * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    TRYH(hipMemcpyAsync(L.in.work_order, L.h_order.p, K * sizeof(uint32_t), hipMemcpyHostToDevice, s));
     TRYH(hipMemcpyAsync(L.dP, L.h_plan.p, sizeof(Plan), hipMemcpyHostToDevice, s));
     TRYH(launch_fill_u8(P.leader, N, 0, s));
     TRYH(launch_fill_u32(P.kbad, K, 0xFFFFFFFFu, s));
     TRYH(launch_decode(P, s));
+    TRYH(launch_leader_scan(P, s));
     TRYH(launch_number_blocks(P, s));
     TRYH(launch_edges(P, s));
     TRYH(launch_fixpoint(P, L.dP, L.fc, s, nullptr, nullptr));
@@ -478,6 +486,9 @@ extern "C" dc_status_t dc_server_create(dc_ctx_t *ctx, const dc_server_opts_t *o
         PlanDims d{lane_instr, S->lane_kernels, S->lane_args, false, waves, LANE_ARENA_ROWS};
         Plan &P = L->P;
         L->in = alloc_plan(L->mem, P, d);
+        /* a lane plans for its worst case: one block, one access and four
+         * built-in records per instruction */
+        alloc_blocks(L->mem, P, lane_instr, lane_instr, 4 * lane_instr, false);
         P.instrs = L->mem.alloc<dc_instr_t>(lane_instr);
         P.ovf_arena = L->mem.alloc<uint32_t>(S->ovf_rows_budget * FIX_ROW_DWORDS);
         P.ovf_bitmaps = L->mem.alloc<uint32_t>(bitmap_words);
@@ -488,6 +499,7 @@ extern "C" dc_status_t dc_server_create(dc_ctx_t *ctx, const dc_server_opts_t *o
                             L->h_a.reserve(S->lane_args) == hipSuccess &&
                             L->h_pb.reserve(S->lane_kernels + 1) == hipSuccess &&
                             L->h_ds.reserve(S->lane_kernels) == hipSuccess && L->h_plan.reserve(1) == hipSuccess &&
+                            L->h_order.reserve(S->lane_kernels) == hipSuccess &&
                             L->h_res.reserve(S->lane_kernels) == hipSuccess &&
                             L->h_acc_off.reserve(S->lane_kernels + 1) == hipSuccess &&
                             L->h_sys_off.reserve(S->lane_kernels + 1) == hipSuccess &&

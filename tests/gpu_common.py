@@ -14,18 +14,29 @@ def _oracle_chunk(args):
     return oracle.analyze_batch(b)
 
 
-def oracle_config(cfg: int, n: int, procs: int = 0):
+class OracleRun:
     """Oracle summaries and dense records for kernels [0, n) of a config,
-    computed in parallel worker processes (each regenerates its shard)."""
-    procs = procs or min(16, os.cpu_count() or 1)
-    step = max(1, (n + procs * 4 - 1) // (procs * 4))
-    jobs = [(cfg, i, min(step, n - i)) for i in range(0, n, step)]
-    with ProcessPoolExecutor(procs) as ex:
-        parts = list(ex.map(_oracle_chunk, jobs))
-    summ = np.concatenate([p[0] for p in parts])
-    acc = np.concatenate([p[1] for p in parts])
-    sys = np.concatenate([p[2] for p in parts])
-    return summ, acc, sys
+    computed in parallel worker processes (each regenerates its shard); the
+    workers start at construction, so the caller can run the GPU meanwhile."""
+
+    def __init__(self, cfg: int, n: int, procs: int = 0, jobs_per_proc: int = 4):
+        procs = procs or min(16, os.cpu_count() or 1)
+        step = max(1, (n + procs * jobs_per_proc - 1) // (procs * jobs_per_proc))
+        self.ex = ProcessPoolExecutor(procs)
+        self.futs = [self.ex.submit(_oracle_chunk, (cfg, i, min(step, n - i))) for i in range(0, n, step)]
+
+    def result(self):
+        parts = [f.result() for f in self.futs]
+        self.ex.shutdown()
+        summ = np.concatenate([p[0] for p in parts])
+        acc = np.concatenate([p[1] for p in parts])
+        sys = np.concatenate([p[2] for p in parts])
+        return summ, acc, sys
+
+
+def oracle_config(cfg: int, n: int, procs: int = 0):
+    """Oracle summaries and dense records for kernels [0, n) of a config."""
+    return OracleRun(cfg, n, procs).result()
 
 
 def compare_summaries(gpu_res, summ, digest: bool = True):

@@ -15,7 +15,7 @@ import pytest
 import asmtext
 import dcgen
 import oracle
-from gpu_common import compare_summaries, oracle_config
+from gpu_common import OracleRun, compare_summaries, oracle_config
 
 pytestmark = pytest.mark.gpu
 
@@ -136,29 +136,67 @@ def test_dense_cfg_main_and_overflow(ctx):
 
 
 def test_c2_full_digest(ctx):
-    """All 65,536 kernels of the 51.2M-instruction workload in the bench's
-    launch configuration: every record and every kernel's state digest; then
-    the run exactly as the bench makes it (no digest, no exported states, so
-    the IN states of chained blocks are never stored), again every record,
-    status, block count and sweep count."""
+    """All 65,536 kernels of the 51.2M-instruction workload: every record and
+    every kernel's state digest; then the run as the bench makes it (no
+    digest, no exported states, so the IN states of chained blocks are never
+    stored) in the launch shape the autotuner picks for it, again every
+    record, status, block count and sweep count."""
     n = 65536
+    orc = OracleRun(2, n)
     b = dcgen.generate(2, n)
     say("c2 full: generated", b.n_instr)
     dev = dc.to_device(b.instrs)
-    say("c2 full: oracle")
-    summ, oacc, osys = oracle_config(2, n)
+    sub = b.subset(np.arange(0, n, 8))
+    sdev = dc.to_device(sub.instrs)
+    shape, ms = ctx.autotune(sub.kernels, sdev, sub.n_instr, sub.args, sample=sub.n_kernels)
+    say(f"c2 full: autotuned shape {shape} ({ms:.2f} ms per run of the sample)")
+    summ, oacc, osys = orc.result()
     say("c2 full: oracle done")
-    for flags, digest in ((dc.OPT_DIGEST, True), (dc.OPT_TIMING, False)):
-        batch = ctx.analyze(b.kernels, dev, b.n_instr, b.args, flags=flags)
+    for flags, digest, kw in ((dc.OPT_DIGEST, True, {}), (dc.OPT_TIMING, False, shape)):
+        batch = ctx.analyze(b.kernels, dev, b.n_instr, b.args, flags=flags, **kw)
         batch.run()
         res = batch.results()
         acc, _ = batch.all_accesses()
         sysv, _ = batch.all_sysvals()
-        say(f"c2 full: gpu done (flags {flags})")
+        say(f"c2 full: gpu done (flags {flags}, {kw})")
         compare_summaries(res, summ, digest=digest)
         assert acc.tobytes() == oacc.tobytes()
         assert sysv.tobytes() == osys.tobytes()
         batch.free()
+
+
+def test_c3_zipf_full(ctx):
+    """All 1,048,576 kernels of the Zipf(1.2) 20-20,000 workload (1.74e9
+    instructions) in one plan, as the bench analyses them: every status,
+    block count, sweep count, record count, state digest and record byte
+    against the oracle (run in worker processes meanwhile); then the run
+    without the digest in the bench's launch shape, every record again."""
+    n = 1048576
+    t = time.time()
+    orc = OracleRun(3, n, jobs_per_proc=16)
+    b = dcgen.generate(3, n)
+    say(f"c3 full: generated {b.n_instr} instructions in {time.time() - t:.1f}s")
+    dev = dc.to_device(b.instrs)
+    torch.cuda.synchronize()
+    say(f"c3 full: uploaded ({time.time() - t:.1f}s)")
+    runs = []
+    for flags, kw in ((dc.OPT_DIGEST, {}), (dc.OPT_TIMING, dict(waves_per_group=2, groups_per_cu=3))):
+        batch = ctx.analyze(b.kernels, dev, b.n_instr, b.args, flags=flags, **kw)
+        batch.run()
+        res = batch.results()
+        acc, _ = batch.all_accesses()
+        sysv, _ = batch.all_sysvals()
+        runs.append((flags, res, acc, sysv))
+        batch.free()
+        say(f"c3 full: gpu done (flags {flags}, {kw}; {time.time() - t:.1f}s)")
+    del dev
+    torch.cuda.empty_cache()
+    summ, oacc, osys = orc.result()
+    say(f"c3 full: oracle done ({time.time() - t:.1f}s)")
+    for flags, res, acc, sysv in runs:
+        compare_summaries(res, summ, digest=flags == dc.OPT_DIGEST)
+        assert acc.tobytes() == oacc.tobytes()
+        assert sysv.tobytes() == osys.tobytes()
 
 
 def _records_and_summaries(ctx, b, summ, oacc, osys, flags, digest, tag):
@@ -174,19 +212,6 @@ def _records_and_summaries(ctx, b, summ, oacc, osys, flags, digest, tag):
     assert sysv.tobytes() == osys.tobytes()
     batch.free()
     return res
-
-
-def test_c3_zipf_65536(ctx):
-    """The first 65,536 kernels of the Zipf(1.2) 20-20,000 workload (about
-    109M instructions): every record, status, sweep count and digest, then
-    again without the digest."""
-    n = 65536
-    b = dcgen.generate(3, n)
-    say("c3 65536: generated", b.n_instr)
-    summ, oacc, osys = oracle_config(3, n)
-    say("c3 65536: oracle done")
-    for flags, digest in ((dc.OPT_DIGEST, True), (0, False)):
-        _records_and_summaries(ctx, b, summ, oacc, osys, flags, digest, "c3 65536")
 
 
 def test_c5_lognormal_65536(ctx):
@@ -370,6 +395,64 @@ def test_errors_do_not_poison_batch(ctx):
     want = [0, -10, 0, -11, -12, 0, -13, -14, -14, -13, 0, 0, 0, 0]
     assert list(res["status"]) == want
 
+
+
+def _nops_like(b):
+    """Records of the same layout as b's (every kernel as long as b's) but
+    each kernel one straight block of s_nop closed by s_endpgm: one block and
+    no records per kernel."""
+    recs = np.zeros(b.n_instr, dcgen.INSTR_DTYPE)
+    recs["op"] = dcgen.opcode("s_nop")
+    recs["r0"] = recs["r1"] = recs["r2"] = dcgen.NONE
+    recs["target"] = -1
+    ends = (b.kernels["instr_begin"] + b.kernels["n_instr"] - 1).astype(np.int64)
+    recs["op"][ends[b.kernels["n_instr"] > 0]] = dcgen.opcode("s_endpgm")
+    return recs
+
+
+def test_rerun_on_other_records_plans_again(ctx):
+    """dc_batch_run on a new record pointer: the batch was planned for
+    records with one block and no records per kernel; the new records of the
+    same layout have loops, hundreds of blocks and thousands of records, and
+    the run plans again for them (block arrays, record regions, arenas).
+    Every result against the oracle, then back on the first records."""
+    b = dcgen.concat([dcgen.generate(2, 300, i0=40).kernel(k) for k in range(300)] +
+                     [dcgen.generate(6, 2).kernel(k) for k in range(2)])
+    dense = dc.to_device(b.instrs)
+    sparse = dc.to_device(_nops_like(b))
+    batch = ctx.analyze(b.kernels, sparse, b.n_instr, b.args, flags=dc.OPT_DIGEST)
+    res = batch.results()
+    assert (res["status"] == 0).all() and (res["n_blocks"] == 1).all() and (res["n_access"] == 0).all()
+    s, oacc, osys = oracle.analyze_batch(b)
+    batch.run(dense)
+    compare_summaries(batch.results(), s)
+    assert batch.all_accesses()[0].tobytes() == oacc.tobytes()
+    assert batch.all_sysvals()[0].tobytes() == osys.tobytes()
+    batch.run(sparse)
+    assert batch.results().tobytes() == res.tobytes()
+    batch.free()
+
+
+def test_records_changed_in_place_fail_with_capacity(ctx):
+    """Records overwritten in place after planning (the caller's error) with
+    more blocks and records than planned: every kernel reports DC_E_CAPACITY
+    and no records, nothing is written outside the plan; the same records
+    under a new pointer are analysed normally."""
+    b = dcgen.generate(2, 200, i0=900)
+    buf = dc.to_device(_nops_like(b))
+    batch = ctx.analyze(b.kernels, buf, b.n_instr, b.args, flags=dc.OPT_DIGEST)
+    assert (batch.results()["status"] == 0).all()
+    buf.copy_(dc.to_device(b.instrs))
+    torch.cuda.synchronize()
+    batch.run()
+    res = batch.results()
+    assert (res["status"] == -16).all()
+    assert len(batch.all_accesses()[0]) == 0 and len(batch.all_sysvals()[0]) == 0
+    batch.run(dc.to_device(b.instrs))
+    s, oacc, osys = oracle.analyze_batch(b)
+    compare_summaries(batch.results(), s)
+    assert batch.all_accesses()[0].tobytes() == oacc.tobytes()
+    batch.free()
 
 def test_nofix_cap(ctx):
     b = dcgen.generate(2, 200)

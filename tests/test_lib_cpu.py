@@ -44,7 +44,7 @@ def test_opcode_numbering_agrees(dc):
 
 
 def test_status_strings(dc):
-    for code in (0, -1, -2, -3, -4, -10, -11, -12, -13, -14, -15):
+    for code in (0, -1, -2, -3, -4, -10, -11, -12, -13, -14, -15, -16):
         assert dc.status_str(code) != "unknown status"
     assert dc.status_str(-99) == "unknown status"
 
