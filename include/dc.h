@@ -126,6 +126,7 @@ typedef struct {
 #define DC_OPT_GRAPH 8u          /* dc_batch_run replays the stages as one captured HIP graph (from the second run
                                     on; not with DC_OPT_EXPORT_STATES or DC_OPT_TIMING, nor on the NULL stream,
                                     where runs stay eager) */
+#define DC_OPT_INDEX_ORDER 16u   /* the fixpoint takes kernels in index order instead of longest first */
 typedef struct {
     uint32_t flags;
     uint32_t sweep_cap;          /* 0 = 64 + 2 * n_blocks per kernel */

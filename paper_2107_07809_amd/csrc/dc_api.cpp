@@ -147,9 +147,12 @@ PlanInputs dc::alloc_plan(DevMem &M, Plan &P, const PlanDims &d) {
     P.blk_cap = 0;
     in.work_order = nullptr;
     P.work_order = nullptr;
+    P.kslots = nullptr;
+    P.with_records = d.cfg_only ? 0u : 1u;
     if (d.cfg_only) return in;
     in.work_order = M.alloc<uint32_t>(K);
     P.work_order = in.work_order;
+    P.kslots = M.alloc<uint32_t>(K * KSLOT_WORDS);
     P.arena_rows = d.arena_rows;
     P.main_waves = (uint32_t)d.waves;
     P.arena = M.alloc<uint32_t>(d.waves * d.arena_rows * FIX_ROW_DWORDS);
@@ -211,7 +214,8 @@ static dc_status_t plan_batch(dc_batch *B, dc_ctx *ctx, const dc_kernel_t *kerne
     B->stream = (hipStream_t)stream;
     B->cfg_only = cfg_only;
     if (opts) B->opts = *opts;
-    if (B->opts.flags & ~(DC_OPT_EXPORT_STATES | DC_OPT_DIGEST | DC_OPT_TIMING | DC_OPT_GRAPH)) return DC_E_INVAL;
+    if (B->opts.flags & ~(DC_OPT_EXPORT_STATES | DC_OPT_DIGEST | DC_OPT_TIMING | DC_OPT_GRAPH | DC_OPT_INDEX_ORDER))
+        return DC_E_INVAL;
     if ((B->opts.flags & DC_OPT_GRAPH) && (B->opts.flags & (DC_OPT_EXPORT_STATES | DC_OPT_TIMING))) return DC_E_INVAL;
     /* waves per group: the fixpoint kernel's LDS per wave must fit a group */
     const size_t lds_wave = fixpoint_lds_per_wave();
@@ -283,7 +287,8 @@ static dc_status_t plan_batch(dc_batch *B, dc_ctx *ctx, const dc_kernel_t *kerne
     /* the fixpoint takes the longest kernels first, so that no long kernel
      * starts last and holds up the end of the launch */
     std::vector<uint32_t> order;
-    if (!cfg_only && K) {
+    if (!cfg_only && (B->opts.flags & DC_OPT_INDEX_ORDER)) P.work_order = nullptr;
+    if (!cfg_only && K && !(B->opts.flags & DC_OPT_INDEX_ORDER)) {
         order.resize(K);
         for (uint32_t k = 0; k < K; k++) order[k] = k;
         std::stable_sort(order.begin(), order.end(),

@@ -84,7 +84,6 @@ struct WaveLds {
     uint64_t optab[80];             /* opcode descriptors */
     uint16_t umap[USLOT_N];         /* slot -> compact index; entries >= NSLOT unused */
     uint16_t uslot[USLOT_N + 64];   /* compact index -> slot; 64-entry scratch tail */
-    uint8_t umark[USLOT_N + 64];    /* slot marks; entries >= NSLOT are scratch */
     uint32_t tail[64];              /* scratch words for single-lane bitmap stores */
     uint8_t argf[64];               /* pointee type bits of the kernel's first 64 arguments */
 };
@@ -399,29 +398,32 @@ __device__ __forceinline__ void state_load(WaveLds &L, const uint32_t *a, uint32
 }
 
 /* a := a join OUT for one slot per lane (provenance and type bits unite;
- * payloads that differ go to TOP), or a := OUT when first; the words are
- * stored unconditionally */
+ * payloads that differ go to TOP), or a := OUT when first.  Only the words
+ * that change are stored (the others go to the lane's scratch words), so a
+ * join that changes nothing writes nothing to the arena. */
 __device__ __forceinline__ bool join_slot(uint32_t *a, uint32_t nu_pad, uint32_t c, bool first, uint32_t pb, uint32_t lb,
-                                          uint32_t hb) {
+                                          uint32_t hb, uint32_t *scr) {
     uint32_t pn = pb, ln = lb, hn = hb;
-    bool ch = first;
+    bool cp = true, cl = true, chh = true;
     if (!first) {   /* uniform */
         const uint32_t pa = a[c], la = a[nu_pad + c], ha = a[2 * nu_pad + c];
         const bool same = la == lb && (ha & 0xFFFFFF00u) == (hb & 0xFFFFFF00u);
         pn = pa | pb;
         ln = same ? la : 0xFFFFFFFFu;
         hn = (same ? (ha & 0xFFFFFF00u) : HTOP) | ((ha | hb) & 0xFFu);
-        ch = pn != pa || ln != la || hn != ha;
+        cp = pn != pa;
+        cl = ln != la;
+        chh = hn != ha;
     }
-    a[c] = pn;
-    a[nu_pad + c] = ln;
-    a[2 * nu_pad + c] = hn;
-    return ch;
+    *(cp ? &a[c] : scr) = pn;
+    *(cl ? &a[nu_pad + c] : scr + 1) = ln;
+    *(chh ? &a[2 * nu_pad + c] : scr + 2) = hn;
+    return cp || cl || chh;
 }
 /* OUT state into the IN states of up to two successors (null when absent);
  * returns the per-successor change bits (bit 0, bit 1) */
 __device__ __forceinline__ uint32_t state_join2(const WaveLds &L, uint32_t *a0, bool first0, uint32_t *a1, bool first1,
-                                                uint32_t nu_pad) {
+                                                uint32_t nu_pad, uint32_t *scr) {
     const uint32_t l = lane_id();
     bool ch0 = false, ch1 = false;
 #pragma unroll
@@ -430,8 +432,8 @@ __device__ __forceinline__ uint32_t state_join2(const WaveLds &L, uint32_t *a0, 
             const uint32_t c = (uint32_t)r * 64 + l;
             const uint64_t x = L.fpt[c], v = L.fv[c];
             const uint32_t pb = fpt_prov(x), lb = (uint32_t)v, hb = pack_hi(v, fpt_type(x));
-            if (a0) ch0 = join_slot(a0, nu_pad, c, first0, pb, lb, hb) || ch0;
-            if (a1) ch1 = join_slot(a1, nu_pad, c, first1, pb, lb, hb) || ch1;
+            if (a0) ch0 = join_slot(a0, nu_pad, c, first0, pb, lb, hb, scr) || ch0;
+            if (a1) ch1 = join_slot(a1, nu_pad, c, first1, pb, lb, hb, scr) || ch1;
         }
     }
     return (ballot(ch0) != 0 ? 1u : 0u) | (ballot(ch1) != 0 ? 2u : 0u);
@@ -1009,38 +1011,17 @@ __device__ __forceinline__ void run_chunk(const Plan *__restrict__ P, WaveLds &L
 /* ------------------------------------------------------------------ */
 /* one kernel                                                           */
 /* ------------------------------------------------------------------ */
-/* mark the slots the kernel names and number them; returns U */
-__device__ __forceinline__ uint32_t build_compact(const Plan *__restrict__ P, WaveLds &L, uint64_t rb, uint32_t n) {
+/* number the slots kernel k names (the decode stage's per-kernel bitmap)
+ * plus vcc, exec, scc and the argument pointer s[4:5]; returns U */
+__device__ __forceinline__ uint32_t build_compact(const Plan *__restrict__ P, WaveLds &L, uint32_t k) {
     const uint32_t l = lane_id();
-    uint32_t *mk = reinterpret_cast<uint32_t *>(L.umark);
-    for (uint32_t j = 0; j < (USLOT_N + 64) / 4; j += 64) mk[(j + l) < (USLOT_N + 64) / 4 ? j + l : l] = 0;
-    __builtin_amdgcn_wave_barrier();
-    const uint4 *recs = reinterpret_cast<const uint4 *>(P->instrs) + rb;
-    const uint32_t junk = USLOT_N + l;
-    for (uint32_t g0 = 0; g0 < n; g0 += 64) {
-        const uint32_t gi = g0 + l < n ? g0 + l : n - 1;
-        const uint4 r = recs[gi];
-        const uint32_t opc = r.x & 0xFFFFu;
-        const uint64_t e = L.optab[opc < (uint32_t)N_OPS ? opc : 0];
-        const uint32_t id[4] = {r.x >> 16, r.y & 0xFFFFu, r.y >> 16, r.z};
-#pragma unroll
-        for (int o = 0; o < 4; o++) {
-            const uint32_t w = e_role(e, o) != RO_NO ? e_width(e, o) : 0;
-#pragma unroll
-            for (uint32_t j = 0; j < 4; j++) {
-                const uint32_t s = id[o] + j;
-                L.umark[(j < w && id[o] < (uint32_t)NSLOT && s < (uint32_t)NSLOT) ? s : junk] = 1;
-            }
-        }
-    }
-    /* vcc, exec, scc (implicit operands) and the argument pointer */
-    L.umark[l < 5 ? 104 + l : (l < 7 ? l - 1 : junk)] = 1;
-    __builtin_amdgcn_wave_barrier();
+    const uint32_t *ks = P->kslots + (uint64_t)k * KSLOT_WORDS;
     uint32_t base = 0;
 #pragma unroll
     for (uint32_t grp = 0; grp < RMAX; grp++) {
         const uint32_t s = grp * 64 + l;
-        const bool f = s < (uint32_t)NSLOT && L.umark[s] != 0;
+        const bool imp = (s >= 104u && s <= 108u) || s == 4u || s == 5u;
+        const bool f = s < (uint32_t)NSLOT && (((ks[s >> 5] >> (s & 31u)) & 1u) != 0 || imp);
         const uint64_t m = ballot(f);
         const uint32_t c = base + lanes_below(m);
         L.umap[s] = (uint16_t)(f ? c : CX_NONE);
@@ -1154,7 +1135,8 @@ __device__ __forceinline__ void analyze(const Plan *__restrict__ P, uint32_t k, 
             }
             P->blk_acc[fb + b] = min(E.ta, E.acap);
             P->blk_sys[fb + b] = min(E.ts, E.scap);
-            const uint32_t chg = state_join2(L, a0, first0, a1, first1, nu_pad);
+            const uint32_t chg = state_join2(L, a0, first0, a1, first1, nu_pad,
+                                             reinterpret_cast<uint32_t *>(M.dummy + l));
             if (first0) reached.set((uint32_t)ps0);
             if (first1) reached.set((uint32_t)ps1);
             if ((chg & 1u) && ps0 != pc) dirty.set((uint32_t)ps0);
@@ -1304,10 +1286,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             fail_kernel(P, k, status, M);
             continue;
         }
-        const uint32_t nb = rfl(P->n_blocks[k]), n = rfl(P->pos_begin[k + 1]) - rfl(P->pos_begin[k]);
-        const dc_kernel_t *D = &P->kernels[k];
-        const uint64_t rb = ((uint64_t)rfl((uint32_t)(D->instr_begin >> 32)) << 32) | rfl((uint32_t)D->instr_begin);
-        const uint32_t nu = rfl(build_compact(P, L, rb, n));
+        const uint32_t nb = rfl(P->n_blocks[k]);
+        const uint32_t nu = rfl(build_compact(P, L, k));
         const uint64_t rows = (uint64_t)nb * ((nu + 63u) >> 6);
         if (!OVF) {
             if (nb > MAIN_MAX_BLOCKS || rows > cap_rows) {

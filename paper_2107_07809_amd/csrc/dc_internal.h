@@ -36,6 +36,9 @@ struct Plan {
                                        yield a built-in) */
     uint32_t *block_id;             /* n_pos: global block id of each position */
     uint32_t *totals;               /* [0] blocks, [1] access capacity, [2] built-in capacity of the batch */
+    uint32_t *kslots;               /* KSLOT_WORDS per kernel: bit s = some record names register slot s (null for
+                                       graph-only plans) */
+    uint32_t with_records;          /* an analysis plan (not graph-only): capacities, regions, fixpoint */
     /* per global block (blk_cap entries, +1 where noted) */
     uint32_t blk_cap;
     uint32_t *block_start;          /* +1: first position of each global block; [total] = n_pos */
@@ -107,7 +110,7 @@ struct FixCfg {
 hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t *p, uint64_t n, uint8_t v, hipStream_t s);
 hipError_t launch_decode(const Plan &P, hipStream_t s);                 /* decode, checks, leaders, capacities */
-hipError_t launch_leader_scan(const Plan &P, hipStream_t s);            /* block count (totals[0]) */
+hipError_t launch_leader_scan(const Plan &P, hipStream_t s);            /* block count, record capacities (totals) */
 hipError_t launch_number_blocks(const Plan &P, hipStream_t s);          /* block numbering, record regions */
 hipError_t launch_edges(const Plan &P, hipStream_t s);                  /* edges, predecessors, RPO, statuses */
 /* entry state, fixpoint, extraction; dP = device copy of P; optional events bracket the main launch */
@@ -116,6 +119,7 @@ hipError_t launch_fixpoint(const Plan &P, const Plan *dP, const FixCfg &c, hipSt
 hipError_t launch_compact(const Plan &P, hipStream_t s);                /* dense outputs */
 uint32_t fixpoint_groups_per_cu(uint32_t waves_per_group);              /* resident fixpoint groups per CU */
 size_t fixpoint_lds_per_wave();                                         /* LDS bytes per fixpoint wavefront */
+constexpr uint32_t KSLOT_WORDS = 12;                                    /* 384 bits >= NSLOT */
 constexpr uint32_t FIX_ROW_DWORDS = 192;                                /* arena dwords per state row */
 constexpr uint32_t FIX_MAX_ROWS = 6;                                    /* state rows of the largest kernel */
 constexpr uint32_t OVF_MAX_WAVES = 512;                                 /* waves of the overflow pass */

@@ -190,9 +190,15 @@ __device__ __forceinline__ uint32_t rec_cap(uint64_t e) {
     return acc | sys << 1;
 }
 
-__device__ __forceinline__ uint32_t wave_sum(uint32_t x) {
+/* OR of x over each run of lanes with the same key k (runs are contiguous),
+ * left in the run's last lane */
+__device__ __forceinline__ uint32_t seg_or(uint32_t x, uint32_t k) {
+    const uint32_t l = lane_id();
 #pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, 64), kk = __shfl_up(k, d, 64);
+        x |= (l >= (uint32_t)d && kk == k) ? y : 0u;
+    }
     return x;
 }
 
@@ -203,42 +209,74 @@ __global__ __launch_bounds__(256) void k_decode(Plan P) {
     const uint32_t t1 = min(P.n_pos, t0 + TILE_LK);
     uint32_t k0, cnt;
     lookup_setup(P.pos_begin, P.n_kernels, t0, t1, lk, &k0, &cnt);
-    uint32_t sum_a = 0, sum_s = 0;
-    for (uint32_t g = t0 + threadIdx.x; g < t1; g += blockDim.x) {
-        const uint32_t k = lookup(P.pos_begin, P.n_kernels, lk, k0, cnt, g);
-        const uint32_t pb = P.pos_begin[k];
-        const uint32_t n = P.pos_begin[k + 1] - pb;
-        const uint32_t i = g - pb;
-        const dc_kernel_t *D = &P.kernels[k];
-        const uint4 r = reinterpret_cast<const uint4 *>(P.instrs)[D->instr_begin + i];
-        const uint32_t op = r.x & 0xFFFFu, r0 = r.x >> 16, r1 = r.y & 0xFFFFu, r2 = r.y >> 16;
-        const int32_t imm = (int32_t)r.z, target = (int32_t)r.w;
-        const uint32_t bad = check_record(op, r0, r1, r2, imm, target, n);
-        if (i == 0) P.leader[g] = 1;
-        if (bad) {
-            P.pcap[g] = 0;
-            atomicMin(&P.kbad[k], (i << 2) | bad);
-            continue;
+    const uint32_t l = lane_id();
+    /* a uniform trip count: the lanes of a wavefront hold consecutive
+     * positions and meet in the cross-lane steps below */
+    for (uint32_t it = 0; it < (uint32_t)TILE_LK / 256u; it++) {
+        const uint32_t g = t0 + it * 256u + threadIdx.x;
+        const bool act = g < t1;
+        uint32_t k = 0xFFFFFFFFu, n = 0, i = 0, pb = 0;
+        if (act) {
+            k = lookup(P.pos_begin, P.n_kernels, lk, k0, cnt, g);
+            pb = P.pos_begin[k];
+            n = P.pos_begin[k + 1] - pb;
+            i = g - pb;
         }
-        const uint64_t e = OPTAB[op];
-        const uint32_t cls = e_cls(e);
-        const uint32_t c = rec_cap(e);
-        P.pcap[g] = (uint8_t)c;
-        sum_a += c & 1u;
-        sum_s += c >> 1;
-        if (ends_block(cls) && i + 1 < n) P.leader[g + 1] = 1;
-        if (cls == C_BR || cls == C_CBR) P.leader[pb + (uint32_t)target] = 1;
-    }
-    /* batch totals of the capacities: one atomic per wavefront */
-    sum_a = wave_sum(sum_a);
-    sum_s = wave_sum(sum_s);
-    if (lane_id() == 0) {
-        atomicAdd(&P.totals[1], sum_a);
-        atomicAdd(&P.totals[2], sum_s);
+        /* named register slots of this instruction, as a 384-bit set */
+        uint32_t mk[KSLOT_WORDS];
+#pragma unroll
+        for (uint32_t w = 0; w < KSLOT_WORDS; w++) mk[w] = 0;
+        if (act && i >= n) {   /* a position no kernel owns (a call whose descriptors failed their checks) */
+            P.pcap[g] = 0;
+        } else if (act) {
+            const dc_kernel_t *D = &P.kernels[k];
+            const uint4 r = reinterpret_cast<const uint4 *>(P.instrs)[D->instr_begin + i];
+            const uint32_t op = r.x & 0xFFFFu, r0 = r.x >> 16, r1 = r.y & 0xFFFFu, r2 = r.y >> 16;
+            const int32_t imm = (int32_t)r.z, target = (int32_t)r.w;
+            const uint32_t bad = check_record(op, r0, r1, r2, imm, target, n);
+            if (i == 0) P.leader[g] = 1;
+            if (bad) {
+                P.pcap[g] = 0;
+                atomicMin(&P.kbad[k], (i << 2) | bad);
+            } else {
+                const uint64_t e = OPTAB[op];
+                const uint32_t cls = e_cls(e);
+                const uint32_t c = rec_cap(e);
+                P.pcap[g] = (uint8_t)c;
+                if (ends_block(cls) && i + 1 < n) P.leader[g + 1] = 1;
+                if (cls == C_BR || cls == C_CBR) P.leader[pb + (uint32_t)target] = 1;
+                const uint32_t id[4] = {r0, r1, r2, (uint32_t)imm};
+#pragma unroll
+                for (int o = 0; o < 4; o++) {
+                    const uint32_t w = e_role(e, o) != RO_NO ? e_width(e, o) : 0u;
+#pragma unroll
+                    for (uint32_t j = 0; j < 4; j++) {
+                        const uint32_t sl = id[o] + j;
+                        const bool on = j < w && id[o] < (uint32_t)NSLOT && sl < (uint32_t)NSLOT;
+#pragma unroll
+                        for (uint32_t q = 0; q < KSLOT_WORDS; q++) mk[q] |= (on && (sl >> 5) == q) ? 1u << (sl & 31u) : 0u;
+                    }
+                }
+            }
+        }
+        if (P.kslots) {
+            /* one atomic OR per word and run of lanes of one kernel */
+            const uint32_t kn = __shfl_down(k, 1, 64);
+            const bool tail = act && (l == 63u || kn != k);
+#pragma unroll
+            for (uint32_t q = 0; q < KSLOT_WORDS; q++) {
+                const uint32_t x = seg_or(mk[q], k);
+                if (tail && x) atomicOr(&P.kslots[(uint64_t)k * KSLOT_WORDS + q], x);
+            }
+        }
     }
 }
 hipError_t launch_decode(const Plan &P, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, P.totals, (uint64_t)4, 0u);
+    if (P.kslots && P.n_kernels) {
+        const hipError_t e = launch_fill_u32(P.kslots, (uint64_t)P.n_kernels * KSLOT_WORDS, 0u, s);
+        if (e != hipSuccess) return e;
+    }
     if (!P.n_pos) return hipGetLastError();
     uint32_t tiles = (P.n_pos + TILE_LK - 1) / TILE_LK;
     hipLaunchKernelGGL(k_decode, dim3(tiles), dim3(256), 0, s, P);
@@ -442,11 +480,23 @@ __global__ __launch_bounds__(256) void k_cap_apply(Plan P, const uint32_t *offs_
     }
 }
 
+/* tile sums of the capacity scan, after the scan scratch */
+__host__ __device__ inline uint32_t *cap_sums(const Plan &P) { return P.scan_tmp + P.scan_tmp_words; }
+
 hipError_t launch_leader_scan(const Plan &P, hipStream_t s) {
-    if (!P.n_pos) return hipSuccess;   /* totals[0] = 0 from the decode stage */
+    if (!P.n_pos) return hipSuccess;   /* the totals are zero from the decode stage */
     /* the exclusive leader counts go to block_id first; k_number rewrites
      * block_id in place (each position reads its own entry before writing) */
-    return scan_excl<uint8_t>(P.leader, P.n_pos, P.block_id, P.totals, P.scan_tmp, s);
+    hipError_t e = scan_excl<uint8_t>(P.leader, P.n_pos, P.block_id, P.totals, P.scan_tmp, s);
+    if (e != hipSuccess || !P.with_records) return e;
+    /* the capacity scan's tile offsets and the batch's capacity totals
+     * (totals[1], totals[2]); the regions are written after numbering */
+    const uint64_t ct = ((uint64_t)P.n_pos + SCAN_TILE - 1) / SCAN_TILE;
+    uint32_t *sums_a = cap_sums(P), *sums_s = sums_a + ct + 1;
+    hipLaunchKernelGGL(k_cap_reduce, dim3((uint32_t)ct), dim3(256), 0, s, P, sums_a, sums_s);
+    e = scan_excl<uint32_t>(sums_a, ct, sums_a, P.totals + 1, P.scan_tmp, s);
+    if (e == hipSuccess) e = scan_excl<uint32_t>(sums_s, ct, sums_s, P.totals + 2, P.scan_tmp, s);
+    return e;
 }
 
 hipError_t launch_number_blocks(const Plan &P, hipStream_t s) {
@@ -463,12 +513,9 @@ hipError_t launch_number_blocks(const Plan &P, hipStream_t s) {
     const uint32_t tiles = (P.n_pos + TILE_LK - 1) / TILE_LK;
     hipLaunchKernelGGL(k_number, dim3(tiles), dim3(256), 0, s, P, P.block_id);
     if (!P.blk_acc_base) return hipGetLastError();   /* graph only: no record regions */
+    /* the tile offsets left by launch_leader_scan */
     const uint64_t ct = ((uint64_t)P.n_pos + SCAN_TILE - 1) / SCAN_TILE;
-    uint32_t *sums_a = P.scan_tmp + P.scan_tmp_words, *sums_s = sums_a + ct + 1;
-    hipLaunchKernelGGL(k_cap_reduce, dim3((uint32_t)ct), dim3(256), 0, s, P, sums_a, sums_s);
-    hipError_t e = scan_excl<uint32_t>(sums_a, ct, sums_a, nullptr, P.scan_tmp, s);
-    if (e == hipSuccess) e = scan_excl<uint32_t>(sums_s, ct, sums_s, nullptr, P.scan_tmp, s);
-    if (e != hipSuccess) return e;
+    uint32_t *sums_a = cap_sums(P), *sums_s = sums_a + ct + 1;
     hipLaunchKernelGGL(k_cap_apply, dim3((uint32_t)ct), dim3(256), 0, s, P, sums_a, sums_s);
     return hipGetLastError();
 }

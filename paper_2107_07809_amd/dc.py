@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libdc.so")
 DC_OK = 0
 STATUS = {0: "OK", -1: "INVAL", -2: "HIP", -3: "OOM", -4: "NOTREADY", -10: "BADOP", -11: "BADREG",
           -12: "BADTARGET", -13: "NOEND", -14: "UNSUPPORTED", -15: "NOFIX", -16: "CAPACITY"}
-OPT_EXPORT_STATES, OPT_DIGEST, OPT_TIMING, OPT_GRAPH = 1, 2, 4, 8
+OPT_EXPORT_STATES, OPT_DIGEST, OPT_TIMING, OPT_GRAPH, OPT_INDEX_ORDER = 1, 2, 4, 8, 16
 NSLOT = 368
 
 INSTR_DTYPE = np.dtype([("op", "<u2"), ("r0", "<u2"), ("r1", "<u2"), ("r2", "<u2"), ("imm", "<i4"),
