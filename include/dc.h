@@ -263,6 +263,48 @@ dc_status_t dc_timing_reset(dc_batch_t *batch);
 void dc_batch_free(dc_batch_t *batch);
 
 /* ------------------------------------------------------------------ */
+/* The analysis without device allocation.                              */
+/* ------------------------------------------------------------------ */
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * analysis as dc_analyze_batch, with every intermediate array in a static
+ * device array of the library of DC_NOALLOC_SCRATCH_BYTES per device
+ * (reserved when the library's code loads on a device and held until the
+ * process ends), and the results in the caller's device buffers.  The call
+ * calls no hipMalloc, hipFree or other allocating routine and does not
+ * synchronise: it enqueues on `stream` and returns.
+ *
+ * Inputs (all device memory): kernels (n_kernels descriptors, records
+ * relative to instrs, arguments relative to args), instrs (n_records),
+ * args (n_args_total).  n_instr_total must be the sum of the descriptors'
+ * n_instr.  flags: 0 or DC_OPT_DIGEST.
+ * Outputs (device memory, written when the stream reaches the work):
+ * results[n_kernels]; accesses[acc_cap] and sysvals[sys_cap], every
+ * kernel's records packed in kernel order; acc_off / sys_off (n_kernels + 1
+ * entries): exclusive offsets of each kernel's records.
+ * Limits: n_kernels <= DC_NOALLOC_MAX_KERNELS and n_instr_total <=
+ * DC_NOALLOC_MAX_INSTR, else DC_E_INVAL (before anything is enqueued).
+ * Per kernel: a kernel with more than 2048 blocks, or too many blocks for
+ * the fixed state arenas (256 blocks of up to 128 named registers or 85 of
+ * more in the main pass; 1024 blocks in the overflow pass), fails with
+ * DC_E_CAPACITY, and so does every kernel when the records or built-ins
+ * outgrow acc_cap or sys_cap (acc_cap = n_instr_total and
+ * sys_cap = 4 * n_instr_total always suffice); a descriptor whose records or
+ * arguments lie outside the arrays fails with DC_E_INVAL; when n_instr_total
+ * differs from the descriptors' sum every kernel fails with DC_E_INVAL.
+ * Every call on a device shares that device's scratch array: calls that
+ * overlap on one device (other streams, other threads) race and must be
+ * serialised by the caller; calls on one stream are ordered. */
+#define DC_NOALLOC_MAX_KERNELS 4096u
+#define DC_NOALLOC_MAX_INSTR 262144u
+#define DC_NOALLOC_SCRATCH_BYTES (96ull << 20)
+dc_status_t dc_analyze_noalloc(dc_ctx_t *ctx, const dc_kernel_t *kernels, uint32_t n_kernels, uint32_t n_instr_total,
+                               const dc_instr_t *instrs, uint64_t n_records, const dc_arg_t *args,
+                               uint64_t n_args_total, uint32_t flags, dc_kernel_result_t *results,
+                               dc_access_t *accesses, uint32_t acc_cap, uint32_t *acc_off, dc_sysval_t *sysvals,
+                               uint32_t sys_cap, uint32_t *sys_off, void *stream);
+
+/* ------------------------------------------------------------------ */
 /* Request server: continuous batching of single-kernel analyses.       */
 /* ------------------------------------------------------------------ */
 /* The server takes analysis requests one kernel at a time as they arrive

@@ -116,6 +116,11 @@ extern "C" dc_status_t dc_ctx_create(int hip_device, dc_ctx_t **out) {
     c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
     c->lds_per_cu = prop.maxSharedMemoryPerMultiProcessor ? prop.maxSharedMemoryPerMultiProcessor : 65536;
     c->lds_per_group = prop.sharedMemPerBlock ? prop.sharedMemPerBlock : 65536;
+    /* set-up of dc_analyze_noalloc on this device: resolve its scratch array */
+    if (!noalloc_setup(hip_device)) {
+        delete c;
+        return DC_E_HIP;
+    }
     *out = c;
     return DC_OK;
 }

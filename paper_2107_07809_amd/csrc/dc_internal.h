@@ -125,6 +125,7 @@ constexpr uint32_t FIX_MAX_ROWS = 6;                                    /* state
 constexpr uint32_t OVF_MAX_WAVES = 512;                                 /* waves of the overflow pass */
 constexpr uint64_t ARENA_BUDGET = 8ull << 30;                           /* arena bytes of either pass */
 uint64_t scan_tmp_words_needed(uint64_t n);
-uint64_t cap_scan_words(uint64_t n);   /* extra scan words of the capacity scan of n positions */
+uint64_t cap_scan_words(uint64_t n);
+void *noalloc_setup(int device);         /* device address of the no-allocation scratch array (current device) */   /* extra scan words of the capacity scan of n positions */
 
 }  // namespace dc

@@ -19,6 +19,7 @@ DC_OK = 0
 STATUS = {0: "OK", -1: "INVAL", -2: "HIP", -3: "OOM", -4: "NOTREADY", -10: "BADOP", -11: "BADREG",
           -12: "BADTARGET", -13: "NOEND", -14: "UNSUPPORTED", -15: "NOFIX", -16: "CAPACITY"}
 OPT_EXPORT_STATES, OPT_DIGEST, OPT_TIMING, OPT_GRAPH, OPT_INDEX_ORDER = 1, 2, 4, 8, 16
+NOALLOC_MAX_KERNELS, NOALLOC_MAX_INSTR = 4096, 262144   # DC_NOALLOC_MAX_KERNELS, DC_NOALLOC_MAX_INSTR
 NSLOT = 368
 
 INSTR_DTYPE = np.dtype([("op", "<u2"), ("r0", "<u2"), ("r1", "<u2"), ("r2", "<u2"), ("imm", "<i4"),
@@ -111,6 +112,7 @@ SIGNATURES = [
     ("dc_get_timing", I32, [VP, ctypes.POINTER(Timing)]),
     ("dc_timing_reset", I32, [VP]),
     ("dc_batch_free", None, [VP]),
+    ("dc_analyze_noalloc", I32, [VP, VP, U32, U32, VP, U64, VP, U64, U32, VP, VP, U32, VP, VP, U32, VP, VP]),
     ("dc_server_create", I32, [VP, ctypes.POINTER(ServerOpts), ctypes.POINTER(VP)]),
     ("dc_server_submit", I32, [VP, VP, ctypes.POINTER(U64)]),
     ("dc_server_poll", I32, [VP, VP, U32, ctypes.POINTER(U32)]),
@@ -221,6 +223,17 @@ class Context:
                                                _np_ptr(args), len(args), ctypes.byref(base), sample,
                                                _stream_ptr(stream), ctypes.byref(best), ctypes.byref(ms)))
         return {"waves_per_group": best.waves_per_group, "groups_per_cu": best.groups_per_cu}, ms.value
+
+    def analyze_noalloc(self, kernels_dev, n_kernels, n_instr_total, instrs_dev, n_records, args_dev, n_args_total,
+                        results_dev, acc_dev, acc_cap, acc_off_dev, sys_dev, sys_cap, sys_off_dev, flags=0,
+                        stream=None):
+        """dc_analyze_noalloc: every argument a device tensor (or a count);
+        enqueues the analysis and returns (the outputs are filled when the
+        stream reaches the work)."""
+        check("dc_analyze_noalloc", lib().dc_analyze_noalloc(
+            self.h, _dev_ptr(kernels_dev), n_kernels, n_instr_total, _dev_ptr(instrs_dev), n_records,
+            _dev_ptr(args_dev), n_args_total, flags, _dev_ptr(results_dev), _dev_ptr(acc_dev), acc_cap,
+            _dev_ptr(acc_off_dev), _dev_ptr(sys_dev), sys_cap, _dev_ptr(sys_off_dev), _stream_ptr(stream)))
 
     def build_cfg(self, kernels, instrs_dev, n_records, stream=None) -> "Cfg":
         kernels = np.ascontiguousarray(np.asarray(kernels, KERNEL_DTYPE))
