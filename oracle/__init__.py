@@ -74,6 +74,13 @@ def lib():
         L.or_analyze.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int,
                                  ctypes.c_uint64, ctypes.POINTER(_Result)]
         L.or_analyze.restype = ctypes.c_int
+        L.or_ssa.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.or_ssa.restype = ctypes.c_int
+        L.or_ssa_free.argtypes = [ctypes.c_void_p]
+        L.or_ssa_uses.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        L.or_ssa_uses.restype = ctypes.c_int
+        L.or_ssa_defs.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        L.or_ssa_defs.restype = ctypes.c_int
         L.or_analyze_batch.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]
@@ -143,6 +150,55 @@ def analyze(recs, desc, args, sweep_cap: int = 0, schedule: int = 0, seed: int =
     if states:
         out["in_states"] = st[:nb * NSLOT].reshape(nb, NSLOT)
     return out
+
+
+PHI_DTYPE = np.dtype([("block", "<u4"), ("slot", "<u2"), ("pad", "<u2"), ("version", "<u4")])
+SSA_NU, SSA_ND, SSA_NONE = 13, 9, 0xFFFFFFFF
+
+
+class _SsaOut(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("n_blocks", ctypes.c_uint32), ("n_phi", ctypes.c_uint32),
+                ("n_args", ctypes.c_uint32), ("idom", ctypes.c_void_p), ("phi", ctypes.c_void_p),
+                ("phi_arg_off", ctypes.c_void_p), ("phi_arg", ctypes.c_void_p), ("use_ver", ctypes.c_void_p),
+                ("def_ver", ctypes.c_void_p), ("n_ver", ctypes.c_uint32 * NSLOT), ("digest", ctypes.c_uint64)]
+
+
+def _copy(ptr, n, dt):
+    if not n:
+        return np.zeros(0, dt)
+    return np.ctypeslib.as_array(ctypes.cast(ptr, ctypes.POINTER(ctypes.c_uint8)), shape=(n * np.dtype(dt).itemsize,)) \
+        .view(dt).copy()
+
+
+def ssa(recs, desc) -> dict:
+    """Register versions of one kernel (minimal SSA form): immediate
+    dominators, phis with their arguments, the version every use reads and
+    every definition makes, the versions per slot, and a digest."""
+    d = _desc(desc)
+    n = int(d[0]["n_instr"])
+    recs = np.ascontiguousarray(recs)
+    R = _SsaOut()
+    L = lib()
+    L.or_ssa(d.ctypes.data, _ptr(recs), ctypes.byref(R))
+    nb = R.n_blocks
+    out = dict(status=R.status, n_blocks=nb, idom=_copy(R.idom, nb, np.uint32), phis=_copy(R.phi, R.n_phi, PHI_DTYPE),
+               phi_arg_off=_copy(R.phi_arg_off, R.n_phi + 1, np.uint32), phi_arg=_copy(R.phi_arg, R.n_args, np.uint32),
+               use_ver=_copy(R.use_ver, SSA_NU * n, np.uint32).reshape(n, SSA_NU),
+               def_ver=_copy(R.def_ver, SSA_ND * n, np.uint32).reshape(n, SSA_ND),
+               n_ver=np.array(R.n_ver[:], np.uint32), digest=R.digest)
+    L.or_ssa_free(ctypes.byref(R))
+    return out
+
+
+def ssa_operands(rec):
+    """(use slots, def slots) of one record in the order the versions are
+    reported."""
+    u = (ctypes.c_uint * SSA_NU)()
+    dd = (ctypes.c_uint * SSA_ND)()
+    rec = np.ascontiguousarray(np.asarray(rec).reshape(1))
+    nu = lib().or_ssa_uses(_ptr(rec), u)
+    nd = lib().or_ssa_defs(_ptr(rec), dd)
+    return list(u[:nu]), list(dd[:nd])
 
 
 def analyze_batch(batch, sweep_cap: int = 0):

@@ -1168,6 +1168,314 @@ int or_apply_path_from(const or_kernel *K, const or_instr *I, const or_arg *args
     return 0;
 }
 
+/* ------------------------------------------------------------------ */
+/* register versions (SSA form)                                         */
+/* ------------------------------------------------------------------ */
+/* Section "Search for control structures": at a block with several
+ * predecessors a register may hold the value of different definitions, and
+ * the paper then creates a variable; the Register record of Section "Search
+ * for memory accesses" carries a version.  The reading: minimal SSA form of
+ * the kernel's control flow graph (Cytron, Ferrante, Rosen, Wegman & Zadeck
+ * 1991).  Every register slot is a variable; a virtual start node before
+ * block 0 defines version 0 of every slot (the ABI entry value); each
+ * definition of an instruction (explicit destination dwords, then the
+ * implicit vcc, exec and scc definitions) makes a new version; a merge (phi)
+ * of a slot sits at every block of the iterated dominance frontier of the
+ * blocks defining it.  Dominators: the iterative algorithm of Cooper, Harvey
+ * & Kennedy (2001) over reverse postorder.  Versions are numbered per slot in
+ * a preorder walk of the dominator tree (children by ascending block
+ * index), phis of a block first (by slot), then the instructions in order.
+ * Only reachable blocks take part. */
+#define SSA_NU 13   /* register uses of one instruction, at most */
+#define SSA_ND 9    /* register definitions of one instruction, at most */
+#define SSA_NONE 0xFFFFFFFFu
+
+/* register slots instruction I reads, in a fixed order: r1, r2, src2 and a
+ * stored r0, dword by dword, then the implicit vcc, exec and scc uses */
+static int ssa_uses(const or_instr *I, unsigned *out) {
+    const opinfo *o = &OPS[I->op];
+    int n = 0;
+    const enum role roles[4] = {o->r1, o->r2, o->src2, o->r0};
+    const unsigned ids[4] = {I->r1, I->r2, (unsigned)I->imm & 0xFFFFu, I->r0};
+    const int ws[4] = {o->w1, o->w2, o->w_src2, o->w0};
+    for (int q = 0; q < 4; q++) {
+        const enum role r = roles[q];
+        if (r == NO || r == SD || r == VD) continue;
+        if (q == 2 && o->src2 == NO) continue;
+        for (int j = 0; j < ws[q]; j++)
+            if (ids[q] < NSLOT && ids[q] + (unsigned)j < NSLOT) out[n++] = ids[q] + (unsigned)j;
+    }
+    if (o->imp_use & I_VCC) { out[n++] = 104; out[n++] = 105; }
+    if (o->imp_use & I_EXEC) { out[n++] = 106; out[n++] = 107; }
+    if (o->imp_use & I_SCC) out[n++] = 108;
+    return n;
+}
+
+/* register slots instruction I defines: the destination dwords, then the
+ * implicit vcc, exec and scc definitions */
+static int ssa_defs(const or_instr *I, unsigned *out) {
+    const opinfo *o = &OPS[I->op];
+    int n = 0;
+    if (o->r0 == SD || o->r0 == VD)
+        for (int j = 0; j < o->w0; j++) out[n++] = I->r0 + (unsigned)j;
+    if (o->imp_def & I_VCC) { out[n++] = 104; out[n++] = 105; }
+    if (o->imp_def & I_EXEC) { out[n++] = 106; out[n++] = 107; }
+    if (o->imp_def & I_SCC) out[n++] = 108;
+    return n;
+}
+
+typedef struct { uint32_t block; uint16_t slot, pad; uint32_t version; } or_phi;
+typedef struct {
+    int32_t status;
+    uint32_t n_blocks, n_phi, n_args;
+    uint32_t *idom;          /* n_blocks: immediate dominator; block 0 -> 0; unreachable -> SSA_NONE */
+    or_phi *phi;             /* n_phi, ascending (block, slot) */
+    uint32_t *phi_arg_off;   /* n_phi + 1 */
+    uint32_t *phi_arg;       /* per phi, one version per incoming edge: block 0's entry edge first, then the
+                                predecessors in ascending order */
+    uint32_t *use_ver;       /* SSA_NU per instruction, in ssa_uses order; SSA_NONE past the uses */
+    uint32_t *def_ver;       /* SSA_ND per instruction, in ssa_defs order; SSA_NONE past the definitions */
+    uint32_t n_ver[NSLOT];   /* versions of each slot, version 0 included */
+    uint64_t digest;
+} or_ssa_out;
+
+/* walk up the dominator tree from a and b to their nearest common dominator
+ * (positions in reverse postorder decrease towards the root) */
+static uint32_t dom_meet(const uint32_t *idom, const int32_t *po, uint32_t a, uint32_t b) {
+    while (a != b) {
+        while (po[a] > po[b]) a = idom[a];
+        while (po[b] > po[a]) b = idom[b];
+    }
+    return a;
+}
+
+/* the digest: a sum over (kind, index, value) items, so its value does not
+ * depend on the order the items are produced in */
+static uint64_t ssa_item(uint64_t kind, uint64_t index, uint64_t value) {
+    return mix64(mix64(kind * 0x9E3779B97F4A7C15ull + index) ^ value);
+}
+
+int or_ssa_uses(const or_instr *I, unsigned *out) { return ssa_uses(I, out); }
+int or_ssa_defs(const or_instr *I, unsigned *out) { return ssa_defs(I, out); }
+
+void or_ssa_free(or_ssa_out *R) {
+    free(R->idom); free(R->phi); free(R->phi_arg_off); free(R->phi_arg); free(R->use_ver); free(R->def_ver);
+    memset(R, 0, sizeof(*R));
+}
+
+int or_ssa(const or_kernel *K, const or_instr *I, or_ssa_out *R) {
+    memset(R, 0, sizeof(*R));
+    const uint32_t n = K->n_instr;
+    R->use_ver = (uint32_t *)malloc(sizeof(uint32_t) * SSA_NU * (n ? n : 1));
+    R->def_ver = (uint32_t *)malloc(sizeof(uint32_t) * SSA_ND * (n ? n : 1));
+    for (uint64_t i = 0; i < (uint64_t)SSA_NU * n; i++) R->use_ver[i] = SSA_NONE;
+    for (uint64_t i = 0; i < (uint64_t)SSA_ND * n; i++) R->def_ver[i] = SSA_NONE;
+    R->phi_arg_off = (uint32_t *)calloc(1, sizeof(uint32_t));
+    R->status = or_kernel_status(K, I);
+    if (R->status != OK) return R->status;
+    cfg_t G;
+    build_cfg(I, n, &G);
+    const uint32_t nb = G.n_blocks;
+    R->n_blocks = nb;
+    /* reverse postorder positions; -1 unreachable */
+    int32_t *po = (int32_t *)malloc(sizeof(int32_t) * nb);
+    for (uint32_t b = 0; b < nb; b++) po[b] = -1;
+    for (uint32_t i = 0; i < G.n_reach; i++) po[G.rpo[i]] = (int32_t)i;
+    /* dominators */
+    uint32_t *idom = (uint32_t *)malloc(sizeof(uint32_t) * nb);
+    for (uint32_t b = 0; b < nb; b++) idom[b] = SSA_NONE;
+    idom[0] = 0;
+    for (int changed = 1; changed;) {
+        changed = 0;
+        for (uint32_t i = 1; i < G.n_reach; i++) {
+            const uint32_t b = G.rpo[i];
+            uint32_t nd = SSA_NONE;
+            for (uint32_t j = G.pred_off[b]; j < G.pred_off[b + 1]; j++) {
+                const uint32_t p = G.pred[j];
+                if (po[p] < 0 || idom[p] == SSA_NONE) continue;
+                nd = nd == SSA_NONE ? p : dom_meet(idom, po, p, nd);
+            }
+            if (nd != idom[b]) { idom[b] = nd; changed = 1; }
+        }
+    }
+    R->idom = idom;
+    /* dominance frontiers (lists per block); the virtual start dominates
+     * block 0, so a predecessor of block 0 climbs to block 0 inclusive */
+    uint32_t *df_n = (uint32_t *)calloc(nb, sizeof(uint32_t)), *df_cap = (uint32_t *)calloc(nb, sizeof(uint32_t));
+    uint32_t **df = (uint32_t **)calloc(nb, sizeof(uint32_t *));
+    uint32_t *mark = (uint32_t *)malloc(sizeof(uint32_t) * nb);
+    for (uint32_t b = 0; b < nb; b++) mark[b] = SSA_NONE;
+    for (uint32_t b = 0; b < nb; b++) {
+        if (po[b] < 0) continue;
+        for (uint32_t j = G.pred_off[b]; j < G.pred_off[b + 1]; j++) {
+            uint32_t r = G.pred[j];
+            if (po[r] < 0) continue;
+            for (;;) {
+                if (b != 0 && r == idom[b]) break;
+                if (mark[r] != b) {
+                    mark[r] = b;
+                    if (df_n[r] == df_cap[r]) {
+                        df_cap[r] = df_cap[r] ? 2 * df_cap[r] : 4;
+                        df[r] = (uint32_t *)realloc(df[r], sizeof(uint32_t) * df_cap[r]);
+                    }
+                    df[r][df_n[r]++] = b;
+                }
+                if (r == 0) break;   /* above block 0 is the virtual start */
+                r = idom[r];
+            }
+        }
+    }
+    /* phi placement: per slot, the iterated dominance frontier of its
+     * defining blocks (worklist) */
+    uint8_t *defines = (uint8_t *)calloc((size_t)nb * NSLOT, 1);
+    for (uint32_t b = 0; b < nb; b++) {
+        if (po[b] < 0) continue;
+        for (uint32_t i = G.block_start[b]; i < G.block_start[b + 1]; i++) {
+            unsigned d[SSA_ND];
+            const int nd = ssa_defs(&I[i], d);
+            for (int q = 0; q < nd; q++) defines[(size_t)b * NSLOT + d[q]] = 1;
+        }
+    }
+    uint8_t *has_phi = (uint8_t *)calloc((size_t)nb * NSLOT, 1);
+    uint32_t *work = (uint32_t *)malloc(sizeof(uint32_t) * (nb + 1)), *inw = (uint32_t *)malloc(sizeof(uint32_t) * nb);
+    for (unsigned v = 0; v < NSLOT; v++) {
+        uint32_t nw = 0;
+        for (uint32_t b = 0; b < nb; b++) {
+            inw[b] = 0;
+            if (defines[(size_t)b * NSLOT + v]) { work[nw++] = b; inw[b] = 1; }
+        }
+        while (nw) {
+            const uint32_t x = work[--nw];
+            for (uint32_t j = 0; j < df_n[x]; j++) {
+                const uint32_t y = df[x][j];
+                if (has_phi[(size_t)y * NSLOT + v]) continue;
+                has_phi[(size_t)y * NSLOT + v] = 1;
+                if (!inw[y]) { inw[y] = 1; work[nw++] = y; }
+            }
+        }
+    }
+    uint32_t n_phi = 0;
+    for (size_t i = 0; i < (size_t)nb * NSLOT; i++) n_phi += has_phi[i];
+    R->n_phi = n_phi;
+    R->phi = (or_phi *)malloc(sizeof(or_phi) * (n_phi ? n_phi : 1));
+    uint32_t *phi_at = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)nb * NSLOT);   /* phi index or SSA_NONE */
+    R->phi_arg_off = (uint32_t *)realloc(R->phi_arg_off, sizeof(uint32_t) * (n_phi + 1));
+    uint32_t np = 0, na = 0;
+    for (uint32_t b = 0; b < nb; b++) {
+        uint32_t inc = 0;   /* incoming edges: reachable predecessors, plus the entry edge of block 0 */
+        for (uint32_t j = G.pred_off[b]; j < G.pred_off[b + 1]; j++) inc += po[G.pred[j]] >= 0;
+        if (b == 0) inc++;
+        for (unsigned v = 0; v < NSLOT; v++) {
+            phi_at[(size_t)b * NSLOT + v] = SSA_NONE;
+            if (!has_phi[(size_t)b * NSLOT + v]) continue;
+            R->phi[np].block = b;
+            R->phi[np].slot = (uint16_t)v;
+            R->phi[np].pad = 0;
+            R->phi[np].version = SSA_NONE;
+            R->phi_arg_off[np] = na;
+            phi_at[(size_t)b * NSLOT + v] = np++;
+            na += inc;
+        }
+    }
+    R->phi_arg_off[np] = na;
+    R->n_args = na;
+    R->phi_arg = (uint32_t *)malloc(sizeof(uint32_t) * (na ? na : 1));
+    for (uint32_t i = 0; i < na; i++) R->phi_arg[i] = SSA_NONE;
+    /* block 0's entry edge carries version 0 */
+    for (unsigned v = 0; v < NSLOT; v++)
+        if (phi_at[v] != SSA_NONE) R->phi_arg[R->phi_arg_off[phi_at[v]]] = 0;
+    /* dominator-tree children, ascending */
+    uint32_t *ch_off = (uint32_t *)calloc(nb + 1, sizeof(uint32_t)), *ch = (uint32_t *)malloc(sizeof(uint32_t) * (nb ? nb : 1));
+    for (uint32_t b = 1; b < nb; b++) if (po[b] >= 0) ch_off[idom[b] + 1]++;
+    for (uint32_t b = 0; b < nb; b++) ch_off[b + 1] += ch_off[b];
+    uint32_t *chf = (uint32_t *)calloc(nb + 1, sizeof(uint32_t));
+    for (uint32_t b = 1; b < nb; b++) if (po[b] >= 0) ch[ch_off[idom[b]] + chf[idom[b]]++] = b;
+    free(chf);
+    /* renaming: a stack of versions per slot; an explicit walk stack of
+     * (block, next child) with the count of versions each visit pushed */
+    uint32_t counter[NSLOT], *vstk[NSLOT], vsp[NSLOT], vcap[NSLOT];
+    for (unsigned v = 0; v < NSLOT; v++) {
+        counter[v] = 1;
+        vcap[v] = 16;
+        vstk[v] = (uint32_t *)malloc(sizeof(uint32_t) * vcap[v]);
+        vstk[v][0] = 0;
+        vsp[v] = 1;
+    }
+#define SSA_PUSH(v, x) do { if (vsp[v] == vcap[v]) { vcap[v] *= 2; vstk[v] = (uint32_t *)realloc(vstk[v], sizeof(uint32_t) * vcap[v]); } vstk[v][vsp[v]++] = (x); } while (0)
+    typedef struct { uint32_t b, next; uint32_t pushed_lo; } frame_t;
+    frame_t *fs = (frame_t *)malloc(sizeof(frame_t) * (nb + 1));
+    uint32_t *pushlog = (uint32_t *)malloc(sizeof(uint32_t) * ((size_t)SSA_ND * n + (size_t)nb * NSLOT + 1));
+    uint32_t pl = 0, fsp = 0;
+    if (nb) { fs[0].b = 0; fs[0].next = SSA_NONE; fs[0].pushed_lo = 0; fsp = 1; }
+    while (fsp) {
+        frame_t *f = &fs[fsp - 1];
+        const uint32_t b = f->b;
+        if (f->next == SSA_NONE) {   /* enter b */
+            f->pushed_lo = pl;
+            for (unsigned v = 0; v < NSLOT; v++) {
+                const uint32_t pi = phi_at[(size_t)b * NSLOT + v];
+                if (pi == SSA_NONE) continue;
+                R->phi[pi].version = counter[v];
+                SSA_PUSH(v, counter[v]);
+                counter[v]++;
+                pushlog[pl++] = v;
+            }
+            for (uint32_t i = G.block_start[b]; i < G.block_start[b + 1]; i++) {
+                unsigned u[SSA_NU], d[SSA_ND];
+                const int nu = ssa_uses(&I[i], u), nd = ssa_defs(&I[i], d);
+                for (int q = 0; q < nu; q++) R->use_ver[(size_t)i * SSA_NU + q] = vstk[u[q]][vsp[u[q]] - 1];
+                for (int q = 0; q < nd; q++) {
+                    R->def_ver[(size_t)i * SSA_ND + q] = counter[d[q]];
+                    SSA_PUSH(d[q], counter[d[q]]);
+                    counter[d[q]]++;
+                    pushlog[pl++] = d[q];
+                }
+            }
+            /* arguments of the successors' phis for the edge from b */
+            for (int e = 0; e < 2; e++) {
+                const int32_t s = G.succ[2 * b + e];
+                if (s < 0) continue;
+                uint32_t k = (s == 0) ? 1 : 0;   /* incoming-edge index of b at s */
+                for (uint32_t j = G.pred_off[s]; j < G.pred_off[s + 1] && G.pred[j] != b; j++) k += po[G.pred[j]] >= 0;
+                for (unsigned v = 0; v < NSLOT; v++) {
+                    const uint32_t pi = phi_at[(size_t)s * NSLOT + v];
+                    if (pi != SSA_NONE) R->phi_arg[R->phi_arg_off[pi] + k] = vstk[v][vsp[v] - 1];
+                }
+            }
+            f->next = ch_off[b];
+        }
+        if (f->next < ch_off[b + 1]) {
+            const uint32_t c = ch[f->next++];
+            fs[fsp].b = c;
+            fs[fsp].next = SSA_NONE;
+            fs[fsp].pushed_lo = 0;
+            fsp++;
+        } else {   /* leave b: pop what it pushed */
+            while (pl > f->pushed_lo) vsp[pushlog[--pl]]--;
+            fsp--;
+        }
+    }
+#undef SSA_PUSH
+    for (unsigned v = 0; v < NSLOT; v++) { R->n_ver[v] = counter[v]; free(vstk[v]); }
+    /* digest over idom, phis, arguments and every use and definition version */
+    uint64_t h = 0;
+    for (uint32_t b = 0; b < nb; b++) h += ssa_item(1, b, idom[b]);
+    for (uint32_t i = 0; i < n_phi; i++)
+        h += ssa_item(2, ((uint64_t)R->phi[i].block << 16) | R->phi[i].slot, R->phi[i].version);
+    for (uint32_t i = 0; i < n_phi; i++)
+        for (uint32_t k = R->phi_arg_off[i]; k < R->phi_arg_off[i + 1]; k++)
+            h += ssa_item(3, ((uint64_t)R->phi[i].block << 24) | ((uint64_t)R->phi[i].slot << 12) | (k - R->phi_arg_off[i]),
+                          R->phi_arg[k]);
+    for (uint64_t i = 0; i < (uint64_t)SSA_NU * n; i++) h += ssa_item(4, i, R->use_ver[i]);
+    for (uint64_t i = 0; i < (uint64_t)SSA_ND * n; i++) h += ssa_item(5, i, R->def_ver[i]);
+    R->digest = h;
+    for (uint32_t b = 0; b < nb; b++) free(df[b]);
+    free(df); free(df_n); free(df_cap); free(mark); free(defines); free(has_phi); free(work); free(inw);
+    free(phi_at); free(ch_off); free(ch); free(fs); free(pushlog); free(po);
+    free_cfg(&G);
+    return OK;
+}
+
 /*
  * Batch driver: per kernel summary (status, n_blocks, sweeps, counts, digest)
  * and the accesses and system values packed densely in kernel order.
