@@ -34,7 +34,8 @@ HBM_PEAK_GBS = 8000.0
 N_CU = 256
 CLOCK_GHZ = 2.4
 PROFILE = os.path.join(ROOT, "profiles", "k_fixpoint_zipf_1048576_kernels.md")
-FIXPOINT_SRC = os.path.join(ROOT, "paper_2107_07809_amd", "csrc", "dc_fixpoint.hip")
+# the fixpoint kernel's source: the per-kernel core and the persistent kernel
+FIXPOINT_SRC = [os.path.join(ROOT, "paper_2107_07809_amd", "csrc", f) for f in ("dc_fixpoint_core.h", "dc_fixpoint.hip")]
 WORKLOADS = {
     3: ("1,048,576 seeded synthetic GCN kernels, Zipf(s=1.2) lengths on [20, 20000], nested exec-mask if/else "
         "and counted loops to depth 3, ~18% float ALU", 1048576),
@@ -53,7 +54,7 @@ def profile_fields():
     counters were taken."""
     try:
         text = open(PROFILE).read()
-        src = hashlib.sha256(open(FIXPOINT_SRC, "rb").read()).hexdigest()
+        src = hashlib.sha256(b"".join(open(f, "rb").read() for f in FIXPOINT_SRC)).hexdigest()
     except OSError:
         return {}
     fields = dict(line.split(": ", 1) for line in text.splitlines() if ": " in line and line[:1].islower())
@@ -204,31 +205,47 @@ def timed_run(ctx, b, stream, steps, warmup, shape, sample_idx=None, lat_steps=5
     }
 
 
-def plain_per_kernel(ctx, b, stream, n_sample):
-    """The plain form for comparison: every kernel analysed by its own
-    sequence of launches (its own batch of one), one after another, on the
-    first n_sample kernels.  Planning happens before the timed region."""
+def plain_per_kernel(ctx, b, stream, n_sample, reps=3):
+    """The plain form for comparison (DC_OPT_PLAIN): one launch per kernel, in
+    which one workgroup runs every stage of that kernel, one launch after
+    another, on the first n_sample kernels.  Planning happens before the
+    timed region."""
+    import torch
+    from paper_2107_07809_amd import dc
+    sub = b.subset(np.arange(n_sample))
+    dev = dc.to_device(sub.instrs)
+    bt = ctx.analyze(sub.kernels, dev, sub.n_instr, sub.args, flags=dc.OPT_PLAIN, stream=stream)
+    bt.wait()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        bt.run(stream=stream)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    failed = int((bt.results()["status"] != 0).sum())
+    bt.free()
+    return {"value": sub.n_instr / dt, "unit": "instructions/s", "kernels": n_sample, "instructions": int(sub.n_instr),
+            "seconds": dt, "failed": failed, "form": "one launch per kernel (DC_OPT_PLAIN)"}
+
+
+def graph_replay_ms(ctx, b, stream, reps=50):
+    """Milliseconds per run of the batch when its stages replay as one captured
+    HIP graph (DC_OPT_GRAPH), beside the eager runs: on a small batch the
+    launches are a visible share of a run."""
     import torch
     from paper_2107_07809_amd import dc
     dev = dc.to_device(b.instrs)
-    batches = []
-    n_instr = 0
-    for k in range(n_sample):
-        d = b.kernels[k:k + 1].copy()
-        ab, na = int(d["arg_begin"][0]), int(d["n_args"][0])
-        d["arg_begin"] = 0
-        batches.append(ctx.analyze(d, dev, b.n_instr, b.args[ab:ab + na], stream=stream))
-        n_instr += int(d["n_instr"][0])
+    bt = ctx.analyze(b.kernels, dev, b.n_instr, b.args, flags=dc.OPT_GRAPH, stream=stream)
+    bt.run(stream=stream)
+    bt.wait()
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for bt in batches:
+    t = time.perf_counter()
+    for _ in range(reps):
         bt.run(stream=stream)
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    for bt in batches:
-        bt.free()
-    return {"value": n_instr / dt, "unit": "instructions/s", "kernels": n_sample, "instructions": n_instr,
-            "seconds": dt}
+    ms = (time.perf_counter() - t) * 1e3 / reps
+    bt.free()
+    return ms
 
 
 def extra_workloads(ctx, stream):
@@ -238,9 +255,11 @@ def extra_workloads(ctx, stream):
     out = {}
     b = dcgen.generate(2, 65536)
     r = timed_run(ctx, b, stream, steps=10, warmup=2, shape={}, lat_steps=0, what="65,536 kernels")
+    plain = plain_per_kernel(ctx, b, stream, 2048)
     out["loguniform_65536_kernels"] = {"instructions": int(b.n_instr), "instructions_per_s": r["value"],
                                        "ms_per_step": r["ms_per_step"], "fixpoint_ms": r["fix_ms"],
-                                       "sweeps_max": r["sweeps"]["max"], "failed": r["failed"]}
+                                       "sweeps_max": r["sweeps"]["max"], "failed": r["failed"],
+                                       "plain": plain, "batched_speedup": r["value"] / plain["value"]}
     b = dcgen.generate(4, 16)
     r = timed_run(ctx, b, stream, steps=2, warmup=0, shape={}, lat_steps=0, what="16 huge kernels")
     out["huge_16_kernels_1M_to_4M"] = {
@@ -251,7 +270,8 @@ def extra_workloads(ctx, stream):
     r = timed_run(ctx, b, stream, steps=50, warmup=2, shape={}, lat_steps=0, what="32 kernels")
     plain = plain_per_kernel(ctx, b, stream, 32)
     out["small_32_kernels"] = {"instructions": int(b.n_instr), "batched_instructions_per_s": r["value"],
-                               "batched_ms": r["ms_per_step"], "plain_instructions_per_s": plain["value"],
+                               "batched_ms": r["ms_per_step"], "graph_replay_ms": graph_replay_ms(ctx, b, stream),
+                               "plain_instructions_per_s": plain["value"],
                                "plain_ms_per_kernel": plain["seconds"] * 1e3 / 32,
                                "batched_speedup": r["value"] / plain["value"]}
     return out
@@ -378,6 +398,7 @@ def main():
                     help="run one 1 GiB device copy first (a known-size reference for HBM counters)")
     ap.add_argument("--waves-per-group", type=int, default=0)
     ap.add_argument("--groups-per-cu", type=int, default=0)
+    ap.add_argument("--longest-first", action="store_true", help="kernels longest first (with an explicit shape)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the library's default launch shape instead of dc_autotune's")
     ap.add_argument("--no-serving", action="store_true")
@@ -410,7 +431,8 @@ def main():
         del src, dst
         log("copy calibration: 1 GiB device-to-device copy done")
     ctx = dc.Context(0)
-    shape = {"waves_per_group": args.waves_per_group, "groups_per_cu": args.groups_per_cu}
+    shape = {"waves_per_group": args.waves_per_group, "groups_per_cu": args.groups_per_cu,
+             "longest_first": args.longest_first}
     tuned = False
     if not args.no_autotune and not (args.waves_per_group or args.groups_per_cu):
         # launch shape from the autotuner on a sample of every stride-th

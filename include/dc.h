@@ -126,7 +126,10 @@ typedef struct {
 #define DC_OPT_GRAPH 8u          /* dc_batch_run replays the stages as one captured HIP graph (from the second run
                                     on; not with DC_OPT_EXPORT_STATES or DC_OPT_TIMING, nor on the NULL stream,
                                     where runs stay eager) */
-#define DC_OPT_INDEX_ORDER 16u   /* the fixpoint takes kernels in index order instead of longest first */
+#define DC_OPT_LONGEST_FIRST 16u /* the fixpoint takes kernels longest first instead of in index order */
+#define DC_OPT_PLAIN 32u         /* the plain form: one launch per kernel, one workgroup doing every stage of that
+                                    kernel (the comparison point of the batched form; not with DC_OPT_EXPORT_STATES
+                                    or DC_OPT_GRAPH) */
 typedef struct {
     uint32_t flags;
     uint32_t sweep_cap;          /* 0 = 64 + 2 * n_blocks per kernel */
@@ -195,13 +198,18 @@ void dc_cfg_free(dc_cfg_t *cfg);
 dc_status_t dc_analyze_batch(dc_ctx_t *ctx, const dc_kernel_t *kernels, uint32_t n_kernels, const dc_instr_t *instrs,
                              uint64_t n_records, const dc_arg_t *args, uint64_t n_args_total,
                              const dc_options_t *opts, void *stream, dc_batch_t **out);
-/* Launch-shape autotuner.  Times whole runs of a sample of the batch
- * (every stride-th kernel, at most `sample` kernels; 0 = 8192) under a few
- * fixpoint launch shapes -- waves per workgroup 1, 2 and the most that fit,
- * each with the most resident groups per CU and three quarters of that --
- * and writes the fastest shape into *best (the other fields are copied from
- * base, which may be NULL) and its time per run into *best_ms.  Synchronous;
- * allocates and frees its own trial batches. */
+/* Autotuner for the fixpoint's launch.  Times whole runs of a sample of the
+ * batch (every stride-th kernel, at most `sample` kernels; 0 = 8192) under
+ * each launch shape -- waves per workgroup 1, 2 and the most that fit, each
+ * with the most resident groups per CU and three quarters of that -- in both
+ * kernel orders (index order, DC_OPT_LONGEST_FIRST), and writes the fastest
+ * into *best (the other fields are copied from base, which may be NULL) and
+ * its time per run of the sample into *best_ms.  The choice is cached per
+ * device size (CUs), batch size bucket (log2 of the mean kernel length and of
+ * the kernel count) and the DIGEST/EXPORT flags of base, in the process and,
+ * when the environment names a file in DC_TUNE_CACHE, in that file; a cached
+ * choice is returned without timing.  Synchronous; allocates and frees its
+ * own trial batches. */
 dc_status_t dc_autotune(dc_ctx_t *ctx, const dc_kernel_t *kernels, uint32_t n_kernels, const dc_instr_t *instrs,
                         uint64_t n_records, const dc_arg_t *args, uint64_t n_args_total, const dc_options_t *base,
                         uint32_t sample, void *stream, dc_options_t *best, float *best_ms);
@@ -255,8 +263,10 @@ dc_status_t dc_get_stats(const dc_batch_t *batch, dc_stats_t *out);
 
 /* Stage times summed over the runs enqueued since the last reset (at most
  * the last 64), from HIP events recorded on the batch's stream (needs
- * DC_OPT_TIMING).  ms_fixpoint brackets exactly the main fixpoint kernel
- * launch.  Waits for the stream. */
+ * DC_OPT_TIMING).  ms_fixpoint brackets exactly the fixpoint's two launches
+ * (the main pass and the overflow pass, which returns at once when no kernel
+ * was deferred to it); with DC_OPT_PLAIN it brackets the per-kernel
+ * launches.  Waits for the stream. */
 typedef struct { uint32_t runs, pad; float ms_total, ms_decode, ms_cfg, ms_fixpoint, ms_compact, ms_pad; } dc_timing_t;
 dc_status_t dc_get_timing(const dc_batch_t *batch, dc_timing_t *out);
 dc_status_t dc_timing_reset(dc_batch_t *batch);

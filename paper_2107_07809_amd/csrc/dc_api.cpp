@@ -7,8 +7,13 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <stdio.h>
+
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <new>
+#include <tuple>
 #include <vector>
 
 #include "dc.h"
@@ -168,7 +173,7 @@ PlanInputs dc::alloc_plan(DevMem &M, Plan &P, const PlanDims &d) {
     P.ovf_bitmaps = nullptr;
     P.dummy = M.alloc<uint4>((d.waves + OVF_MAX_WAVES) * 64);
     P.ovf_list = M.alloc<uint32_t>(K);
-    P.counters = M.alloc<uint32_t>(4);
+    P.counters = M.alloc<uint32_t>(8);
     P.results = M.alloc<dc_kernel_result_t>(K);
     P.acc_count = M.alloc<uint32_t>(K + 1);
     P.sys_count = M.alloc<uint32_t>(K + 1);
@@ -219,7 +224,10 @@ static dc_status_t plan_batch(dc_batch *B, dc_ctx *ctx, const dc_kernel_t *kerne
     B->stream = (hipStream_t)stream;
     B->cfg_only = cfg_only;
     if (opts) B->opts = *opts;
-    if (B->opts.flags & ~(DC_OPT_EXPORT_STATES | DC_OPT_DIGEST | DC_OPT_TIMING | DC_OPT_GRAPH | DC_OPT_INDEX_ORDER))
+    if (B->opts.flags & ~(DC_OPT_EXPORT_STATES | DC_OPT_DIGEST | DC_OPT_TIMING | DC_OPT_GRAPH | DC_OPT_LONGEST_FIRST |
+                          DC_OPT_PLAIN))
+        return DC_E_INVAL;
+    if ((B->opts.flags & DC_OPT_PLAIN) && (cfg_only || (B->opts.flags & (DC_OPT_EXPORT_STATES | DC_OPT_GRAPH))))
         return DC_E_INVAL;
     if ((B->opts.flags & DC_OPT_GRAPH) && (B->opts.flags & (DC_OPT_EXPORT_STATES | DC_OPT_TIMING))) return DC_E_INVAL;
     /* waves per group: the fixpoint kernel's LDS per wave must fit a group */
@@ -256,8 +264,18 @@ static dc_status_t plan_batch(dc_batch *B, dc_ctx *ctx, const dc_kernel_t *kerne
     P.n_pos = (uint32_t)N;
     P.n_records = n_records;
     P.n_args = n_args_total;
+    const bool plain = (B->opts.flags & DC_OPT_PLAIN) != 0;
+    uint64_t n_max = 0;
+    for (uint32_t k = 0; k < n_kernels; k++) n_max = std::max<uint64_t>(n_max, kernels[k].n_instr);
     PlanDims dims{N, K, n_args_total, cfg_only, 0, 0};
-    if (!cfg_only) {
+    if (plain) {
+        /* one scratch plan for the longest kernel: the launches run in turn */
+        dims.N = n_max;
+        dims.waves = 1;
+        dims.arena_rows = (uint32_t)(FIX_MAX_ROWS * std::max<uint64_t>(n_max, 1));
+        B->fc.waves_per_group = 1;
+        B->fc.groups = 1;
+    } else if (!cfg_only) {
         const uint32_t wpg = B->opts.waves_per_group;
         /* persistent grid: as many groups per CU as the fixpoint kernel's
          * registers and LDS allow */
@@ -279,6 +297,17 @@ static dc_status_t plan_batch(dc_batch *B, dc_ctx *ctx, const dc_kernel_t *kerne
         P.sweep_cap = B->opts.sweep_cap;
         P.flags = B->opts.flags;
     }
+    if (plain) {
+        /* block arrays and regions for the longest kernel; dense outputs for
+         * the batch (one access and four built-in records per instruction) */
+        P.n_pos = (uint32_t)n_max;
+        alloc_blocks(B->bmem, P, n_max, n_max, 4 * n_max, false);
+        P.acc_dense = M.alloc<dc_access_t>(N);
+        P.sys_dense = M.alloc<dc_sysval_t>(4 * N);
+        P.ovf_bitmaps = M.alloc<uint32_t>(2 * ((n_max + 31) / 32) + 64);
+        P.ovf_block_cap = (uint32_t)n_max;
+        B->blocks_planned = B->ovf_planned = true;
+    }
     B->dP = M.alloc<Plan>(1);
     if (M.failed) return DC_E_OOM;
     hipStream_t s = B->stream;
@@ -289,11 +318,13 @@ static dc_status_t plan_batch(dc_batch *B, dc_ctx *ctx, const dc_kernel_t *kerne
     if (e == hipSuccess)
         e = hipMemcpyAsync(d_pb, B->pos_begin.data(), (K + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, s);
     if (e == hipSuccess && K) e = hipMemcpyAsync(d_ds, dstat.data(), K * sizeof(int32_t), hipMemcpyHostToDevice, s);
-    /* the fixpoint takes the longest kernels first, so that no long kernel
-     * starts last and holds up the end of the launch */
+    /* DC_OPT_LONGEST_FIRST: the fixpoint takes the longest kernels first, so
+     * that no long kernel starts last and holds up the end of the launch (it
+     * also runs the longest kernels side by side, whose larger arenas compete
+     * for the caches; the autotuner measures which order is faster) */
     std::vector<uint32_t> order;
-    if (!cfg_only && (B->opts.flags & DC_OPT_INDEX_ORDER)) P.work_order = nullptr;
-    if (!cfg_only && K && !(B->opts.flags & DC_OPT_INDEX_ORDER)) {
+    if (!cfg_only && !(B->opts.flags & DC_OPT_LONGEST_FIRST)) P.work_order = nullptr;
+    if (!cfg_only && K && (B->opts.flags & DC_OPT_LONGEST_FIRST)) {
         order.resize(K);
         for (uint32_t k = 0; k < K; k++) order[k] = k;
         std::stable_sort(order.begin(), order.end(),
@@ -435,6 +466,16 @@ static dc_status_t enqueue(dc_batch *B) {
         if (e != hipSuccess) return hip_fail(e); \
     } while (0)
     if (B->have_events) TRY(hipEventRecord(ev[EV_START], s));
+    if (B->opts.flags & DC_OPT_PLAIN) {
+        if (B->have_events) {
+            TRY(hipEventRecord(ev[EV_DECODE], s));
+            TRY(hipEventRecord(ev[EV_CFG], s));
+        }
+        TRY(launch_plain(P, B->dP, s, B->have_events ? ev[EV_FIXB] : nullptr, B->have_events ? ev[EV_FIX] : nullptr));
+        if (B->have_events) TRY(hipEventRecord(ev[EV_END], s));
+        B->runs++;
+        return DC_OK;
+    }
     TRY(launch_fill_u8(P.leader, B->N, 0, s));
     TRY(launch_fill_u32(P.kbad, B->K, 0xFFFFFFFFu, s));
     TRY(launch_decode(P, s));
@@ -512,6 +553,59 @@ extern "C" dc_status_t dc_analyze_batch(dc_ctx_t *ctx, const dc_kernel_t *kernel
     return DC_OK;
 }
 
+/* Autotuner cache: the choice for a batch of this size bucket on a device of
+ * this many CUs (in the process; in the file named by DC_TUNE_CACHE when
+ * set, one entry per line: cus len_bucket k_bucket flags waves groups order ms) */
+struct TuneKey {
+    int cus;
+    uint32_t len_bucket, k_bucket, flags;
+    bool operator<(const TuneKey &o) const {
+        return std::tie(cus, len_bucket, k_bucket, flags) < std::tie(o.cus, o.len_bucket, o.k_bucket, o.flags);
+    }
+};
+struct TuneVal {
+    uint32_t waves, groups, order;
+    float ms;
+};
+static std::mutex g_tune_mu;
+static std::map<TuneKey, TuneVal> g_tune;
+static bool g_tune_loaded = false;
+
+static uint32_t log2_bucket(uint64_t x) {
+    uint32_t b = 0;
+    while (x > 1) {
+        x >>= 1;
+        b++;
+    }
+    return b;
+}
+
+static void tune_load_locked() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *path = getenv("DC_TUNE_CACHE");
+    if (!path) return;
+    FILE *f = fopen(path, "r");
+    if (!f) return;
+    TuneKey k;
+    TuneVal v;
+    while (fscanf(f, "%d %u %u %u %u %u %u %f", &k.cus, &k.len_bucket, &k.k_bucket, &k.flags, &v.waves, &v.groups,
+                  &v.order, &v.ms) == 8)
+        g_tune[k] = v;
+    fclose(f);
+}
+
+static void tune_store_locked(const TuneKey &k, const TuneVal &v) {
+    g_tune[k] = v;
+    const char *path = getenv("DC_TUNE_CACHE");
+    if (!path) return;
+    FILE *f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "%d %u %u %u %u %u %u %.4f\n", k.cus, k.len_bucket, k.k_bucket, k.flags, v.waves, v.groups, v.order,
+            v.ms);
+    fclose(f);
+}
+
 extern "C" dc_status_t dc_autotune(dc_ctx_t *ctx, const dc_kernel_t *kernels, uint32_t n_kernels,
                                    const dc_instr_t *instrs, uint64_t n_records, const dc_arg_t *args,
                                    uint64_t n_args_total, const dc_options_t *base, uint32_t sample, void *stream,
@@ -521,7 +615,26 @@ extern "C" dc_status_t dc_autotune(dc_ctx_t *ctx, const dc_kernel_t *kernels, ui
     if (sample == 0) sample = 8192;
     const uint32_t stride = std::max<uint32_t>(1, (n_kernels + sample - 1) / sample);
     std::vector<dc_kernel_t> ks;
-    for (uint32_t k = 0; k < n_kernels; k += stride) ks.push_back(kernels[k]);
+    uint64_t n_sum = 0;
+    for (uint32_t k = 0; k < n_kernels; k += stride) {
+        ks.push_back(kernels[k]);
+        n_sum += kernels[k].n_instr;
+    }
+    const uint32_t keep = base ? base->flags & (DC_OPT_DIGEST | DC_OPT_EXPORT_STATES) : 0u;
+    const TuneKey key{ctx->n_cu, log2_bucket(ks.empty() ? 0 : n_sum / ks.size()), log2_bucket(n_kernels), keep};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_load_locked();
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            *best = base ? *base : dc_options_t{};
+            best->waves_per_group = it->second.waves;
+            best->groups_per_cu = it->second.groups;
+            best->flags = (best->flags & ~DC_OPT_LONGEST_FIRST) | it->second.order;
+            *best_ms = it->second.ms;
+            return DC_OK;
+        }
+    }
     const size_t lds_wave = fixpoint_lds_per_wave();
     const uint32_t wmax = (uint32_t)std::max<size_t>(1, std::min<size_t>(4, ctx->lds_per_group / lds_wave));
     std::vector<std::pair<uint32_t, uint32_t>> shapes;
@@ -534,31 +647,41 @@ extern "C" dc_status_t dc_autotune(dc_ctx_t *ctx, const dc_kernel_t *kernels, ui
     }
     dc_options_t o{};
     if (base) o = *base;
-    o.flags = (o.flags & ~DC_OPT_EXPORT_STATES) | DC_OPT_TIMING;
+    o.flags = (o.flags & ~(DC_OPT_EXPORT_STATES | DC_OPT_LONGEST_FIRST)) | DC_OPT_TIMING;
     float best_t = -1.0f;
-    for (auto [w, pc] : shapes) {
-        o.waves_per_group = w;
-        o.groups_per_cu = pc;
-        dc_batch_t *B = nullptr;
-        dc_status_t st = dc_analyze_batch(ctx, ks.data(), (uint32_t)ks.size(), instrs, n_records, args, n_args_total,
-                                          &o, stream, &B);
-        if (st != DC_OK) return st;
-        dc_timing_t t{};
-        st = dc_batch_wait(B);
-        if (st == DC_OK) st = dc_timing_reset(B);
-        for (int r = 0; r < 3 && st == DC_OK; r++) st = dc_batch_run(B, nullptr, stream);
-        if (st == DC_OK) st = dc_get_timing(B, &t);
-        dc_batch_free(B);
-        if (st != DC_OK) return st;
-        const float ms = t.runs ? t.ms_total / t.runs : 0.0f;
-        if (best_t < 0.0f || ms < best_t) {
-            best_t = ms;
-            *best = base ? *base : dc_options_t{};
-            best->waves_per_group = w;
-            best->groups_per_cu = pc;
+    TuneVal bv{};
+    for (uint32_t order : {0u, DC_OPT_LONGEST_FIRST}) {
+        for (auto [w, pc] : shapes) {
+            o.waves_per_group = w;
+            o.groups_per_cu = pc;
+            const uint32_t f0 = o.flags;
+            o.flags = f0 | order;
+            dc_batch_t *B = nullptr;
+            dc_status_t st = dc_analyze_batch(ctx, ks.data(), (uint32_t)ks.size(), instrs, n_records, args,
+                                              n_args_total, &o, stream, &B);
+            o.flags = f0;
+            if (st != DC_OK) return st;
+            dc_timing_t t{};
+            st = dc_batch_wait(B);
+            if (st == DC_OK) st = dc_timing_reset(B);
+            for (int r = 0; r < 3 && st == DC_OK; r++) st = dc_batch_run(B, nullptr, stream);
+            if (st == DC_OK) st = dc_get_timing(B, &t);
+            dc_batch_free(B);
+            if (st != DC_OK) return st;
+            const float ms = t.runs ? t.ms_total / t.runs : 0.0f;
+            if (best_t < 0.0f || ms < best_t) {
+                best_t = ms;
+                bv = TuneVal{w, pc, order, ms};
+            }
         }
     }
+    *best = base ? *base : dc_options_t{};
+    best->waves_per_group = bv.waves;
+    best->groups_per_cu = bv.groups;
+    best->flags = (best->flags & ~DC_OPT_LONGEST_FIRST) | bv.order;
     *best_ms = best_t;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_store_locked(key, bv);
     return DC_OK;
 }
 

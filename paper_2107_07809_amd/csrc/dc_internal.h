@@ -75,7 +75,8 @@ struct Plan {
     uint32_t ovf_waves;
     uint32_t *ovf_list;             /* K */
     uint4 *dummy;                   /* (main_waves + ovf_waves) * 64: per-lane scratch stores */
-    uint32_t *counters;             /* [0] work counter, [1] overflow count, [2] overflow work counter */
+    uint32_t *counters;             /* [0] work counter, [1] overflow count, [2] overflow work counter; plain form:
+                                       [4], [5] records written so far (8 words) */
     uint32_t sweep_cap;
     uint32_t flags;
     uint32_t acc_cap, sys_cap;      /* record slots allocated (acc_sparse/acc_dense, sys_sparse/sys_dense) */
@@ -117,6 +118,8 @@ hipError_t launch_edges(const Plan &P, hipStream_t s);                  /* edges
 hipError_t launch_fixpoint(const Plan &P, const Plan *dP, const FixCfg &c, hipStream_t s, hipEvent_t before,
                            hipEvent_t after);
 hipError_t launch_compact(const Plan &P, hipStream_t s);                /* dense outputs */
+/* the plain form: one launch per kernel (dc_plain.hip); events bracket the launches */
+hipError_t launch_plain(const Plan &P, const Plan *dP, hipStream_t s, hipEvent_t before, hipEvent_t after);
 uint32_t fixpoint_groups_per_cu(uint32_t waves_per_group);              /* resident fixpoint groups per CU */
 size_t fixpoint_lds_per_wave();                                         /* LDS bytes per fixpoint wavefront */
 constexpr uint32_t KSLOT_WORDS = 12;                                    /* 384 bits >= NSLOT */

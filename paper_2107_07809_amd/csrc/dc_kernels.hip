@@ -25,66 +25,9 @@
  * with DC_E_CAPACITY instead of writing past an array.
  */
 #include "dc_device.h"
+#include "dc_records.h"
 
 namespace dc {
-
-/* ------------------------------------------------------------------ */
-/* record checks (per thread)                                           */
-/* ------------------------------------------------------------------ */
-__device__ __forceinline__ bool sreg_ok(uint32_t id, uint32_t w) {
-    switch (w) {
-    case 1: return id <= 107u || id == 109u;
-    case 2: return (id & 1u) == 0 && (id <= 102u || id == 104u || id == 106u);
-    case 4: return (id & 3u) == 0 && id <= 100u;
-    }
-    return false;
-}
-__device__ __forceinline__ bool vreg_ok(uint32_t id, uint32_t w) { return id >= 112u && id + w <= 368u; }
-__device__ __forceinline__ bool inl_ok(uint32_t id) {
-    return (id >= 0x8000u && id <= 0x8050u) || (id >= 0x8060u && id <= 0x8067u);
-}
-__device__ bool role_ok(uint32_t role, uint32_t id, uint32_t w, bool lit) {
-    switch (role) {
-    case RO_NO: return id == 0xFFFFu;
-    case RO_SD:
-    case RO_SU: return sreg_ok(id, w);
-    case RO_SC: return sreg_ok(id, w) || inl_ok(id) || (lit && id == 0xFFFEu);
-    case RO_VD:
-    case RO_VU: return vreg_ok(id, w);
-    case RO_VC: return vreg_ok(id, w) || sreg_ok(id, w) || inl_ok(id) || (lit && id == 0xFFFEu);
-    case RO_SADDR: return id == 0xFFFFu || (sreg_ok(id, 2) && id <= 102u);
-    }
-    return false;
-}
-/* 0 ok, 1 bad opcode, 2 bad operand, 3 bad target */
-__device__ uint32_t check_record(uint32_t op, uint32_t r0, uint32_t r1, uint32_t r2, int32_t imm, int32_t target,
-                                 uint32_t n) {
-    if (op >= (uint32_t)N_OPS) return 1;
-    const uint64_t e = OPTAB[op];
-    const uint32_t cls = e_cls(e);
-    if (cls == C_SMEM) {
-        const uint32_t w = e_width(e, 0);
-        if (!(sreg_ok(r0, w) && r0 + w <= 104u)) return 2;
-        if (!(sreg_ok(r1, 2) && r1 <= 102u)) return 2;
-        if (r2 != 0xFFFFu) return 2;
-    } else {
-        const bool lit = !e_immoff(e) && e_role(e, 3) == RO_NO;
-        if (!role_ok(e_role(e, 0), r0, e_width(e, 0), false)) return 2;
-        if (!role_ok(e_role(e, 1), r1, e_width(e, 1), lit)) return 2;
-        if (!role_ok(e_role(e, 2), r2, e_width(e, 2), lit)) return 2;
-        if (e_role(e, 3) != RO_NO) {
-            if (imm < 0 || imm > 0xFFFF) return 2;
-            if (!role_ok(e_role(e, 3), (uint32_t)imm, e_width(e, 3), false)) return 2;
-        }
-    }
-    if (cls == C_BR || cls == C_CBR) {
-        if (target < 0 || (uint32_t)target >= n) return 3;
-    } else if (target != -1) {
-        return 3;
-    }
-    return 0;
-}
-__device__ __forceinline__ bool ends_block(uint32_t cls) { return cls == C_BR || cls == C_CBR || cls == C_END; }
 
 /* ------------------------------------------------------------------ */
 /* fills                                                                 */
@@ -173,103 +116,74 @@ __device__ __forceinline__ uint32_t lookup(const uint32_t *pos_begin, uint32_t K
 /* ------------------------------------------------------------------ */
 /* decode, check, leader flags                                          */
 /* ------------------------------------------------------------------ */
-/* Record capacity of one instruction: one access record for a memory
- * instruction; one built-in record per explicit definition dword of a rule
- * that can yield a work-item built-in (moves, selects, adds, multiplies,
- * shifts, argument loads).  The other rules yield only constants, pointer
- * halves, sign words or unknowns, none of which is a built-in.  Packed as
- * bit 0 (access) and bits 3:1 (built-ins). */
-__device__ __forceinline__ uint32_t rec_cap(uint64_t e) {
-    const uint32_t cls = e_cls(e), pr = e_prule(e), r0 = e_role(e, 0);
-    const uint32_t acc = cls >= C_GLD ? 1u : 0u;
-    const bool alu = cls == C_SALU || cls == C_VALU;
-    const bool can = cls == C_SMEM || (alu && (pr == PR_MOV || pr == PR_SEL || pr == PR_ADD || pr == PR_MUL ||
-                                               pr == PR_MUL24 || pr == PR_MAD24 || pr == PR_SHL || pr == PR_LSHR ||
-                                               pr == PR_SHL64));
-    const uint32_t sys = can && (r0 == RO_SD || r0 == RO_VD) ? e_width(e, 0) : 0u;
-    return acc | sys << 1;
-}
+constexpr uint32_t KM_KERNELS = 64;   /* kernels of a tile whose slot bitmaps are gathered in LDS */
 
-/* OR of x over each run of lanes with the same key k (runs are contiguous),
- * left in the run's last lane */
-__device__ __forceinline__ uint32_t seg_or(uint32_t x, uint32_t k) {
-    const uint32_t l = lane_id();
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t y = __shfl_up(x, d, 64), kk = __shfl_up(k, d, 64);
-        x |= (l >= (uint32_t)d && kk == k) ? y : 0u;
-    }
-    return x;
+/* OR `bits` into word w of kernel k's slot bitmap: in the tile's LDS copy
+ * when the kernel has one (kk < KM_KERNELS), else in global memory */
+__device__ __forceinline__ void mark_word(const Plan &P, uint32_t *km, uint32_t kk, uint32_t k, uint32_t w,
+                                          uint32_t bits) {
+    if (!bits) return;
+    if (kk < KM_KERNELS) atomicOr(&km[kk * KSLOT_WORDS + w], bits);
+    else atomicOr(&P.kslots[(uint64_t)k * KSLOT_WORDS + w], bits);
 }
 
 __global__ __launch_bounds__(256) void k_decode(Plan P) {
     __shared__ uint32_t lk[LK_CAP];
+    __shared__ uint32_t km[KM_KERNELS * KSLOT_WORDS];
     const uint32_t t0 = blockIdx.x * TILE_LK;
     if (t0 >= P.n_pos) return;
     const uint32_t t1 = min(P.n_pos, t0 + TILE_LK);
     uint32_t k0, cnt;
     lookup_setup(P.pos_begin, P.n_kernels, t0, t1, lk, &k0, &cnt);
-    const uint32_t l = lane_id();
-    /* a uniform trip count: the lanes of a wavefront hold consecutive
-     * positions and meet in the cross-lane steps below */
-    for (uint32_t it = 0; it < (uint32_t)TILE_LK / 256u; it++) {
-        const uint32_t g = t0 + it * 256u + threadIdx.x;
-        const bool act = g < t1;
-        uint32_t k = 0xFFFFFFFFu, n = 0, i = 0, pb = 0;
-        if (act) {
-            k = lookup(P.pos_begin, P.n_kernels, lk, k0, cnt, g);
-            pb = P.pos_begin[k];
-            n = P.pos_begin[k + 1] - pb;
-            i = g - pb;
-        }
-        /* named register slots of this instruction, as a 384-bit set */
-        uint32_t mk[KSLOT_WORDS];
-#pragma unroll
-        for (uint32_t w = 0; w < KSLOT_WORDS; w++) mk[w] = 0;
-        if (act && i >= n) {   /* a position no kernel owns (a call whose descriptors failed their checks) */
+    for (uint32_t i = threadIdx.x; i < KM_KERNELS * KSLOT_WORDS; i += blockDim.x) km[i] = 0;
+    __syncthreads();
+    for (uint32_t g = t0 + threadIdx.x; g < t1; g += blockDim.x) {
+        const uint32_t k = lookup(P.pos_begin, P.n_kernels, lk, k0, cnt, g);
+        const uint32_t pb = P.pos_begin[k];
+        const uint32_t n = P.pos_begin[k + 1] - pb;
+        const uint32_t i = g - pb;
+        if (i >= n) {   /* a position no kernel owns (a call whose descriptors failed their checks) */
             P.pcap[g] = 0;
-        } else if (act) {
-            const dc_kernel_t *D = &P.kernels[k];
-            const uint4 r = reinterpret_cast<const uint4 *>(P.instrs)[D->instr_begin + i];
-            const uint32_t op = r.x & 0xFFFFu, r0 = r.x >> 16, r1 = r.y & 0xFFFFu, r2 = r.y >> 16;
-            const int32_t imm = (int32_t)r.z, target = (int32_t)r.w;
-            const uint32_t bad = check_record(op, r0, r1, r2, imm, target, n);
-            if (i == 0) P.leader[g] = 1;
-            if (bad) {
-                P.pcap[g] = 0;
-                atomicMin(&P.kbad[k], (i << 2) | bad);
-            } else {
-                const uint64_t e = OPTAB[op];
-                const uint32_t cls = e_cls(e);
-                const uint32_t c = rec_cap(e);
-                P.pcap[g] = (uint8_t)c;
-                if (ends_block(cls) && i + 1 < n) P.leader[g + 1] = 1;
-                if (cls == C_BR || cls == C_CBR) P.leader[pb + (uint32_t)target] = 1;
-                const uint32_t id[4] = {r0, r1, r2, (uint32_t)imm};
-#pragma unroll
-                for (int o = 0; o < 4; o++) {
-                    const uint32_t w = e_role(e, o) != RO_NO ? e_width(e, o) : 0u;
-#pragma unroll
-                    for (uint32_t j = 0; j < 4; j++) {
-                        const uint32_t sl = id[o] + j;
-                        const bool on = j < w && id[o] < (uint32_t)NSLOT && sl < (uint32_t)NSLOT;
-#pragma unroll
-                        for (uint32_t q = 0; q < KSLOT_WORDS; q++) mk[q] |= (on && (sl >> 5) == q) ? 1u << (sl & 31u) : 0u;
-                    }
-                }
-            }
+            continue;
         }
-        if (P.kslots) {
-            /* one atomic OR per word and run of lanes of one kernel */
-            const uint32_t kn = __shfl_down(k, 1, 64);
-            const bool tail = act && (l == 63u || kn != k);
+        const dc_kernel_t *D = &P.kernels[k];
+        const uint4 r = reinterpret_cast<const uint4 *>(P.instrs)[D->instr_begin + i];
+        const uint32_t op = r.x & 0xFFFFu, r0 = r.x >> 16, r1 = r.y & 0xFFFFu, r2 = r.y >> 16;
+        const int32_t imm = (int32_t)r.z, target = (int32_t)r.w;
+        const uint32_t bad = check_record(op, r0, r1, r2, imm, target, n);
+        if (i == 0) P.leader[g] = 1;
+        if (bad) {
+            P.pcap[g] = 0;
+            atomicMin(&P.kbad[k], (i << 2) | bad);
+            continue;
+        }
+        const uint64_t e = OPTAB[op];
+        const uint32_t cls = e_cls(e);
+        P.pcap[g] = (uint8_t)rec_cap(e);
+        if (ends_block(cls) && i + 1 < n) P.leader[g + 1] = 1;
+        if (cls == C_BR || cls == C_CBR) P.leader[pb + (uint32_t)target] = 1;
+        if (!P.kslots) continue;
+        /* the register slots the record names: each operand covers a run of
+         * at most four slots, in one or two bitmap words */
+        const uint32_t id[4] = {r0, r1, r2, (uint32_t)imm};
+        const uint32_t kk = cnt ? k - k0 : KM_KERNELS;
 #pragma unroll
-            for (uint32_t q = 0; q < KSLOT_WORDS; q++) {
-                const uint32_t x = seg_or(mk[q], k);
-                if (tail && x) atomicOr(&P.kslots[(uint64_t)k * KSLOT_WORDS + q], x);
-            }
+        for (int o = 0; o < 4; o++) {
+            const uint32_t w = e_role(e, o) != RO_NO ? e_width(e, o) : 0u;
+            if (w == 0 || id[o] >= (uint32_t)NSLOT) continue;
+            const uint32_t first = id[o], last = min(id[o] + w, (uint32_t)NSLOT) - 1u;
+            const uint32_t wa = first >> 5, wb = last >> 5;
+            const uint32_t hi_a = wa == wb ? (last & 31u) : 31u;
+            const uint32_t ma = (0xFFFFFFFFu >> (31u - hi_a)) & (0xFFFFFFFFu << (first & 31u));
+            mark_word(P, km, kk, k, wa, ma);
+            if (wb != wa) mark_word(P, km, kk, k, wb, 0xFFFFFFFFu >> (31u - (last & 31u)));
         }
     }
+    if (!P.kslots || !cnt) return;
+    __syncthreads();
+    const uint32_t nk = min(cnt, KM_KERNELS);
+    for (uint32_t t = threadIdx.x; t < nk * KSLOT_WORDS; t += blockDim.x)
+        if (km[t]) atomicOr(&P.kslots[(uint64_t)(k0 + t / KSLOT_WORDS) * KSLOT_WORDS + t % KSLOT_WORDS], km[t]);
 }
 hipError_t launch_decode(const Plan &P, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, P.totals, (uint64_t)4, 0u);

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libdc.so")
 DC_OK = 0
 STATUS = {0: "OK", -1: "INVAL", -2: "HIP", -3: "OOM", -4: "NOTREADY", -10: "BADOP", -11: "BADREG",
           -12: "BADTARGET", -13: "NOEND", -14: "UNSUPPORTED", -15: "NOFIX", -16: "CAPACITY"}
-OPT_EXPORT_STATES, OPT_DIGEST, OPT_TIMING, OPT_GRAPH, OPT_INDEX_ORDER = 1, 2, 4, 8, 16
+OPT_EXPORT_STATES, OPT_DIGEST, OPT_TIMING, OPT_GRAPH, OPT_LONGEST_FIRST, OPT_PLAIN = 1, 2, 4, 8, 16, 32
 NOALLOC_MAX_KERNELS, NOALLOC_MAX_INSTR = 4096, 262144   # DC_NOALLOC_MAX_KERNELS, DC_NOALLOC_MAX_INSTR
 NSLOT = 368
 
@@ -201,7 +201,8 @@ class Context:
             pass
 
     def analyze(self, kernels, instrs_dev, n_records, args=None, flags=0, sweep_cap=0, waves_per_group=0,
-                groups_per_cu=0, block_cap=0, stream=None) -> "Batch":
+                groups_per_cu=0, block_cap=0, stream=None, longest_first=False) -> "Batch":
+        flags |= OPT_LONGEST_FIRST if longest_first else 0
         kernels = np.ascontiguousarray(np.asarray(kernels, KERNEL_DTYPE))
         args = np.ascontiguousarray(np.asarray(args if args is not None else np.zeros(0, ARG_DTYPE), ARG_DTYPE))
         o = Options(flags, sweep_cap, waves_per_group, groups_per_cu, block_cap)
@@ -212,8 +213,8 @@ class Context:
         return Batch(h, len(kernels), instrs_dev, stream)
 
     def autotune(self, kernels, instrs_dev, n_records, args=None, flags=0, sample=0, stream=None):
-        """Fastest fixpoint launch shape on a sample of the batch:
-        (dict of options for analyze(), ms per run of the sample)."""
+        """Fastest fixpoint launch shape and kernel order on a sample of the
+        batch: (dict of options for analyze(), ms per run of the sample)."""
         kernels = np.ascontiguousarray(np.asarray(kernels, KERNEL_DTYPE))
         args = np.ascontiguousarray(np.asarray(args if args is not None else np.zeros(0, ARG_DTYPE), ARG_DTYPE))
         base = Options(flags, 0, 0, 0, 0)
@@ -222,7 +223,8 @@ class Context:
         check("dc_autotune", lib().dc_autotune(self.h, _np_ptr(kernels), len(kernels), _dev_ptr(instrs_dev), n_records,
                                                _np_ptr(args), len(args), ctypes.byref(base), sample,
                                                _stream_ptr(stream), ctypes.byref(best), ctypes.byref(ms)))
-        return {"waves_per_group": best.waves_per_group, "groups_per_cu": best.groups_per_cu}, ms.value
+        return {"waves_per_group": best.waves_per_group, "groups_per_cu": best.groups_per_cu,
+                "longest_first": bool(best.flags & OPT_LONGEST_FIRST)}, ms.value
 
     def analyze_noalloc(self, kernels_dev, n_kernels, n_instr_total, instrs_dev, n_records, args_dev, n_args_total,
                         results_dev, acc_dev, acc_cap, acc_off_dev, sys_dev, sys_cap, sys_off_dev, flags=0,

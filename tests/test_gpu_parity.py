@@ -170,7 +170,9 @@ def test_c3_zipf_full(ctx):
     instructions) in one plan, as the bench analyses them: every status,
     block count, sweep count, record count, state digest and record byte
     against the oracle (run in worker processes meanwhile); then the run
-    without the digest in the bench's launch shape, every record again."""
+    without the digest in the launch shape and kernel order the autotuner
+    picks for it (on the bench's sample of every 16th kernel), every record
+    again."""
     n = 1048576
     t = time.time()
     orc = OracleRun(3, n, jobs_per_proc=16)
@@ -179,8 +181,13 @@ def test_c3_zipf_full(ctx):
     dev = dc.to_device(b.instrs)
     torch.cuda.synchronize()
     say(f"c3 full: uploaded ({time.time() - t:.1f}s)")
+    sub = b.subset(np.arange(0, n, 16))
+    sdev = dc.to_device(sub.instrs)
+    shape, ms = ctx.autotune(sub.kernels, sdev, sub.n_instr, sub.args, sample=sub.n_kernels)
+    del sdev, sub
+    say(f"c3 full: autotuned {shape} ({ms:.1f} ms per run of the sample)")
     runs = []
-    for flags, kw in ((dc.OPT_DIGEST, {}), (dc.OPT_TIMING, dict(waves_per_group=2, groups_per_cu=3))):
+    for flags, kw in ((dc.OPT_DIGEST, {}), (dc.OPT_TIMING, shape)):
         batch = ctx.analyze(b.kernels, dev, b.n_instr, b.args, flags=flags, **kw)
         batch.run()
         res = batch.results()
@@ -454,6 +461,41 @@ def test_records_changed_in_place_fail_with_capacity(ctx):
     assert batch.all_accesses()[0].tobytes() == oacc.tobytes()
     batch.free()
 
+def test_plain_form(ctx):
+    """The plain form (one launch per kernel, one workgroup doing every stage):
+    the small workload, a sample with loops, kernels of 1,600 to 2,600 blocks
+    (bitmaps in global memory past 2,048), malformed and
+    unsupported kernels and the hand-written rule kernels, every record,
+    status, sweep count and state digest against the oracle, and the same
+    bytes as the batched form."""
+    import hand_kernels as hk
+    good = dcgen.generate(2, 6)
+    r, d, a = good.kernel(0)
+    bad_op = r.copy()
+    bad_op[5]["op"] = 200
+    d_unsup = d.copy()
+    d_unsup["useargs"] = 0
+    parts = [dcgen.generate(1, 32).kernel(k) for k in range(32)] + \
+        [dcgen.generate(2, 120, i0=2000).kernel(k) for k in range(120)] + \
+        [dcgen.generate(6, 12).kernel(k) for k in (0, 5, 9)] + \
+        [(bad_op, d, a), (r, d_unsup, a), (r[:-1].copy(), d, a)] + [k for _, k in hk.all_kernels()]
+    b = dcgen.concat(parts)
+    dev = dc.to_device(b.instrs)
+    s, oacc, osys = oracle.analyze_batch(b)
+    plain = ctx.analyze(b.kernels, dev, b.n_instr, b.args, flags=dc.OPT_DIGEST | dc.OPT_PLAIN)
+    res = plain.results()
+    compare_summaries(res, s)
+    assert plain.all_accesses()[0].tobytes() == oacc.tobytes()
+    assert plain.all_sysvals()[0].tobytes() == osys.tobytes()
+    assert (res["n_blocks"] > 2048).any() and (res["status"] < 0).sum() == 3
+    batched = ctx.analyze(b.kernels, dev, b.n_instr, b.args, flags=dc.OPT_DIGEST)
+    assert batched.results().tobytes() == res.tobytes()
+    plain.run()
+    assert plain.results().tobytes() == res.tobytes()
+    plain.free()
+    batched.free()
+
+
 def test_nofix_cap(ctx):
     b = dcgen.generate(2, 200)
     s, _, _ = oracle.analyze_batch(b)
@@ -574,6 +616,9 @@ def test_autotune_shape_gives_same_results(ctx):
     shape, ms = ctx.autotune(b.kernels, dev, b.n_instr, b.args, flags=dc.OPT_DIGEST, sample=4096)
     say(f"autotune: {shape}, {ms:.3f} ms per run of the sample")
     assert 1 <= shape["waves_per_group"] <= 4 and shape["groups_per_cu"] >= 1 and ms > 0
+    t = time.time()
+    again, ms2 = ctx.autotune(b.kernels, dev, b.n_instr, b.args, flags=dc.OPT_DIGEST, sample=4096)
+    assert again == shape and ms2 == ms and time.time() - t < 0.5   # the cached choice
     ref = ctx.analyze(b.kernels, dev, b.n_instr, b.args, flags=dc.OPT_DIGEST)
     tuned = ctx.analyze(b.kernels, dev, b.n_instr, b.args, flags=dc.OPT_DIGEST, **shape)
     assert tuned.results().tobytes() == ref.results().tobytes()
