@@ -248,6 +248,47 @@ def graph_replay_ms(ctx, b, stream, reps=50):
     return ms
 
 
+def ssa_workload(ctx, b, stream, steps=5, cpu_kernels=2048):
+    """Register versions (dc_build_ssa) of a workload: whole runs (the graph
+    stages, then the version stages) with the records in HBM; the version
+    stages' time from HIP events on the same stream; the oracle's versions on
+    one core over the first cpu_kernels kernels."""
+    import torch
+    import oracle
+    from paper_2107_07809_amd import dc
+    dev = dc.to_device(b.instrs)
+    s = ctx.build_ssa(b.kernels, dev, b.n_instr, timing=True, stream=stream)
+    s.run()
+    s.wait()
+    res0 = s.results()
+    s.timing_reset()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        s.run()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / steps
+    tm = s.timing()
+    res = s.results()
+    s.free()
+    ok = res["status"] == 0
+    ssa_ms = tm["ms_fixpoint"] / max(1, tm["runs"])
+    alg = (16 * b.n_instr + b.n_instr + 4 * int(res["n_operands"].sum()) + 12 * int(res["n_phi"].sum()) +
+           4 * int(res["n_phi_args"].sum()) + 4 * int(res["n_blocks"].sum()) + 32 * b.n_kernels)
+    sub = b.subset(np.arange(min(cpu_kernels, b.n_kernels)))
+    t = time.perf_counter()
+    osum = oracle.ssa_batch(sub)
+    cpu_dt = time.perf_counter() - t
+    return {"instructions_per_s": b.n_instr / dt, "ms_per_step": dt * 1e3, "ssa_stages_ms": ssa_ms,
+            "graph_stages_ms": (tm["ms_decode"] + tm["ms_cfg"]) / max(1, tm["runs"]),
+            "merges": int(res["n_phi"].sum()), "merge_args": int(res["n_phi_args"].sum()),
+            "operand_versions": int(res["n_operands"].sum()), "failed": int((~ok).sum()),
+            "rerun_identical": bool(res.tobytes() == res0.tobytes()),
+            "sample_matches_oracle": bool(res[:sub.n_kernels]["digest"].tobytes() == osum["digest"].tobytes()),
+            "alg_bytes": alg, "ssa_stages_GBps": alg / (ssa_ms * 1e-3) / 1e9 if ssa_ms else None,
+            "cpu_oracle": {"instructions_per_s": sub.n_instr / cpu_dt, "cores": 1, "kernels": sub.n_kernels}}
+
+
 def extra_workloads(ctx, stream):
     """The other configurations, each timed as whole-path runs with its
     records in HBM."""
@@ -260,6 +301,8 @@ def extra_workloads(ctx, stream):
                                        "ms_per_step": r["ms_per_step"], "fixpoint_ms": r["fix_ms"],
                                        "sweeps_max": r["sweeps"]["max"], "failed": r["failed"],
                                        "plain": plain, "batched_speedup": r["value"] / plain["value"]}
+    log("65,536 kernels: register versions")
+    out["loguniform_65536_kernels"]["ssa"] = ssa_workload(ctx, b, stream)
     b = dcgen.generate(4, 16)
     r = timed_run(ctx, b, stream, steps=2, warmup=0, shape={}, lat_steps=0, what="16 huge kernels")
     out["huge_16_kernels_1M_to_4M"] = {

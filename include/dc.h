@@ -315,6 +315,90 @@ dc_status_t dc_analyze_noalloc(dc_ctx_t *ctx, const dc_kernel_t *kernels, uint32
                                uint32_t sys_cap, uint32_t *sys_off, void *stream);
 
 /* ------------------------------------------------------------------ */
+/* Register versions (minimal SSA form).                                */
+/* ------------------------------------------------------------------ */
+/* Section "Search for control structures": at a block with several
+ * predecessors a register can hold the values of different definitions, and
+ * the method then introduces a variable; the Register record of Section
+ * "Search for memory accesses" carries a version.  Read here as the minimal
+ * SSA form (Cytron, Ferrante, Rosen, Wegman & Zadeck 1991) of each kernel's
+ * control flow graph over the DC_NSLOT register slots:
+ *   - a virtual start before block 0 defines version 0 of every slot (its
+ *     ABI entry value);
+ *   - each definition makes a new version: an instruction defines its
+ *     destination dwords, then the implicit vcc (two slots), exec (two) and
+ *     scc, in that order (a slot written twice by one instruction gets two
+ *     versions);
+ *   - a merge (phi) of a slot sits at every block of the iterated dominance
+ *     frontier of the blocks that define it (the start counts as a
+ *     predecessor of block 0); its arguments are, per incoming edge, the
+ *     version live at the end of the edge's source (block 0's entry edge
+ *     first, carrying version 0, then the reachable predecessors in
+ *     ascending order);
+ *   - versions of a slot are numbered 1, 2, ... in a preorder walk of the
+ *     dominator tree (children by ascending block index), a block's merges
+ *     first (by slot), then its instructions in order;
+ *   - dominators are those of the reachable blocks; unreachable blocks have
+ *     no dominator (DC_SSA_NONE), no merges and no versions.
+ * Uses of an instruction, in order: the dwords of r1, r2, the third source
+ * (imm) and a stored r0 that name register slots, then the implicit vcc,
+ * exec and scc uses.  A kernel whose records fail their checks gets that
+ * status and nothing else. */
+#define DC_SSA_NU 13             /* uses of one instruction, at most */
+#define DC_SSA_ND 9              /* definitions of one instruction, at most */
+#define DC_SSA_NONE 0xFFFFFFFFu
+typedef struct {
+    uint32_t block;              /* the merge's block */
+    uint16_t slot, pad;          /* register slot (0..DC_NSLOT-1) */
+    uint32_t version;
+} dc_phi_t;                      /* 12 B */
+typedef struct {
+    dc_status_t status;
+    uint32_t n_blocks, n_phi, n_phi_args;
+    uint32_t n_operands;         /* versions stored: the uses and definitions of every instruction */
+    uint32_t pad;
+    uint64_t digest;             /* sum over the items (kind, index, value) of splitmix64(splitmix64(kind *
+                                    0x9E3779B97F4A7C15 + index) ^ value): kind 1 per block (index block, value
+                                    its dominator), 2 per merge ((block << 16) | slot, version), 3 per merge
+                                    argument ((block << 24) | (slot << 12) | edge, version), 4 per use entry and
+                                    5 per definition entry of the fixed layouts of dc_ssa_get_versions (index
+                                    instruction * DC_SSA_NU + q, resp. * DC_SSA_ND + q, value the version or
+                                    DC_SSA_NONE); 0 for a failed kernel */
+} dc_ssa_result_t;               /* 32 B */
+typedef struct dc_ssa dc_ssa_t;
+
+/* Versions for n_kernels kernels whose records are in `instrs` (device,
+ * n_records entries): the graph stages of dc_build_cfg, then the versions,
+ * on `stream`.  opts may be NULL; its flags may hold DC_OPT_TIMING only.
+ * The first run sizes the version tables from the graph (it waits for the
+ * stream twice); dc_ssa_run on the same records allocates nothing and does
+ * not synchronise, on other records it sizes them again. */
+dc_status_t dc_build_ssa(dc_ctx_t *ctx, const dc_kernel_t *kernels, uint32_t n_kernels, const dc_instr_t *instrs,
+                         uint64_t n_records, const dc_options_t *opts, void *stream, dc_ssa_t **out);
+dc_status_t dc_ssa_run(dc_ssa_t *ssa, const dc_instr_t *instrs);
+dc_status_t dc_ssa_wait(dc_ssa_t *ssa);
+/* Getters (wait for the stream; two-call idiom as dc_get_accesses).
+ * results: the first min(cap, n_kernels) kernels.  idom: kernel k's
+ * immediate dominators, one per block.  phis: ascending (block, slot).
+ * phi_args: per merge in that order, one version per incoming edge.
+ * versions: use_ver (DC_SSA_NU per instruction) and def_ver (DC_SSA_ND per
+ * instruction, either may be NULL) in the orders above, DC_SSA_NONE past an
+ * instruction's operands and for unreachable instructions; *n_instr = the
+ * kernel's instruction count, and min(cap_instr, n_instr) instructions are
+ * written. */
+dc_status_t dc_ssa_get_results(dc_ssa_t *ssa, dc_ssa_result_t *out, uint32_t cap);
+dc_status_t dc_ssa_get_idom(dc_ssa_t *ssa, uint32_t k, uint32_t *buf, uint32_t cap, uint32_t *n_total);
+dc_status_t dc_ssa_get_phis(dc_ssa_t *ssa, uint32_t k, dc_phi_t *buf, uint32_t cap, uint32_t *n_total);
+dc_status_t dc_ssa_get_phi_args(dc_ssa_t *ssa, uint32_t k, uint32_t *buf, uint32_t cap, uint32_t *n_total);
+dc_status_t dc_ssa_get_versions(dc_ssa_t *ssa, uint32_t k, uint32_t *use_ver, uint32_t *def_ver, uint32_t cap_instr,
+                                uint32_t *n_instr);
+/* Stage times (needs DC_OPT_TIMING): ms_decode, ms_cfg as for a batch,
+ * ms_fixpoint = the version stages, ms_compact = 0. */
+dc_status_t dc_ssa_get_timing(dc_ssa_t *ssa, dc_timing_t *out);
+dc_status_t dc_ssa_timing_reset(dc_ssa_t *ssa);
+void dc_ssa_free(dc_ssa_t *ssa);
+
+/* ------------------------------------------------------------------ */
 /* Request server: continuous batching of single-kernel analyses.       */
 /* ------------------------------------------------------------------ */
 /* The server takes analysis requests one kernel at a time as they arrive

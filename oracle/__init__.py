@@ -77,6 +77,8 @@ def lib():
         L.or_ssa.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         L.or_ssa.restype = ctypes.c_int
         L.or_ssa_free.argtypes = [ctypes.c_void_p]
+        L.or_ssa_batch.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p]
+        L.or_ssa_batch.restype = ctypes.c_int
         L.or_ssa_uses.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
         L.or_ssa_uses.restype = ctypes.c_int
         L.or_ssa_defs.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
@@ -199,6 +201,18 @@ def ssa_operands(rec):
     nu = lib().or_ssa_uses(_ptr(rec), u)
     nd = lib().or_ssa_defs(_ptr(rec), dd)
     return list(u[:nu]), list(dd[:nd])
+
+
+SSA_SUMMARY_DTYPE = np.dtype([("status", "<i4"), ("n_blocks", "<u4"), ("n_phi", "<u4"), ("n_args", "<u4"),
+                              ("n_operands", "<u4"), ("pad", "<u4"), ("digest", "<u8")])
+
+
+def ssa_batch(batch):
+    """Per-kernel version summaries (status, blocks, merges, merge
+    arguments, stored operand versions, digest) for a dcgen.Batch."""
+    summ = np.zeros(batch.n_kernels, SSA_SUMMARY_DTYPE)
+    lib().or_ssa_batch(_ptr(batch.kernels), batch.n_kernels, _ptr(batch.instrs), _ptr(summ))
+    return summ
 
 
 def analyze_batch(batch, sweep_cap: int = 0):

@@ -1476,6 +1476,34 @@ int or_ssa(const or_kernel *K, const or_instr *I, or_ssa_out *R) {
     return OK;
 }
 
+/* Batch driver of the versions: per kernel status, block count, merges,
+ * merge arguments, stored operand versions (the uses and definitions of
+ * every instruction of a kernel that passed its checks) and the digest. */
+typedef struct { int32_t status; uint32_t n_blocks, n_phi, n_args, n_operands, pad; uint64_t digest; } or_ssa_summary;
+
+int or_ssa_batch(const or_kernel *kernels, uint32_t n_kernels, const or_instr *instrs, or_ssa_summary *sum) {
+    for (uint32_t k = 0; k < n_kernels; k++) {
+        const or_kernel *K = &kernels[k];
+        const or_instr *I = instrs + K->instr_begin;
+        or_ssa_out R;
+        or_ssa(K, I, &R);
+        memset(&sum[k], 0, sizeof(sum[k]));
+        sum[k].status = R.status;
+        if (R.status == OK) {
+            sum[k].n_blocks = R.n_blocks;
+            sum[k].n_phi = R.n_phi;
+            sum[k].n_args = R.n_args;
+            for (uint32_t i = 0; i < K->n_instr; i++) {
+                unsigned u[SSA_NU], d[SSA_ND];
+                sum[k].n_operands += (uint32_t)(ssa_uses(&I[i], u) + ssa_defs(&I[i], d));
+            }
+            sum[k].digest = R.digest;
+        }
+        or_ssa_free(&R);
+    }
+    return 0;
+}
+
 /*
  * Batch driver: per kernel summary (status, n_blocks, sweeps, counts, digest)
  * and the accesses and system values packed densely in kernel order.

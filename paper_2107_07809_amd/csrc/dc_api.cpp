@@ -79,6 +79,7 @@ struct dc_batch {
     std::vector<uint32_t> k_nblocks, k_nreach, h_block_start, h_pred_off, h_pred, h_rpo;
     std::vector<int32_t> h_succ;
     std::vector<uint32_t> v_block_start, v_pred_off;   /* scratch for one view */
+    dc_ssa *ssa = nullptr;   /* a register-version run on this graph (its stages follow the graph's) */
 };
 struct dc_cfg {
     dc_batch b;
@@ -453,6 +454,8 @@ static dc_status_t enqueue_graph(dc_batch *B) {
     return DC_OK;
 }
 
+static dc_status_t enqueue_ssa_stages(dc_ssa *X);
+
 static dc_status_t enqueue(dc_batch *B) {
     Plan &P = B->P;
     hipStream_t s = B->stream;
@@ -492,8 +495,12 @@ static dc_status_t enqueue(dc_batch *B) {
     TRY(launch_edges(P, s));
     if (B->have_events) TRY(hipEventRecord(ev[EV_CFG], s));
     if (B->cfg_only) {
+        if (B->have_events) TRY(hipEventRecord(ev[EV_FIXB], s));
+        if (B->ssa) {
+            const dc_status_t st = enqueue_ssa_stages(B->ssa);
+            if (st != DC_OK) return st;
+        }
         if (B->have_events) {
-            TRY(hipEventRecord(ev[EV_FIXB], s));
             TRY(hipEventRecord(ev[EV_FIX], s));
             TRY(hipEventRecord(ev[EV_END], s));
         }
@@ -1025,4 +1032,296 @@ extern "C" void dc_cfg_free(dc_cfg_t *C) {
     hipSetDevice(C->b.ctx->device);
     hipStreamSynchronize(C->b.stream);
     delete C;
+}
+
+/* ---------------------------------------------------------------- register versions */
+struct dc_ssa {
+    dc_cfg c;
+    DevMem smem;   /* per-block arrays, tables and outputs, sized by the first run on these records */
+    SsaPlan S{};
+    bool sized = false;
+    bool host_valid = false;     /* results, offsets and first blocks copied since the last run */
+    bool arrays_valid = false;   /* dominators, merges, arguments and versions copied since the last run */
+    std::vector<dc_ssa_result_t> res;
+    std::vector<uint64_t> offs;
+    std::vector<uint32_t> first_block, idom, args, vers;
+    std::vector<dc_phi_t> phis;
+    std::vector<uint8_t> opn;
+};
+
+/* Enqueue the version stages after the graph stages.  The first run on a
+ * set of records sizes the tables and then the outputs from the counts it
+ * reads back (two waits for the stream); later runs reuse them. */
+static dc_status_t enqueue_ssa_stages(dc_ssa *X) {
+    dc_batch *B = &X->c.b;
+    const Plan &P = B->P;
+    SsaPlan &S = X->S;
+    hipStream_t s = B->stream;
+    const uint32_t K = B->K;
+    X->host_valid = false;
+    hipError_t e = hipSuccess;
+    auto total = [&](uint32_t a, uint64_t *out) {
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(out, S.offs + (uint64_t)a * (K + 1) + K, sizeof(uint64_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+    };
+    if (!X->sized) {
+        X->smem.reset();
+        const uint64_t blocks = std::max<uint32_t>(P.blk_cap, 1);
+        S.idom = X->smem.alloc<uint32_t>(blocks);
+        S.scr = X->smem.alloc<uint32_t>(3 * blocks);
+        S.opn = X->smem.alloc<uint8_t>(std::max<uint64_t>(B->N, 1));
+        S.tab_a = S.tab_b = nullptr;
+        S.phis = nullptr;
+        S.phi_args = S.vers = nullptr;
+        S.tab_cap = S.phi_cap = S.arg_cap = S.ops_cap = 0;
+        if (X->smem.failed) return DC_E_OOM;
+        e = launch_ssa_size(P, S, s);
+        uint64_t words = 0;
+        if (K) total(0, &words);
+        if (e != hipSuccess) return hip_fail(e);
+        S.tab_a = X->smem.alloc<uint32_t>(words);
+        S.tab_b = X->smem.alloc<uint32_t>(words);
+        S.tab_cap = words;
+        if (X->smem.failed) return DC_E_OOM;
+        e = launch_ssa_graph(P, S, s);
+        uint64_t t[3] = {0, 0, 0};
+        for (uint32_t a = 1; a <= 3 && K; a++) total(a, &t[a - 1]);
+        if (e != hipSuccess) return hip_fail(e);
+        S.phis = X->smem.alloc<dc_phi_t>(t[0]);
+        S.phi_args = X->smem.alloc<uint32_t>(t[1]);
+        S.vers = X->smem.alloc<uint32_t>(t[2]);
+        S.phi_cap = t[0];
+        S.arg_cap = t[1];
+        S.ops_cap = t[2];
+        if (X->smem.failed) return DC_E_OOM;
+        X->sized = true;
+    } else {
+        e = launch_ssa_size(P, S, s);
+        if (e == hipSuccess) e = launch_ssa_graph(P, S, s);
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    e = launch_ssa_emit(P, S, s);
+    return e == hipSuccess ? DC_OK : hip_fail(e);
+}
+
+extern "C" dc_status_t dc_build_ssa(dc_ctx_t *ctx, const dc_kernel_t *kernels, uint32_t n_kernels,
+                                    const dc_instr_t *instrs, uint64_t n_records, const dc_options_t *opts,
+                                    void *stream, dc_ssa_t **out) {
+    if (!out) return DC_E_INVAL;
+    *out = nullptr;
+    if (opts && (opts->flags & ~DC_OPT_TIMING)) return DC_E_INVAL;
+    dc_ssa *X = new (std::nothrow) dc_ssa;
+    if (!X) return DC_E_OOM;
+    dc_batch *B = &X->c.b;
+    /* the graph plan, as dc_build_cfg makes it, plus the per-kernel bitmaps of
+     * the register slots the records name and the per-kernel version arrays */
+    std::vector<dc_kernel_t> ks_noargs(kernels, kernels + (kernels ? n_kernels : 0));
+    for (auto &k : ks_noargs) {
+        k.n_args = 0;
+        k.arg_begin = 0;
+    }
+    dc_options_t o{};
+    if (opts) o.flags = opts->flags;
+    dc_status_t st = plan_batch(B, ctx, kernels ? ks_noargs.data() : nullptr, n_kernels, instrs, n_records, nullptr, 0,
+                                &o, stream, true);
+    if (st == DC_OK) {
+        const uint64_t K = n_kernels;
+        B->P.kslots = B->mem.alloc<uint32_t>(std::max<uint64_t>(K, 1) * KSLOT_WORDS);
+        X->S.counts = B->mem.alloc<uint32_t>(4 * std::max<uint64_t>(K, 1));
+        X->S.offs = B->mem.alloc<uint64_t>(4 * (K + 1));
+        X->S.status = B->mem.alloc<int32_t>(std::max<uint64_t>(K, 1));
+        X->S.res = B->mem.alloc<dc_ssa_result_t>(std::max<uint64_t>(K, 1));
+        if (B->mem.failed) st = DC_E_OOM;
+    }
+    if (st == DC_OK) {
+        std::vector<int32_t> ds(n_kernels);
+        for (uint32_t k = 0; k < n_kernels; k++) ds[k] = descriptor_status(kernels[k]);
+        if (n_kernels &&
+            hipMemcpy((void *)B->P.desc_status, ds.data(), n_kernels * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess)
+            st = DC_E_HIP;
+        if (st == DC_OK && hipMemcpy(B->dP, &B->P, sizeof(Plan), hipMemcpyHostToDevice) != hipSuccess) st = DC_E_HIP;
+    }
+    if (st == DC_OK) {
+        B->ssa = X;
+        st = enqueue(B);
+    }
+    if (st != DC_OK) {
+        hipStreamSynchronize(B->stream);
+        delete X;
+        return st;
+    }
+    *out = X;
+    return DC_OK;
+}
+
+extern "C" dc_status_t dc_ssa_run(dc_ssa_t *X, const dc_instr_t *instrs) {
+    if (!X || (X->c.b.n_records && !instrs)) return DC_E_INVAL;
+    dc_batch *B = &X->c.b;
+    if (hipSetDevice(B->ctx->device) != hipSuccess) return DC_E_HIP;
+    if (instrs != B->P.instrs) {
+        /* other records: plan the blocks and the version arrays again */
+        if (hipStreamSynchronize(B->stream) != hipSuccess) return DC_E_HIP;
+        B->P.instrs = instrs;
+        B->blocks_planned = false;
+        X->sized = false;
+    }
+    return enqueue(B);
+}
+
+extern "C" dc_status_t dc_ssa_wait(dc_ssa_t *X) {
+    if (!X) return DC_E_INVAL;
+    return dc_batch_wait(&X->c.b);
+}
+
+static dc_status_t fetch_ssa(dc_ssa *X) {
+    if (X->host_valid) return DC_OK;
+    dc_batch *B = &X->c.b;
+    dc_status_t st = dc_batch_wait(B);
+    if (st != DC_OK) return st;
+    const uint32_t K = B->K;
+    const SsaPlan &S = X->S;
+    X->res.resize(K);
+    X->offs.resize(4 * ((size_t)K + 1));
+    X->first_block.resize(K);
+    hipError_t e = hipSuccess;
+    if (K) e = hipMemcpy(X->res.data(), S.res, K * sizeof(dc_ssa_result_t), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(X->offs.data(), S.offs, X->offs.size() * sizeof(uint64_t), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && K)
+        e = hipMemcpy(X->first_block.data(), B->P.first_block, K * sizeof(uint32_t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e);
+    X->host_valid = true;
+    X->arrays_valid = false;
+    return DC_OK;
+}
+
+/* the graph's dominators, the merges, their arguments and the operand
+ * versions, copied on first use after a run */
+static dc_status_t fetch_ssa_arrays(dc_ssa *X) {
+    dc_status_t st = fetch_ssa(X);
+    if (st != DC_OK || X->arrays_valid) return st;
+    dc_batch *B = &X->c.b;
+    const uint32_t K = B->K;
+    const SsaPlan &S = X->S;
+    hipError_t e = hipSuccess;
+    const uint64_t nblk = B->P.blk_cap, np = X->offs[2 * ((size_t)K + 1) - 1], na = X->offs[3 * ((size_t)K + 1) - 1],
+                   no = X->offs[4 * ((size_t)K + 1) - 1];
+    X->idom.resize(nblk);
+    X->phis.resize(std::min<uint64_t>(np, S.phi_cap));
+    X->args.resize(std::min<uint64_t>(na, S.arg_cap));
+    X->vers.resize(std::min<uint64_t>(no, S.ops_cap));
+    X->opn.resize(B->N);
+    if (nblk) e = hipMemcpy(X->idom.data(), S.idom, nblk * sizeof(uint32_t), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && !X->phis.empty())
+        e = hipMemcpy(X->phis.data(), S.phis, X->phis.size() * sizeof(dc_phi_t), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && !X->args.empty())
+        e = hipMemcpy(X->args.data(), S.phi_args, X->args.size() * sizeof(uint32_t), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && !X->vers.empty())
+        e = hipMemcpy(X->vers.data(), S.vers, X->vers.size() * sizeof(uint32_t), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && B->N) e = hipMemcpy(X->opn.data(), S.opn, B->N, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e);
+    X->arrays_valid = true;
+    return DC_OK;
+}
+
+extern "C" dc_status_t dc_ssa_get_results(dc_ssa_t *X, dc_ssa_result_t *out, uint32_t cap) {
+    if (!X || (cap && !out)) return DC_E_INVAL;
+    dc_status_t st = fetch_ssa(X);
+    if (st != DC_OK) return st;
+    const uint32_t n = std::min<uint32_t>(cap, X->c.b.K);
+    if (n) memcpy(out, X->res.data(), n * sizeof(dc_ssa_result_t));
+    return DC_OK;
+}
+
+/* kernel k's slice [lo, hi) of count array a, when the kernel succeeded */
+static bool ssa_slice(dc_ssa *X, uint32_t k, uint32_t a, uint64_t *lo, uint64_t *hi) {
+    const uint32_t K = X->c.b.K;
+    *lo = *hi = 0;
+    if (X->res[k].status != DC_OK) return false;
+    *lo = X->offs[(size_t)a * (K + 1) + k];
+    *hi = X->offs[(size_t)a * (K + 1) + k + 1];
+    return true;
+}
+
+extern "C" dc_status_t dc_ssa_get_idom(dc_ssa_t *X, uint32_t k, uint32_t *buf, uint32_t cap, uint32_t *n_total) {
+    if (!X || !n_total || (cap && !buf) || k >= X->c.b.K) return DC_E_INVAL;
+    dc_status_t st = fetch_ssa_arrays(X);
+    if (st != DC_OK) return st;
+    const uint32_t nb = X->res[k].status == DC_OK ? X->res[k].n_blocks : 0;
+    *n_total = nb;
+    if (std::min(cap, nb)) memcpy(buf, X->idom.data() + X->first_block[k], std::min(cap, nb) * sizeof(uint32_t));
+    return DC_OK;
+}
+
+extern "C" dc_status_t dc_ssa_get_phis(dc_ssa_t *X, uint32_t k, dc_phi_t *buf, uint32_t cap, uint32_t *n_total) {
+    if (!X || !n_total || (cap && !buf) || k >= X->c.b.K) return DC_E_INVAL;
+    dc_status_t st = fetch_ssa_arrays(X);
+    if (st != DC_OK) return st;
+    uint64_t lo, hi;
+    ssa_slice(X, k, 1, &lo, &hi);
+    *n_total = (uint32_t)(hi - lo);
+    if (std::min<uint64_t>(cap, hi - lo)) memcpy(buf, X->phis.data() + lo, std::min<uint64_t>(cap, hi - lo) * sizeof(dc_phi_t));
+    return DC_OK;
+}
+
+extern "C" dc_status_t dc_ssa_get_phi_args(dc_ssa_t *X, uint32_t k, uint32_t *buf, uint32_t cap, uint32_t *n_total) {
+    if (!X || !n_total || (cap && !buf) || k >= X->c.b.K) return DC_E_INVAL;
+    dc_status_t st = fetch_ssa_arrays(X);
+    if (st != DC_OK) return st;
+    uint64_t lo, hi;
+    ssa_slice(X, k, 2, &lo, &hi);
+    *n_total = (uint32_t)(hi - lo);
+    if (std::min<uint64_t>(cap, hi - lo)) memcpy(buf, X->args.data() + lo, std::min<uint64_t>(cap, hi - lo) * sizeof(uint32_t));
+    return DC_OK;
+}
+
+extern "C" dc_status_t dc_ssa_get_versions(dc_ssa_t *X, uint32_t k, uint32_t *use_ver, uint32_t *def_ver,
+                                           uint32_t cap_instr, uint32_t *n_instr) {
+    if (!X || !n_instr || k >= X->c.b.K) return DC_E_INVAL;
+    dc_status_t st = fetch_ssa_arrays(X);
+    if (st != DC_OK) return st;
+    dc_batch *B = &X->c.b;
+    const uint32_t n = B->kernels[k].n_instr, m = std::min(cap_instr, n);
+    *n_instr = n;
+    if (use_ver)
+        for (uint64_t i = 0; i < (uint64_t)m * DC_SSA_NU; i++) use_ver[i] = DC_SSA_NONE;
+    if (def_ver)
+        for (uint64_t i = 0; i < (uint64_t)m * DC_SSA_ND; i++) def_ver[i] = DC_SSA_NONE;
+    uint64_t lo, hi;
+    if (!ssa_slice(X, k, 3, &lo, &hi)) return DC_OK;
+    const uint32_t pb = B->pos_begin[k];
+    uint64_t o = lo;
+    for (uint32_t i = 0; i < m; i++) {
+        const uint32_t nu = X->opn[pb + i] & 15u, nd = X->opn[pb + i] >> 4;
+        if (o + nu + nd > hi || nu > DC_SSA_NU || nd > DC_SSA_ND) return DC_E_HIP;
+        for (uint32_t q = 0; q < nu; q++)
+            if (use_ver) use_ver[(uint64_t)i * DC_SSA_NU + q] = X->vers[o + q];
+        for (uint32_t q = 0; q < nd; q++)
+            if (def_ver) def_ver[(uint64_t)i * DC_SSA_ND + q] = X->vers[o + nu + q];
+        o += nu + nd;
+    }
+    return DC_OK;
+}
+
+extern "C" dc_status_t dc_ssa_get_timing(dc_ssa_t *X, dc_timing_t *out) {
+    if (!X) return DC_E_INVAL;
+    dc_status_t st = dc_get_timing(&X->c.b, out);
+    if (st == DC_OK) out->ms_compact = 0;
+    return st;
+}
+
+extern "C" dc_status_t dc_ssa_timing_reset(dc_ssa_t *X) {
+    if (!X) return DC_E_INVAL;
+    return dc_timing_reset(&X->c.b);
+}
+
+extern "C" void dc_ssa_free(dc_ssa_t *X) {
+    if (!X) return;
+    hipSetDevice(X->c.b.ctx->device);
+    hipStreamSynchronize(X->c.b.stream);
+    dc_batch *B = &X->c.b;
+    if (B->have_events)
+        for (int r = 0; r < TIMING_RING; r++)
+            for (int i = 0; i < N_EV; i++) hipEventDestroy(B->ev[r][i]);
+    delete X;
 }

@@ -128,7 +128,33 @@ constexpr uint32_t FIX_MAX_ROWS = 6;                                    /* state
 constexpr uint32_t OVF_MAX_WAVES = 512;                                 /* waves of the overflow pass */
 constexpr uint64_t ARENA_BUDGET = 8ull << 30;                           /* arena bytes of either pass */
 uint64_t scan_tmp_words_needed(uint64_t n);
-uint64_t cap_scan_words(uint64_t n);
-void *noalloc_setup(int device);         /* device address of the no-allocation scratch array (current device) */   /* extra scan words of the capacity scan of n positions */
+uint64_t cap_scan_words(uint64_t n);     /* extra scan words of the capacity scan of n positions */
+void *noalloc_setup(int device);         /* device address of the no-allocation scratch array (current device) */
+
+/* Device arrays of a register-version run (dc_ssa.hip) over a plan's graph.
+ * Per-kernel counts and their offsets come in four arrays: 0 table words
+ * (blocks x named slots), 1 merges, 2 merge arguments, 3 operand versions. */
+struct SsaPlan {
+    uint32_t *idom;                 /* per global block: immediate dominator (local id), block 0 -> 0,
+                                       unreachable -> DC_SSA_NONE */
+    uint32_t *scr;                  /* 3 per global block: preorder scratch of kernels whose graph is not in LDS */
+    uint32_t *counts;               /* 4 x K */
+    uint64_t *offs;                 /* 4 x (K + 1): exclusive scans of counts */
+    int32_t *status;                /* K */
+    uint32_t *tab_a;                /* per (block, slot): first version in the block | merge flag << 31 */
+    uint32_t *tab_b;                /* per (block, slot): version live at the block's end */
+    uint64_t tab_cap;
+    dc_phi_t *phis;                 /* ascending (block, slot) per kernel */
+    uint64_t phi_cap;
+    uint32_t *phi_args;
+    uint64_t arg_cap;
+    uint32_t *vers;                 /* per instruction its use versions, then its definition versions */
+    uint64_t ops_cap;
+    uint8_t *opn;                   /* per position: uses | definitions << 4 */
+    dc_ssa_result_t *res;           /* K */
+};
+hipError_t launch_ssa_size(const Plan &P, const SsaPlan &S, hipStream_t s);    /* table sizes and offsets */
+hipError_t launch_ssa_graph(const Plan &P, const SsaPlan &S, hipStream_t s);   /* dominators, merges, numbering */
+hipError_t launch_ssa_emit(const Plan &P, const SsaPlan &S, hipStream_t s);    /* merges, arguments, versions */
 
 }  // namespace dc

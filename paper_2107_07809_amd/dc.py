@@ -34,6 +34,11 @@ ACCESS_DTYPE = np.dtype([("instr", "<u4"), ("kind", "u1"), ("space", "u1"), ("wi
 SYSVAL_DTYPE = np.dtype([("instr", "<u4"), ("slot", "<u2"), ("kind", "u1"), ("dim", "u1")])
 RESULT_DTYPE = np.dtype([("status", "<i4"), ("n_blocks", "<u4"), ("sweeps", "<u4"), ("n_access", "<u4"),
                          ("n_sysval", "<u4"), ("pad", "<u4"), ("digest", "<u8")])
+# register versions (dc_build_ssa)
+SSA_NU, SSA_ND, SSA_NONE = 13, 9, 0xFFFFFFFF
+PHI_DTYPE = np.dtype([("block", "<u4"), ("slot", "<u2"), ("pad", "<u2"), ("version", "<u4")])
+SSA_RESULT_DTYPE = np.dtype([("status", "<i4"), ("n_blocks", "<u4"), ("n_phi", "<u4"), ("n_phi_args", "<u4"),
+                             ("n_operands", "<u4"), ("pad", "<u4"), ("digest", "<u8")])
 # dc_request_t and dc_result_t of the request server
 REQUEST_DTYPE = np.dtype([("kernel", KERNEL_DTYPE), ("instrs", "<u8"), ("args", "<u8"), ("tag", "<u8")])
 SERVER_RESULT_DTYPE = np.dtype([("ticket", "<u8"), ("tag", "<u8"), ("summary", RESULT_DTYPE), ("accesses", "<u8"),
@@ -113,6 +118,17 @@ SIGNATURES = [
     ("dc_timing_reset", I32, [VP]),
     ("dc_batch_free", None, [VP]),
     ("dc_analyze_noalloc", I32, [VP, VP, U32, U32, VP, U64, VP, U64, U32, VP, VP, U32, VP, VP, U32, VP, VP]),
+    ("dc_build_ssa", I32, [VP, VP, U32, VP, U64, ctypes.POINTER(Options), VP, ctypes.POINTER(VP)]),
+    ("dc_ssa_run", I32, [VP, VP]),
+    ("dc_ssa_wait", I32, [VP]),
+    ("dc_ssa_get_results", I32, [VP, VP, U32]),
+    ("dc_ssa_get_idom", I32, [VP, U32, VP, U32, ctypes.POINTER(U32)]),
+    ("dc_ssa_get_phis", I32, [VP, U32, VP, U32, ctypes.POINTER(U32)]),
+    ("dc_ssa_get_phi_args", I32, [VP, U32, VP, U32, ctypes.POINTER(U32)]),
+    ("dc_ssa_get_versions", I32, [VP, U32, VP, VP, U32, ctypes.POINTER(U32)]),
+    ("dc_ssa_get_timing", I32, [VP, ctypes.POINTER(Timing)]),
+    ("dc_ssa_timing_reset", I32, [VP]),
+    ("dc_ssa_free", None, [VP]),
     ("dc_server_create", I32, [VP, ctypes.POINTER(ServerOpts), ctypes.POINTER(VP)]),
     ("dc_server_submit", I32, [VP, VP, ctypes.POINTER(U64)]),
     ("dc_server_poll", I32, [VP, VP, U32, ctypes.POINTER(U32)]),
@@ -243,6 +259,15 @@ class Context:
         check("dc_build_cfg", lib().dc_build_cfg(self.h, _np_ptr(kernels), len(kernels), _dev_ptr(instrs_dev),
                                                  n_records, _stream_ptr(stream), ctypes.byref(h)))
         return Cfg(h, len(kernels))
+
+    def build_ssa(self, kernels, instrs_dev, n_records, timing=False, stream=None) -> "Ssa":
+        kernels = np.ascontiguousarray(np.asarray(kernels, KERNEL_DTYPE))
+        o = Options()
+        o.flags = OPT_TIMING if timing else 0
+        h = VP()
+        check("dc_build_ssa", lib().dc_build_ssa(self.h, _np_ptr(kernels), len(kernels), _dev_ptr(instrs_dev),
+                                                 n_records, ctypes.byref(o), _stream_ptr(stream), ctypes.byref(h)))
+        return Ssa(h, kernels, instrs_dev)
 
 
 class Batch:
@@ -437,5 +462,75 @@ class Server:
     def __del__(self):
         try:
             self.close()
+        except Exception:
+            pass
+
+
+class Ssa:
+    """Register versions of a batch (dc_build_ssa): merges, their arguments,
+    the version of every use and definition."""
+
+    def __init__(self, h, kernels, instrs_dev):
+        self.h = h
+        self.kernels = kernels
+        self.n_kernels = len(kernels)
+        self._keep = instrs_dev
+
+    def run(self, instrs_dev=None):
+        if instrs_dev is not None:
+            self._keep = instrs_dev
+        check("dc_ssa_run", lib().dc_ssa_run(self.h, _dev_ptr(self._keep)))
+
+    def wait(self):
+        check("dc_ssa_wait", lib().dc_ssa_wait(self.h))
+
+    def results(self) -> np.ndarray:
+        out = np.zeros(self.n_kernels, SSA_RESULT_DTYPE)
+        check("dc_ssa_get_results", lib().dc_ssa_get_results(self.h, _np_ptr(out), self.n_kernels))
+        return out
+
+    def _get(self, name, k, dtype):
+        n = U32()
+        f = getattr(lib(), name)
+        check(name, f(self.h, k, None, 0, ctypes.byref(n)))
+        out = np.zeros(n.value, dtype)
+        if n.value:
+            check(name, f(self.h, k, _np_ptr(out), n.value, ctypes.byref(n)))
+        return out
+
+    def idom(self, k: int) -> np.ndarray:
+        return self._get("dc_ssa_get_idom", k, np.uint32)
+
+    def phis(self, k: int) -> np.ndarray:
+        return self._get("dc_ssa_get_phis", k, PHI_DTYPE)
+
+    def phi_args(self, k: int) -> np.ndarray:
+        return self._get("dc_ssa_get_phi_args", k, np.uint32)
+
+    def versions(self, k: int):
+        n = int(self.kernels[k]["n_instr"])
+        use = np.zeros((n, SSA_NU), np.uint32)
+        dfn = np.zeros((n, SSA_ND), np.uint32)
+        m = U32()
+        check("dc_ssa_get_versions", lib().dc_ssa_get_versions(self.h, k, _np_ptr(use), _np_ptr(dfn), n,
+                                                               ctypes.byref(m)))
+        return use, dfn
+
+    def timing(self) -> dict:
+        t = Timing()
+        check("dc_ssa_get_timing", lib().dc_ssa_get_timing(self.h, ctypes.byref(t)))
+        return {k: getattr(t, k) for k, _ in t._fields_ if k not in ("pad", "ms_pad", "ms_compact")}
+
+    def timing_reset(self):
+        check("dc_ssa_timing_reset", lib().dc_ssa_timing_reset(self.h))
+
+    def free(self):
+        if self.h:
+            lib().dc_ssa_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
         except Exception:
             pass

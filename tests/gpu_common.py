@@ -50,3 +50,35 @@ def compare_summaries(gpu_res, summ, digest: bool = True):
     if digest:
         bad = np.nonzero(gpu_res["digest"] != summ["digest"])[0]
         assert len(bad) == 0, ("digest", bad[:10])
+
+
+def _oracle_ssa_chunk(args):
+    cfg, i0, n = args
+    b = dcgen.generate(cfg, n, i0=i0, threads=1)
+    return oracle.ssa_batch(b)
+
+
+class OracleSsaRun:
+    """Oracle version summaries for kernels [0, n) of a config, in parallel
+    worker processes started at construction."""
+
+    def __init__(self, cfg: int, n: int, procs: int = 0, jobs_per_proc: int = 4):
+        procs = procs or min(16, os.cpu_count() or 1)
+        step = max(1, (n + procs * jobs_per_proc - 1) // (procs * jobs_per_proc))
+        self.ex = ProcessPoolExecutor(procs)
+        self.futs = [self.ex.submit(_oracle_ssa_chunk, (cfg, i, min(step, n - i))) for i in range(0, n, step)]
+
+    def result(self):
+        parts = [f.result() for f in self.futs]
+        self.ex.shutdown()
+        return np.concatenate(parts)
+
+
+def compare_ssa_summaries(gpu_res, summ):
+    """Per-kernel status, blocks, merges, merge arguments, operand count and
+    digest of the versions."""
+    assert len(gpu_res) == len(summ)
+    for f_gpu, f_or in [("status", "status"), ("n_blocks", "n_blocks"), ("n_phi", "n_phi"),
+                        ("n_phi_args", "n_args"), ("n_operands", "n_operands"), ("digest", "digest")]:
+        bad = np.nonzero(gpu_res[f_gpu] != summ[f_or])[0]
+        assert len(bad) == 0, (f_gpu, bad[:10], gpu_res[f_gpu][bad[:10]], summ[f_or][bad[:10]])
