@@ -86,6 +86,10 @@ def lib():
         L.dcgen_generate.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32,
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
+        L.dcgen_render.restype = ctypes.c_void_p
+        L.dcgen_render.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.POINTER(ctypes.c_uint64)]
+        L.dcgen_free.argtypes = [ctypes.c_void_p]
         _lib = L
     return _lib
 
@@ -180,6 +184,24 @@ def concat(parts) -> Batch:
     kernels = np.array(descs, KERNEL_DTYPE) if descs else np.zeros(0, KERNEL_DTYPE)
     args = np.concatenate(argl) if argl else np.zeros(0, ARG_DTYPE)
     return Batch(instrs, kernels, args)
+
+
+def render(batch: Batch) -> bytes:
+    """The batch as listing text (the format of the paper's Listings 1 and 3:
+    .kernel / .config / .text sections, .dims, .cws, .useargs, .arg lines,
+    labels, one instruction per line), with comments, blank lines and tabs
+    sprinkled in deterministically."""
+    n = ctypes.c_uint64(0)
+    kernels = np.ascontiguousarray(batch.kernels)
+    instrs = np.ascontiguousarray(batch.instrs)
+    args = np.ascontiguousarray(batch.args)
+    p = lib().dcgen_render(kernels.ctypes.data if len(kernels) else None, len(kernels),
+                           instrs.ctypes.data if len(instrs) else None, args.ctypes.data if len(args) else None,
+                           ctypes.byref(n))
+    try:
+        return ctypes.string_at(p, n.value)
+    finally:
+        lib().dcgen_free(p)
 
 
 def descriptor(n_instr: int, dims: int = 1, cws=(64, 1, 1), useargs: int = 1, n_args: int = 0):

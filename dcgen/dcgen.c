@@ -23,6 +23,8 @@
  */
 #include <math.h>
 #include <pthread.h>
+#include <stdarg.h>
+#include <stdio.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -572,3 +574,208 @@ int dcgen_generate(int cfg, uint64_t i0, uint32_t n, const uint64_t *ioff, const
     else for (int t = 0; t < threads; t++) pthread_join(th[t], 0);
     return 0;
 }
+
+/* ---- text rendering: the listing format of the paper's Listings 1 and 3 ----
+ * Each kernel becomes
+ *   .kernel k<index>
+ *     .config
+ *       .dims x|xy|xyz
+ *       .cws a, b, c
+ *       <ignored directives>, .useargs, six hidden .arg lines, user .arg lines
+ *     .text
+ *   L<i>:              (before every branch target i)
+ *       <mnemonic> <operands>
+ * with comment lines, trailing comments, blank lines and tabs sprinkled in
+ * deterministically, so that a reader must cope with them.  The operand
+ * syntax per opcode is the one of the tests' assembler. */
+typedef struct { char *p; uint64_t n, cap; } sbuf;
+
+static void sb_grow(sbuf *b, uint64_t more) {
+    if (b->n + more + 1 <= b->cap) return;
+    uint64_t c = b->cap ? b->cap : 4096;
+    while (c < b->n + more + 1) c *= 2;
+    b->p = (char *)realloc(b->p, c);
+    b->cap = c;
+}
+static void sb_str(sbuf *b, const char *s) {
+    const size_t l = strlen(s);
+    sb_grow(b, l);
+    memcpy(b->p + b->n, s, l);
+    b->n += l;
+}
+static void sb_fmt(sbuf *b, const char *fmt, ...) {
+    char tmp[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(tmp, sizeof tmp, fmt, ap);
+    va_end(ap);
+    sb_str(b, tmp);
+}
+
+/* register width of operand slot o (0 r0, 1 r1, 2 r2, 3 src2) of op, for
+ * the register-range syntax only */
+static int op_width(int op, int o) {
+    switch (op) {
+    case S_LOAD_DWORD: return o == 0 ? 1 : 2;
+    case S_LOAD_DWORDX2: return 2;
+    case S_LOAD_DWORDX4: return o == 0 ? 4 : 2;
+    case S_MOV_B64: case S_AND_SAVEEXEC_B64: case S_OR_SAVEEXEC_B64: case S_AND_B64: case S_OR_B64:
+    case S_XOR_B64: case S_ANDN2_B64: case V_ADD_F64: case V_MUL_F64: case V_FMA_F64:
+        return 2;
+    case V_CVT_F64_F32: return o == 0 ? 2 : 1;
+    case V_LSHLREV_B64: return o == 1 ? 1 : 2;
+    case GLOBAL_LOAD_DWORD: case GLOBAL_STORE_DWORD: return o == 0 ? 1 : 2;
+    case FLAT_LOAD_DWORD: case FLAT_STORE_DWORD: return o == 0 ? 1 : 2;
+    case GLOBAL_LOAD_DWORDX2: case GLOBAL_STORE_DWORDX2: return 2;
+    default: return 1;
+    }
+}
+
+static const char *const FLOAT_TEXT[8] = {"0.5", "-0.5", "1.0", "-1.0", "2.0", "-2.0", "4.0", "-4.0"};
+
+static void operand_text(sbuf *b, uint16_t id, int w, int32_t imm, uint64_t salt) {
+    if (id >= 0x8000 && id <= 0x8050) { sb_fmt(b, "%d", (int)id - 0x8000 - 16); return; }
+    if (id >= 0x8060 && id <= 0x8067) { sb_str(b, FLOAT_TEXT[id - 0x8060]); return; }
+    if (id == LIT) {
+        if (imm < 0 || (salt & 1)) sb_fmt(b, "%d", imm);
+        else sb_fmt(b, "0x%x", (uint32_t)imm);
+        return;
+    }
+    if (id == NONE) { sb_str(b, "off"); return; }
+    if (id == 104) { sb_str(b, w == 2 ? "vcc" : "vcc_lo"); return; }
+    if (id == 105) { sb_str(b, "vcc_hi"); return; }
+    if (id == 106) { sb_str(b, w == 2 ? "exec" : "exec_lo"); return; }
+    if (id == 107) { sb_str(b, "exec_hi"); return; }
+    if (id == 108) { sb_str(b, "scc"); return; }
+    if (id == 109) { sb_str(b, "m0"); return; }
+    const char c = id >= 112 ? 'v' : 's';
+    const int n = id >= 112 ? id - 112 : id;
+    if (w == 1) sb_fmt(b, "%c%d", c, n);
+    else sb_fmt(b, "%c[%d:%d]", c, n, n + w - 1);
+}
+
+static const char *type_name(uint8_t t) {
+    switch (t) {
+    case T_INT: return "int";
+    case T_UINT: return "uint";
+    case T_FLOAT: return "float";
+    case T_DOUBLE: return "double";
+    default: return "void";
+    }
+}
+
+static void render_kernel(sbuf *b, uint64_t index, const gen_kernel *k, const gen_instr *ins, const gen_arg *args) {
+    uint64_t salt = 0x5EED0000u + index;
+    sb_fmt(b, ".kernel k%llu\n  .config\n", (unsigned long long)index);
+    static const char *const DIMS[4] = {"", "x", "xy", "xyz"};
+    sb_fmt(b, "    .dims %s\n", k->dims <= 3 ? DIMS[k->dims] : "xyzw");
+    sb_fmt(b, "    .cws %u, %u, %u\n", k->cws[0], k->cws[1], k->cws[2]);
+    sb_str(b, "    .sgprsnum 104\n    .vgprsnum 256\n    .floatmode 0xc0\n");
+    if (k->useargs) sb_str(b, "    .useargs\n");
+    sb_str(b, "    .priority 0\n"
+              "    .arg _.global_offset_0, \"size_t\", long\n"
+              "    .arg _.global_offset_1, \"size_t\", long\n"
+              "    .arg _.global_offset_2, \"size_t\", long\n"
+              "    .arg _.printf_buffer, \"size_t\", void*, global, , rdonly\n"
+              "    .arg _.vqueue_pointer,\"size_t\", long\n"
+              "    .arg _.aqlwrap_pointer,\"size_t\", long\n");
+    for (uint32_t a = 0; a < k->n_args; a++) {
+        const gen_arg *g = &args[a];
+        if (g->type == T_PTR) {
+            const char *t = type_name(g->flags);
+            sb_fmt(b, "    .arg a%u, \"%s*\", %s*, global,\n", a, t, t);
+        } else {
+            const char *t = type_name(g->type);
+            sb_fmt(b, "    .arg a%u, \"%s\", %s\n", a, t, t);
+        }
+    }
+    sb_str(b, "  .text\n");
+    const uint32_t n = k->n_instr;
+    uint8_t *tgt = (uint8_t *)calloc(n ? n : 1, 1);
+    for (uint32_t i = 0; i < n; i++)
+        if (ins[i].target >= 0 && (uint32_t)ins[i].target < n) tgt[ins[i].target] = 1;
+    for (uint32_t i = 0; i < n; i++) {
+        const gen_instr *x = &ins[i];
+        salt = salt * 6364136223846793005ull + 1442695040888963407ull;
+        if (tgt[i]) sb_fmt(b, "L%u:\n", i);
+        if ((salt >> 59) == 0) sb_str(b, "\n");
+        if ((salt >> 58) == 3) sb_str(b, "    // note\n");
+        sb_str(b, (salt >> 40) & 1 ? "\t" : "    ");
+        const int op = x->op;
+        if (op >= N_OPS) { sb_fmt(b, "op%d\n", op); continue; }
+        sb_str(b, OP_NAMES[op]);
+        const uint64_t s2 = salt >> 20;
+#define OPND(id, o) operand_text(b, (id), op_width(op, (o)), x->imm, s2)
+        switch (op) {
+        case S_LOAD_DWORD: case S_LOAD_DWORDX2: case S_LOAD_DWORDX4:
+            sb_str(b, " "); OPND(x->r0, 0); sb_str(b, ", "); OPND(x->r1, 1); sb_fmt(b, ", 0x%x", (uint32_t)x->imm);
+            break;
+        case S_BRANCH: case S_CBRANCH_SCC0: case S_CBRANCH_SCC1: case S_CBRANCH_VCCZ: case S_CBRANCH_VCCNZ:
+        case S_CBRANCH_EXECZ: case S_CBRANCH_EXECNZ:
+            sb_fmt(b, " L%d", x->target);
+            break;
+        case S_WAITCNT: sb_str(b, " lgkmcnt(0)"); break;
+        case S_BARRIER: case S_ENDPGM: break;
+        case S_NOP: sb_str(b, " 0"); break;
+        case S_CMP_EQ_U32: case S_CMP_LT_U32: case S_CMP_GT_U32: case S_CMP_LT_I32:
+            sb_str(b, " "); OPND(x->r1, 1); sb_str(b, ", "); OPND(x->r2, 2);
+            break;
+        case V_CMP_EQ_U32: case V_CMP_GT_U32: case V_CMP_LT_U32: case V_CMP_LT_I32: case V_CMP_GT_F32:
+            sb_str(b, " vcc, "); OPND(x->r1, 1); sb_str(b, ", "); OPND(x->r2, 2);
+            break;
+        case GLOBAL_LOAD_DWORD: case GLOBAL_LOAD_DWORDX2:
+            sb_str(b, " "); OPND(x->r0, 0); sb_str(b, ", "); OPND(x->r1, 1); sb_str(b, ", "); OPND(x->r2, 2);
+            if (x->imm) sb_fmt(b, " offset:%d", x->imm);
+            break;
+        case FLAT_LOAD_DWORD: case DS_READ_B32:
+            sb_str(b, " "); OPND(x->r0, 0); sb_str(b, ", "); OPND(x->r1, 1);
+            if (x->imm) sb_fmt(b, " offset:%d", x->imm);
+            break;
+        case GLOBAL_STORE_DWORD: case GLOBAL_STORE_DWORDX2:
+            sb_str(b, " "); OPND(x->r1, 1); sb_str(b, ", "); OPND(x->r0, 0); sb_str(b, ", "); OPND(x->r2, 2);
+            if (x->imm) sb_fmt(b, " offset:%d", x->imm);
+            break;
+        case FLAT_STORE_DWORD: case DS_WRITE_B32:
+            sb_str(b, " "); OPND(x->r1, 1); sb_str(b, ", "); OPND(x->r0, 0);
+            if (x->imm) sb_fmt(b, " offset:%d", x->imm);
+            break;
+        case V_ADD_CO_U32: case V_SUB_CO_U32: case V_ADDC_CO_U32:
+            sb_str(b, " "); OPND(x->r0, 0); sb_str(b, ", vcc, "); OPND(x->r1, 1); sb_str(b, ", "); OPND(x->r2, 2);
+            if (op == V_ADDC_CO_U32) sb_str(b, ", vcc");
+            break;
+        case V_CNDMASK_B32:
+            sb_str(b, " "); OPND(x->r0, 0); sb_str(b, ", "); OPND(x->r1, 1); sb_str(b, ", "); OPND(x->r2, 2);
+            sb_str(b, ", vcc");
+            break;
+        case V_MAD_U32_U24: case V_MAD_F32: case V_FMA_F32: case V_FMA_F64:
+            sb_str(b, " "); OPND(x->r0, 0); sb_str(b, ", "); OPND(x->r1, 1); sb_str(b, ", "); OPND(x->r2, 2);
+            sb_str(b, ", "); operand_text(b, (uint16_t)x->imm, op_width(op, 3), 0, s2);
+            break;
+        case S_MOV_B32: case S_MOV_B64: case S_AND_SAVEEXEC_B64: case S_OR_SAVEEXEC_B64: case V_MOV_B32:
+        case V_CVT_F32_U32: case V_CVT_U32_F32: case V_CVT_F64_F32:
+            sb_str(b, " "); OPND(x->r0, 0); sb_str(b, ", "); OPND(x->r1, 1);
+            break;
+        default:
+            sb_str(b, " "); OPND(x->r0, 0); sb_str(b, ", "); OPND(x->r1, 1); sb_str(b, ", "); OPND(x->r2, 2);
+        }
+#undef OPND
+        if ((salt >> 56) == 7) sb_str(b, "   ; trailing");
+        sb_str(b, (salt >> 30) % 13 == 0 ? " \r\n" : "\n");
+    }
+    free(tgt);
+}
+
+/* Render n kernels (records relative to instrs, args relative to args) into
+ * a malloc'ed buffer; *out_len = its length.  Free it with dcgen_free. */
+char *dcgen_render(const gen_kernel *kernels, uint32_t n, const gen_instr *instrs, const gen_arg *args,
+                   uint64_t *out_len) {
+    sbuf b = {0, 0, 0};
+    sb_str(&b, "// seeded synthetic kernels\n");
+    for (uint32_t k = 0; k < n; k++)
+        render_kernel(&b, k, &kernels[k], instrs + kernels[k].instr_begin, args + kernels[k].arg_begin);
+    sb_grow(&b, 0);
+    b.p[b.n] = 0;
+    *out_len = b.n;
+    return b.p;
+}
+void dcgen_free(void *p) { free(p); }

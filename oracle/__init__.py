@@ -8,7 +8,9 @@ wrapper.
 
 Parity: pinned by tests/test_oracle_*.py (the paper's worked statements,
 textbook basic blocks, meet-over-all-paths for the distributive tiers,
-schedule independence, lattice laws).  The payload tier beyond the paper's
+schedule independence, lattice laws; register versions against brute-force
+dominators, join sets and path walks; the text front end against the
+paper's Listings 1 and 3 written out by hand and the generator's renderer).  The payload tier beyond the paper's
 printed cases is "parity unpinned": only invariants pin it (monotone rules,
 meet over all paths below the fixpoint, schedule independence, constant
 folding in closed form), since the paper prints no further values.
@@ -79,6 +81,9 @@ def lib():
         L.or_ssa_free.argtypes = [ctypes.c_void_p]
         L.or_ssa_batch.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p]
         L.or_ssa_batch.restype = ctypes.c_int
+        L.or_parse_text.argtypes = [ctypes.c_char_p, ctypes.c_uint64, ctypes.c_void_p]
+        L.or_parse_text.restype = ctypes.c_int
+        L.or_text_free.argtypes = [ctypes.c_void_p]
         L.or_ssa_uses.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
         L.or_ssa_uses.restype = ctypes.c_int
         L.or_ssa_defs.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
@@ -189,6 +194,29 @@ def ssa(recs, desc) -> dict:
                def_ver=_copy(R.def_ver, SSA_ND * n, np.uint32).reshape(n, SSA_ND),
                n_ver=np.array(R.n_ver[:], np.uint32), digest=R.digest)
     L.or_ssa_free(ctypes.byref(R))
+    return out
+
+
+class _TextOut(ctypes.Structure):
+    _fields_ = [("n_kernels", ctypes.c_uint32), ("n_instr", ctypes.c_uint64), ("n_args", ctypes.c_uint64),
+                ("kernels", ctypes.c_void_p), ("instrs", ctypes.c_void_p), ("args", ctypes.c_void_p),
+                ("name_off", ctypes.c_void_p), ("name_len", ctypes.c_void_p)]
+
+
+def parse_text(text: bytes) -> dict:
+    """The text front end: a listing (Listings 1-3 format) to descriptors,
+    records and argument tables, plus each kernel's name."""
+    from dcgen import ARG_DTYPE, INSTR_DTYPE, KERNEL_DTYPE
+    R = _TextOut()
+    L = lib()
+    L.or_parse_text(text, len(text), ctypes.byref(R))
+    k = _copy(R.kernels, R.n_kernels, KERNEL_DTYPE)
+    out = dict(kernels=k, instrs=_copy(R.instrs, R.n_instr, INSTR_DTYPE), args=_copy(R.args, R.n_args, ARG_DTYPE))
+    off = _copy(R.name_off, R.n_kernels, np.uint64)
+    ln = _copy(R.name_len, R.n_kernels, np.uint32)
+    out["names"] = [bytes(text[int(o):int(o) + int(n)]) for o, n in zip(off, ln)]
+    out["name_off"], out["name_len"] = off, ln
+    L.or_text_free(ctypes.byref(R))
     return out
 
 

@@ -1536,3 +1536,406 @@ int or_analyze_batch(const or_kernel *kernels, uint32_t n_kernels, const or_inst
     if (n_sys_total) *n_sys_total = ns;
     return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* text front end (Section "The body extraction")                       */
+/* ------------------------------------------------------------------ */
+/* Listing 2's extraction loop over the lines of a listing: a line holding
+ * ".kernel" opens a kernel whose name is its second word; a line ".config"
+ * switches to the configuration state and ".text" to the instruction state;
+ * lines in those states are collected into the kernel's configuration and
+ * body; anything else is skipped.  Each kernel is then processed: the
+ * configuration gives .dims, .cws, .useargs and the .arg lines of Listing 3;
+ * the body gives one record per instruction line, labels (a line "NAME:")
+ * naming the index of the next instruction.  Readings (the paper fixes no
+ * grammar): comments run from "//" or ";" to the end of the line; blanks
+ * are spaces, tabs and carriage returns; ".dims" (or "dims", as Listing 1
+ * prints it) takes x, xy or xyz; ".cws" takes up to three integers (a
+ * missing later one is 1; without .cws every size is 0); args whose names
+ * begin with "_." are the six hidden slots of Listing 3 and take no entry;
+ * user args are laid out from byte 0x30, each aligned to its size.  An
+ * unknown mnemonic gives opcode 0xFFFF, an operand that is not a register,
+ * inline constant or integer gives operand id 0xFFFD, a malformed offset
+ * gives opcode 0xFFFF, and an unknown branch label gives target 0x7FFFFFFF,
+ * so the record checks of the analysis report each of them. */
+#define TX_BAD 0xFFFDu
+#define TX_NONE 0xFFFFu
+#define TX_LIT 0xFFFEu
+
+typedef struct { const char *p; uint32_t n; } tx_span;
+
+static int tx_blank(char c) { return c == ' ' || c == '\t' || c == '\r'; }
+
+/* the line without its comment and surrounding blanks */
+static tx_span tx_clean(const char *p, uint32_t n) {
+    for (uint32_t i = 0; i < n; i++)
+        if (p[i] == ';' || (p[i] == '/' && i + 1 < n && p[i + 1] == '/')) { n = i; break; }
+    while (n && tx_blank(p[n - 1])) n--;
+    while (n && tx_blank(p[0])) { p++; n--; }
+    tx_span s = {p, n};
+    return s;
+}
+static tx_span tx_trim(tx_span s) { return tx_clean(s.p, s.n); }
+static int tx_eq(tx_span s, const char *lit) { return strlen(lit) == s.n && memcmp(s.p, lit, s.n) == 0; }
+/* first blank-separated word of s; *rest = what follows it */
+static tx_span tx_word(tx_span s, tx_span *rest) {
+    uint32_t i = 0;
+    while (i < s.n && !tx_blank(s.p[i])) i++;
+    tx_span w = {s.p, i};
+    if (rest) { tx_span r = {s.p + i, s.n - i}; *rest = tx_trim(r); }
+    return w;
+}
+/* field k of a comma-separated list (trimmed); n = 0 when absent */
+static tx_span tx_field(tx_span s, int k) {
+    uint32_t a = 0;
+    for (int f = 0; f <= k; f++) {
+        uint32_t b = a;
+        while (b < s.n && s.p[b] != ',') b++;
+        if (f == k) { tx_span r = {s.p + a, b - a}; return tx_trim(r); }
+        if (b >= s.n) { tx_span z = {s.p, 0}; return z; }
+        a = b + 1;
+    }
+    tx_span z = {s.p, 0};
+    return z;
+}
+static int tx_nfields(tx_span s) {
+    if (!s.n) return 0;
+    int n = 1;
+    for (uint32_t i = 0; i < s.n; i++) n += s.p[i] == ',';
+    return n;
+}
+/* integer: optional '-', then 0x hex digits or decimal digits; 0 on error */
+static int tx_int(tx_span s, int64_t *v) {
+    uint32_t i = 0;
+    int neg = 0;
+    if (i < s.n && s.p[i] == '-') { neg = 1; i++; }
+    if (i >= s.n) return 0;
+    uint64_t x = 0;
+    if (i + 1 < s.n && s.p[i] == '0' && (s.p[i + 1] == 'x' || s.p[i + 1] == 'X')) {
+        i += 2;
+        if (i >= s.n) return 0;
+        for (; i < s.n; i++) {
+            const char c = s.p[i];
+            int d = c >= '0' && c <= '9' ? c - '0' : c >= 'a' && c <= 'f' ? c - 'a' + 10 : c >= 'A' && c <= 'F' ? c - 'A' + 10 : -1;
+            if (d < 0 || x >> 60) return 0;
+            x = x * 16 + (uint64_t)d;
+        }
+    } else {
+        for (; i < s.n; i++) {
+            const char c = s.p[i];
+            if (c < '0' || c > '9' || x > 100000000000000000ull) return 0;
+            x = x * 10 + (uint64_t)(c - '0');
+        }
+    }
+    *v = neg ? -(int64_t)x : (int64_t)x;
+    return 1;
+}
+static unsigned tx_lower(char c) { return (c >= 'A' && c <= 'Z') ? (unsigned)(c - 'A' + 'a') : (unsigned)(unsigned char)c; }
+static int tx_ieq(tx_span s, const char *lit) {
+    if (strlen(lit) != s.n) return 0;
+    for (uint32_t i = 0; i < s.n; i++)
+        if (tx_lower(s.p[i]) != (unsigned char)lit[i]) return 0;
+    return 1;
+}
+
+/* a register, inline constant or literal; *lit set for a literal */
+static unsigned tx_operand(tx_span t, int *has_lit, int32_t *lit) {
+    static const char *const special[] = {"vcc", "vcc_lo", "vcc_hi", "exec", "exec_lo", "exec_hi", "scc", "m0", "off"};
+    static const unsigned special_id[] = {104, 104, 105, 106, 106, 107, 108, 109, TX_NONE};
+    for (int i = 0; i < 9; i++)
+        if (tx_ieq(t, special[i])) return special_id[i];
+    if (t.n >= 2 && (tx_lower(t.p[0]) == 's' || tx_lower(t.p[0]) == 'v')) {
+        const int vec = tx_lower(t.p[0]) == 'v';
+        const int64_t lim = vec ? 255 : 103;
+        int64_t a, b;
+        if (t.p[1] == '[') {
+            uint32_t c = 2;
+            while (c < t.n && t.p[c] != ':') c++;
+            if (c >= t.n || t.p[t.n - 1] != ']') return TX_BAD;
+            tx_span x = {t.p + 2, c - 2}, y = {t.p + c + 1, t.n - c - 2};
+            if (!tx_int(x, &a) || !tx_int(y, &b) || a < 0 || b < a || b > lim || x.p[0] == '-') return TX_BAD;
+        } else {
+            tx_span x = {t.p + 1, t.n - 1};
+            if (x.p[0] == '-' || !tx_int(x, &a) || a < 0 || a > lim) return TX_BAD;
+        }
+        return vec ? 112u + (unsigned)a : (unsigned)a;
+    }
+    static const char *const floats[8] = {"0.5", "-0.5", "1.0", "-1.0", "2.0", "-2.0", "4.0", "-4.0"};
+    for (int i = 0; i < 8; i++)
+        if (tx_eq(t, floats[i])) return 0x8060u + (unsigned)i;
+    int64_t v;
+    if (!tx_int(t, &v)) return TX_BAD;
+    if (v >= -16 && v <= 64) return 0x8000u + (unsigned)(v + 16);
+    *has_lit = 1;
+    *lit = (int32_t)(uint32_t)(uint64_t)v;
+    return TX_LIT;
+}
+
+typedef struct { tx_span name; uint32_t index; } tx_label;
+
+static int tx_find_op(tx_span w) {
+    for (int op = 0; op < N_OPS; op++)
+        if (tx_ieq(w, OPS[op].name)) return op;
+    return -1;
+}
+
+/* one instruction line -> record */
+static or_instr tx_instr(tx_span line, const tx_label *labels, uint32_t n_labels) {
+    or_instr r = {TX_NONE, TX_NONE, TX_NONE, TX_NONE, 0, -1};
+    tx_span rest;
+    const tx_span w = tx_word(line, &rest);
+    const int op = tx_find_op(w);
+    if (op < 0) { r.op = TX_NONE; return r; }
+    r.op = (uint16_t)op;
+    const opinfo *o = &OPS[op];
+    /* operands: comma-separated fields, each an operand word followed by
+     * modifier words; without any comma (as the paper prints
+     * "s_load_dwordx2 s[2:3] s[4:5] 0x0") every blank-separated word is an
+     * operand, except modifiers.  A modifier is a word with ':' and no '['
+     * (key:value); only offset:N is read. */
+    int bad_num = 0;
+    int nf = 0;
+    tx_span f[8];
+    int has_comma = 0;
+    for (uint32_t i = 0; i < rest.n; i++) has_comma |= rest.p[i] == ',';
+    const int nfields = has_comma ? tx_nfields(rest) : 1;
+    for (int k = 0; k < nfields; k++) {
+        tx_span words = has_comma ? tx_field(rest, k) : rest;
+        int first = 1;
+        while (words.n) {
+            tx_span more;
+            const tx_span mw = tx_word(words, &more);
+            int colon = 0, bracket = 0;
+            for (uint32_t i = 0; i < mw.n; i++) { colon |= mw.p[i] == ':'; bracket |= mw.p[i] == '['; }
+            if (colon && !bracket) {
+                if (mw.n > 7 && memcmp(mw.p, "offset:", 7) == 0) {
+                    tx_span num = {mw.p + 7, mw.n - 7};
+                    int64_t v;
+                    if (tx_int(num, &v)) r.imm = (int32_t)(uint32_t)(uint64_t)v;
+                    else bad_num = 1;
+                }
+            } else if (first || !has_comma) {
+                if (nf < 8) f[nf] = mw;
+                nf++;
+                first = 0;
+            }
+            words = more;
+        }
+        if (has_comma && first) {   /* an empty field still counts */
+            if (nf < 8) f[nf].p = rest.p, f[nf].n = 0;
+            nf++;
+        }
+    }
+    if (nf > 8) nf = 8;
+    int has_lit = 0;
+    int32_t lit = 0;
+#define OPD(k) ((k) < nf && f[k].n ? (uint16_t)tx_operand(f[k], &has_lit, &lit) : (uint16_t)TX_BAD)
+    switch (o->cls) {
+    case C_SMEM: {
+        r.r0 = OPD(0);
+        r.r1 = OPD(1);
+        int64_t v;
+        if (nf > 2 && tx_int(f[2], &v)) r.imm = (int32_t)(uint32_t)(uint64_t)v;
+        else bad_num = 1;
+        break;
+    }
+    case C_BRANCH:
+    case C_CBRANCH: {
+        r.target = 0x7FFFFFFF;
+        if (nf > 0) {
+            int found = 0;
+            for (uint32_t j = 0; j < n_labels && !found; j++)
+                if (labels[j].name.n == f[0].n && memcmp(labels[j].name.p, f[0].p, f[0].n) == 0) {
+                    r.target = (int32_t)labels[j].index;
+                    found = 1;
+                }
+            int64_t v;
+            if (!found && tx_int(f[0], &v) && v >= 0 && v < 0x7FFFFFFF) r.target = (int32_t)v;
+        }
+        break;
+    }
+    case C_NOP:
+    case C_END: break;
+    case C_SCMP: r.r1 = OPD(0); r.r2 = OPD(1); break;
+    case C_VCMP: r.r1 = OPD(1); r.r2 = OPD(2); break;
+    case C_GLOAD: r.r0 = OPD(0); r.r1 = OPD(1); r.r2 = OPD(2); break;
+    case C_FLOAD:
+    case C_DSREAD: r.r0 = OPD(0); r.r1 = OPD(1); break;
+    case C_GSTORE: r.r1 = OPD(0); r.r0 = OPD(1); r.r2 = OPD(2); break;
+    case C_FSTORE:
+    case C_DSWRITE: r.r1 = OPD(0); r.r0 = OPD(1); break;
+    default:
+        if (o->cls == C_VALU && (o->imp_def & I_VCC)) {   /* dst, vcc, src0, src1 */
+            r.r0 = OPD(0); r.r1 = OPD(2); r.r2 = OPD(3);
+        } else if (o->src2 != NO) {                        /* dst, src0, src1, src2 */
+            r.r0 = OPD(0); r.r1 = OPD(1); r.r2 = OPD(2);
+            r.imm = (int32_t)OPD(3);
+        } else if (o->r2 == NO) {                          /* dst, src */
+            r.r0 = OPD(0); r.r1 = OPD(1);
+        } else {                                           /* dst, src0, src1 */
+            r.r0 = OPD(0); r.r1 = OPD(1); r.r2 = OPD(2);
+        }
+    }
+#undef OPD
+    if (has_lit && !o->imm_is_offset && o->src2 == NO) r.imm = lit;
+    if (bad_num) r.op = TX_NONE;
+    return r;
+}
+
+/* Listing 3's .arg type: size, type bits, pointee bits */
+static void tx_argtype(tx_span t, uint16_t *size, uint8_t *type, uint8_t *flags) {
+    int ptr = 0;
+    if (t.n && t.p[t.n - 1] == '*') {
+        ptr = 1;
+        t.n--;
+        t = tx_trim(t);
+    }
+    static const char *const names[] = {"char", "uchar", "short", "ushort", "int", "uint", "long", "ulong",
+                                        "float", "double", "size_t", "void"};
+    static const uint8_t bits[] = {1, 2, 1, 2, 1, 2, 1, 2, 4, 8, 2, 0};
+    static const uint16_t sizes[] = {1, 1, 2, 2, 4, 4, 8, 8, 4, 8, 8, 4};
+    uint8_t b = 0;
+    uint16_t sz = 4;
+    for (int i = 0; i < 12; i++)
+        if (tx_eq(t, names[i])) { b = bits[i]; sz = sizes[i]; break; }
+    if (ptr) { *size = 8; *type = 16; *flags = b; }
+    else { *size = sz; *type = b; *flags = 0; }
+}
+
+typedef struct {
+    uint32_t n_kernels;
+    uint64_t n_instr, n_args;
+    or_kernel *kernels;
+    or_instr *instrs;
+    or_arg *args;
+    uint64_t *name_off;      /* per kernel: byte offset of its name in the text */
+    uint32_t *name_len;
+} or_text_out;
+
+typedef struct { uint64_t *off; uint32_t *len; uint32_t n, cap; } tx_lines;
+static void tx_push(tx_lines *L, uint64_t off, uint32_t len) {
+    if (L->n == L->cap) {
+        L->cap = L->cap ? 2 * L->cap : 64;
+        L->off = (uint64_t *)realloc(L->off, sizeof(uint64_t) * L->cap);
+        L->len = (uint32_t *)realloc(L->len, sizeof(uint32_t) * L->cap);
+    }
+    L->off[L->n] = off;
+    L->len[L->n] = len;
+    L->n++;
+}
+
+/* process_data of Listing 2: one kernel's configuration and body */
+static void tx_process(const char *text, uint64_t name_off, uint32_t name_len, const tx_lines *cfg,
+                       const tx_lines *body, or_text_out *O) {
+    or_kernel K;
+    memset(&K, 0, sizeof(K));
+    K.instr_begin = O->n_instr;
+    K.arg_begin = (uint32_t)O->n_args;
+    uint32_t cursor = 0x30;
+    for (uint32_t j = 0; j < cfg->n; j++) {
+        tx_span line = {text + cfg->off[j], cfg->len[j]}, rest;
+        const tx_span w = tx_word(line, &rest);
+        if (tx_eq(w, ".dims") || tx_eq(w, "dims")) {
+            const tx_span d = tx_word(rest, 0);
+            K.dims = tx_eq(d, "x") ? 1 : tx_eq(d, "xy") ? 2 : tx_eq(d, "xyz") ? 3 : 0;
+        } else if (tx_eq(w, ".cws")) {
+            for (int d = 0; d < 3; d++) {
+                const tx_span v = tx_field(rest, d);
+                int64_t x;
+                K.cws[d] = v.n == 0 ? 1u : (tx_int(v, &x) && x >= 0 && x <= 0xFFFFFFFFll ? (uint32_t)x : 0u);
+            }
+        } else if (tx_eq(w, ".useargs")) {
+            K.useargs = 1;
+        } else if (tx_eq(w, ".arg")) {
+            const tx_span name = tx_field(rest, 0);
+            if (name.n >= 2 && name.p[0] == '_' && name.p[1] == '.') continue;
+            or_arg a;
+            tx_argtype(tx_field(rest, 2), &a.size, &a.type, &a.flags);
+            cursor = (cursor + a.size - 1) / a.size * a.size;
+            a.offset = cursor;
+            cursor += a.size;
+            O->args = (or_arg *)realloc(O->args, sizeof(or_arg) * (O->n_args + 1));
+            O->args[O->n_args++] = a;
+            K.n_args++;
+        }
+    }
+    /* labels: the index of the next instruction line */
+    tx_label *labels = (tx_label *)malloc(sizeof(tx_label) * (body->n ? body->n : 1));
+    uint32_t n_labels = 0, n_ins = 0;
+    for (uint32_t j = 0; j < body->n; j++) {
+        tx_span line = {text + body->off[j], body->len[j]};
+        tx_span rest;
+        tx_word(line, &rest);
+        if (line.p[line.n - 1] == ':' && rest.n == 0) {
+            tx_span nm = {line.p, line.n - 1};
+            int seen = 0;
+            for (uint32_t q = 0; q < n_labels; q++)
+                if (labels[q].name.n == nm.n && memcmp(labels[q].name.p, nm.p, nm.n) == 0) seen = 1;
+            if (!seen) { labels[n_labels].name = nm; labels[n_labels].index = n_ins; n_labels++; }
+        } else {
+            n_ins++;
+        }
+    }
+    O->instrs = (or_instr *)realloc(O->instrs, sizeof(or_instr) * (O->n_instr + n_ins + 1));
+    for (uint32_t j = 0; j < body->n; j++) {
+        tx_span line = {text + body->off[j], body->len[j]};
+        tx_span rest;
+        tx_word(line, &rest);
+        if (line.p[line.n - 1] == ':' && rest.n == 0) continue;
+        O->instrs[O->n_instr++] = tx_instr(line, labels, n_labels);
+    }
+    free(labels);
+    K.n_instr = n_ins;
+    O->kernels = (or_kernel *)realloc(O->kernels, sizeof(or_kernel) * (O->n_kernels + 1));
+    O->name_off = (uint64_t *)realloc(O->name_off, sizeof(uint64_t) * (O->n_kernels + 1));
+    O->name_len = (uint32_t *)realloc(O->name_len, sizeof(uint32_t) * (O->n_kernels + 1));
+    O->kernels[O->n_kernels] = K;
+    O->name_off[O->n_kernels] = name_off;
+    O->name_len[O->n_kernels] = name_len;
+    O->n_kernels++;
+}
+
+int or_parse_text(const char *text, uint64_t len, or_text_out *O) {
+    memset(O, 0, sizeof(*O));
+    enum { S_START, S_KERNEL, S_CONFIG, S_TEXT } state = S_START;
+    tx_lines cfg = {0, 0, 0, 0}, body = {0, 0, 0, 0};
+    int open = 0;
+    uint64_t name_off = 0;
+    uint32_t name_len = 0;
+    uint64_t a = 0;
+    while (a <= len) {
+        uint64_t b = a;
+        while (b < len && text[b] != '\n') b++;
+        const tx_span line = tx_clean(text + a, (uint32_t)(b - a));
+        if (line.n) {
+            tx_span rest;
+            const tx_span w = tx_word(line, &rest);
+            if (tx_eq(w, ".kernel")) {
+                if (open) tx_process(text, name_off, name_len, &cfg, &body, O);
+                cfg.n = body.n = 0;
+                open = 1;
+                const tx_span nm = tx_word(rest, 0);
+                name_off = (uint64_t)(nm.p - text);
+                name_len = nm.n;
+                state = S_KERNEL;
+            } else if (open && tx_eq(line, ".config")) {
+                state = S_CONFIG;
+            } else if (open && tx_eq(line, ".text")) {
+                state = S_TEXT;
+            } else if (state == S_CONFIG) {
+                tx_push(&cfg, (uint64_t)(line.p - text), line.n);
+            } else if (state == S_TEXT) {
+                tx_push(&body, (uint64_t)(line.p - text), line.n);
+            }
+        }
+        a = b + 1;
+    }
+    if (open) tx_process(text, name_off, name_len, &cfg, &body, O);
+    free(cfg.off); free(cfg.len); free(body.off); free(body.len);
+    return 0;
+}
+
+void or_text_free(or_text_out *O) {
+    free(O->kernels); free(O->instrs); free(O->args); free(O->name_off); free(O->name_len);
+    memset(O, 0, sizeof(*O));
+}
