@@ -448,6 +448,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=50000.0)
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--no-extra", action="store_true", help="skip the other workloads")
+    ap.add_argument("--only-ssa", action="store_true",
+                    help="time only the register versions (dc_build_ssa) of the workload and print their figures")
     ap.add_argument("--lat-steps", type=int, default=5, help="runs timed one by one for the latency percentiles")
     ap.add_argument("--tune-sample", type=int, default=65536,
                     help="kernels in the autotuner's sample (every stride-th kernel; enough work to fill the GPU)")
@@ -466,6 +468,12 @@ def main():
     b = dcgen.generate(cfg, n_k)
     log(f"generated {b.n_kernels} kernels, {b.n_instr} instructions in {time.perf_counter() - t:.1f}s")
     stream = torch.cuda.current_stream()
+    if args.only_ssa:
+        ctx = dc.Context(0)
+        r = ssa_workload(ctx, b, stream, steps=args.steps)
+        ctx.close()
+        print(json.dumps({"workload": desc, "kernels": b.n_kernels, "instructions": b.n_instr, "ssa": r}), flush=True)
+        return
     if args.copy_calibration:
         src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
