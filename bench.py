@@ -257,7 +257,12 @@ def ssa_workload(ctx, b, stream, steps=5, cpu_kernels=2048):
     import oracle
     from paper_2107_07809_amd import dc
     dev = dc.to_device(b.instrs)
-    s = ctx.build_ssa(b.kernels, dev, b.n_instr, timing=True, stream=stream)
+    # the digests of one run are checked against the oracle on a sample; the
+    # timed object computes none (as a caller that wants the versions would)
+    s = ctx.build_ssa(b.kernels, dev, b.n_instr, digest=True, stream=stream)
+    dig = s.results()
+    s.free()
+    s = ctx.build_ssa(b.kernels, dev, b.n_instr, timing=True, digest=False, stream=stream)
     s.run()
     s.wait()
     res0 = s.results()
@@ -284,9 +289,51 @@ def ssa_workload(ctx, b, stream, steps=5, cpu_kernels=2048):
             "merges": int(res["n_phi"].sum()), "merge_args": int(res["n_phi_args"].sum()),
             "operand_versions": int(res["n_operands"].sum()), "failed": int((~ok).sum()),
             "rerun_identical": bool(res.tobytes() == res0.tobytes()),
-            "sample_matches_oracle": bool(res[:sub.n_kernels]["digest"].tobytes() == osum["digest"].tobytes()),
+            "sample_matches_oracle": bool(dig[:sub.n_kernels]["digest"].tobytes() == osum["digest"].tobytes()),
+            "counts_match_digest_run": bool(np.array_equal(dig["n_operands"], res["n_operands"]) and
+                                            np.array_equal(dig["n_phi"], res["n_phi"])),
             "alg_bytes": alg, "ssa_stages_GBps": alg / (ssa_ms * 1e-3) / 1e9 if ssa_ms else None,
             "cpu_oracle": {"instructions_per_s": sub.n_instr / cpu_dt, "cores": 1, "kernels": sub.n_kernels}}
+
+
+def text_workload(ctx, b, stream, steps=5, cpu_kernels=2048):
+    """The text front end (dc_parse_text) on a workload rendered as one
+    listing: whole runs (line starts, kinds, per-kernel counts, labels and
+    records) with the text in HBM, stage times from HIP events; the oracle's
+    parser on one core over the listing of the first cpu_kernels kernels."""
+    import torch
+    import dcgen
+    import oracle
+    from paper_2107_07809_amd import dc
+    text = dcgen.render(b)
+    dev = dc.text_to_device(text)
+    t = ctx.parse_text(dev, len(text), timing=True, stream=stream)
+    t.run()
+    t.wait()
+    t.timing_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        t.run()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    tm = t.timing()
+    c = t.counts()
+    ok = bool(t.kernels().tobytes() == b.kernels.tobytes() and t.args().tobytes() == b.args.tobytes())
+    t.free()
+    runs = max(1, tm["runs"])
+    alg = len(text) + 16 * c["n_instr"] + 8 * c["n_args"] + 32 * c["n_kernels"]
+    sub = dcgen.render(b.subset(np.arange(min(cpu_kernels, b.n_kernels))))
+    t0 = time.perf_counter()
+    oracle.parse_text(sub)
+    cpu_dt = time.perf_counter() - t0
+    return {"text_bytes": len(text), "lines": c["n_lines"], "instructions": c["n_instr"],
+            "instructions_per_s": c["n_instr"] / dt, "GB_per_s": len(text) / dt / 1e9, "ms_per_step": dt * 1e3,
+            "stage_ms": {"lines_and_kinds": tm["ms_decode"] / runs, "counts": tm["ms_cfg"] / runs,
+                         "records": tm["ms_fixpoint"] / runs},
+            "descriptors_and_args_match": ok, "alg_bytes": alg,
+            "alg_GBps": alg / (tm["ms_total"] / runs * 1e-3) / 1e9 if tm["ms_total"] else None,
+            "cpu_oracle": {"bytes_per_s": len(sub) / cpu_dt, "cores": 1, "kernels": min(cpu_kernels, b.n_kernels)}}
 
 
 def extra_workloads(ctx, stream):
@@ -303,6 +350,8 @@ def extra_workloads(ctx, stream):
                                        "plain": plain, "batched_speedup": r["value"] / plain["value"]}
     log("65,536 kernels: register versions")
     out["loguniform_65536_kernels"]["ssa"] = ssa_workload(ctx, b, stream)
+    log("65,536 kernels: text front end")
+    out["loguniform_65536_kernels"]["text"] = text_workload(ctx, b, stream)
     b = dcgen.generate(4, 16)
     r = timed_run(ctx, b, stream, steps=2, warmup=0, shape={}, lat_steps=0, what="16 huge kernels")
     out["huge_16_kernels_1M_to_4M"] = {
@@ -448,6 +497,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=50000.0)
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--no-extra", action="store_true", help="skip the other workloads")
+    ap.add_argument("--only-text", action="store_true",
+                    help="time only the text front end (dc_parse_text) on the workload rendered as one listing")
     ap.add_argument("--only-ssa", action="store_true",
                     help="time only the register versions (dc_build_ssa) of the workload and print their figures")
     ap.add_argument("--lat-steps", type=int, default=5, help="runs timed one by one for the latency percentiles")
@@ -468,6 +519,12 @@ def main():
     b = dcgen.generate(cfg, n_k)
     log(f"generated {b.n_kernels} kernels, {b.n_instr} instructions in {time.perf_counter() - t:.1f}s")
     stream = torch.cuda.current_stream()
+    if args.only_text:
+        ctx = dc.Context(0)
+        r = text_workload(ctx, b, stream, steps=args.steps)
+        ctx.close()
+        print(json.dumps({"workload": desc, "kernels": b.n_kernels, "instructions": b.n_instr, "text": r}), flush=True)
+        return
     if args.only_ssa:
         ctx = dc.Context(0)
         r = ssa_workload(ctx, b, stream, steps=args.steps)

@@ -315,6 +315,76 @@ dc_status_t dc_analyze_noalloc(dc_ctx_t *ctx, const dc_kernel_t *kernels, uint32
                                uint32_t sys_cap, uint32_t *sys_off, void *stream);
 
 /* ------------------------------------------------------------------ */
+/* Text front end.                                                      */
+/* ------------------------------------------------------------------ */
+/* Section "The body extraction": listings in the format of the paper's
+ * Listings 1-3 become kernel descriptors, records and argument tables.  The
+ * paper's extraction loop is followed: a ".kernel NAME" line opens a kernel,
+ * ".config" and ".text" lines switch between collecting its configuration and
+ * its body; lines before the first .kernel, and between .kernel and the first
+ * switch, are skipped.  The grammar (the paper fixes none):
+ *   - a comment runs from "//" or ";" to the end of the line; blanks are
+ *     space, tab and carriage return; lines end at '\n';
+ *   - configuration: ".dims" (or "dims") x | xy | xyz -> dims 1..3 (else 0);
+ *     ".cws a[, b[, c]]" (integers; a missing later size is 1; without .cws
+ *     all sizes are 0); ".useargs"; ".arg name, "ctype", type[, ...]" -- args
+ *     named "_." are the six hidden 8-byte slots and take no entry, user
+ *     arguments are laid out from 0x30, each at the next multiple of its size
+ *     (char 1, short 2, int/uint/float 4, long/ulong/double/size_t/pointers
+ *     8; other types 4 bytes, no type bits), type bits from the type (signed
+ *     int -> DC_TY_INT, unsigned -> DC_TY_UINT, float, double; "T*" ->
+ *     DC_TY_PTR with T's bits in flags); the last .dims / .cws wins; other
+ *     lines are skipped;
+ *   - body: a line "NAME:" is a label naming the index of the next
+ *     instruction (the first definition of a name wins); every other line is
+ *     one instruction: a mnemonic (case-insensitive, dc_opcode_name) and
+ *     operands separated by commas (or, with no comma, by blanks); words
+ *     "key:value" without '[' are modifiers, of which "offset:N" sets imm;
+ *     operands: s<n>, v<n>, s[a:b], v[a:b] (the first register), vcc(_lo/_hi),
+ *     exec(_lo/_hi), scc, m0, off (none), the integers -16..64 and the floats
+ *     +-0.5, +-1.0, +-2.0, +-4.0 as inline constants, other integers (decimal
+ *     or 0x hex) as a literal in imm; operand order per opcode as in
+ *     s_load_dword sdst, sbase, offset / v_cmp vcc, a, b / v_add_co_u32 dst,
+ *     vcc, a, b / global_load dst, vaddr, saddr|off / global_store vaddr,
+ *     data, saddr|off / ds_write addr, data / three-source dst, a, b, c /
+ *     two-operand dst, a / dst, a, b; a branch names a label (or an index);
+ *   - a malformed line still yields its record: unknown mnemonic -> op
+ *     0xFFFF, an operand that is none of the above -> operand id 0xFFFD, a
+ *     malformed offset -> op 0xFFFF, an unknown label -> target 0x7FFFFFFF;
+ *     the analysis' record checks then fail that kernel.
+ * Labels are told apart by a 64-bit hash of their names (two names of one
+ * kernel with the same hash would be taken for one).
+ * `text` is device memory (n_bytes, no terminator needed); the outputs stay
+ * in device memory owned by the object (dc_text_device_arrays: descriptors
+ * with instr_begin / arg_begin into the record and argument arrays, ready for
+ * dc_analyze_batch) and are copied to the host by the getters.  opts may be
+ * NULL; its flags may hold DC_OPT_TIMING only.  The first run on a text sizes
+ * the arrays from its counts (three waits for the stream); dc_text_run on the
+ * same pointer and size allocates nothing and does not synchronise (a text
+ * changed in place to other counts makes the getters return
+ * DC_E_CAPACITY), on another it sizes them again. */
+typedef struct dc_text dc_text_t;
+typedef struct { uint32_t n_kernels, fail; uint64_t n_lines, n_instr, n_args; } dc_text_counts_t;
+dc_status_t dc_parse_text(dc_ctx_t *ctx, const char *text, uint64_t n_bytes, const dc_options_t *opts, void *stream,
+                          dc_text_t **out);
+dc_status_t dc_text_run(dc_text_t *t, const char *text, uint64_t n_bytes);
+dc_status_t dc_text_wait(dc_text_t *t);
+dc_status_t dc_text_get_counts(dc_text_t *t, dc_text_counts_t *out);
+dc_status_t dc_text_device_arrays(dc_text_t *t, const dc_kernel_t **kernels, const dc_instr_t **instrs,
+                                  const dc_arg_t **args);
+dc_status_t dc_text_get_kernels(dc_text_t *t, dc_kernel_t *buf, uint32_t cap, uint32_t *n_total);
+dc_status_t dc_text_get_records(dc_text_t *t, dc_instr_t *buf, uint64_t cap, uint64_t *n_total);
+dc_status_t dc_text_get_args(dc_text_t *t, dc_arg_t *buf, uint64_t cap, uint64_t *n_total);
+/* each kernel's name as a byte offset into the text and a length */
+dc_status_t dc_text_get_names(dc_text_t *t, uint64_t *name_off, uint32_t *name_len, uint32_t cap, uint32_t *n_total);
+/* stage times (needs DC_OPT_TIMING): ms_decode = line starts and kinds,
+ * ms_cfg = per-kernel counts, ms_fixpoint = labels, configuration and
+ * records, ms_compact = 0 */
+dc_status_t dc_text_get_timing(dc_text_t *t, dc_timing_t *out);
+dc_status_t dc_text_timing_reset(dc_text_t *t);
+void dc_text_free(dc_text_t *t);
+
+/* ------------------------------------------------------------------ */
 /* Register versions (minimal SSA form).                                */
 /* ------------------------------------------------------------------ */
 /* Section "Search for control structures": at a block with several
@@ -363,13 +433,14 @@ typedef struct {
                                     argument ((block << 24) | (slot << 12) | edge, version), 4 per use entry and
                                     5 per definition entry of the fixed layouts of dc_ssa_get_versions (index
                                     instruction * DC_SSA_NU + q, resp. * DC_SSA_ND + q, value the version or
-                                    DC_SSA_NONE); 0 for a failed kernel */
+                                    DC_SSA_NONE); 0 for a failed kernel or without DC_OPT_DIGEST */
 } dc_ssa_result_t;               /* 32 B */
 typedef struct dc_ssa dc_ssa_t;
 
 /* Versions for n_kernels kernels whose records are in `instrs` (device,
  * n_records entries): the graph stages of dc_build_cfg, then the versions,
- * on `stream`.  opts may be NULL; its flags may hold DC_OPT_TIMING only.
+ * on `stream`.  opts may be NULL; its flags may hold DC_OPT_TIMING and
+ * DC_OPT_DIGEST (without it dc_ssa_result_t.digest is 0).
  * The first run sizes the version tables from the graph (it waits for the
  * stream twice); dc_ssa_run on the same records allocates nothing and does
  * not synchronise, on other records it sizes them again. */

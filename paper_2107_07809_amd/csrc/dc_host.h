@@ -5,6 +5,8 @@
 #include <hip/hip_runtime_api.h>
 #include <stdint.h>
 
+#include <stdlib.h>
+
 #include <algorithm>
 #include <vector>
 
@@ -20,18 +22,28 @@ struct dc_ctx {
 
 namespace dc {
 
+/* Failure injection for tests: with DC_FAULT_ALLOC=n in the environment the
+ * n-th device allocation of every allocation list fails as if the device
+ * were out of memory (0 or unset: none). */
+inline uint64_t fault_alloc_nth() {
+    const char *e = getenv("DC_FAULT_ALLOC");
+    return e ? strtoull(e, nullptr, 10) : 0;
+}
+
 /* one device allocation list per object, freed together */
 struct DevMem {
     std::vector<void *> ptrs;
     bool failed = false;
     uint64_t bytes_total = 0;
+    uint64_t n_allocs = 0;
     template <typename T>
     T *alloc(uint64_t count) {
         void *p = nullptr;
         uint64_t bytes = count * sizeof(T);
         if (bytes == 0) bytes = 16;
         bytes = (bytes + 255) & ~255ull;
-        if (hipMalloc(&p, bytes) != hipSuccess) {
+        const uint64_t nth = fault_alloc_nth();
+        if (++n_allocs == nth || hipMalloc(&p, bytes) != hipSuccess) {
             failed = true;
             return nullptr;
         }

@@ -152,7 +152,45 @@ struct SsaPlan {
     uint64_t ops_cap;
     uint8_t *opn;                   /* per position: uses | definitions << 4 */
     dc_ssa_result_t *res;           /* K */
+    uint32_t digest;                /* compute the per-kernel digest */
 };
+/* Device arrays of a text front end run (dc_text.hip).  Sizes come from the
+ * counts of the first run on a text (line ends, .kernel lines, then per
+ * kernel instructions, label-table slots and user arguments). */
+struct TextPlan {
+    const uint8_t *text;            /* the listing (caller's device memory) */
+    uint64_t n_bytes;
+    uint32_t n_tiles;               /* 4 KiB tiles of text */
+    uint32_t *tile_cnt;             /* n_tiles: line ends per tile */
+    uint64_t *tile_off;             /* n_tiles + 1 */
+    uint64_t n_lines;               /* line ends + 1 */
+    uint64_t *line_start;           /* n_lines + 1 ([n_lines] = n_bytes + 1) */
+    uint8_t *kind;                  /* n_lines */
+    uint32_t n_ltiles;              /* tiles of 4096 lines */
+    uint32_t *ltile_cnt;            /* .kernel lines per line tile */
+    uint64_t *ltile_off;            /* n_ltiles + 1 */
+    uint32_t n_kernels, k_cap;
+    uint64_t *kline;                /* k_cap + 1: line of each .kernel; [K] = n_lines */
+    uint32_t *kcounts;              /* 3 x K: instructions, label-table slots, user arguments */
+    uint64_t *koffs;                /* 3 x (K + 1): exclusive scans of kcounts */
+    unsigned long long *lab_key;    /* lab_cap: hash of the label name (0 = empty) */
+    uint32_t *lab_idx;              /* lab_cap: instruction index the label names */
+    uint32_t *lab_line;             /* lab_cap: its line, relative to the kernel's first line */
+    uint64_t lab_cap;
+    dc_kernel_t *kernels;           /* k_cap */
+    uint64_t *name_off;             /* k_cap: byte offset of the kernel's name in the text */
+    uint32_t *name_len;             /* k_cap */
+    dc_instr_t *instrs;
+    uint64_t instr_cap;
+    dc_arg_t *args;
+    uint64_t arg_cap;
+    uint32_t *fail;                 /* set when the text does not fit the plan */
+};
+hipError_t launch_text_lines(const TextPlan &T, hipStream_t s);      /* line ends per tile, their scan */
+hipError_t launch_text_classify(const TextPlan &T, hipStream_t s);   /* line starts, kinds, .kernel counts */
+hipError_t launch_text_kernels1(const TextPlan &T, hipStream_t s);   /* kernel starts, per-kernel counts, scans */
+hipError_t launch_text_kernels2(const TextPlan &T, hipStream_t s);   /* labels, configuration, records */
+
 hipError_t launch_ssa_size(const Plan &P, const SsaPlan &S, hipStream_t s);    /* table sizes and offsets */
 hipError_t launch_ssa_graph(const Plan &P, const SsaPlan &S, hipStream_t s);   /* dominators, merges, numbering */
 hipError_t launch_ssa_emit(const Plan &P, const SsaPlan &S, hipStream_t s);    /* merges, arguments, versions */

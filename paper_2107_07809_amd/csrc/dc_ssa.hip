@@ -23,7 +23,7 @@
  *                and the version live at each block's end; output counts
  *   k_ssa_scan   exclusive scans of the per-kernel counts (offsets)
  *   k_ssa_emit   the merges with their arguments, every operand's version,
- *                the digest
+ *                the digest (when asked for)
  *
  * Merge placement without frontier lists: a join block b has the slot's
  * merge when some block on one of b's frontier walks (from each reachable
@@ -450,6 +450,7 @@ __global__ __launch_bounds__(64) void k_ssa_graph(Plan P, SsaPlan S) {
 /* ------------------------------------------------------------------ */
 /* k_ssa_emit                                                            */
 /* ------------------------------------------------------------------ */
+template <bool DIGEST>
 __global__ __launch_bounds__(64) void k_ssa_emit(Plan P, SsaPlan S) {
     __shared__ uint16_t s_rank[SLOTS_MAX], s_slot[SLOTS_MAX];
     __shared__ uint32_t s_cnt[SLOTS_MAX];
@@ -473,7 +474,8 @@ __global__ __launch_bounds__(64) void k_ssa_emit(Plan P, SsaPlan S) {
     const uint32_t *idom = S.idom + fb, *poff = P.pred_cnt + fb;
     const int32_t *pos = P.rpo_pos + fb;
     uint64_t h = 0;
-    for (uint32_t b = l; b < nb; b += 64) h += ssa_item(1, b, idom[b]);
+    if (DIGEST)
+        for (uint32_t b = l; b < nb; b += 64) h += ssa_item(1, b, idom[b]);
 
     /* merges (ascending block, then slot) and their arguments */
     uint32_t np = 0, na = 0;
@@ -496,12 +498,12 @@ __global__ __launch_bounds__(64) void k_ssa_emit(Plan P, SsaPlan S) {
                 f.pad = 0;
                 f.version = ver;
                 S.phis[po + idx] = f;
-                h += ssa_item(2, ((uint64_t)b << 16) | v, ver);
+                if (DIGEST) h += ssa_item(2, ((uint64_t)b << 16) | v, ver);
                 uint32_t *arg = S.phi_args + ao + na + (uint64_t)(idx - np_b) * inc;
                 uint32_t kk = 0;
                 if (b == 0) {
                     arg[0] = 0;
-                    h += ssa_item(3, ((uint64_t)b << 24) | ((uint64_t)v << 12), 0);
+                    if (DIGEST) h += ssa_item(3, ((uint64_t)b << 24) | ((uint64_t)v << 12), 0);
                     kk = 1;
                 }
                 for (uint32_t e = poff[b]; e < poff[b + 1]; e++) {
@@ -509,7 +511,7 @@ __global__ __launch_bounds__(64) void k_ssa_emit(Plan P, SsaPlan S) {
                     if (pos[p] < 0) continue;
                     const uint32_t x = Bt[(uint64_t)p * U + u];
                     arg[kk] = x;
-                    h += ssa_item(3, ((uint64_t)b << 24) | ((uint64_t)v << 12) | kk, x);
+                    if (DIGEST) h += ssa_item(3, ((uint64_t)b << 24) | ((uint64_t)v << 12) | kk, x);
                     kk++;
                 }
             }
@@ -559,7 +561,7 @@ __global__ __launch_bounds__(64) void k_ssa_emit(Plan P, SsaPlan S) {
                                            (uint32_t)__popcll(s_m2[r] & below);
                         const uint32_t ver = c ? base + ph + c - 1 : (ph ? base : (b == 0 ? 0u : Bt[prow + r]));
                         out[q] = ver;
-                        h += ssa_item(4, (uint64_t)i * DC_SSA_NU + q, ver);
+                        if (DIGEST) h += ssa_item(4, (uint64_t)i * DC_SSA_NU + q, ver);
                     });
                     for_defs(x, [&](uint32_t q, uint32_t v, uint32_t again) {
                         const uint32_t r = s_rank[v], a = A[row + r], base = a & ~PHI_BIT, ph = a >> 31;
@@ -567,20 +569,22 @@ __global__ __launch_bounds__(64) void k_ssa_emit(Plan P, SsaPlan S) {
                                            (uint32_t)__popcll(s_m2[r] & below) + again;
                         const uint32_t ver = base + ph + c;
                         out[nu + q] = ver;
-                        h += ssa_item(5, (uint64_t)i * DC_SSA_ND + q, ver);
+                        if (DIGEST) h += ssa_item(5, (uint64_t)i * DC_SSA_ND + q, ver);
                     });
                 } else {
                     for (uint32_t q = 0; q < nu; q++) {
                         out[q] = SSA_NONE;
-                        h += ssa_item(4, (uint64_t)i * DC_SSA_NU + q, SSA_NONE);
+                        if (DIGEST) h += ssa_item(4, (uint64_t)i * DC_SSA_NU + q, SSA_NONE);
                     }
                     for (uint32_t q = 0; q < nd; q++) {
                         out[nu + q] = SSA_NONE;
-                        h += ssa_item(5, (uint64_t)i * DC_SSA_ND + q, SSA_NONE);
+                        if (DIGEST) h += ssa_item(5, (uint64_t)i * DC_SSA_ND + q, SSA_NONE);
                     }
                 }
-                for (uint32_t q = nu; q < DC_SSA_NU; q++) h += ssa_item(4, (uint64_t)i * DC_SSA_NU + q, SSA_NONE);
-                for (uint32_t q = nd; q < DC_SSA_ND; q++) h += ssa_item(5, (uint64_t)i * DC_SSA_ND + q, SSA_NONE);
+                if (DIGEST) {
+                    for (uint32_t q = nu; q < DC_SSA_NU; q++) h += ssa_item(4, (uint64_t)i * DC_SSA_NU + q, SSA_NONE);
+                    for (uint32_t q = nd; q < DC_SSA_ND; q++) h += ssa_item(5, (uint64_t)i * DC_SSA_ND + q, SSA_NONE);
+                }
                 S.opn[pb + i] = (uint8_t)(nu | nd << 4);
             }
             __syncthreads();
@@ -595,7 +599,7 @@ __global__ __launch_bounds__(64) void k_ssa_emit(Plan P, SsaPlan S) {
             opos += tot;
         }
     }
-    h = wave_sum64(h);
+    if (DIGEST) h = wave_sum64(h);
     res.n_blocks = nb;
     res.n_phi = np;
     res.n_phi_args = na;
@@ -624,7 +628,8 @@ hipError_t launch_ssa_graph(const Plan &P, const SsaPlan &S, hipStream_t s) {
 hipError_t launch_ssa_emit(const Plan &P, const SsaPlan &S, hipStream_t s) {
     const uint32_t K = P.n_kernels;
     if (!K) return hipSuccess;
-    hipLaunchKernelGGL(k_ssa_emit, dim3(K), dim3(64), 0, s, P, S);
+    if (S.digest) hipLaunchKernelGGL(k_ssa_emit<true>, dim3(K), dim3(64), 0, s, P, S);
+    else hipLaunchKernelGGL(k_ssa_emit<false>, dim3(K), dim3(64), 0, s, P, S);
     return hipGetLastError();
 }
 

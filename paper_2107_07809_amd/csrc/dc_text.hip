@@ -1,0 +1,772 @@
+/*
+ * dc_text.hip -- the text front end (Section "The body extraction"): listings
+ * in the format of the paper's Listings 1-3 to kernel descriptors, 16-byte
+ * records and argument tables, for many kernels at once.
+ *
+ * The extraction loop the paper gives walks the lines one by one: a ".kernel"
+ * line opens a kernel (its second word is the name), ".config" and ".text"
+ * switch between collecting configuration lines and instruction lines.  Here
+ * every line is looked at by its own thread, and the loop's state at a line
+ * -- the last .config or .text marker since its kernel's .kernel line -- is a
+ * max-scan over the lines of that kernel.  Grammar (the paper fixes none;
+ * identical to the reading documented with dc_parse_text): comments from "//"
+ * or ";", blanks are space, tab and carriage return; ".dims"/"dims" x|xy|xyz;
+ * ".cws" up to three integers; ".useargs"; ".arg name, "ctype", type" with
+ * the six "_."-named hidden slots skipped and user arguments laid out from
+ * 0x30 at their natural alignment; "NAME:" lines are labels; every other
+ * line of the body is one instruction.
+ *
+ * Stages:
+ *   k_tx_count    per 4 KiB tile of text: its line ends
+ *   k_tx_scan     exclusive scans of per-tile or per-kernel counts
+ *   k_tx_lines    per tile: the start of every line
+ *   k_tx_classify per line: blank, .kernel, .config, .text, label, user
+ *                 argument, other (after removing comment and blanks)
+ *   k_tx_kcount / k_tx_klist  the .kernel lines (kernel starts)
+ *   k_tx_kernel1  one workgroup per kernel: extraction state of each line,
+ *                 counts of instructions, labels and user arguments
+ *   k_tx_kernel2  one workgroup per kernel: labels into the kernel's hash
+ *                 table, the configuration and argument table, one record
+ *                 per instruction line, the descriptor
+ */
+#include "dc_device.h"
+#include "dc_opnames.h"
+
+namespace dc {
+
+constexpr uint32_t TX_TILE = 4096;       /* bytes (or lines) per tile */
+constexpr uint32_t TX_T = 256;           /* threads of the per-kernel workgroups */
+constexpr uint16_t TX_BAD = 0xFFFD, TX_NONE = 0xFFFF, TX_LIT = 0xFFFE;
+enum : uint8_t { K_EMPTY, K_KERNEL, K_CONFIG, K_TEXT, K_LABEL, K_ARG, K_OTHER };
+
+static __constant__ char OPN[N_OPS][24] = {DC_OPNAME_LIST};
+
+/* ------------------------------------------------------------------ */
+/* spans of the text                                                     */
+/* ------------------------------------------------------------------ */
+struct Sp {
+    const uint8_t *p;
+    uint32_t n;
+};
+__device__ __forceinline__ bool blank(uint8_t c) { return c == ' ' || c == '\t' || c == '\r'; }
+__device__ __forceinline__ uint8_t lower(uint8_t c) { return (c >= 'A' && c <= 'Z') ? (uint8_t)(c - 'A' + 'a') : c; }
+__device__ Sp trim(Sp s) {
+    while (s.n && blank(s.p[s.n - 1])) s.n--;
+    while (s.n && blank(s.p[0])) {
+        s.p++;
+        s.n--;
+    }
+    return s;
+}
+/* the line without its comment and surrounding blanks */
+__device__ Sp clean(const uint8_t *p, uint32_t n) {
+    for (uint32_t i = 0; i < n; i++)
+        if (p[i] == ';' || (p[i] == '/' && i + 1 < n && p[i + 1] == '/')) {
+            n = i;
+            break;
+        }
+    return trim(Sp{p, n});
+}
+__device__ Sp word(Sp s, Sp *rest) {
+    uint32_t i = 0;
+    while (i < s.n && !blank(s.p[i])) i++;
+    if (rest) *rest = trim(Sp{s.p + i, s.n - i});
+    return Sp{s.p, i};
+}
+__device__ Sp field(Sp s, int k) {
+    uint32_t a = 0;
+    for (int f = 0;; f++) {
+        uint32_t b = a;
+        while (b < s.n && s.p[b] != ',') b++;
+        if (f == k) return trim(Sp{s.p + a, b - a});
+        if (b >= s.n) return Sp{s.p, 0};
+        a = b + 1;
+    }
+}
+__device__ int nfields(Sp s) {
+    if (!s.n) return 0;
+    int n = 1;
+    for (uint32_t i = 0; i < s.n; i++) n += s.p[i] == ',';
+    return n;
+}
+__device__ bool eq(Sp s, const char *lit) {
+    uint32_t i = 0;
+    for (; lit[i]; i++)
+        if (i >= s.n || s.p[i] != (uint8_t)lit[i]) return false;
+    return i == s.n;
+}
+__device__ bool ieq(Sp s, const char *lit) {
+    uint32_t i = 0;
+    for (; lit[i]; i++)
+        if (i >= s.n || lower(s.p[i]) != (uint8_t)lit[i]) return false;
+    return i == s.n;
+}
+__device__ bool same(Sp a, Sp b) {
+    if (a.n != b.n) return false;
+    for (uint32_t i = 0; i < a.n; i++)
+        if (a.p[i] != b.p[i]) return false;
+    return true;
+}
+/* integer: optional '-', then 0x hex digits or decimal digits */
+__device__ bool to_int(Sp s, int64_t *v) {
+    uint32_t i = 0;
+    bool neg = false;
+    if (i < s.n && s.p[i] == '-') {
+        neg = true;
+        i++;
+    }
+    if (i >= s.n) return false;
+    uint64_t x = 0;
+    if (i + 1 < s.n && s.p[i] == '0' && (s.p[i + 1] == 'x' || s.p[i + 1] == 'X')) {
+        i += 2;
+        if (i >= s.n) return false;
+        for (; i < s.n; i++) {
+            const uint8_t c = s.p[i];
+            const int d = c >= '0' && c <= '9' ? c - '0' : c >= 'a' && c <= 'f' ? c - 'a' + 10
+                        : c >= 'A' && c <= 'F' ? c - 'A' + 10 : -1;
+            if (d < 0 || (x >> 60)) return false;
+            x = x * 16 + (uint64_t)d;
+        }
+    } else {
+        for (; i < s.n; i++) {
+            const uint8_t c = s.p[i];
+            if (c < '0' || c > '9' || x > 100000000000000000ull) return false;
+            x = x * 10 + (uint64_t)(c - '0');
+        }
+    }
+    *v = neg ? -(int64_t)x : (int64_t)x;
+    return true;
+}
+__device__ uint64_t fnv(Sp s) {
+    uint64_t h = 0xcbf29ce484222325ull;
+    for (uint32_t i = 0; i < s.n; i++) h = (h ^ s.p[i]) * 0x100000001b3ull;
+    return h ? h : 1ull;
+}
+
+/* line j of the text (without its '\n'), cleaned; empty when the line
+ * table does not describe the text (it changed after planning) */
+__device__ Sp line_clean(const TextPlan &T, uint64_t j) {
+    const uint64_t s = T.line_start[j], e1 = T.line_start[j + 1];
+    if (e1 < s + 1 || e1 > T.n_bytes + 1) return Sp{T.text, 0};
+    return clean(T.text + s, (uint32_t)(e1 - 1 - s));
+}
+
+/* ------------------------------------------------------------------ */
+/* operands and records                                                  */
+/* ------------------------------------------------------------------ */
+__device__ uint16_t operand(Sp t, bool *has_lit, int32_t *lit) {
+    if (ieq(t, "vcc") || ieq(t, "vcc_lo")) return 104;
+    if (ieq(t, "vcc_hi")) return 105;
+    if (ieq(t, "exec") || ieq(t, "exec_lo")) return 106;
+    if (ieq(t, "exec_hi")) return 107;
+    if (ieq(t, "scc")) return 108;
+    if (ieq(t, "m0")) return 109;
+    if (ieq(t, "off")) return TX_NONE;
+    if (t.n >= 2 && (lower(t.p[0]) == 's' || lower(t.p[0]) == 'v')) {
+        const bool vec = lower(t.p[0]) == 'v';
+        const int64_t lim = vec ? 255 : 103;
+        int64_t a, b;
+        if (t.p[1] == '[') {
+            uint32_t c = 2;
+            while (c < t.n && t.p[c] != ':') c++;
+            if (c >= t.n || t.p[t.n - 1] != ']') return TX_BAD;
+            const Sp x{t.p + 2, c - 2}, y{t.p + c + 1, t.n - c - 2};
+            if (!to_int(x, &a) || !to_int(y, &b) || a < 0 || b < a || b > lim || x.p[0] == '-') return TX_BAD;
+        } else {
+            const Sp x{t.p + 1, t.n - 1};
+            if (x.p[0] == '-' || !to_int(x, &a) || a < 0 || a > lim) return TX_BAD;
+        }
+        return (uint16_t)(vec ? 112 + a : a);
+    }
+    const char *const fl[8] = {"0.5", "-0.5", "1.0", "-1.0", "2.0", "-2.0", "4.0", "-4.0"};
+    for (int i = 0; i < 8; i++)
+        if (eq(t, fl[i])) return (uint16_t)(0x8060 + i);
+    int64_t v;
+    if (!to_int(t, &v)) return TX_BAD;
+    if (v >= -16 && v <= 64) return (uint16_t)(0x8000 + (v + 16));
+    *has_lit = true;
+    *lit = (int32_t)(uint32_t)(uint64_t)v;
+    return TX_LIT;
+}
+
+/* the kernel's label table: open addressing on the name's hash */
+struct Labels {
+    unsigned long long *key;
+    uint32_t *idx;
+    uint32_t *line;       /* line of the definition, relative to the kernel's first line */
+    uint32_t cap;         /* power of two, or 0 */
+    const TextPlan *T;
+    uint64_t l0, l1;
+};
+__device__ Sp label_name(const Labels &L, uint32_t rel) {
+    if (L.l0 + rel >= L.l1) return Sp{L.T->text, 0};
+    Sp c = line_clean(*L.T, L.l0 + rel);
+    if (c.n) c.n--;   /* drop the ':' */
+    return c;
+}
+__device__ bool label_find(const Labels &L, Sp name, uint32_t *index) {
+    if (!L.cap) return false;
+    const uint64_t h = fnv(name);
+    for (uint32_t slot = (uint32_t)h & (L.cap - 1), n = 0; n < L.cap; slot = (slot + 1) & (L.cap - 1), n++) {
+        const unsigned long long k = __hip_atomic_load(&L.key[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (k == 0) return false;
+        if (k == h) {
+            const uint32_t rel = __hip_atomic_load(&L.line[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (!same(label_name(L, rel), name)) return false;
+            *index = __hip_atomic_load(&L.idx[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return true;
+        }
+    }
+    return false;
+}
+
+__device__ int find_op(Sp w, const char (*names)[24]) {
+    for (int op = 0; op < N_OPS; op++) {
+        const char *nm = names[op];
+        uint32_t i = 0;
+        for (; nm[i]; i++)
+            if (i >= w.n || lower(w.p[i]) != (uint8_t)nm[i]) break;
+        if (!nm[i] && i == w.n) return op;
+    }
+    return -1;
+}
+
+/* one instruction line -> record */
+__device__ dc_instr_t parse_instr(Sp line, const Labels &L, const char (*names)[24]) {
+    dc_instr_t r;
+    r.op = TX_NONE;
+    r.r0 = r.r1 = r.r2 = TX_NONE;
+    r.imm = 0;
+    r.target = -1;
+    Sp rest;
+    const Sp w = word(line, &rest);
+    const int op = find_op(w, names);
+    if (op < 0) return r;
+    r.op = (uint16_t)op;
+    const uint64_t e = OPTAB[op];
+    /* operand words (a comma-separated field's first word; without commas
+     * every word) and modifiers (key:value words without '['; offset:N) */
+    bool bad_num = false;
+    int nf = 0;
+    Sp f[8];
+    for (int k = 0; k < 8; k++) f[k] = Sp{rest.p, 0};
+    bool has_comma = false;
+    for (uint32_t i = 0; i < rest.n; i++) has_comma |= rest.p[i] == ',';
+    const int nfl = has_comma ? nfields(rest) : 1;
+    for (int k = 0; k < nfl; k++) {
+        Sp words = has_comma ? field(rest, k) : rest;
+        bool first = true;
+        while (words.n) {
+            Sp more;
+            const Sp mw = word(words, &more);
+            bool colon = false, bracket = false;
+            for (uint32_t i = 0; i < mw.n; i++) {
+                colon |= mw.p[i] == ':';
+                bracket |= mw.p[i] == '[';
+            }
+            if (colon && !bracket) {
+                if (mw.n > 7 && eq(Sp{mw.p, 7}, "offset:")) {
+                    int64_t v;
+                    if (to_int(Sp{mw.p + 7, mw.n - 7}, &v)) r.imm = (int32_t)(uint32_t)(uint64_t)v;
+                    else bad_num = true;
+                }
+            } else if (first || !has_comma) {
+                if (nf < 8) f[nf] = mw;
+                nf++;
+                first = false;
+            }
+            words = more;
+        }
+        if (has_comma && first) {
+            if (nf < 8) f[nf] = Sp{rest.p, 0};
+            nf++;
+        }
+    }
+    if (nf > 8) nf = 8;
+    bool has_lit = false;
+    int32_t lit = 0;
+    auto opd = [&](int k) -> uint16_t { return (k < nf && f[k].n) ? operand(f[k], &has_lit, &lit) : TX_BAD; };
+    const uint32_t cls = e_cls(e);
+    switch (cls) {
+    case C_SMEM: {
+        r.r0 = opd(0);
+        r.r1 = opd(1);
+        int64_t v;
+        if (nf > 2 && to_int(f[2], &v)) r.imm = (int32_t)(uint32_t)(uint64_t)v;
+        else bad_num = true;
+        break;
+    }
+    case C_BR:
+    case C_CBR: {
+        r.target = 0x7FFFFFFF;
+        if (nf > 0) {
+            uint32_t idx;
+            int64_t v;
+            if (label_find(L, f[0], &idx)) r.target = (int32_t)idx;
+            else if (to_int(f[0], &v) && v >= 0 && v < 0x7FFFFFFF) r.target = (int32_t)v;
+        }
+        break;
+    }
+    case C_NOP:
+    case C_END: break;
+    case C_SCMP:
+        r.r1 = opd(0);
+        r.r2 = opd(1);
+        break;
+    case C_VCMP:
+        r.r1 = opd(1);
+        r.r2 = opd(2);
+        break;
+    case C_GLD:
+        r.r0 = opd(0);
+        r.r1 = opd(1);
+        r.r2 = opd(2);
+        break;
+    case C_FLD:
+    case C_DSR:
+        r.r0 = opd(0);
+        r.r1 = opd(1);
+        break;
+    case C_GST:
+        r.r1 = opd(0);
+        r.r0 = opd(1);
+        r.r2 = opd(2);
+        break;
+    case C_FST:
+    case C_DSW:
+        r.r1 = opd(0);
+        r.r0 = opd(1);
+        break;
+    default:
+        if (cls == C_VALU && (e_idef(e) & IM_VCC)) {   /* dst, vcc, src0, src1 */
+            r.r0 = opd(0);
+            r.r1 = opd(2);
+            r.r2 = opd(3);
+        } else if (e_role(e, 3) != RO_NO) {            /* dst, src0, src1, src2 */
+            r.r0 = opd(0);
+            r.r1 = opd(1);
+            r.r2 = opd(2);
+            r.imm = (int32_t)opd(3);
+        } else if (e_role(e, 2) == RO_NO) {            /* dst, src */
+            r.r0 = opd(0);
+            r.r1 = opd(1);
+        } else {                                       /* dst, src0, src1 */
+            r.r0 = opd(0);
+            r.r1 = opd(1);
+            r.r2 = opd(2);
+        }
+    }
+    if (has_lit && !e_immoff(e) && e_role(e, 3) == RO_NO) r.imm = lit;
+    if (bad_num) r.op = TX_NONE;
+    return r;
+}
+
+/* .arg type: size, type bits, pointee bits */
+__device__ void arg_type(Sp t, uint16_t *size, uint8_t *type, uint8_t *flags) {
+    bool ptr = false;
+    if (t.n && t.p[t.n - 1] == '*') {
+        ptr = true;
+        t.n--;
+        t = trim(t);
+    }
+    const char *const names[12] = {"char", "uchar", "short", "ushort", "int", "uint", "long", "ulong",
+                                   "float", "double", "size_t", "void"};
+    const uint8_t bits[12] = {1, 2, 1, 2, 1, 2, 1, 2, 4, 8, 2, 0};
+    const uint16_t sizes[12] = {1, 1, 2, 2, 4, 4, 8, 8, 4, 8, 8, 4};
+    uint8_t b = 0;
+    uint16_t sz = 4;
+    for (int i = 0; i < 12; i++)
+        if (eq(t, names[i])) {
+            b = bits[i];
+            sz = sizes[i];
+            break;
+        }
+    if (ptr) {
+        *size = 8;
+        *type = 16;
+        *flags = b;
+    } else {
+        *size = sz;
+        *type = b;
+        *flags = 0;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* block-wide scans (TX_T threads)                                       */
+/* ------------------------------------------------------------------ */
+__device__ uint32_t block_excl_sum(uint32_t x, uint32_t *total, uint32_t *wsum) {
+    const uint32_t t = threadIdx.x, w = t >> 6, l = lane_id();
+    uint32_t y = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t z = __shfl_up(y, d, 64);
+        if (l >= (uint32_t)d) y += z;
+    }
+    if (l == 63) wsum[w] = y;
+    __syncthreads();
+    uint32_t before = 0, tot = 0;
+    for (uint32_t i = 0; i < TX_T / 64; i++) {
+        before += i < w ? wsum[i] : 0u;
+        tot += wsum[i];
+    }
+    __syncthreads();
+    *total = tot;
+    return before + y - x;
+}
+__device__ uint32_t block_incl_max(uint32_t x, uint32_t *all_max, uint32_t *wsum) {
+    const uint32_t t = threadIdx.x, w = t >> 6, l = lane_id();
+    uint32_t y = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t z = __shfl_up(y, d, 64);
+        if (l >= (uint32_t)d) y = max(y, z);
+    }
+    if (l == 63) wsum[w] = y;
+    __syncthreads();
+    uint32_t before = 0, tot = 0;
+    for (uint32_t i = 0; i < TX_T / 64; i++) {
+        before = i < w ? max(before, wsum[i]) : before;
+        tot = max(tot, wsum[i]);
+    }
+    __syncthreads();
+    *all_max = tot;
+    return max(before, y);
+}
+
+/* ------------------------------------------------------------------ */
+/* lines                                                                 */
+/* ------------------------------------------------------------------ */
+__global__ __launch_bounds__(256) void k_tx_count(TextPlan T) {
+    __shared__ uint32_t ws[4];
+    const uint64_t t0 = (uint64_t)blockIdx.x * TX_TILE;
+    uint32_t c = 0;
+    for (uint32_t i = threadIdx.x; i < TX_TILE; i += 256) {
+        const uint64_t g = t0 + i;
+        c += (g < T.n_bytes && T.text[g] == '\n') ? 1u : 0u;
+    }
+    uint32_t tot;
+    block_excl_sum(c, &tot, ws);
+    if (threadIdx.x == 0) T.tile_cnt[blockIdx.x] = tot;
+}
+
+/* exclusive scan of n counts into n + 1 offsets (one workgroup) */
+__global__ __launch_bounds__(1024) void k_tx_scan(const uint32_t *in, uint64_t *out, uint64_t n) {
+    const uint32_t t = threadIdx.x, w = t >> 6, l = lane_id();
+    __shared__ uint64_t wsum[16], carry;
+    if (t == 0) carry = 0;
+    __syncthreads();
+    for (uint64_t c = 0; c < n; c += 1024) {
+        const uint64_t i = c + t;
+        const uint64_t x = i < n ? in[i] : 0;
+        uint64_t y = x;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint64_t z = __shfl_up(y, d, 64);
+            if (l >= (uint32_t)d) y += z;
+        }
+        if (l == 63) wsum[w] = y;
+        __syncthreads();
+        uint64_t before = carry;
+        for (uint32_t j = 0; j < w; j++) before += wsum[j];
+        if (i < n) out[i] = before + y - x;
+        __syncthreads();
+        if (t == 1023) carry = before + y;
+        __syncthreads();
+    }
+    if (t == 0) out[n] = carry;
+}
+
+__global__ __launch_bounds__(256) void k_tx_lines(TextPlan T) {
+    __shared__ uint32_t ws[4];
+    const uint64_t t0 = (uint64_t)blockIdx.x * TX_TILE + (uint64_t)threadIdx.x * 16;
+    uint32_t c = 0;
+    for (uint32_t i = 0; i < 16; i++) {
+        const uint64_t g = t0 + i;
+        c += (g < T.n_bytes && T.text[g] == '\n') ? 1u : 0u;
+    }
+    uint32_t tot;
+    const uint32_t ex = block_excl_sum(c, &tot, ws);
+    uint64_t o = T.tile_off[blockIdx.x] + ex + 1;
+    for (uint32_t i = 0; i < 16; i++) {
+        const uint64_t g = t0 + i;
+        if (g < T.n_bytes && T.text[g] == '\n') {
+            if (o < T.n_lines) T.line_start[o] = g + 1;   /* more line ends than planned: flagged below */
+            o++;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        T.line_start[0] = 0;
+        T.line_start[T.n_lines] = T.n_bytes + 1;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_tx_classify(TextPlan T) {
+    for (uint64_t j = (uint64_t)blockIdx.x * 256 + threadIdx.x; j < T.n_lines; j += (uint64_t)gridDim.x * 256) {
+        const Sp c = line_clean(T, j);
+        uint8_t kd = K_EMPTY;
+        if (c.n) {
+            Sp rest;
+            const Sp w = word(c, &rest);
+            if (eq(w, ".kernel")) kd = K_KERNEL;
+            else if (eq(c, ".config")) kd = K_CONFIG;
+            else if (eq(c, ".text")) kd = K_TEXT;
+            else if (c.p[c.n - 1] == ':' && rest.n == 0) kd = K_LABEL;
+            else if (eq(w, ".arg")) {
+                const Sp nm = field(rest, 0);
+                kd = (nm.n >= 2 && nm.p[0] == '_' && nm.p[1] == '.') ? K_OTHER : K_ARG;
+            } else kd = K_OTHER;
+        }
+        T.kind[j] = kd;
+    }
+}
+
+/* .kernel lines: count per tile of lines, then their indices */
+__global__ __launch_bounds__(256) void k_tx_kcount(TextPlan T) {
+    __shared__ uint32_t ws[4];
+    const uint64_t t0 = (uint64_t)blockIdx.x * TX_TILE;
+    uint32_t c = 0;
+    for (uint32_t i = threadIdx.x; i < TX_TILE; i += 256) {
+        const uint64_t j = t0 + i;
+        c += (j < T.n_lines && T.kind[j] == K_KERNEL) ? 1u : 0u;
+    }
+    uint32_t tot;
+    block_excl_sum(c, &tot, ws);
+    if (threadIdx.x == 0) T.ltile_cnt[blockIdx.x] = tot;
+}
+__global__ __launch_bounds__(256) void k_tx_klist(TextPlan T) {
+    __shared__ uint32_t ws[4];
+    const uint64_t t0 = (uint64_t)blockIdx.x * TX_TILE + (uint64_t)threadIdx.x * 16;
+    uint32_t c = 0;
+    for (uint32_t i = 0; i < 16; i++) {
+        const uint64_t j = t0 + i;
+        c += (j < T.n_lines && T.kind[j] == K_KERNEL) ? 1u : 0u;
+    }
+    uint32_t tot;
+    const uint32_t ex = block_excl_sum(c, &tot, ws);
+    uint64_t o = T.ltile_off[blockIdx.x] + ex;
+    for (uint32_t i = 0; i < 16; i++) {
+        const uint64_t j = t0 + i;
+        if (j < T.n_lines && T.kind[j] == K_KERNEL) {
+            if (o < T.k_cap) T.kline[o] = j;
+            o++;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && T.n_kernels <= T.k_cap) T.kline[T.n_kernels] = T.n_lines;
+}
+
+/* the text has the line and kernel counts it was planned for (else every
+ * later stage stops and the run reports DC_E_CAPACITY) */
+__global__ void k_tx_check(TextPlan T) {
+    if (threadIdx.x == 0 && (T.tile_off[T.n_tiles] + 1 != T.n_lines || T.ltile_off[T.n_ltiles] != T.n_kernels))
+        atomicOr(T.fail, 1u);
+}
+
+/* the extraction state of a chunk of a kernel's lines: 1 config, 2 text,
+ * 0 before either (marker = (relative line + 1) << 2 | state) */
+__device__ uint32_t chunk_state(uint8_t kd, uint32_t rel, uint32_t *carry, uint32_t *ws) {
+    const uint32_t m = kd == K_CONFIG ? ((rel + 1) << 2 | 1u) : kd == K_TEXT ? ((rel + 1) << 2 | 2u) : 0u;
+    uint32_t all;
+    const uint32_t mm = block_incl_max(m, &all, ws);
+    const uint32_t st = mm ? (mm & 3u) : *carry;
+    __syncthreads();
+    if (all) *carry = all & 3u;
+    return st;
+}
+
+__global__ __launch_bounds__(TX_T) void k_tx_kernel1(TextPlan T) {
+    __shared__ uint32_t ws[4];
+    const uint32_t k = blockIdx.x, K = T.n_kernels;
+    if (k >= K || K > T.k_cap || *T.fail) return;
+    const uint64_t l0 = T.kline[k] + 1, l1 = T.kline[k + 1];
+    uint32_t carry = 0, ni = 0, nl = 0, na = 0;
+    for (uint64_t c = l0; c < l1; c += TX_T) {
+        const uint64_t j = c + threadIdx.x;
+        const bool act = j < l1;
+        const uint8_t kd = act ? T.kind[j] : K_EMPTY;
+        const uint32_t st = chunk_state(kd, (uint32_t)(j - l0), &carry, ws);
+        const uint32_t is_i = act && st == 2 && (kd == K_OTHER || kd == K_ARG);
+        const uint32_t is_l = act && st == 2 && kd == K_LABEL;
+        const uint32_t is_a = act && st == 1 && kd == K_ARG;
+        uint32_t a, b, d;
+        block_excl_sum(is_i, &a, ws);
+        block_excl_sum(is_l, &b, ws);
+        block_excl_sum(is_a, &d, ws);
+        ni += a;
+        nl += b;
+        na += d;
+    }
+    if (threadIdx.x == 0) {
+        T.kcounts[k] = ni;
+        uint32_t cap = 0;
+        if (nl) {
+            cap = 2;
+            while (cap < 2 * nl) cap <<= 1;
+        }
+        T.kcounts[(uint64_t)K + k] = cap;
+        T.kcounts[2ull * K + k] = na;
+    }
+}
+
+__global__ __launch_bounds__(TX_T) void k_tx_kernel2(TextPlan T) {
+    __shared__ uint32_t ws[4];
+    __shared__ char names[N_OPS][24];
+    __shared__ uint32_t s_dims, s_cws, s_use;
+    const uint32_t k = blockIdx.x, K = T.n_kernels, t = threadIdx.x;
+    if (k >= K || K > T.k_cap || *T.fail) return;
+    for (uint32_t i = t; i < N_OPS * 24; i += TX_T) (&names[0][0])[i] = (&OPN[0][0])[i];
+    if (t == 0) {
+        s_dims = s_cws = s_use = 0;
+    }
+    const uint64_t l0 = T.kline[k] + 1, l1 = T.kline[k + 1];
+    const uint64_t ib = T.koffs[k], lb = T.koffs[(uint64_t)(K + 1) + k], ab = T.koffs[2ull * (K + 1) + k];
+    const uint32_t ni = T.kcounts[k], cap = T.kcounts[(uint64_t)K + k], na = T.kcounts[2ull * K + k];
+    const bool fits = ib + ni <= T.instr_cap && lb + cap <= T.lab_cap && ab + na <= T.arg_cap;
+    if (!fits) {
+        if (t == 0) atomicOr(T.fail, 1u);
+        return;
+    }
+    Labels L{T.lab_key + lb, T.lab_idx + lb, T.lab_line + lb, cap, &T, l0, l1};
+    __syncthreads();
+    /* labels, configuration lines, argument order */
+    uint32_t carry = 0, icount = 0, acount = 0;
+    for (uint64_t c = l0; c < l1; c += TX_T) {
+        const uint64_t j = c + t;
+        const bool act = j < l1;
+        const uint8_t kd = act ? T.kind[j] : K_EMPTY;
+        const uint32_t rel = (uint32_t)(j - l0);
+        const uint32_t st = chunk_state(kd, rel, &carry, ws);
+        const uint32_t is_i = act && st == 2 && (kd == K_OTHER || kd == K_ARG);
+        const uint32_t is_a = act && st == 1 && kd == K_ARG;
+        uint32_t ti, ta;
+        const uint32_t xi = block_excl_sum(is_i, &ti, ws);
+        const uint32_t xa = block_excl_sum(is_a, &ta, ws);
+        if (act && st == 2 && kd == K_LABEL) {
+            const Sp nm = label_name(L, rel);
+            const uint64_t h = fnv(nm);
+            for (uint32_t slot = (uint32_t)h & (cap - 1), n = 0; n < cap; slot = (slot + 1) & (cap - 1), n++) {
+                const unsigned long long old = atomicCAS(&L.key[slot], 0ull, (unsigned long long)h);
+                if (old == 0 || old == h) {
+                    atomicMin(&L.idx[slot], icount + xi);
+                    atomicMin(&L.line[slot], rel);
+                    break;
+                }
+            }
+        }
+        if (act && st == 1 && kd == K_OTHER) {
+            const Sp w = word(line_clean(T, j), nullptr);
+            if (eq(w, ".dims") || eq(w, "dims")) atomicMax(&s_dims, rel + 1);
+            else if (eq(w, ".cws")) atomicMax(&s_cws, rel + 1);
+            else if (eq(w, ".useargs")) atomicOr(&s_use, 1u);
+        }
+        if (is_a && acount + xa < na) T.args[ab + acount + xa].offset = rel;   /* the line, until the layout pass */
+        icount += ti;
+        acount += ta;
+    }
+    __threadfence();
+    __syncthreads();
+    /* records */
+    carry = 0;
+    icount = 0;
+    for (uint64_t c = l0; c < l1; c += TX_T) {
+        const uint64_t j = c + t;
+        const bool act = j < l1;
+        const uint8_t kd = act ? T.kind[j] : K_EMPTY;
+        const uint32_t st = chunk_state(kd, (uint32_t)(j - l0), &carry, ws);
+        const uint32_t is_i = act && st == 2 && (kd == K_OTHER || kd == K_ARG);
+        uint32_t ti;
+        const uint32_t xi = block_excl_sum(is_i, &ti, ws);
+        if (is_i && icount + xi < ni) T.instrs[ib + icount + xi] = parse_instr(line_clean(T, j), L, names);
+        icount += ti;
+    }
+    __syncthreads();
+    if (t != 0) return;
+    /* configuration, argument layout, descriptor, name (one thread) */
+    dc_kernel_t D;
+    D.instr_begin = ib;
+    D.n_instr = ni;
+    D.dims = 0;
+    D.useargs = (uint8_t)s_use;
+    D.n_args = (uint16_t)na;
+    D.cws[0] = D.cws[1] = D.cws[2] = 0;
+    D.arg_begin = (uint32_t)ab;
+    auto line_at = [&](uint32_t rel) { return l0 + rel < l1 ? line_clean(T, l0 + rel) : Sp{T.text, 0}; };
+    if (s_dims) {
+        Sp rest;
+        word(line_at(s_dims - 1), &rest);
+        const Sp d = word(rest, nullptr);
+        D.dims = eq(d, "x") ? 1 : eq(d, "xy") ? 2 : eq(d, "xyz") ? 3 : 0;
+    }
+    if (s_cws) {
+        Sp rest;
+        word(line_at(s_cws - 1), &rest);
+        for (int d = 0; d < 3; d++) {
+            const Sp v = field(rest, d);
+            int64_t x;
+            D.cws[d] = v.n == 0 ? 1u : (to_int(v, &x) && x >= 0 && x <= 0xFFFFFFFFll ? (uint32_t)x : 0u);
+        }
+    }
+    uint32_t cursor = 0x30;
+    for (uint32_t a = 0; a < na; a++) {
+        dc_arg_t *A = &T.args[ab + a];
+        Sp rest;
+        word(line_at(A->offset), &rest);
+        dc_arg_t out;
+        arg_type(field(rest, 2), &out.size, &out.type, &out.flags);
+        cursor = (cursor + out.size - 1) / out.size * out.size;
+        out.offset = cursor;
+        cursor += out.size;
+        *A = out;
+    }
+    T.kernels[k] = D;
+    {
+        Sp rest;
+        word(line_clean(T, l0 - 1), &rest);
+        const Sp nm = word(rest, nullptr);
+        T.name_off[k] = (uint64_t)(nm.p - T.text);
+        T.name_len[k] = nm.n;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* launchers                                                             */
+/* ------------------------------------------------------------------ */
+static uint32_t tx_grid(uint64_t n) {
+    const uint64_t g = (n + 255) / 256;
+    return g < 1 ? 1u : g > (1u << 20) ? (1u << 20) : (uint32_t)g;
+}
+
+hipError_t launch_text_lines(const TextPlan &T, hipStream_t s) {
+    hipLaunchKernelGGL(k_tx_count, dim3(T.n_tiles), dim3(256), 0, s, T);
+    hipLaunchKernelGGL(k_tx_scan, dim3(1), dim3(1024), 0, s, T.tile_cnt, T.tile_off, (uint64_t)T.n_tiles);
+    return hipGetLastError();
+}
+hipError_t launch_text_classify(const TextPlan &T, hipStream_t s) {
+    hipLaunchKernelGGL(k_tx_lines, dim3(T.n_tiles), dim3(256), 0, s, T);
+    hipLaunchKernelGGL(k_tx_classify, dim3(tx_grid(T.n_lines)), dim3(256), 0, s, T);
+    hipLaunchKernelGGL(k_tx_kcount, dim3(T.n_ltiles), dim3(256), 0, s, T);
+    hipLaunchKernelGGL(k_tx_scan, dim3(1), dim3(1024), 0, s, T.ltile_cnt, T.ltile_off, (uint64_t)T.n_ltiles);
+    return hipGetLastError();
+}
+hipError_t launch_text_kernels1(const TextPlan &T, hipStream_t s) {
+    hipLaunchKernelGGL(k_tx_check, dim3(1), dim3(64), 0, s, T);
+    hipLaunchKernelGGL(k_tx_klist, dim3(T.n_ltiles), dim3(256), 0, s, T);
+    if (T.n_kernels) {
+        hipLaunchKernelGGL(k_tx_kernel1, dim3(T.n_kernels), dim3(TX_T), 0, s, T);
+        for (int a = 0; a < 3; a++)
+            hipLaunchKernelGGL(k_tx_scan, dim3(1), dim3(1024), 0, s, T.kcounts + (uint64_t)a * T.n_kernels,
+                               T.koffs + (uint64_t)a * (T.n_kernels + 1), (uint64_t)T.n_kernels);
+    }
+    return hipGetLastError();
+}
+hipError_t launch_text_kernels2(const TextPlan &T, hipStream_t s) {
+    if (!T.n_kernels) return hipSuccess;
+    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(T.lab_key), 2 * T.lab_cap, 0u, s);
+    if (e == hipSuccess) e = launch_fill_u32(T.lab_idx, T.lab_cap, 0xFFFFFFFFu, s);
+    if (e == hipSuccess) e = launch_fill_u32(T.lab_line, T.lab_cap, 0xFFFFFFFFu, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_tx_kernel2, dim3(T.n_kernels), dim3(TX_T), 0, s, T);
+    return hipGetLastError();
+}
+
+}  // namespace dc

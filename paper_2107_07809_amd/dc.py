@@ -83,6 +83,11 @@ class Timing(ctypes.Structure):
                 ("ms_compact", ctypes.c_float), ("ms_pad", ctypes.c_float)]
 
 
+class TextCounts(ctypes.Structure):
+    _fields_ = [("n_kernels", ctypes.c_uint32), ("fail", ctypes.c_uint32), ("n_lines", ctypes.c_uint64),
+                ("n_instr", ctypes.c_uint64), ("n_args", ctypes.c_uint64)]
+
+
 class CfgView(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("n_blocks", ctypes.c_uint32), ("n_reach", ctypes.c_uint32),
                 ("n_pred", ctypes.c_uint32), ("block_start", ctypes.POINTER(ctypes.c_uint32)),
@@ -118,6 +123,18 @@ SIGNATURES = [
     ("dc_timing_reset", I32, [VP]),
     ("dc_batch_free", None, [VP]),
     ("dc_analyze_noalloc", I32, [VP, VP, U32, U32, VP, U64, VP, U64, U32, VP, VP, U32, VP, VP, U32, VP, VP]),
+    ("dc_parse_text", I32, [VP, VP, U64, ctypes.POINTER(Options), VP, ctypes.POINTER(VP)]),
+    ("dc_text_run", I32, [VP, VP, U64]),
+    ("dc_text_wait", I32, [VP]),
+    ("dc_text_get_counts", I32, [VP, ctypes.POINTER(TextCounts)]),
+    ("dc_text_device_arrays", I32, [VP, ctypes.POINTER(VP), ctypes.POINTER(VP), ctypes.POINTER(VP)]),
+    ("dc_text_get_kernels", I32, [VP, VP, U32, ctypes.POINTER(U32)]),
+    ("dc_text_get_records", I32, [VP, VP, U64, ctypes.POINTER(U64)]),
+    ("dc_text_get_args", I32, [VP, VP, U64, ctypes.POINTER(U64)]),
+    ("dc_text_get_names", I32, [VP, VP, VP, U32, ctypes.POINTER(U32)]),
+    ("dc_text_get_timing", I32, [VP, ctypes.POINTER(Timing)]),
+    ("dc_text_timing_reset", I32, [VP]),
+    ("dc_text_free", None, [VP]),
     ("dc_build_ssa", I32, [VP, VP, U32, VP, U64, ctypes.POINTER(Options), VP, ctypes.POINTER(VP)]),
     ("dc_ssa_run", I32, [VP, VP]),
     ("dc_ssa_wait", I32, [VP]),
@@ -181,6 +198,21 @@ def _np_ptr(a):
     return a.ctypes.data if a is not None and a.size else None
 
 
+class DevicePtr:
+    """A raw device address owned elsewhere (e.g. a library object's output
+    array), usable wherever a device tensor is taken."""
+
+    def __init__(self, addr: int, owner=None):
+        self.addr = addr
+        self.owner = owner      # keeps the owning object alive
+
+    def data_ptr(self) -> int:
+        return self.addr
+
+    def numel(self) -> int:
+        return 1 if self.addr else 0
+
+
 def _dev_ptr(t):
     return t.data_ptr() if t is not None and t.numel() else None
 
@@ -189,6 +221,13 @@ def _stream_ptr(stream):
     if stream is None:
         return None
     return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def text_to_device(text: bytes, device="cuda:0"):
+    """A listing's bytes as a uint8 tensor on the device (at least one byte)."""
+    import torch
+    buf = np.frombuffer(text, np.uint8) if text else np.zeros(1, np.uint8)
+    return torch.from_numpy(buf.copy()).to(device)
 
 
 def to_device(records: np.ndarray, device="cuda:0"):
@@ -260,10 +299,20 @@ class Context:
                                                  n_records, _stream_ptr(stream), ctypes.byref(h)))
         return Cfg(h, len(kernels))
 
-    def build_ssa(self, kernels, instrs_dev, n_records, timing=False, stream=None) -> "Ssa":
-        kernels = np.ascontiguousarray(np.asarray(kernels, KERNEL_DTYPE))
+    def parse_text(self, text_dev, n_bytes, timing=False, stream=None) -> "Text":
+        """The text front end on a listing already in device memory (a uint8
+        tensor, see text_to_device)."""
         o = Options()
         o.flags = OPT_TIMING if timing else 0
+        h = VP()
+        check("dc_parse_text", lib().dc_parse_text(self.h, _dev_ptr(text_dev), n_bytes, ctypes.byref(o),
+                                                   _stream_ptr(stream), ctypes.byref(h)))
+        return Text(h, text_dev, n_bytes)
+
+    def build_ssa(self, kernels, instrs_dev, n_records, timing=False, digest=True, stream=None) -> "Ssa":
+        kernels = np.ascontiguousarray(np.asarray(kernels, KERNEL_DTYPE))
+        o = Options()
+        o.flags = (OPT_TIMING if timing else 0) | (OPT_DIGEST if digest else 0)
         h = VP()
         check("dc_build_ssa", lib().dc_build_ssa(self.h, _np_ptr(kernels), len(kernels), _dev_ptr(instrs_dev),
                                                  n_records, ctypes.byref(o), _stream_ptr(stream), ctypes.byref(h)))
@@ -527,6 +576,88 @@ class Ssa:
     def free(self):
         if self.h:
             lib().dc_ssa_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Text:
+    """A text front end run (dc_parse_text): descriptors, records, argument
+    tables and kernel names of a listing."""
+
+    def __init__(self, h, text_dev, n_bytes):
+        self.h = h
+        self._keep = text_dev
+        self.n_bytes = n_bytes
+
+    def run(self, text_dev=None, n_bytes=None):
+        if text_dev is not None:
+            self._keep = text_dev
+            self.n_bytes = n_bytes
+        check("dc_text_run", lib().dc_text_run(self.h, _dev_ptr(self._keep), self.n_bytes))
+
+    def wait(self):
+        check("dc_text_wait", lib().dc_text_wait(self.h))
+
+    def counts(self) -> dict:
+        c = TextCounts()
+        check("dc_text_get_counts", lib().dc_text_get_counts(self.h, ctypes.byref(c)))
+        return {k: getattr(c, k) for k, _ in c._fields_}
+
+    def device_arrays(self):
+        """(descriptors, records, arguments) as DevicePtr to the object's
+        device arrays (valid until free)."""
+        k, i, a = VP(), VP(), VP()
+        check("dc_text_device_arrays", lib().dc_text_device_arrays(self.h, ctypes.byref(k), ctypes.byref(i),
+                                                                   ctypes.byref(a)))
+        return DevicePtr(k.value or 0, self), DevicePtr(i.value or 0, self), DevicePtr(a.value or 0, self)
+
+    def kernels(self) -> np.ndarray:
+        n = U32()
+        check("dc_text_get_kernels", lib().dc_text_get_kernels(self.h, None, 0, ctypes.byref(n)))
+        out = np.zeros(n.value, KERNEL_DTYPE)
+        check("dc_text_get_kernels", lib().dc_text_get_kernels(self.h, _np_ptr(out), n.value, ctypes.byref(n)))
+        return out
+
+    def records(self) -> np.ndarray:
+        n = U64()
+        check("dc_text_get_records", lib().dc_text_get_records(self.h, None, 0, ctypes.byref(n)))
+        out = np.zeros(n.value, INSTR_DTYPE)
+        check("dc_text_get_records", lib().dc_text_get_records(self.h, _np_ptr(out), n.value, ctypes.byref(n)))
+        return out
+
+    def args(self) -> np.ndarray:
+        n = U64()
+        check("dc_text_get_args", lib().dc_text_get_args(self.h, None, 0, ctypes.byref(n)))
+        out = np.zeros(n.value, ARG_DTYPE)
+        check("dc_text_get_args", lib().dc_text_get_args(self.h, _np_ptr(out), n.value, ctypes.byref(n)))
+        return out
+
+    def names(self):
+        """(byte offsets, lengths) of the kernels' names in the text."""
+        n = U32()
+        check("dc_text_get_names", lib().dc_text_get_names(self.h, None, None, 0, ctypes.byref(n)))
+        off = np.zeros(n.value, np.uint64)
+        ln = np.zeros(n.value, np.uint32)
+        check("dc_text_get_names", lib().dc_text_get_names(self.h, _np_ptr(off), _np_ptr(ln), n.value,
+                                                           ctypes.byref(n)))
+        return off, ln
+
+    def timing(self) -> dict:
+        t = Timing()
+        check("dc_text_get_timing", lib().dc_text_get_timing(self.h, ctypes.byref(t)))
+        return {k: getattr(t, k) for k, _ in t._fields_ if k not in ("pad", "ms_pad", "ms_compact")}
+
+    def timing_reset(self):
+        check("dc_text_timing_reset", lib().dc_text_timing_reset(self.h))
+
+    def free(self):
+        if self.h:
+            lib().dc_text_free(self.h)
             self.h = None
 
     def __del__(self):

@@ -50,24 +50,7 @@ LISTING3 = b""".kernel copy
 """
 
 
-def test_listing3_configuration_and_arguments():
-    r = oracle.parse_text(LISTING3)
-    assert r["names"] == [b"copy"]
-    k = r["kernels"][0]
-    assert (k["dims"], list(k["cws"]), k["useargs"], k["n_args"], k["n_instr"]) == (1, [64, 1, 1], 1, 2, 3)
-    # the six hidden slots take 0x00-0x2f; data is a pointer to int at 0x30,
-    # x an int at 0x38
-    assert r["args"].tolist() == [(0x30, 8, dcgen.T_PTR, dcgen.T_INT), (0x38, 4, dcgen.T_INT, 0)]
-    assert r["instrs"].tolist() == [rec("s_load_dwordx2", 2, 4, NONE, 0), rec("s_add_u32", 0, 4, 0),
-                                    rec("s_endpgm")]
-
-
-def test_argument_layout_alignment():
-    """User arguments follow the six hidden 8-byte slots from 0x30, each at
-    the next multiple of its size: an int at 0x30 puts the next pointer at
-    0x38; a char then a short then a double go to 0x3c, 0x3e, 0x40; unsigned
-    and float types give their bits; void* points to nothing."""
-    text = b""".kernel a
+ALIGN_TEXT = b""".kernel a
  .config
   .dims x
   .cws 64, 1, 1
@@ -83,18 +66,8 @@ def test_argument_layout_alignment():
  .text
   s_endpgm
 """
-    r = oracle.parse_text(text)
-    T = dcgen
-    assert r["args"].tolist() == [(0x30, 4, T.T_INT, 0), (0x38, 8, T.T_PTR, T.T_FLOAT), (0x40, 4, T.T_UINT, 0),
-                                  (0x44, 1, T.T_INT, 0), (0x46, 2, T.T_UINT, 0), (0x48, 8, T.T_DOUBLE, 0),
-                                  (0x50, 8, T.T_PTR, 0)]
 
-
-def test_listing1_structure():
-    """Listing 1: dims xyz (printed without the dot) and .cws 8, 8, 2 mean a
-    3-D range of 8x8x2 work-groups; other configuration lines are skipped;
-    the body ends at s_endpgm (whose trailing words are not operands)."""
-    text = b""".kernel k1
+LISTING1_TEXT = b""".kernel k1
     .config
         dims xyz
         .cws 8, 8, 2
@@ -103,17 +76,8 @@ def test_listing1_structure():
         v_mov_b32 v3, v0
         s_endpgm <- end of program
 """
-    r = oracle.parse_text(text)
-    k = r["kernels"][0]
-    assert (k["dims"], list(k["cws"]), k["useargs"], k["n_args"], k["n_instr"]) == (3, [8, 8, 2], 0, 0, 2)
-    assert r["instrs"].tolist() == [rec("v_mov_b32", 112 + 3, 112 + 0), rec("s_endpgm")]
 
-
-def test_extraction_states():
-    """Listing 2's loop: lines before the first .kernel and between .kernel
-    and .config are skipped; .config and .text switch the state (again and
-    again); a kernel without .text has no body; kernels follow one another."""
-    text = b"""garbage before
+STATES_TEXT = b"""garbage before
 s_nop 0
 .kernel a
   s_nop 0
@@ -134,20 +98,8 @@ s_nop 0
 L:
     s_branch L
 """
-    r = oracle.parse_text(text)
-    assert r["names"] == [b"a", b"b", b"c"]
-    ka, kb, kc = r["kernels"]
-    assert (ka["dims"], list(ka["cws"]), ka["useargs"], ka["n_instr"]) == (2, [16, 4, 1], 1, 2)
-    assert (kb["dims"], list(kb["cws"]), kb["n_instr"], kb["instr_begin"]) == (1, [0, 0, 0], 0, 2)
-    assert (kc["dims"], kc["n_instr"], kc["instr_begin"]) == (0, 1, 2)
-    assert r["instrs"].tolist() == [rec("s_nop"), rec("s_endpgm"), rec("s_branch", target=0)]
 
-
-def test_operand_syntax():
-    """Registers, specials, ranges, inline integers and floats, literals in
-    decimal and hex, saddr off, offsets, labels, blank-separated operands,
-    comments and carriage returns."""
-    text = b""".kernel t
+SYNTAX_TEXT = b""".kernel t
 .config
   .dims x
   .cws 64, 1, 1
@@ -185,6 +137,78 @@ END:
   // another
   s_endpgm
 """
+
+MALFORMED_TEXT = b""".kernel e
+.config
+  .dims x
+.text
+  s_frobnicate s0, s1
+  s_mov_b32 s104, s1
+  v_mov_b32 v256, v1
+  v_mov_b32 v1, v[4:3]
+  s_add_u32 s0, s1
+  ds_read_b32 v1, v2 offset:zz
+  s_branch NOWHERE
+  v_mul_f32 v1, 3.0, v2
+  s_endpgm
+"""
+
+
+def test_listing3_configuration_and_arguments():
+    r = oracle.parse_text(LISTING3)
+    assert r["names"] == [b"copy"]
+    k = r["kernels"][0]
+    assert (k["dims"], list(k["cws"]), k["useargs"], k["n_args"], k["n_instr"]) == (1, [64, 1, 1], 1, 2, 3)
+    # the six hidden slots take 0x00-0x2f; data is a pointer to int at 0x30,
+    # x an int at 0x38
+    assert r["args"].tolist() == [(0x30, 8, dcgen.T_PTR, dcgen.T_INT), (0x38, 4, dcgen.T_INT, 0)]
+    assert r["instrs"].tolist() == [rec("s_load_dwordx2", 2, 4, NONE, 0), rec("s_add_u32", 0, 4, 0),
+                                    rec("s_endpgm")]
+
+
+def test_argument_layout_alignment():
+    """User arguments follow the six hidden 8-byte slots from 0x30, each at
+    the next multiple of its size: an int at 0x30 puts the next pointer at
+    0x38; a char then a short then a double go to 0x3c, 0x3e, 0x40; unsigned
+    and float types give their bits; void* points to nothing."""
+    text = ALIGN_TEXT
+    r = oracle.parse_text(text)
+    T = dcgen
+    assert r["args"].tolist() == [(0x30, 4, T.T_INT, 0), (0x38, 8, T.T_PTR, T.T_FLOAT), (0x40, 4, T.T_UINT, 0),
+                                  (0x44, 1, T.T_INT, 0), (0x46, 2, T.T_UINT, 0), (0x48, 8, T.T_DOUBLE, 0),
+                                  (0x50, 8, T.T_PTR, 0)]
+
+
+def test_listing1_structure():
+    """Listing 1: dims xyz (printed without the dot) and .cws 8, 8, 2 mean a
+    3-D range of 8x8x2 work-groups; other configuration lines are skipped;
+    the body ends at s_endpgm (whose trailing words are not operands)."""
+    text = LISTING1_TEXT
+    r = oracle.parse_text(text)
+    k = r["kernels"][0]
+    assert (k["dims"], list(k["cws"]), k["useargs"], k["n_args"], k["n_instr"]) == (3, [8, 8, 2], 0, 0, 2)
+    assert r["instrs"].tolist() == [rec("v_mov_b32", 112 + 3, 112 + 0), rec("s_endpgm")]
+
+
+def test_extraction_states():
+    """Listing 2's loop: lines before the first .kernel and between .kernel
+    and .config are skipped; .config and .text switch the state (again and
+    again); a kernel without .text has no body; kernels follow one another."""
+    text = STATES_TEXT
+    r = oracle.parse_text(text)
+    assert r["names"] == [b"a", b"b", b"c"]
+    ka, kb, kc = r["kernels"]
+    assert (ka["dims"], list(ka["cws"]), ka["useargs"], ka["n_instr"]) == (2, [16, 4, 1], 1, 2)
+    assert (kb["dims"], list(kb["cws"]), kb["n_instr"], kb["instr_begin"]) == (1, [0, 0, 0], 0, 2)
+    assert (kc["dims"], kc["n_instr"], kc["instr_begin"]) == (0, 1, 2)
+    assert r["instrs"].tolist() == [rec("s_nop"), rec("s_endpgm"), rec("s_branch", target=0)]
+
+
+def test_operand_syntax():
+    """Registers, specials, ranges, inline integers and floats, literals in
+    decimal and hex, saddr off, offsets, labels, blank-separated operands,
+    comments and carriage returns."""
+    text = SYNTAX_TEXT
     r = oracle.parse_text(text)
     V = lambda n: 112 + n  # noqa: E731
     I = lambda v: 0x8000 + v + 16  # noqa: E731
@@ -212,20 +236,7 @@ def test_malformed_lines_become_failing_records():
     register out of range or a reversed range (operand 0xFFFD), a missing
     operand (0xFFFD), a malformed offset (opcode 0xFFFF), an unknown label
     (target 0x7FFFFFFF), a float other than the eight inline ones."""
-    text = b""".kernel e
-.config
-  .dims x
-.text
-  s_frobnicate s0, s1
-  s_mov_b32 s104, s1
-  v_mov_b32 v256, v1
-  v_mov_b32 v1, v[4:3]
-  s_add_u32 s0, s1
-  ds_read_b32 v1, v2 offset:zz
-  s_branch NOWHERE
-  v_mul_f32 v1, 3.0, v2
-  s_endpgm
-"""
+    text = MALFORMED_TEXT
     r = oracle.parse_text(text)
     got = r["instrs"].tolist()
     assert got[0][0] == NONE
@@ -250,17 +261,15 @@ def canonical(b):
     inline range [-16, 64] reads back as that inline constant (imm 0)."""
     r = b.instrs.copy()
     names = dcgen.op_names()
-    noimm = {i for i, n in enumerate(names) if n.startswith(("s_load", "global_", "flat_", "ds_"))
-             or n in ("v_mad_u32_u24", "v_mad_f32", "v_fma_f32", "v_fma_f64")}
-    for i in range(len(r)):
-        if r[i]["op"] in noimm:
-            continue
-        v = int(r[i]["imm"])
-        if -16 <= v <= 64 and LIT in (r[i]["r1"], r[i]["r2"]):
-            for f in ("r1", "r2"):
-                if r[i][f] == LIT:
-                    r[i][f] = 0x8000 + v + 16
-            r[i]["imm"] = 0
+    noimm = np.array([n.startswith(("s_load", "global_", "flat_", "ds_"))
+                      or n in ("v_mad_u32_u24", "v_mad_f32", "v_fma_f32", "v_fma_f64") for n in names] + [True] * 65536)
+    imm = r["imm"].astype(np.int64)
+    hit = ~noimm[r["op"]] & (imm >= -16) & (imm <= 64) & ((r["r1"] == LIT) | (r["r2"] == LIT))
+    inline = (0x8000 + imm + 16).astype(np.uint16)
+    for f in ("r1", "r2"):
+        m = hit & (r[f] == LIT)
+        r[f][m] = inline[m]
+    r["imm"][hit] = 0
     return r
 
 
@@ -283,3 +292,7 @@ def test_round_trip_generated_batches():
                 assert np.array_equal(r["args"][f], b.args[f]), f
         assert r["instrs"].tobytes() == canonical(b).tobytes()
         assert r["names"] == [f"k{k}".encode() for k in range(b.n_kernels)]
+
+
+# every hand-written listing above, for the GPU parser's parity test
+ALL_TEXTS = [LISTING3, ALIGN_TEXT, LISTING1_TEXT, STATES_TEXT, SYNTAX_TEXT, MALFORMED_TEXT]
