@@ -81,6 +81,11 @@ def lib():
         L.or_ssa_free.argtypes = [ctypes.c_void_p]
         L.or_ssa_batch.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p]
         L.or_ssa_batch.restype = ctypes.c_int
+        L.or_structure.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.or_structure.restype = ctypes.c_int
+        L.or_structure_free.argtypes = [ctypes.c_void_p]
+        L.or_structure_batch.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p]
+        L.or_structure_batch.restype = ctypes.c_int
         L.or_parse_text.argtypes = [ctypes.c_char_p, ctypes.c_uint64, ctypes.c_void_p]
         L.or_parse_text.restype = ctypes.c_int
         L.or_text_free.argtypes = [ctypes.c_void_p]
@@ -195,6 +200,39 @@ def ssa(recs, desc) -> dict:
                n_ver=np.array(R.n_ver[:], np.uint32), digest=R.digest)
     L.or_ssa_free(ctypes.byref(R))
     return out
+
+
+MERGE_DTYPE = np.dtype([("region", "<u4"), ("kind", "u1"), ("n", "u1"), ("pad", "<u2"), ("member", "<u4", (4,))])
+RG_LINEAR, RG_IF, RG_IFELSE, RG_WHILE, RG_LOOP = 1, 2, 3, 4, 5
+STRUCT_SUMMARY_DTYPE = np.dtype([("status", "<i4"), ("n_blocks", "<u4"), ("n_merges", "<u4"), ("n_left", "<u4"),
+                                 ("root", "<u4"), ("pad", "<u4"), ("digest", "<u8")])
+
+
+class _StructOut(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("n_blocks", ctypes.c_uint32), ("n_merges", ctypes.c_uint32),
+                ("n_left", ctypes.c_uint32), ("root", ctypes.c_uint32), ("pad", ctypes.c_uint32),
+                ("digest", ctypes.c_uint64), ("merges", ctypes.c_void_p)]
+
+
+def structure(recs, desc) -> dict:
+    """Region-graph structuring of one kernel: the merges in the order they
+    were made (new region, kind, members; blocks are regions 0..n_blocks-1),
+    the regions left, the root when one is left, and a digest."""
+    d = _desc(desc)
+    recs = np.ascontiguousarray(recs)
+    R = _StructOut()
+    L = lib()
+    L.or_structure(d.ctypes.data, _ptr(recs), ctypes.byref(R))
+    out = dict(status=R.status, n_blocks=R.n_blocks, n_left=R.n_left, root=R.root, digest=R.digest,
+               merges=_copy(R.merges, R.n_merges, MERGE_DTYPE))
+    L.or_structure_free(ctypes.byref(R))
+    return out
+
+
+def structure_batch(batch):
+    summ = np.zeros(batch.n_kernels, STRUCT_SUMMARY_DTYPE)
+    lib().or_structure_batch(_ptr(batch.kernels), batch.n_kernels, _ptr(batch.instrs), _ptr(summ))
+    return summ
 
 
 class _TextOut(ctypes.Structure):

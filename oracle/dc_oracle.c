@@ -1939,3 +1939,241 @@ void or_text_free(or_text_out *O) {
     free(O->kernels); free(O->instrs); free(O->args); free(O->name_off); free(O->name_len);
     memset(O, 0, sizeof(*O));
 }
+
+/* ------------------------------------------------------------------ */
+/* structuring (Section "Search for control structures")                */
+/* ------------------------------------------------------------------ */
+/* The region graph starts as the reachable blocks of the control flow graph
+ * (consecutive instructions of a block form one region).  A depth-first
+ * search from the entry region visits the regions in preorder (fall-through
+ * successor first); the first region that heads a known template has the
+ * template's regions merged into a new region; the search starts again until
+ * one region is left or no region heads a template.  Templates, checked in
+ * this order at a header H:
+ *   if-else  H's two successors A, B each have H as their only predecessor
+ *            and one common single successor J (not H, A, B); J joins the
+ *            merge when A and B are its only predecessors;
+ *   if       (Fig. 2) of H's two successors, T has H as only predecessor and
+ *            the other, F, as only successor; F joins the merge when H and T
+ *            are its only predecessors, else the merge is H and T (the two
+ *            cases of the Fig. 3 trace);
+ *   while    one successor B of H has H as only predecessor and H as only
+ *            successor: H and B merge, the back edge disappears;
+ *   linear   H's only successor S is not H, has H as only predecessor and at
+ *            most one successor of its own, or H among its successors (which
+ *            closes a loop: the merge has an edge to itself);
+ *   loop     H has an edge to itself: it disappears.
+ * The entry counts one predecessor more (the start), so it is never the
+ * inner region of a template.  The paper names the if and linear templates
+ * and several exec-mask forms of if-else whose figures are missing; if-else
+ * is read as the standard diamond, and while / loop are this reading's
+ * additions so that counted loops reduce. */
+enum { RG_LINEAR = 1, RG_IF = 2, RG_IFELSE = 3, RG_WHILE = 4, RG_LOOP = 5 };
+typedef struct { uint32_t region; uint8_t kind, n; uint16_t pad; uint32_t member[4]; } or_merge;   /* 24 B */
+typedef struct {
+    int32_t status;
+    uint32_t n_blocks, n_merges, n_left, root, pad;
+    uint64_t digest;
+    or_merge *merges;
+} or_struct_out;
+
+typedef struct {
+    uint32_t cap, entry, next;
+    int32_t *succ;      /* 2 per region, -1 none */
+    uint32_t *npred;    /* edges in (+1 for the entry) */
+    uint8_t *alive;
+} rg_t;
+
+static int rg_nsucc(const rg_t *g, uint32_t x) { return (g->succ[2 * x] >= 0) + (g->succ[2 * x + 1] >= 0); }
+static int32_t rg_only(const rg_t *g, uint32_t x) {   /* the single successor, or -1 */
+    if (rg_nsucc(g, x) != 1) return -1;
+    return g->succ[2 * x] >= 0 ? g->succ[2 * x] : g->succ[2 * x + 1];
+}
+static int rg_has(const rg_t *g, uint32_t x, uint32_t y) {
+    return g->succ[2 * x] == (int32_t)y || g->succ[2 * x + 1] == (int32_t)y;
+}
+
+/* merge members m[0..n) (m[0] the header) into a new region */
+static uint32_t rg_merge(rg_t *g, const uint32_t *m, int n, int kind) {
+    const uint32_t H = m[0], R = g->next++;
+    int32_t out[2] = {-1, -1};
+    int no = 0, self = 0;
+    uint32_t into_h = 0;   /* edges from members into H */
+    for (int i = 0; i < n; i++)
+        for (int e = 0; e < 2; e++) {
+            const int32_t y = g->succ[2 * m[i] + e];
+            if (y < 0) continue;
+            int inside = 0;
+            for (int j = 0; j < n; j++) inside |= (uint32_t)y == m[j];
+            if ((uint32_t)y == H) {
+                into_h++;
+                if (kind != RG_WHILE && kind != RG_LOOP && !self) {
+                    self = 1;
+                    if (no < 2) out[no++] = (int32_t)R;
+                }
+                continue;
+            }
+            if (inside) continue;
+            g->npred[y]--;
+            int dup = 0;
+            for (int k = 0; k < no; k++) dup |= out[k] == y;
+            if (!dup) {
+                g->npred[y]++;
+                if (no < 2) out[no++] = y;
+            }
+        }
+    g->succ[2 * R] = out[0];
+    g->succ[2 * R + 1] = out[1];
+    g->npred[R] = g->npred[H] - into_h + (uint32_t)self;
+    /* edges from outside into H now enter R (no other member has any) */
+    for (uint32_t x = 0; x < g->next - 1; x++) {
+        if (!g->alive[x]) continue;
+        int mem = 0;
+        for (int j = 0; j < n; j++) mem |= x == m[j];
+        if (mem) continue;
+        for (int e = 0; e < 2; e++)
+            if (g->succ[2 * x + e] == (int32_t)H) g->succ[2 * x + e] = (int32_t)R;
+    }
+    for (int i = 0; i < n; i++) g->alive[m[i]] = 0;
+    g->alive[R] = 1;
+    if (g->entry == H) g->entry = R;
+    return R;
+}
+
+/* the template headed by x: members into m, returns the kind (0 none) */
+static int rg_match(const rg_t *g, uint32_t x, uint32_t *m, int *n) {
+    const int32_t a = g->succ[2 * x], b = g->succ[2 * x + 1];
+    if (a >= 0 && b >= 0 && a != (int32_t)x && b != (int32_t)x) {
+        const int32_t ja = rg_only(g, (uint32_t)a), jb = rg_only(g, (uint32_t)b);
+        if (g->npred[a] == 1 && g->npred[b] == 1 && ja >= 0 && ja == jb && ja != (int32_t)x && ja != a && ja != b) {
+            m[0] = x; m[1] = (uint32_t)a; m[2] = (uint32_t)b; *n = 3;
+            if (g->npred[ja] == 2) { m[3] = (uint32_t)ja; *n = 4; }
+            return RG_IFELSE;
+        }
+        for (int k = 0; k < 2; k++) {
+            const int32_t t = k == 0 ? a : b, f = k == 0 ? b : a;
+            if (g->npred[t] == 1 && rg_only(g, (uint32_t)t) == f) {
+                m[0] = x; m[1] = (uint32_t)t; *n = 2;
+                if (g->npred[f] == 2) { m[2] = (uint32_t)f; *n = 3; }
+                return RG_IF;
+            }
+        }
+        for (int k = 0; k < 2; k++) {
+            const int32_t t = k == 0 ? a : b;
+            if (g->npred[t] == 1 && rg_only(g, (uint32_t)t) == (int32_t)x) {
+                m[0] = x; m[1] = (uint32_t)t; *n = 2;
+                return RG_WHILE;
+            }
+        }
+    }
+    const int32_t s = rg_only(g, x);
+    if (s >= 0 && s != (int32_t)x && g->npred[s] == 1 && (rg_nsucc(g, (uint32_t)s) <= 1 || rg_has(g, (uint32_t)s, x))) {
+        m[0] = x; m[1] = (uint32_t)s; *n = 2;
+        return RG_LINEAR;
+    }
+    if (rg_has(g, x, x)) {
+        m[0] = x; *n = 1;
+        return RG_LOOP;
+    }
+    return 0;
+}
+
+int or_structure(const or_kernel *K, const or_instr *I, or_struct_out *R) {
+    memset(R, 0, sizeof(*R));
+    R->status = or_kernel_status(K, I);
+    if (R->status != OK) return R->status;
+    cfg_t G;
+    build_cfg(I, K->n_instr, &G);
+    const uint32_t nb = G.n_blocks;
+    R->n_blocks = nb;
+    rg_t g;
+    g.cap = 3 * nb + 2;   /* merges: at most nb - 1 that join regions, and one loop per edge to itself */
+    g.entry = 0;
+    g.next = nb;
+    g.succ = (int32_t *)malloc(sizeof(int32_t) * 2 * g.cap);
+    g.npred = (uint32_t *)calloc(g.cap, sizeof(uint32_t));
+    g.alive = (uint8_t *)calloc(g.cap, 1);
+    for (uint32_t i = 0; i < 2 * g.cap; i++) g.succ[i] = -1;
+    for (uint32_t i = 0; i < G.n_reach; i++) g.alive[G.rpo[i]] = 1;
+    for (uint32_t b = 0; b < nb; b++) {
+        if (!g.alive[b]) continue;
+        g.succ[2 * b] = G.succ[2 * b];
+        g.succ[2 * b + 1] = G.succ[2 * b + 1];
+        for (int e = 0; e < 2; e++)
+            if (G.succ[2 * b + e] >= 0) g.npred[G.succ[2 * b + e]]++;
+    }
+    g.npred[0]++;   /* the start */
+    R->merges = (or_merge *)malloc(sizeof(or_merge) * (g.cap + 1));
+    uint32_t *order = (uint32_t *)malloc(sizeof(uint32_t) * g.cap), *stack = (uint32_t *)malloc(sizeof(uint32_t) * 2 * g.cap);
+    uint8_t *seen = (uint8_t *)malloc(g.cap);
+    uint32_t n_alive = G.n_reach;
+    while (n_alive > 1) {
+        /* preorder from the entry, fall-through successor first */
+        memset(seen, 0, g.cap);
+        uint32_t no = 0, sp = 0;
+        stack[sp++] = g.entry;
+        while (sp) {
+            const uint32_t x = stack[--sp];
+            if (seen[x]) continue;
+            seen[x] = 1;
+            order[no++] = x;
+            for (int e = 1; e >= 0; e--) {
+                const int32_t y = g.succ[2 * x + e];
+                if (y >= 0 && !seen[y]) stack[sp++] = (uint32_t)y;
+            }
+        }
+        int done = 0;
+        for (uint32_t i = 0; i < no && !done; i++) {
+            uint32_t m[4];
+            int n = 0;
+            const int kind = rg_match(&g, order[i], m, &n);
+            if (!kind) continue;
+            const uint32_t r = rg_merge(&g, m, n, kind);
+            or_merge *M = &R->merges[R->n_merges++];
+            memset(M, 0, sizeof(*M));
+            M->region = r;
+            M->kind = (uint8_t)kind;
+            M->n = (uint8_t)n;
+            for (int j = 0; j < 4; j++) M->member[j] = j < n ? m[j] : 0xFFFFFFFFu;
+            n_alive -= (uint32_t)n - 1;
+            done = 1;
+        }
+        if (!done) break;
+    }
+    R->n_left = n_alive;
+    R->root = n_alive == 1 ? g.entry : 0xFFFFFFFFu;
+    uint64_t h = 0;
+    for (uint32_t j = 0; j < R->n_merges; j++) {
+        const or_merge *M = &R->merges[j];
+        uint64_t v = ((uint64_t)M->kind << 56) ^ ((uint64_t)M->n << 48) ^ M->region;
+        for (int k = 0; k < 4; k++) v = mix64(v + M->member[k] + 0x9E3779B97F4A7C15ull * (uint64_t)(k + 1));
+        h += mix64(mix64(0x5354ull * 0x9E3779B97F4A7C15ull + j) ^ v);
+    }
+    R->digest = h;
+    free(order); free(stack); free(seen);
+    free(g.succ); free(g.npred); free(g.alive);
+    free_cfg(&G);
+    return OK;
+}
+
+void or_structure_free(or_struct_out *R) { free(R->merges); R->merges = 0; }
+
+/* Batch driver of the structuring: per kernel status, blocks, merges,
+ * regions left, root and digest. */
+typedef struct { int32_t status; uint32_t n_blocks, n_merges, n_left, root, pad; uint64_t digest; } or_struct_summary;
+
+int or_structure_batch(const or_kernel *kernels, uint32_t n_kernels, const or_instr *instrs, or_struct_summary *sum) {
+    for (uint32_t k = 0; k < n_kernels; k++) {
+        or_struct_out R;
+        or_structure(&kernels[k], instrs + kernels[k].instr_begin, &R);
+        sum[k].status = R.status;
+        sum[k].n_blocks = R.n_blocks;
+        sum[k].n_merges = R.n_merges;
+        sum[k].n_left = R.n_left;
+        sum[k].root = R.root;
+        sum[k].pad = 0;
+        sum[k].digest = R.digest;
+        or_structure_free(&R);
+    }
+    return 0;
+}
