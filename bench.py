@@ -336,6 +336,42 @@ def text_workload(ctx, b, stream, steps=5, cpu_kernels=2048):
             "cpu_oracle": {"bytes_per_s": len(sub) / cpu_dt, "cores": 1, "kernels": min(cpu_kernels, b.n_kernels)}}
 
 
+def struct_workload(ctx, b, stream, steps=5, cpu_kernels=2048):
+    """Region-graph structuring (dc_structure) of a workload: whole runs (the
+    graph stages, then one search per kernel) with the records in HBM, the
+    structuring's own time from HIP events; the oracle on one core over the
+    first cpu_kernels kernels."""
+    import torch
+    import oracle
+    from paper_2107_07809_amd import dc
+    dev = dc.to_device(b.instrs)
+    s = ctx.structure(b.kernels, dev, b.n_instr, timing=True, stream=stream)
+    s.run()
+    s.wait()
+    res0 = s.results()
+    s.timing_reset()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        s.run()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / steps
+    tm = s.timing()
+    res = s.results()
+    s.free()
+    sub = b.subset(np.arange(min(cpu_kernels, b.n_kernels)))
+    t = time.perf_counter()
+    osum = oracle.structure_batch(sub)
+    cpu_dt = time.perf_counter() - t
+    return {"instructions_per_s": b.n_instr / dt, "ms_per_step": dt * 1e3,
+            "struct_ms": tm["ms_fixpoint"] / max(1, tm["runs"]),
+            "graph_stages_ms": (tm["ms_decode"] + tm["ms_cfg"]) / max(1, tm["runs"]),
+            "merges": int(res["n_merges"].sum()), "kernels_reduced_to_one_region": int((res["n_left"] == 1).sum()),
+            "failed": int((res["status"] != 0).sum()), "rerun_identical": bool(res.tobytes() == res0.tobytes()),
+            "sample_matches_oracle": bool(res[:sub.n_kernels]["digest"].tobytes() == osum["digest"].tobytes()),
+            "cpu_oracle": {"instructions_per_s": sub.n_instr / cpu_dt, "cores": 1, "kernels": sub.n_kernels}}
+
+
 def extra_workloads(ctx, stream):
     """The other configurations, each timed as whole-path runs with its
     records in HBM."""
@@ -350,6 +386,8 @@ def extra_workloads(ctx, stream):
                                        "plain": plain, "batched_speedup": r["value"] / plain["value"]}
     log("65,536 kernels: register versions")
     out["loguniform_65536_kernels"]["ssa"] = ssa_workload(ctx, b, stream)
+    log("65,536 kernels: structuring")
+    out["loguniform_65536_kernels"]["structure"] = struct_workload(ctx, b, stream)
     log("65,536 kernels: text front end")
     out["loguniform_65536_kernels"]["text"] = text_workload(ctx, b, stream)
     b = dcgen.generate(4, 16)
@@ -497,6 +535,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=50000.0)
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--no-extra", action="store_true", help="skip the other workloads")
+    ap.add_argument("--only-struct", action="store_true",
+                    help="time only the structuring (dc_structure) of the workload")
     ap.add_argument("--only-text", action="store_true",
                     help="time only the text front end (dc_parse_text) on the workload rendered as one listing")
     ap.add_argument("--only-ssa", action="store_true",
@@ -519,6 +559,13 @@ def main():
     b = dcgen.generate(cfg, n_k)
     log(f"generated {b.n_kernels} kernels, {b.n_instr} instructions in {time.perf_counter() - t:.1f}s")
     stream = torch.cuda.current_stream()
+    if args.only_struct:
+        ctx = dc.Context(0)
+        r = struct_workload(ctx, b, stream, steps=args.steps)
+        ctx.close()
+        print(json.dumps({"workload": desc, "kernels": b.n_kernels, "instructions": b.n_instr, "structure": r}),
+              flush=True)
+        return
     if args.only_text:
         ctx = dc.Context(0)
         r = text_workload(ctx, b, stream, steps=args.steps)

@@ -385,6 +385,79 @@ dc_status_t dc_text_timing_reset(dc_text_t *t);
 void dc_text_free(dc_text_t *t);
 
 /* ------------------------------------------------------------------ */
+/* Structuring (region graph).                                          */
+/* ------------------------------------------------------------------ */
+/* Section "Search for control structures": the control flow graph becomes a
+ * region graph (initially the reachable blocks; region id = block index);
+ * a depth-first search from the entry region visits regions in preorder
+ * (fall-through successor first) and the first region that heads one of the
+ * templates below has the template's regions merged into a new region (ids
+ * n_blocks, n_blocks + 1, ... in merge order); the search starts again until
+ * one region is left or no region heads a template.  Templates at header H,
+ * tried in this order:
+ *   DC_RG_IFELSE  H's successors A, B have H as only predecessor and one
+ *                 common single successor J (not H, A, B): members H, A, B,
+ *                 and J when A and B are its only predecessors;
+ *   DC_RG_IF      (Fig. 2) a successor T (the fall-through one first) has H
+ *                 as only predecessor and H's other successor F as only
+ *                 successor: members H, T, and F when H and T are its only
+ *                 predecessors (the two cases of the Fig. 3 trace);
+ *   DC_RG_WHILE   a successor B has H as only predecessor and only
+ *                 successor: members H, B (the back edge disappears);
+ *   DC_RG_LINEAR  H's only successor S (not H) has H as only predecessor
+ *                 and at most one successor, or H among its successors
+ *                 (closing a loop: the new region has an edge to itself);
+ *   DC_RG_LOOP    H has an edge to itself: member H (the edge disappears).
+ * The entry counts the start as one more predecessor.  The new region's
+ * successors are the members' successors outside the template (and itself,
+ * for an edge back to H), in member order, each once.  The paper's if
+ * template and linear region are the two it names; its exec-mask forms of
+ * if-else (figures missing) are read as the standard diamond, which the
+ * compiler's exec-mask shape reduces to as two nested ifs; while and loop
+ * are this reading's additions so that counted loops reduce.  A kernel
+ * whose records fail their checks gets that status and no merges. */
+#define DC_RG_LINEAR 1
+#define DC_RG_IF 2
+#define DC_RG_IFELSE 3
+#define DC_RG_WHILE 4
+#define DC_RG_LOOP 5
+typedef struct {
+    uint32_t region;             /* the new region's id */
+    uint8_t kind, n;             /* DC_RG_*, members (1..4) */
+    uint16_t pad;
+    uint32_t member[4];          /* header first; DC_SSA_NONE past n */
+} dc_merge_t;                    /* 24 B */
+typedef struct {
+    dc_status_t status;
+    uint32_t n_blocks, n_merges;
+    uint32_t n_left;             /* regions left: 1 when the kernel reduces to one region */
+    uint32_t root;               /* the last region when one is left, else DC_SSA_NONE */
+    uint32_t pad;
+    uint64_t digest;             /* sum over merges j of splitmix64(splitmix64(0x5354 * 0x9E3779B97F4A7C15 + j)
+                                    ^ v), v folding (kind << 56) ^ (n << 48) ^ region with the four members
+                                    by v = splitmix64(v + member[k] + 0x9E3779B97F4A7C15 * (k + 1)) */
+} dc_struct_result_t;            /* 32 B */
+typedef struct dc_struct dc_struct_t;
+/* Structuring of n_kernels kernels whose records are in `instrs` (device):
+ * the graph stages of dc_build_cfg, then one search per kernel, on
+ * `stream`.  opts may be NULL; its flags may hold DC_OPT_TIMING only.  The
+ * first run sizes the region arrays from the block count (one wait);
+ * dc_struct_run on the same records allocates nothing and does not
+ * synchronise. */
+dc_status_t dc_structure(dc_ctx_t *ctx, const dc_kernel_t *kernels, uint32_t n_kernels, const dc_instr_t *instrs,
+                         uint64_t n_records, const dc_options_t *opts, void *stream, dc_struct_t **out);
+dc_status_t dc_struct_run(dc_struct_t *st, const dc_instr_t *instrs);
+dc_status_t dc_struct_wait(dc_struct_t *st);
+dc_status_t dc_struct_get_results(dc_struct_t *st, dc_struct_result_t *out, uint32_t cap);
+/* kernel k's merges in the order they were made (two-call idiom) */
+dc_status_t dc_struct_get_merges(dc_struct_t *st, uint32_t k, dc_merge_t *buf, uint32_t cap, uint32_t *n_total);
+/* stage times (needs DC_OPT_TIMING): ms_decode, ms_cfg as for a batch,
+ * ms_fixpoint = the structuring */
+dc_status_t dc_struct_get_timing(dc_struct_t *st, dc_timing_t *out);
+dc_status_t dc_struct_timing_reset(dc_struct_t *st);
+void dc_struct_free(dc_struct_t *st);
+
+/* ------------------------------------------------------------------ */
 /* Register versions (minimal SSA form).                                */
 /* ------------------------------------------------------------------ */
 /* Section "Search for control structures": at a block with several

@@ -2080,6 +2080,7 @@ static int rg_match(const rg_t *g, uint32_t x, uint32_t *m, int *n) {
 
 int or_structure(const or_kernel *K, const or_instr *I, or_struct_out *R) {
     memset(R, 0, sizeof(*R));
+    R->root = 0xFFFFFFFFu;   /* no region is left of a kernel that fails its checks */
     R->status = or_kernel_status(K, I);
     if (R->status != OK) return R->status;
     cfg_t G;
@@ -2087,7 +2088,7 @@ int or_structure(const or_kernel *K, const or_instr *I, or_struct_out *R) {
     const uint32_t nb = G.n_blocks;
     R->n_blocks = nb;
     rg_t g;
-    g.cap = 3 * nb + 2;   /* merges: at most nb - 1 that join regions, and one loop per edge to itself */
+    g.cap = 4 * nb + 2;   /* ids: blocks, at most nb - 1 joining merges, one loop merge per edge to itself */
     g.entry = 0;
     g.next = nb;
     g.succ = (int32_t *)malloc(sizeof(int32_t) * 2 * g.cap);

@@ -9,7 +9,8 @@ LIB = os.path.join(HERE, "libdc.so")
 SOURCES = [os.path.join(CSRC, "dc_kernels.hip"), os.path.join(CSRC, "dc_fixpoint.hip"),
            os.path.join(CSRC, "dc_noalloc.hip"), os.path.join(CSRC, "dc_plain.hip"),
            os.path.join(CSRC, "dc_ssa.hip"),
-           os.path.join(CSRC, "dc_text.hip"), os.path.join(CSRC, "dc_api.cpp"), os.path.join(CSRC, "dc_text_api.cpp"), os.path.join(CSRC, "dc_server.cpp")]
+           os.path.join(CSRC, "dc_text.hip"),
+           os.path.join(CSRC, "dc_struct.hip"), os.path.join(CSRC, "dc_api.cpp"), os.path.join(CSRC, "dc_text_api.cpp"), os.path.join(CSRC, "dc_server.cpp")]
 HEADERS = [os.path.join(CSRC, "dc_internal.h"), os.path.join(CSRC, "dc_fixpoint_core.h"), os.path.join(CSRC, "dc_records.h"), os.path.join(CSRC, "dc_opnames.h"), os.path.join(CSRC, "dc_host.h"), os.path.join(CSRC, "dc_isa.h"),
            os.path.join(CSRC, "dc_device.h"), os.path.join(ROOT, "include", "dc.h")]
 

@@ -67,7 +67,9 @@ struct dc_batch {
     std::vector<uint32_t> k_nblocks, k_nreach, h_block_start, h_pred_off, h_pred, h_rpo;
     std::vector<int32_t> h_succ;
     std::vector<uint32_t> v_block_start, v_pred_off;   /* scratch for one view */
-    dc_ssa *ssa = nullptr;   /* a register-version run on this graph (its stages follow the graph's) */
+    /* a run on this graph whose stages follow the graph's (versions, structuring) */
+    dc_status_t (*after_graph)(void *) = nullptr;
+    void *after_graph_arg = nullptr;
 };
 struct dc_cfg {
     dc_batch b;
@@ -442,8 +444,6 @@ static dc_status_t enqueue_graph(dc_batch *B) {
     return DC_OK;
 }
 
-static dc_status_t enqueue_ssa_stages(dc_ssa *X);
-
 static dc_status_t enqueue(dc_batch *B) {
     Plan &P = B->P;
     hipStream_t s = B->stream;
@@ -484,8 +484,8 @@ static dc_status_t enqueue(dc_batch *B) {
     if (B->have_events) TRY(hipEventRecord(ev[EV_CFG], s));
     if (B->cfg_only) {
         if (B->have_events) TRY(hipEventRecord(ev[EV_FIXB], s));
-        if (B->ssa) {
-            const dc_status_t st = enqueue_ssa_stages(B->ssa);
+        if (B->after_graph) {
+            const dc_status_t st = B->after_graph(B->after_graph_arg);
             if (st != DC_OK) return st;
         }
         if (B->have_events) {
@@ -1040,7 +1040,8 @@ struct dc_ssa {
 /* Enqueue the version stages after the graph stages.  The first run on a
  * set of records sizes the tables and then the outputs from the counts it
  * reads back (two waits for the stream); later runs reuse them. */
-static dc_status_t enqueue_ssa_stages(dc_ssa *X) {
+static dc_status_t enqueue_ssa_stages(void *arg) {
+    dc_ssa *X = static_cast<dc_ssa *>(arg);
     dc_batch *B = &X->c.b;
     const Plan &P = B->P;
     SsaPlan &S = X->S;
@@ -1132,7 +1133,8 @@ extern "C" dc_status_t dc_build_ssa(dc_ctx_t *ctx, const dc_kernel_t *kernels, u
         if (st == DC_OK && hipMemcpy(B->dP, &B->P, sizeof(Plan), hipMemcpyHostToDevice) != hipSuccess) st = DC_E_HIP;
     }
     if (st == DC_OK) {
-        B->ssa = X;
+        B->after_graph = enqueue_ssa_stages;
+        B->after_graph_arg = X;
         st = enqueue(B);
     }
     if (st != DC_OK) {
@@ -1305,6 +1307,177 @@ extern "C" dc_status_t dc_ssa_timing_reset(dc_ssa_t *X) {
 }
 
 extern "C" void dc_ssa_free(dc_ssa_t *X) {
+    if (!X) return;
+    hipSetDevice(X->c.b.ctx->device);
+    hipStreamSynchronize(X->c.b.stream);
+    dc_batch *B = &X->c.b;
+    if (B->have_events)
+        for (int r = 0; r < TIMING_RING; r++)
+            for (int i = 0; i < N_EV; i++) hipEventDestroy(B->ev[r][i]);
+    delete X;
+}
+
+/* ---------------------------------------------------------------- structuring */
+struct dc_struct {
+    dc_cfg c;
+    DevMem smem;   /* region arrays, sized by the block count of the first run on these records */
+    StructPlan S{};
+    bool sized = false;
+    bool host_valid = false, merges_valid = false;
+    std::vector<dc_struct_result_t> res;
+    std::vector<dc_merge_t> merges;
+    std::vector<uint32_t> first_block;
+};
+
+static dc_status_t enqueue_struct_stages(void *arg) {
+    dc_struct *X = static_cast<dc_struct *>(arg);
+    dc_batch *B = &X->c.b;
+    const Plan &P = B->P;
+    StructPlan &S = X->S;
+    X->host_valid = false;
+    if (!X->sized) {
+        X->smem.reset();
+        const uint64_t slots = 4ull * std::max<uint32_t>(P.blk_cap, 1) + 2ull * B->K;
+        S.succ = X->smem.alloc<int32_t>(2 * slots);
+        S.npred = X->smem.alloc<uint32_t>(slots);
+        S.fwd = X->smem.alloc<uint32_t>(slots);
+        S.mark = X->smem.alloc<uint32_t>(slots);
+        S.stack = X->smem.alloc<uint32_t>(2 * slots);
+        S.merges = X->smem.alloc<dc_merge_t>(slots);
+        if (X->smem.failed) return DC_E_OOM;
+        X->sized = true;
+    }
+    const hipError_t e = launch_struct(P, S, B->stream);
+    return e == hipSuccess ? DC_OK : hip_fail(e);
+}
+
+extern "C" dc_status_t dc_structure(dc_ctx_t *ctx, const dc_kernel_t *kernels, uint32_t n_kernels,
+                                    const dc_instr_t *instrs, uint64_t n_records, const dc_options_t *opts,
+                                    void *stream, dc_struct_t **out) {
+    if (!out) return DC_E_INVAL;
+    *out = nullptr;
+    if (opts && (opts->flags & ~DC_OPT_TIMING)) return DC_E_INVAL;
+    dc_struct *X = new (std::nothrow) dc_struct;
+    if (!X) return DC_E_OOM;
+    dc_batch *B = &X->c.b;
+    std::vector<dc_kernel_t> ks_noargs(kernels, kernels + (kernels ? n_kernels : 0));
+    for (auto &k : ks_noargs) {
+        k.n_args = 0;
+        k.arg_begin = 0;
+    }
+    dc_options_t o{};
+    if (opts) o.flags = opts->flags;
+    dc_status_t st = plan_batch(B, ctx, kernels ? ks_noargs.data() : nullptr, n_kernels, instrs, n_records, nullptr, 0,
+                                &o, stream, true);
+    if (st == DC_OK) {
+        X->S.res = B->mem.alloc<dc_struct_result_t>(std::max<uint64_t>(n_kernels, 1));
+        if (B->mem.failed) st = DC_E_OOM;
+    }
+    if (st == DC_OK) {
+        std::vector<int32_t> ds(n_kernels);
+        for (uint32_t k = 0; k < n_kernels; k++) ds[k] = descriptor_status(kernels[k]);
+        if (n_kernels &&
+            hipMemcpy((void *)B->P.desc_status, ds.data(), n_kernels * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess)
+            st = DC_E_HIP;
+    }
+    if (st == DC_OK) {
+        B->after_graph = enqueue_struct_stages;
+        B->after_graph_arg = X;
+        st = enqueue(B);
+    }
+    if (st != DC_OK) {
+        hipStreamSynchronize(B->stream);
+        delete X;
+        return st;
+    }
+    *out = X;
+    return DC_OK;
+}
+
+extern "C" dc_status_t dc_struct_run(dc_struct_t *X, const dc_instr_t *instrs) {
+    if (!X || (X->c.b.n_records && !instrs)) return DC_E_INVAL;
+    dc_batch *B = &X->c.b;
+    if (hipSetDevice(B->ctx->device) != hipSuccess) return DC_E_HIP;
+    if (instrs != B->P.instrs) {
+        if (hipStreamSynchronize(B->stream) != hipSuccess) return DC_E_HIP;
+        B->P.instrs = instrs;
+        B->blocks_planned = false;
+        X->sized = false;
+    }
+    return enqueue(B);
+}
+
+extern "C" dc_status_t dc_struct_wait(dc_struct_t *X) {
+    if (!X) return DC_E_INVAL;
+    return dc_batch_wait(&X->c.b);
+}
+
+static dc_status_t fetch_struct(dc_struct *X) {
+    if (X->host_valid) return DC_OK;
+    dc_batch *B = &X->c.b;
+    dc_status_t st = dc_batch_wait(B);
+    if (st != DC_OK) return st;
+    const uint32_t K = B->K;
+    X->res.resize(K);
+    X->first_block.resize(K);
+    hipError_t e = hipSuccess;
+    if (K) e = hipMemcpy(X->res.data(), X->S.res, K * sizeof(dc_struct_result_t), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && K)
+        e = hipMemcpy(X->first_block.data(), B->P.first_block, K * sizeof(uint32_t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e);
+    X->host_valid = true;
+    X->merges_valid = false;
+    return DC_OK;
+}
+
+/* the merge records, copied on first use after a run */
+static dc_status_t fetch_struct_merges(dc_struct *X) {
+    dc_status_t st = fetch_struct(X);
+    if (st != DC_OK || X->merges_valid) return st;
+    const uint64_t slots = 4ull * std::max<uint32_t>(X->c.b.P.blk_cap, 1) + 2ull * X->c.b.K;
+    X->merges.resize(slots);
+    if (X->S.merges &&
+        hipMemcpy(X->merges.data(), X->S.merges, slots * sizeof(dc_merge_t), hipMemcpyDeviceToHost) != hipSuccess)
+        return DC_E_HIP;
+    X->merges_valid = true;
+    return DC_OK;
+}
+
+extern "C" dc_status_t dc_struct_get_results(dc_struct_t *X, dc_struct_result_t *out, uint32_t cap) {
+    if (!X || (cap && !out)) return DC_E_INVAL;
+    dc_status_t st = fetch_struct(X);
+    if (st != DC_OK) return st;
+    const uint32_t n = std::min<uint32_t>(cap, X->c.b.K);
+    if (n) memcpy(out, X->res.data(), n * sizeof(dc_struct_result_t));
+    return DC_OK;
+}
+
+extern "C" dc_status_t dc_struct_get_merges(dc_struct_t *X, uint32_t k, dc_merge_t *buf, uint32_t cap,
+                                            uint32_t *n_total) {
+    if (!X || !n_total || (cap && !buf) || k >= X->c.b.K) return DC_E_INVAL;
+    dc_status_t st = fetch_struct_merges(X);
+    if (st != DC_OK) return st;
+    const dc_struct_result_t &r = X->res[k];
+    *n_total = r.status == DC_OK ? r.n_merges : 0;
+    const uint64_t base = 4ull * X->first_block[k] + 2ull * k;
+    const uint32_t n = std::min(cap, *n_total);
+    if (n) memcpy(buf, X->merges.data() + base, n * sizeof(dc_merge_t));
+    return DC_OK;
+}
+
+extern "C" dc_status_t dc_struct_get_timing(dc_struct_t *X, dc_timing_t *out) {
+    if (!X) return DC_E_INVAL;
+    dc_status_t st = dc_get_timing(&X->c.b, out);
+    if (st == DC_OK) out->ms_compact = 0;
+    return st;
+}
+
+extern "C" dc_status_t dc_struct_timing_reset(dc_struct_t *X) {
+    if (!X) return DC_E_INVAL;
+    return dc_timing_reset(&X->c.b);
+}
+
+extern "C" void dc_struct_free(dc_struct_t *X) {
     if (!X) return;
     hipSetDevice(X->c.b.ctx->device);
     hipStreamSynchronize(X->c.b.stream);

@@ -191,6 +191,17 @@ hipError_t launch_text_classify(const TextPlan &T, hipStream_t s);   /* line sta
 hipError_t launch_text_kernels1(const TextPlan &T, hipStream_t s);   /* kernel starts, per-kernel counts, scans */
 hipError_t launch_text_kernels2(const TextPlan &T, hipStream_t s);   /* labels, configuration, records */
 
+/* Device arrays of a structuring run (dc_struct.hip): kernel k's regions
+ * are ids 0 .. 4 n_blocks + 1 at 4 first_block + 2 k of each array. */
+struct StructPlan {
+    int32_t *succ;                  /* 2 per region */
+    uint32_t *npred, *fwd, *mark;
+    uint32_t *stack;                /* 2 per region */
+    dc_merge_t *merges;             /* per region slot: the kernel's merges in order */
+    dc_struct_result_t *res;        /* K */
+};
+hipError_t launch_struct(const Plan &P, const StructPlan &S, hipStream_t s);
+
 hipError_t launch_ssa_size(const Plan &P, const SsaPlan &S, hipStream_t s);    /* table sizes and offsets */
 hipError_t launch_ssa_graph(const Plan &P, const SsaPlan &S, hipStream_t s);   /* dominators, merges, numbering */
 hipError_t launch_ssa_emit(const Plan &P, const SsaPlan &S, hipStream_t s);    /* merges, arguments, versions */

@@ -36,6 +36,7 @@ namespace dc {
 
 constexpr uint32_t TX_TILE = 4096;       /* bytes (or lines) per tile */
 constexpr uint32_t TX_T = 256;           /* threads of the per-kernel workgroups */
+constexpr uint32_t TX_STAGE = 16384;     /* bytes of a chunk of lines staged in LDS */
 constexpr uint16_t TX_BAD = 0xFFFD, TX_NONE = 0xFFFF, TX_LIT = 0xFFFE;
 enum : uint8_t { K_EMPTY, K_KERNEL, K_CONFIG, K_TEXT, K_LABEL, K_ARG, K_OTHER };
 
@@ -178,9 +179,14 @@ __device__ uint16_t operand(Sp t, bool *has_lit, int32_t *lit) {
         }
         return (uint16_t)(vec ? 112 + a : a);
     }
-    const char *const fl[8] = {"0.5", "-0.5", "1.0", "-1.0", "2.0", "-2.0", "4.0", "-4.0"};
-    for (int i = 0; i < 8; i++)
-        if (eq(t, fl[i])) return (uint16_t)(0x8060 + i);
+    if (eq(t, "0.5")) return 0x8060;
+    if (eq(t, "-0.5")) return 0x8061;
+    if (eq(t, "1.0")) return 0x8062;
+    if (eq(t, "-1.0")) return 0x8063;
+    if (eq(t, "2.0")) return 0x8064;
+    if (eq(t, "-2.0")) return 0x8065;
+    if (eq(t, "4.0")) return 0x8066;
+    if (eq(t, "-4.0")) return 0x8067;
     int64_t v;
     if (!to_int(t, &v)) return TX_BAD;
     if (v >= -16 && v <= 64) return (uint16_t)(0x8000 + (v + 16));
@@ -248,8 +254,7 @@ __device__ dc_instr_t parse_instr(Sp line, const Labels &L, const char (*names)[
      * every word) and modifiers (key:value words without '['; offset:N) */
     bool bad_num = false;
     int nf = 0;
-    Sp f[8];
-    for (int k = 0; k < 8; k++) f[k] = Sp{rest.p, 0};
+    Sp f0{rest.p, 0}, f1{rest.p, 0}, f2{rest.p, 0}, f3{rest.p, 0};   /* operand words 0..3 (no template uses more) */
     bool has_comma = false;
     for (uint32_t i = 0; i < rest.n; i++) has_comma |= rest.p[i] == ',';
     const int nfl = has_comma ? nfields(rest) : 1;
@@ -271,28 +276,35 @@ __device__ dc_instr_t parse_instr(Sp line, const Labels &L, const char (*names)[
                     else bad_num = true;
                 }
             } else if (first || !has_comma) {
-                if (nf < 8) f[nf] = mw;
+                f0 = nf == 0 ? mw : f0;
+                f1 = nf == 1 ? mw : f1;
+                f2 = nf == 2 ? mw : f2;
+                f3 = nf == 3 ? mw : f3;
                 nf++;
                 first = false;
             }
             words = more;
         }
         if (has_comma && first) {
-            if (nf < 8) f[nf] = Sp{rest.p, 0};
+            const Sp z{rest.p, 0};
+            f0 = nf == 0 ? z : f0;
+            f1 = nf == 1 ? z : f1;
+            f2 = nf == 2 ? z : f2;
+            f3 = nf == 3 ? z : f3;
             nf++;
         }
     }
     if (nf > 8) nf = 8;
     bool has_lit = false;
     int32_t lit = 0;
-    auto opd = [&](int k) -> uint16_t { return (k < nf && f[k].n) ? operand(f[k], &has_lit, &lit) : TX_BAD; };
+#define OPD(k, fk) (((k) < nf && (fk).n) ? operand((fk), &has_lit, &lit) : TX_BAD)
     const uint32_t cls = e_cls(e);
     switch (cls) {
     case C_SMEM: {
-        r.r0 = opd(0);
-        r.r1 = opd(1);
+        r.r0 = OPD(0, f0);
+        r.r1 = OPD(1, f1);
         int64_t v;
-        if (nf > 2 && to_int(f[2], &v)) r.imm = (int32_t)(uint32_t)(uint64_t)v;
+        if (nf > 2 && to_int(f2, &v)) r.imm = (int32_t)(uint32_t)(uint64_t)v;
         else bad_num = true;
         break;
     }
@@ -302,64 +314,70 @@ __device__ dc_instr_t parse_instr(Sp line, const Labels &L, const char (*names)[
         if (nf > 0) {
             uint32_t idx;
             int64_t v;
-            if (label_find(L, f[0], &idx)) r.target = (int32_t)idx;
-            else if (to_int(f[0], &v) && v >= 0 && v < 0x7FFFFFFF) r.target = (int32_t)v;
+            if (label_find(L, f0, &idx)) r.target = (int32_t)idx;
+            else if (to_int(f0, &v) && v >= 0 && v < 0x7FFFFFFF) r.target = (int32_t)v;
         }
         break;
     }
     case C_NOP:
     case C_END: break;
     case C_SCMP:
-        r.r1 = opd(0);
-        r.r2 = opd(1);
+        r.r1 = OPD(0, f0);
+        r.r2 = OPD(1, f1);
         break;
     case C_VCMP:
-        r.r1 = opd(1);
-        r.r2 = opd(2);
+        r.r1 = OPD(1, f1);
+        r.r2 = OPD(2, f2);
         break;
     case C_GLD:
-        r.r0 = opd(0);
-        r.r1 = opd(1);
-        r.r2 = opd(2);
+        r.r0 = OPD(0, f0);
+        r.r1 = OPD(1, f1);
+        r.r2 = OPD(2, f2);
         break;
     case C_FLD:
     case C_DSR:
-        r.r0 = opd(0);
-        r.r1 = opd(1);
+        r.r0 = OPD(0, f0);
+        r.r1 = OPD(1, f1);
         break;
     case C_GST:
-        r.r1 = opd(0);
-        r.r0 = opd(1);
-        r.r2 = opd(2);
+        r.r1 = OPD(0, f0);
+        r.r0 = OPD(1, f1);
+        r.r2 = OPD(2, f2);
         break;
     case C_FST:
     case C_DSW:
-        r.r1 = opd(0);
-        r.r0 = opd(1);
+        r.r1 = OPD(0, f0);
+        r.r0 = OPD(1, f1);
         break;
     default:
         if (cls == C_VALU && (e_idef(e) & IM_VCC)) {   /* dst, vcc, src0, src1 */
-            r.r0 = opd(0);
-            r.r1 = opd(2);
-            r.r2 = opd(3);
+            r.r0 = OPD(0, f0);
+            r.r1 = OPD(2, f2);
+            r.r2 = OPD(3, f3);
         } else if (e_role(e, 3) != RO_NO) {            /* dst, src0, src1, src2 */
-            r.r0 = opd(0);
-            r.r1 = opd(1);
-            r.r2 = opd(2);
-            r.imm = (int32_t)opd(3);
+            r.r0 = OPD(0, f0);
+            r.r1 = OPD(1, f1);
+            r.r2 = OPD(2, f2);
+            r.imm = (int32_t)OPD(3, f3);
         } else if (e_role(e, 2) == RO_NO) {            /* dst, src */
-            r.r0 = opd(0);
-            r.r1 = opd(1);
+            r.r0 = OPD(0, f0);
+            r.r1 = OPD(1, f1);
         } else {                                       /* dst, src0, src1 */
-            r.r0 = opd(0);
-            r.r1 = opd(1);
-            r.r2 = opd(2);
+            r.r0 = OPD(0, f0);
+            r.r1 = OPD(1, f1);
+            r.r2 = OPD(2, f2);
         }
     }
+#undef OPD
     if (has_lit && !e_immoff(e) && e_role(e, 3) == RO_NO) r.imm = lit;
     if (bad_num) r.op = TX_NONE;
     return r;
 }
+
+static __constant__ char TY_NAME[12][8] = {"char", "uchar", "short", "ushort", "int", "uint",
+                                            "long", "ulong", "float", "double", "size_t", "void"};
+static __constant__ uint8_t TY_BITS[12] = {1, 2, 1, 2, 1, 2, 1, 2, 4, 8, 2, 0};
+static __constant__ uint16_t TY_SIZE[12] = {1, 1, 2, 2, 4, 4, 8, 8, 4, 8, 8, 4};
 
 /* .arg type: size, type bits, pointee bits */
 __device__ void arg_type(Sp t, uint16_t *size, uint8_t *type, uint8_t *flags) {
@@ -369,16 +387,12 @@ __device__ void arg_type(Sp t, uint16_t *size, uint8_t *type, uint8_t *flags) {
         t.n--;
         t = trim(t);
     }
-    const char *const names[12] = {"char", "uchar", "short", "ushort", "int", "uint", "long", "ulong",
-                                   "float", "double", "size_t", "void"};
-    const uint8_t bits[12] = {1, 2, 1, 2, 1, 2, 1, 2, 4, 8, 2, 0};
-    const uint16_t sizes[12] = {1, 1, 2, 2, 4, 4, 8, 8, 4, 8, 8, 4};
     uint8_t b = 0;
     uint16_t sz = 4;
     for (int i = 0; i < 12; i++)
-        if (eq(t, names[i])) {
-            b = bits[i];
-            sz = sizes[i];
+        if (eq(t, TY_NAME[i])) {
+            b = TY_BITS[i];
+            sz = TY_SIZE[i];
             break;
         }
     if (ptr) {
@@ -612,6 +626,7 @@ __global__ __launch_bounds__(TX_T) void k_tx_kernel2(TextPlan T) {
     __shared__ uint32_t ws[4];
     __shared__ char names[N_OPS][24];
     __shared__ uint32_t s_dims, s_cws, s_use;
+    __shared__ uint8_t s_txt[TX_STAGE];
     const uint32_t k = blockIdx.x, K = T.n_kernels, t = threadIdx.x;
     if (k >= K || K > T.k_cap || *T.fail) return;
     for (uint32_t i = t; i < N_OPS * 24; i += TX_T) (&names[0][0])[i] = (&OPN[0][0])[i];
@@ -665,7 +680,8 @@ __global__ __launch_bounds__(TX_T) void k_tx_kernel2(TextPlan T) {
     }
     __threadfence();
     __syncthreads();
-    /* records */
+    /* records: each chunk's text is staged in LDS with coalesced loads when
+     * it fits, and its lines are parsed from there */
     carry = 0;
     icount = 0;
     for (uint64_t c = l0; c < l1; c += TX_T) {
@@ -676,7 +692,20 @@ __global__ __launch_bounds__(TX_T) void k_tx_kernel2(TextPlan T) {
         const uint32_t is_i = act && st == 2 && (kd == K_OTHER || kd == K_ARG);
         uint32_t ti;
         const uint32_t xi = block_excl_sum(is_i, &ti, ws);
-        if (is_i && icount + xi < ni) T.instrs[ib + icount + xi] = parse_instr(line_clean(T, j), L, names);
+        const uint64_t cend = c + TX_T < l1 ? c + TX_T : l1;
+        const uint64_t cs = T.line_start[c];
+        uint64_t ce = T.line_start[cend];
+        if (ce > T.n_bytes) ce = T.n_bytes;
+        const bool staged = ce >= cs && ce - cs <= TX_STAGE;
+        if (staged)
+            for (uint64_t i = t; i < ce - cs; i += TX_T) s_txt[i] = T.text[cs + i];
+        __syncthreads();
+        if (is_i && icount + xi < ni) {
+            Sp ln = line_clean(T, j);
+            if (staged && ln.n) ln.p = s_txt + (ln.p - (T.text + cs));
+            T.instrs[ib + icount + xi] = parse_instr(ln, L, names);
+        }
+        __syncthreads();
         icount += ti;
     }
     __syncthreads();

@@ -39,6 +39,11 @@ SSA_NU, SSA_ND, SSA_NONE = 13, 9, 0xFFFFFFFF
 PHI_DTYPE = np.dtype([("block", "<u4"), ("slot", "<u2"), ("pad", "<u2"), ("version", "<u4")])
 SSA_RESULT_DTYPE = np.dtype([("status", "<i4"), ("n_blocks", "<u4"), ("n_phi", "<u4"), ("n_phi_args", "<u4"),
                              ("n_operands", "<u4"), ("pad", "<u4"), ("digest", "<u8")])
+# structuring (dc_structure)
+RG_LINEAR, RG_IF, RG_IFELSE, RG_WHILE, RG_LOOP = 1, 2, 3, 4, 5
+MERGE_DTYPE = np.dtype([("region", "<u4"), ("kind", "u1"), ("n", "u1"), ("pad", "<u2"), ("member", "<u4", (4,))])
+STRUCT_RESULT_DTYPE = np.dtype([("status", "<i4"), ("n_blocks", "<u4"), ("n_merges", "<u4"), ("n_left", "<u4"),
+                                ("root", "<u4"), ("pad", "<u4"), ("digest", "<u8")])
 # dc_request_t and dc_result_t of the request server
 REQUEST_DTYPE = np.dtype([("kernel", KERNEL_DTYPE), ("instrs", "<u8"), ("args", "<u8"), ("tag", "<u8")])
 SERVER_RESULT_DTYPE = np.dtype([("ticket", "<u8"), ("tag", "<u8"), ("summary", RESULT_DTYPE), ("accesses", "<u8"),
@@ -135,6 +140,14 @@ SIGNATURES = [
     ("dc_text_get_timing", I32, [VP, ctypes.POINTER(Timing)]),
     ("dc_text_timing_reset", I32, [VP]),
     ("dc_text_free", None, [VP]),
+    ("dc_structure", I32, [VP, VP, U32, VP, U64, ctypes.POINTER(Options), VP, ctypes.POINTER(VP)]),
+    ("dc_struct_run", I32, [VP, VP]),
+    ("dc_struct_wait", I32, [VP]),
+    ("dc_struct_get_results", I32, [VP, VP, U32]),
+    ("dc_struct_get_merges", I32, [VP, U32, VP, U32, ctypes.POINTER(U32)]),
+    ("dc_struct_get_timing", I32, [VP, ctypes.POINTER(Timing)]),
+    ("dc_struct_timing_reset", I32, [VP]),
+    ("dc_struct_free", None, [VP]),
     ("dc_build_ssa", I32, [VP, VP, U32, VP, U64, ctypes.POINTER(Options), VP, ctypes.POINTER(VP)]),
     ("dc_ssa_run", I32, [VP, VP]),
     ("dc_ssa_wait", I32, [VP]),
@@ -308,6 +321,15 @@ class Context:
         check("dc_parse_text", lib().dc_parse_text(self.h, _dev_ptr(text_dev), n_bytes, ctypes.byref(o),
                                                    _stream_ptr(stream), ctypes.byref(h)))
         return Text(h, text_dev, n_bytes)
+
+    def structure(self, kernels, instrs_dev, n_records, timing=False, stream=None) -> "Struct":
+        kernels = np.ascontiguousarray(np.asarray(kernels, KERNEL_DTYPE))
+        o = Options()
+        o.flags = OPT_TIMING if timing else 0
+        h = VP()
+        check("dc_structure", lib().dc_structure(self.h, _np_ptr(kernels), len(kernels), _dev_ptr(instrs_dev),
+                                                 n_records, ctypes.byref(o), _stream_ptr(stream), ctypes.byref(h)))
+        return Struct(h, kernels, instrs_dev)
 
     def build_ssa(self, kernels, instrs_dev, n_records, timing=False, digest=True, stream=None) -> "Ssa":
         kernels = np.ascontiguousarray(np.asarray(kernels, KERNEL_DTYPE))
@@ -658,6 +680,58 @@ class Text:
     def free(self):
         if self.h:
             lib().dc_text_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Struct:
+    """Region-graph structuring of a batch (dc_structure): per kernel the
+    merges in the order made, the regions left and the root."""
+
+    def __init__(self, h, kernels, instrs_dev):
+        self.h = h
+        self.kernels = kernels
+        self.n_kernels = len(kernels)
+        self._keep = instrs_dev
+
+    def run(self, instrs_dev=None):
+        if instrs_dev is not None:
+            self._keep = instrs_dev
+        check("dc_struct_run", lib().dc_struct_run(self.h, _dev_ptr(self._keep)))
+
+    def wait(self):
+        check("dc_struct_wait", lib().dc_struct_wait(self.h))
+
+    def results(self) -> np.ndarray:
+        out = np.zeros(self.n_kernels, STRUCT_RESULT_DTYPE)
+        check("dc_struct_get_results", lib().dc_struct_get_results(self.h, _np_ptr(out), self.n_kernels))
+        return out
+
+    def merges(self, k: int) -> np.ndarray:
+        n = U32()
+        check("dc_struct_get_merges", lib().dc_struct_get_merges(self.h, k, None, 0, ctypes.byref(n)))
+        out = np.zeros(n.value, MERGE_DTYPE)
+        if n.value:
+            check("dc_struct_get_merges", lib().dc_struct_get_merges(self.h, k, _np_ptr(out), n.value,
+                                                                     ctypes.byref(n)))
+        return out
+
+    def timing(self) -> dict:
+        t = Timing()
+        check("dc_struct_get_timing", lib().dc_struct_get_timing(self.h, ctypes.byref(t)))
+        return {k: getattr(t, k) for k, _ in t._fields_ if k not in ("pad", "ms_pad", "ms_compact")}
+
+    def timing_reset(self):
+        check("dc_struct_timing_reset", lib().dc_struct_timing_reset(self.h))
+
+    def free(self):
+        if self.h:
+            lib().dc_struct_free(self.h)
             self.h = None
 
     def __del__(self):

@@ -82,3 +82,32 @@ def compare_ssa_summaries(gpu_res, summ):
                         ("n_phi_args", "n_args"), ("n_operands", "n_operands"), ("digest", "digest")]:
         bad = np.nonzero(gpu_res[f_gpu] != summ[f_or])[0]
         assert len(bad) == 0, (f_gpu, bad[:10], gpu_res[f_gpu][bad[:10]], summ[f_or][bad[:10]])
+
+
+def _oracle_struct_chunk(args):
+    cfg, i0, n = args
+    b = dcgen.generate(cfg, n, i0=i0, threads=1)
+    return oracle.structure_batch(b)
+
+
+class OracleStructRun:
+    """Oracle structuring summaries for kernels [0, n) of a config, in
+    parallel worker processes started at construction."""
+
+    def __init__(self, cfg: int, n: int, procs: int = 0, jobs_per_proc: int = 4):
+        procs = procs or min(16, os.cpu_count() or 1)
+        step = max(1, (n + procs * jobs_per_proc - 1) // (procs * jobs_per_proc))
+        self.ex = ProcessPoolExecutor(procs)
+        self.futs = [self.ex.submit(_oracle_struct_chunk, (cfg, i, min(step, n - i))) for i in range(0, n, step)]
+
+    def result(self):
+        parts = [f.result() for f in self.futs]
+        self.ex.shutdown()
+        return np.concatenate(parts)
+
+
+def compare_struct_summaries(gpu_res, summ):
+    assert len(gpu_res) == len(summ)
+    for f in ("status", "n_blocks", "n_merges", "n_left", "root", "digest"):
+        bad = np.nonzero(gpu_res[f] != summ[f])[0]
+        assert len(bad) == 0, (f, bad[:10], gpu_res[f][bad[:10]], summ[f][bad[:10]])

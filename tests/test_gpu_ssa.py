@@ -199,3 +199,23 @@ def test_ssa_empty_batch(ctx):
     s = ctx.build_ssa(kern, dev, 1)
     assert len(s.results()) == 0
     s.free()
+
+
+def test_ssa_c3_zipf_full(ctx):
+    """All 1,048,576 kernels of the Zipf(1.2) 20-20,000 workload (1.74e9
+    instructions) in one object: per-kernel status, blocks, merges,
+    arguments, operand count and digest against the oracle (worker
+    processes, started first)."""
+    n = 1048576
+    orc = OracleSsaRun(3, n, jobs_per_proc=16)
+    b = dcgen.generate(3, n)
+    dev = dc.to_device(b.instrs)
+    torch.cuda.synchronize()
+    t = time.time()
+    s = ctx.build_ssa(b.kernels, dev, b.n_instr)
+    res = s.results()
+    say(f"ssa c3: gpu done in {time.time() - t:.1f}s, merges {int(res['n_phi'].sum())}")
+    s.free()
+    del dev
+    torch.cuda.empty_cache()
+    compare_ssa_summaries(res, orc.result())
