@@ -9,7 +9,8 @@ wrapper.
 Parity: pinned by tests/test_oracle_*.py (the paper's worked statements,
 textbook basic blocks, meet-over-all-paths for the distributive tiers,
 schedule independence, lattice laws; register versions against brute-force
-dominators, join sets and path walks; the text front end against the
+dominators, join sets and path walks; variables and their types against the paper's
+suffix statement and hand-derived cases; the text front end against the
 paper's Listings 1 and 3 written out by hand and the generator's renderer).  The payload tier beyond the paper's
 printed cases is "parity unpinned": only invariants pin it (monotone rules,
 meet over all paths below the fixpoint, schedule independence, constant
@@ -86,6 +87,12 @@ def lib():
         L.or_structure_free.argtypes = [ctypes.c_void_p]
         L.or_structure_batch.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p]
         L.or_structure_batch.restype = ctypes.c_int
+        L.or_types.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.or_types.restype = ctypes.c_int
+        L.or_types_free.argtypes = [ctypes.c_void_p]
+        L.or_types_batch.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p]
+        L.or_types_batch.restype = ctypes.c_int
         L.or_parse_text.argtypes = [ctypes.c_char_p, ctypes.c_uint64, ctypes.c_void_p]
         L.or_parse_text.restype = ctypes.c_int
         L.or_text_free.argtypes = [ctypes.c_void_p]
@@ -232,6 +239,43 @@ def structure(recs, desc) -> dict:
 def structure_batch(batch):
     summ = np.zeros(batch.n_kernels, STRUCT_SUMMARY_DTYPE)
     lib().or_structure_batch(_ptr(batch.kernels), batch.n_kernels, _ptr(batch.instrs), _ptr(summ))
+    return summ
+
+
+VAR_DTYPE = np.dtype([("slot", "<u2"), ("type", "u1"), ("flags", "u1"), ("version", "<u4"), ("var", "<u4"),
+                      ("tclass", "<u4")])
+VF_MERGE, VF_LIVE = 1, 2
+TYPES_SUMMARY_DTYPE = np.dtype([("status", "<i4"), ("n_nodes", "<u4"), ("n_vars", "<u4"), ("n_tclasses", "<u4"),
+                                ("n_live_merges", "<u4"), ("n_ternary", "<u4"), ("digest", "<u8")])
+assert VAR_DTYPE.itemsize == 16 and TYPES_SUMMARY_DTYPE.itemsize == 32
+
+
+class _TypesOut(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("n_nodes", ctypes.c_uint32), ("n_vars", ctypes.c_uint32),
+                ("n_tclasses", ctypes.c_uint32), ("n_live_merges", ctypes.c_uint32), ("n_ternary", ctypes.c_uint32),
+                ("digest", ctypes.c_uint64), ("nodes", ctypes.c_void_p)]
+
+
+def types(recs, desc, args) -> dict:
+    """Variables and types over the register versions of one kernel: one
+    entry per (slot, version) node with its variable (merges joined with
+    their arguments), type class (also joined through copies and
+    v_cndmask_b32), the class's type bits and the merge / live flags."""
+    d = _desc(desc)
+    recs = np.ascontiguousarray(recs)
+    args = np.ascontiguousarray(args)
+    R = _TypesOut()
+    L = lib()
+    L.or_types(d.ctypes.data, _ptr(recs), _ptr(args), ctypes.byref(R))
+    out = dict(status=R.status, n_vars=R.n_vars, n_tclasses=R.n_tclasses, n_live_merges=R.n_live_merges,
+               n_ternary=R.n_ternary, digest=R.digest, nodes=_copy(R.nodes, R.n_nodes, VAR_DTYPE))
+    L.or_types_free(ctypes.byref(R))
+    return out
+
+
+def types_batch(batch):
+    summ = np.zeros(batch.n_kernels, TYPES_SUMMARY_DTYPE)
+    lib().or_types_batch(_ptr(batch.kernels), batch.n_kernels, _ptr(batch.instrs), _ptr(batch.args), _ptr(summ))
     return summ
 
 

@@ -2178,3 +2178,282 @@ int or_structure_batch(const or_kernel *kernels, uint32_t n_kernels, const or_in
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* variables and their types over the register versions                 */
+/* ------------------------------------------------------------------ */
+/* Section "Search for control structures": a register whose value at a
+ * block with several predecessors depends on the path taken becomes a
+ * variable when it is used later.  Section "Data type recovery": types come
+ * from the .arg lines of the configuration and from instruction suffixes,
+ * and a suffix types the values an instruction reads as well as the one it
+ * writes (an unsigned add adds two unsigned integers).  The ternary operator
+ * (the same section) is one instruction, v_cndmask_b32.  Readings, over the
+ * versions of or_ssa:
+ *   nodes: every version 0 .. n_ver - 1 of every register slot that some
+ *     record of the kernel names as an operand, and of vcc, exec and scc;
+ *     ordered by slot, then version;
+ *   variable: a merge and each of its arguments are one variable (the
+ *     variable made at the join); the classes of that relation;
+ *   type class: the same, plus a move's destination dword with the source
+ *     dword it copies, and v_cndmask_b32's result with each of its two values;
+ *   the representative of a class is its first node;
+ *   type of a node: the union over its type class of the type each
+ *     definition gives its destination dwords and each use gives the
+ *     registers it reads:
+ *       definition: the first type suffix of the mnemonic (i -> INT, u ->
+ *       UINT, f32 -> FLOAT, f64 -> DOUBLE; b and no suffix: none); a scalar
+ *       load through the kernel-argument pointer (s4 and s5 both at version
+ *       0) at dword offset o: UINT for the global offsets (o < 0x18) and the
+ *       work dimension (0x20010), none for the other hidden slots
+ *       (0x18 <= o < 0x30), else the type of the .arg covering o (none when
+ *       no argument does);
+ *       use: a mnemonic whose last suffix is typed gives that type to every
+ *       register it reads as an explicit source; a global or flat access's
+ *       address registers are pointers (the saddr pair when the record has
+ *       one, its vaddr then being an unsigned offset); an LDS address and an
+ *       s_load base are unsigned and pointer respectively;
+ *   live: a node a reachable instruction reads, or an argument of a live
+ *     merge; a live merge is a variable the method creates.
+ */
+typedef struct { uint16_t slot; uint8_t type, flags; uint32_t version, var, tclass; } or_var;
+#define VF_MERGE 1
+#define VF_LIVE 2
+
+static int suffix_type(const char *tok, int n) {
+    if (n < 2 || !(tok[0] == 'i' || tok[0] == 'u' || tok[0] == 'f' || tok[0] == 'b')) return -1;
+    for (int j = 1; j < n; j++)
+        if (tok[j] < '0' || tok[j] > '9') return -1;
+    if (tok[0] == 'i') return TY_INT;
+    if (tok[0] == 'u') return TY_UINT;
+    if (tok[0] == 'f') return (n == 3 && tok[1] == '6' && tok[2] == '4') ? TY_DOUBLE : TY_FLOAT;
+    return 0;   /* b: bits, no type */
+}
+
+/* the first and last type suffix of a mnemonic ("v_cvt_f32_u32": FLOAT, UINT) */
+static void mnemonic_types(const char *name, int *first, int *last) {
+    *first = *last = -1;
+    const char *p = name;
+    while (*p) {
+        const char *q = p;
+        while (*q && *q != '_') q++;
+        const int t = suffix_type(p, (int)(q - p));
+        if (t >= 0) {
+            if (*first < 0) *first = t;
+            *last = t;
+        }
+        p = *q ? q + 1 : q;
+    }
+    if (*first < 0) *first = 0;
+    if (*last < 0) *last = 0;
+}
+
+static uint32_t uf_find(uint32_t *par, uint32_t x) {
+    while (par[x] != x) x = par[x];
+    return x;
+}
+static void uf_union(uint32_t *par, uint32_t a, uint32_t b) {
+    a = uf_find(par, a);
+    b = uf_find(par, b);
+    if (a < b) par[b] = a;
+    else if (b < a) par[a] = b;
+}
+
+static uint8_t smem_arg_type(const or_kernel *K, const or_arg *args, uint32_t o) {
+    if (o < 0x18) return TY_UINT;
+    if (o < 0x30) return 0;
+    if (o == 0x20010) return TY_UINT;
+    for (unsigned k = 0; k < K->n_args; k++)
+        if ((uint64_t)args[k].offset <= o && (uint64_t)o < (uint64_t)args[k].offset + args[k].size) return args[k].type;
+    return 0;
+}
+
+typedef struct {
+    int32_t status;
+    uint32_t n_nodes, n_vars, n_tclasses, n_live_merges, n_ternary;
+    uint64_t digest;
+    or_var *nodes;
+} or_types_out;
+
+int or_types(const or_kernel *K, const or_instr *I, const or_arg *args, or_types_out *R) {
+    memset(R, 0, sizeof(*R));
+    or_ssa_out S;
+    or_ssa(K, I, &S);
+    R->status = S.status;
+    if (S.status != OK) {
+        or_ssa_free(&S);
+        return R->status;
+    }
+    const uint32_t n = K->n_instr;
+    /* the slots the records name, plus vcc, exec and scc */
+    uint8_t named[NSLOT];
+    memset(named, 0, sizeof(named));
+    for (unsigned v = 104; v <= 108; v++) named[v] = 1;
+    for (uint32_t i = 0; i < n; i++) {
+        const opinfo *o = &OPS[I[i].op];
+        const enum role roles[4] = {o->r0, o->r1, o->r2, o->src2};
+        const unsigned ids[4] = {I[i].r0, I[i].r1, I[i].r2, (unsigned)I[i].imm};
+        const int ws[4] = {o->w0, o->w1, o->w2, o->w_src2};
+        for (int q = 0; q < 4; q++) {
+            if (roles[q] == NO) continue;
+            for (int j = 0; j < ws[q]; j++)
+                if (ids[q] < NSLOT && ids[q] + (unsigned)j < NSLOT) named[ids[q] + (unsigned)j] = 1;
+        }
+    }
+    uint32_t base[NSLOT], N = 0;
+    for (unsigned v = 0; v < NSLOT; v++) {
+        base[v] = N;
+        if (named[v]) N += S.n_ver[v];
+    }
+    R->n_nodes = N;
+    R->nodes = (or_var *)calloc(N ? N : 1, sizeof(or_var));
+    uint32_t *pv = (uint32_t *)malloc(sizeof(uint32_t) * (N ? N : 1));   /* variable classes */
+    uint32_t *pt = (uint32_t *)malloc(sizeof(uint32_t) * (N ? N : 1));   /* type classes */
+    uint8_t *ty = (uint8_t *)calloc(N ? N : 1, 1);
+    uint8_t *live = (uint8_t *)calloc(N ? N : 1, 1);
+    for (unsigned v = 0; v < NSLOT; v++)
+        if (named[v])
+            for (uint32_t x = 0; x < S.n_ver[v]; x++) {
+                R->nodes[base[v] + x].slot = (uint16_t)v;
+                R->nodes[base[v] + x].version = x;
+            }
+    for (uint32_t x = 0; x < N; x++) pv[x] = pt[x] = x;
+
+    /* merges: one variable with each argument */
+    for (uint32_t p = 0; p < S.n_phi; p++) {
+        const uint32_t m = base[S.phi[p].slot] + S.phi[p].version;
+        R->nodes[m].flags |= VF_MERGE;
+        for (uint32_t a = S.phi_arg_off[p]; a < S.phi_arg_off[p + 1]; a++) {
+            const uint32_t y = base[S.phi[p].slot] + S.phi_arg[a];
+            uf_union(pv, m, y);
+            uf_union(pt, m, y);
+        }
+    }
+    /* instructions: types of definitions and uses, copies, ternaries */
+    for (uint32_t i = 0; i < n; i++) {
+        const or_instr *X = &I[i];
+        const opinfo *o = &OPS[X->op];
+        unsigned us[SSA_NU], ds[SSA_ND];
+        const int nu = ssa_uses(X, us), nd = ssa_defs(X, ds);
+        const uint32_t *uv = S.use_ver + (uint64_t)i * SSA_NU, *dv = S.def_ver + (uint64_t)i * SSA_ND;
+        if (nd > 0 && dv[0] == SSA_NONE) continue;   /* unreachable */
+        if (nu > 0 && uv[0] == SSA_NONE) continue;
+        int tfirst, tlast;
+        mnemonic_types(o->name, &tfirst, &tlast);
+        /* the type each use gives: walk the explicit sources as ssa_uses does */
+        const enum role roles[4] = {o->r1, o->r2, o->src2, o->r0};
+        const unsigned ids[4] = {X->r1, X->r2, (unsigned)X->imm & 0xFFFFu, X->r0};
+        const int ws[4] = {o->w1, o->w2, o->w_src2, o->w0};
+        const int has_saddr = o->r2 == SADDR && X->r2 < NSLOT;
+        int q = 0;
+        int first_use[4] = {-1, -1, -1, -1};   /* use index of each operand's first dword */
+        for (int f = 0; f < 4; f++) {
+            const enum role r = roles[f];
+            if (r == NO || r == SD || r == VD) continue;
+            if (f == 2 && o->src2 == NO) continue;
+            for (int j = 0; j < ws[f]; j++) {
+                if (!(ids[f] < NSLOT && ids[f] + (unsigned)j < NSLOT)) continue;
+                if (j == 0) first_use[f] = q;
+                uint8_t t = 0;
+                if (o->cls == C_GLOAD || o->cls == C_GSTORE || o->cls == C_FLOAD || o->cls == C_FSTORE) {
+                    if (f == 0) t = has_saddr ? TY_UINT : TY_PTR;   /* vaddr */
+                    else if (f == 1) t = TY_PTR;                     /* saddr */
+                } else if (o->cls == C_DSREAD || o->cls == C_DSWRITE) {
+                    if (f == 0) t = TY_UINT;
+                } else if (o->cls == C_SMEM) {
+                    t = TY_PTR;
+                } else if (f != 3) {
+                    t = (uint8_t)tlast;
+                }
+                const uint32_t node = base[us[q]] + uv[q];
+                ty[node] |= t;
+                live[node] = 1;
+                q++;
+            }
+        }
+        for (; q < nu; q++) live[base[us[q]] + uv[q]] = 1;   /* implicit uses */
+        /* the type each definition gives its destination dwords */
+        const int nexp = (o->r0 == SD || o->r0 == VD) ? o->w0 : 0;
+        for (int j = 0; j < nexp; j++) {
+            const uint32_t node = base[ds[j]] + dv[j];
+            uint8_t t = (uint8_t)tfirst;
+            if (o->cls == C_SMEM) {
+                t = 0;
+                if (X->r1 == 4 && uv[0] == 0 && uv[1] == 0)
+                    t = smem_arg_type(K, args, (uint32_t)X->imm + 4u * (uint32_t)j);
+            }
+            ty[node] |= t;
+        }
+        /* copies and the ternary */
+        if (o->trule == T_MOVE && first_use[0] >= 0)
+            for (int j = 0; j < nexp && j < o->w1; j++)
+                uf_union(pt, base[ds[j]] + dv[j], base[us[first_use[0] + j]] + uv[first_use[0] + j]);
+        if (o->prule == R_SEL) {
+            R->n_ternary++;
+            for (int f = 0; f < 2; f++)
+                if (first_use[f] >= 0) uf_union(pt, base[ds[0]] + dv[0], base[us[first_use[f]]] + uv[first_use[f]]);
+        }
+    }
+    /* live merges: repeat until no argument of a live merge turns live */
+    for (int changed = 1; changed;) {
+        changed = 0;
+        for (uint32_t p = 0; p < S.n_phi; p++) {
+            const uint32_t m = base[S.phi[p].slot] + S.phi[p].version;
+            if (!live[m]) continue;
+            for (uint32_t a = S.phi_arg_off[p]; a < S.phi_arg_off[p + 1]; a++) {
+                const uint32_t y = base[S.phi[p].slot] + S.phi_arg[a];
+                if (!live[y]) { live[y] = 1; changed = 1; }
+            }
+        }
+    }
+    /* the type of a class is the union over its members */
+    uint8_t *cty = (uint8_t *)calloc(N ? N : 1, 1);
+    for (uint32_t x = 0; x < N; x++) cty[uf_find(pt, x)] |= ty[x];
+    uint64_t h = 0;
+    for (uint32_t x = 0; x < N; x++) {
+        or_var *V = &R->nodes[x];
+        V->var = uf_find(pv, x);
+        V->tclass = uf_find(pt, x);
+        V->type = cty[V->tclass];
+        if (live[x]) V->flags |= VF_LIVE;
+        R->n_vars += V->var == x;
+        R->n_tclasses += V->tclass == x;
+        R->n_live_merges += (V->flags & (VF_MERGE | VF_LIVE)) == (VF_MERGE | VF_LIVE);
+        h += ssa_item(6, x, ((uint64_t)V->var << 32) | V->tclass);
+        h += ssa_item(7, x, ((uint64_t)V->slot << 48) | ((uint64_t)V->version << 16) | ((uint64_t)V->type << 8) | V->flags);
+    }
+    R->digest = h;
+    free(pv); free(pt); free(ty); free(live); free(cty);
+    or_ssa_free(&S);
+    return OK;
+}
+
+void or_types_free(or_types_out *R) { free(R->nodes); R->nodes = 0; }
+
+/* Batch driver: per kernel status, nodes, variables, type classes, live
+ * merges, ternaries and digest. */
+typedef struct {
+    int32_t status;
+    uint32_t n_nodes, n_vars, n_tclasses, n_live_merges, n_ternary;
+    uint64_t digest;
+} or_types_summary;
+
+int or_types_batch(const or_kernel *kernels, uint32_t n_kernels, const or_instr *instrs, const or_arg *args,
+                   or_types_summary *sum) {
+    for (uint32_t k = 0; k < n_kernels; k++) {
+        or_types_out R;
+        or_types(&kernels[k], instrs + kernels[k].instr_begin, args + kernels[k].arg_begin, &R);
+        memset(&sum[k], 0, sizeof(sum[k]));
+        sum[k].status = R.status;
+        if (R.status == OK) {
+            sum[k].n_nodes = R.n_nodes;
+            sum[k].n_vars = R.n_vars;
+            sum[k].n_tclasses = R.n_tclasses;
+            sum[k].n_live_merges = R.n_live_merges;
+            sum[k].n_ternary = R.n_ternary;
+            sum[k].digest = R.digest;
+        }
+        or_types_free(&R);
+    }
+    return 0;
+}
