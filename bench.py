@@ -296,6 +296,58 @@ def ssa_workload(ctx, b, stream, steps=5, cpu_kernels=2048):
             "cpu_oracle": {"instructions_per_s": sub.n_instr / cpu_dt, "cores": 1, "kernels": sub.n_kernels}}
 
 
+def types_workload(ctx, b, stream, steps=5, cpu_kernels=2048):
+    """Variables and types over the register versions (dc_build_types) of a
+    workload: whole runs (graph stages, version stages, type stage) with the
+    records in HBM; the type stage's time from HIP events on the same stream;
+    the oracle on one core over the first cpu_kernels kernels."""
+    import torch
+    import oracle
+    from paper_2107_07809_amd import dc
+    dev = dc.to_device(b.instrs)
+    t = ctx.build_types(b.kernels, dev, b.n_instr, b.args, digest=True, stream=stream)
+    dig = t.types()
+    t.free()
+    t = ctx.build_types(b.kernels, dev, b.n_instr, b.args, timing=True, digest=False, stream=stream)
+    t.run()
+    t.wait()
+    res0 = t.types()
+    t.timing_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        t.run()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    tm = t.timing()
+    res = t.types()
+    sres = t.results()
+    t.free()
+    ok = res["status"] == 0
+    runs = max(1, tm["runs"])
+    ty_ms = tm["ms_compact"] / runs
+    nodes = int(res["n_nodes"].sum())
+    # the type stage reads the records, operand versions, merges and their
+    # arguments, and writes 16 B per node
+    alg = (16 * b.n_instr + 4 * int(sres["n_operands"].sum()) + 16 * int(sres["n_phi"].sum()) +
+           4 * int(sres["n_phi_args"].sum()) + 16 * nodes + 32 * b.n_kernels)
+    sub = b.subset(np.arange(min(cpu_kernels, b.n_kernels)))
+    t0 = time.perf_counter()
+    osum = oracle.types_batch(sub)
+    cpu_dt = time.perf_counter() - t0
+    return {"instructions_per_s": b.n_instr / dt, "ms_per_step": dt * 1e3, "type_stage_ms": ty_ms,
+            "version_stages_ms": tm["ms_fixpoint"] / runs,
+            "graph_stages_ms": (tm["ms_decode"] + tm["ms_cfg"]) / runs,
+            "nodes": nodes, "variables": int(res["n_vars"].sum()), "type_classes": int(res["n_tclasses"].sum()),
+            "live_merges": int(res["n_live_merges"].sum()), "ternaries": int(res["n_ternary"].sum()),
+            "failed": int((~ok).sum()), "rerun_identical": bool(res.tobytes() == res0.tobytes()),
+            "sample_matches_oracle": bool(dig[:sub.n_kernels]["digest"].tobytes() == osum["digest"].tobytes()),
+            "counts_match_digest_run": bool(np.array_equal(dig["n_vars"], res["n_vars"]) and
+                                            np.array_equal(dig["n_live_merges"], res["n_live_merges"])),
+            "alg_bytes": alg, "type_stage_GBps": alg / (ty_ms * 1e-3) / 1e9 if ty_ms else None,
+            "cpu_oracle": {"instructions_per_s": sub.n_instr / cpu_dt, "cores": 1, "kernels": sub.n_kernels}}
+
+
 def text_workload(ctx, b, stream, steps=5, cpu_kernels=2048):
     """The text front end (dc_parse_text) on a workload rendered as one
     listing: whole runs (line starts, kinds, per-kernel counts, labels and
@@ -386,6 +438,8 @@ def extra_workloads(ctx, stream):
                                        "plain": plain, "batched_speedup": r["value"] / plain["value"]}
     log("65,536 kernels: register versions")
     out["loguniform_65536_kernels"]["ssa"] = ssa_workload(ctx, b, stream)
+    log("65,536 kernels: variables and types")
+    out["loguniform_65536_kernels"]["types"] = types_workload(ctx, b, stream)
     log("65,536 kernels: structuring")
     out["loguniform_65536_kernels"]["structure"] = struct_workload(ctx, b, stream)
     log("65,536 kernels: text front end")
@@ -539,6 +593,8 @@ def main():
                     help="time only the structuring (dc_structure) of the workload")
     ap.add_argument("--only-text", action="store_true",
                     help="time only the text front end (dc_parse_text) on the workload rendered as one listing")
+    ap.add_argument("--only-types", action="store_true",
+                    help="time only the variables and types (dc_build_types) of the workload")
     ap.add_argument("--only-ssa", action="store_true",
                     help="time only the register versions (dc_build_ssa) of the workload and print their figures")
     ap.add_argument("--lat-steps", type=int, default=5, help="runs timed one by one for the latency percentiles")
@@ -571,6 +627,13 @@ def main():
         r = text_workload(ctx, b, stream, steps=args.steps)
         ctx.close()
         print(json.dumps({"workload": desc, "kernels": b.n_kernels, "instructions": b.n_instr, "text": r}), flush=True)
+        return
+    if args.only_types:
+        ctx = dc.Context(0)
+        r = types_workload(ctx, b, stream, steps=args.steps)
+        ctx.close()
+        print(json.dumps({"workload": desc, "kernels": b.n_kernels, "instructions": b.n_instr, "types": r}),
+              flush=True)
         return
     if args.only_ssa:
         ctx = dc.Context(0)

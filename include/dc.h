@@ -537,10 +537,85 @@ dc_status_t dc_ssa_get_phi_args(dc_ssa_t *ssa, uint32_t k, uint32_t *buf, uint32
 dc_status_t dc_ssa_get_versions(dc_ssa_t *ssa, uint32_t k, uint32_t *use_ver, uint32_t *def_ver, uint32_t cap_instr,
                                 uint32_t *n_instr);
 /* Stage times (needs DC_OPT_TIMING): ms_decode, ms_cfg as for a batch,
- * ms_fixpoint = the version stages, ms_compact = 0. */
+ * ms_fixpoint = the version stages, ms_compact = the variable and type
+ * stage of an object made by dc_build_types (0 otherwise). */
 dc_status_t dc_ssa_get_timing(dc_ssa_t *ssa, dc_timing_t *out);
 dc_status_t dc_ssa_timing_reset(dc_ssa_t *ssa);
 void dc_ssa_free(dc_ssa_t *ssa);
+
+/* ------------------------------------------------------------------ */
+/* Variables and types over the register versions.                      */
+/* ------------------------------------------------------------------ */
+/* Section "Data type recovery": types come from the .arg lines of the
+ * configuration (Listing 3) and from instruction suffixes, a suffix typing
+ * the values an instruction reads as well as the one it writes (an unsigned
+ * add adds two unsigned integers).  Section "Search for control
+ * structures": a register whose value at a join depends on the path becomes
+ * a variable when it is used later; the ternary operator is one instruction
+ * (v_cndmask_b32).  Read over the versions above, per kernel:
+ *   - nodes: versions 0 .. n-1 of every register slot that some record of
+ *     the kernel names as an operand, and of vcc, exec and scc; ordered by
+ *     slot, then version (dc_var_t.slot, .version);
+ *   - var: a merge and each of its arguments are one variable (the variable
+ *     made at the join); the classes of that relation;
+ *   - tclass: the same relation, plus a move's destination dword with the
+ *     source dword it copies (s_mov_b32, s_mov_b64 dword by dword,
+ *     v_mov_b32) and v_cndmask_b32's result with each of its two values;
+ *   - a class is named by its first node (an index into the kernel's nodes);
+ *   - type: the union over the node's tclass of the type each definition
+ *     gives its destination dwords and each use gives the registers it
+ *     reads (DC_TY_* bits):
+ *       definition: the mnemonic's first type suffix (i INT, u UINT, f32
+ *       FLOAT, f64 DOUBLE; b and none: nothing); a scalar load through the
+ *       kernel-argument pointer (s4 and s5 both at version 0) at dword
+ *       offset o: UINT for o < 0x18 and o = 0x20010, nothing for
+ *       0x18 <= o < 0x30, else the .arg type of the argument covering o
+ *       (nothing when none does);
+ *       use: a mnemonic whose last suffix is typed gives it to every register
+ *       read as an explicit source; a global or flat access's address pair is
+ *       a pointer (the saddr pair when the record has one, the vaddr pair
+ *       then UINT), an s_load base a pointer, an LDS address UINT;
+ *   - flags: DC_VF_MERGE for a merge's version; DC_VF_LIVE for a node some
+ *     reachable instruction reads or that is an argument of a live merge (a
+ *     live merge is a variable the method creates);
+ *   - records that no path reaches make no versions and take no part.
+ * A kernel whose records fail their checks gets that status and nothing
+ * else. */
+#define DC_VF_MERGE 1u
+#define DC_VF_LIVE 2u
+typedef struct {
+    uint16_t slot;
+    uint8_t type;                /* DC_TY_* bits of the node's type class */
+    uint8_t flags;               /* DC_VF_* */
+    uint32_t version;
+    uint32_t var;                /* first node of the node's variable */
+    uint32_t tclass;             /* first node of the node's type class */
+} dc_var_t;                      /* 16 B */
+typedef struct {
+    dc_status_t status;
+    uint32_t n_nodes;
+    uint32_t n_vars;             /* variables (classes of var) */
+    uint32_t n_tclasses;         /* type classes */
+    uint32_t n_live_merges;
+    uint32_t n_ternary;          /* reachable v_cndmask_b32 records */
+    uint64_t digest;             /* sum over the nodes x of splitmix64(splitmix64(6 * 0x9E3779B97F4A7C15 + x) ^
+                                    (var << 32 | tclass)) and splitmix64(splitmix64(7 * 0x9E3779B97F4A7C15 + x) ^
+                                    (slot << 48 | version << 16 | type << 8 | flags)); 0 for a failed kernel or
+                                    without DC_OPT_DIGEST */
+} dc_types_result_t;             /* 32 B */
+
+/* As dc_build_ssa, plus the variables and types, for kernels whose
+ * argument tables are `args` (host, n_args entries, as dc_analyze_batch
+ * takes them; copied).  The object is a dc_ssa_t: dc_ssa_run, _wait, the
+ * version getters, _get_timing and dc_ssa_free apply; the first run also
+ * sizes the node arrays (one more wait for the stream). */
+dc_status_t dc_build_types(dc_ctx_t *ctx, const dc_kernel_t *kernels, uint32_t n_kernels, const dc_instr_t *instrs,
+                           uint64_t n_records, const dc_arg_t *args, uint64_t n_args, const dc_options_t *opts,
+                           void *stream, dc_ssa_t **out);
+/* results: the first min(cap, n_kernels) kernels; vars: kernel k's nodes in
+ * order (two-call idiom).  DC_E_INVAL on an object dc_build_ssa made. */
+dc_status_t dc_types_get_results(dc_ssa_t *ssa, dc_types_result_t *out, uint32_t cap);
+dc_status_t dc_types_get_vars(dc_ssa_t *ssa, uint32_t k, dc_var_t *buf, uint32_t cap, uint32_t *n_total);
 
 /* ------------------------------------------------------------------ */
 /* Request server: continuous batching of single-kernel analyses.       */

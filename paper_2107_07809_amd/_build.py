@@ -8,10 +8,10 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdc.so")
 SOURCES = [os.path.join(CSRC, "dc_kernels.hip"), os.path.join(CSRC, "dc_fixpoint.hip"),
            os.path.join(CSRC, "dc_noalloc.hip"), os.path.join(CSRC, "dc_plain.hip"),
-           os.path.join(CSRC, "dc_ssa.hip"),
+           os.path.join(CSRC, "dc_ssa.hip"), os.path.join(CSRC, "dc_types.hip"),
            os.path.join(CSRC, "dc_text.hip"),
            os.path.join(CSRC, "dc_struct.hip"), os.path.join(CSRC, "dc_api.cpp"), os.path.join(CSRC, "dc_text_api.cpp"), os.path.join(CSRC, "dc_server.cpp")]
-HEADERS = [os.path.join(CSRC, "dc_internal.h"), os.path.join(CSRC, "dc_fixpoint_core.h"), os.path.join(CSRC, "dc_records.h"), os.path.join(CSRC, "dc_opnames.h"), os.path.join(CSRC, "dc_host.h"), os.path.join(CSRC, "dc_isa.h"),
+HEADERS = [os.path.join(CSRC, "dc_internal.h"), os.path.join(CSRC, "dc_fixpoint_core.h"), os.path.join(CSRC, "dc_records.h"), os.path.join(CSRC, "dc_opnames.h"), os.path.join(CSRC, "dc_ssa_ops.h"), os.path.join(CSRC, "dc_host.h"), os.path.join(CSRC, "dc_isa.h"),
            os.path.join(CSRC, "dc_device.h"), os.path.join(ROOT, "include", "dc.h")]
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -70,6 +70,7 @@ struct dc_batch {
     /* a run on this graph whose stages follow the graph's (versions, structuring) */
     dc_status_t (*after_graph)(void *) = nullptr;
     void *after_graph_arg = nullptr;
+    dc_status_t (*after_fix)(void *) = nullptr;   /* a graph-only batch's last stage, timed as ms_compact */
 };
 struct dc_cfg {
     dc_batch b;
@@ -488,10 +489,12 @@ static dc_status_t enqueue(dc_batch *B) {
             const dc_status_t st = B->after_graph(B->after_graph_arg);
             if (st != DC_OK) return st;
         }
-        if (B->have_events) {
-            TRY(hipEventRecord(ev[EV_FIX], s));
-            TRY(hipEventRecord(ev[EV_END], s));
+        if (B->have_events) TRY(hipEventRecord(ev[EV_FIX], s));
+        if (B->after_fix) {
+            const dc_status_t st = B->after_fix(B->after_graph_arg);
+            if (st != DC_OK) return st;
         }
+        if (B->have_events) TRY(hipEventRecord(ev[EV_END], s));
         B->runs++;
         return DC_OK;
     }
@@ -1027,6 +1030,7 @@ struct dc_ssa {
     dc_cfg c;
     DevMem smem;   /* per-block arrays, tables and outputs, sized by the first run on these records */
     SsaPlan S{};
+    bool types = false;          /* made by dc_build_types: the variable and type stage follows */
     bool sized = false;
     bool host_valid = false;     /* results, offsets and first blocks copied since the last run */
     bool arrays_valid = false;   /* dominators, merges, arguments and versions copied since the last run */
@@ -1064,18 +1068,29 @@ static dc_status_t enqueue_ssa_stages(void *arg) {
         S.phis = nullptr;
         S.phi_args = S.vers = nullptr;
         S.tab_cap = S.phi_cap = S.arg_cap = S.ops_cap = 0;
+        S.aoff = S.tscr = nullptr;
+        S.vars = nullptr;
+        S.col_cap = S.node_cap = S.scr_cap = 0;
+        /* non-null marks the type stages in the graph stage (sized below) */
+        S.nver = X->types ? X->smem.alloc<uint32_t>(1) : nullptr;
         if (X->smem.failed) return DC_E_OOM;
         e = launch_ssa_size(P, S, s);
-        uint64_t words = 0;
+        uint64_t words = 0, cols = 0;
         if (K) total(0, &words);
+        if (K && X->types) total(4, &cols);
         if (e != hipSuccess) return hip_fail(e);
         S.tab_a = X->smem.alloc<uint32_t>(words);
         S.tab_b = X->smem.alloc<uint32_t>(words);
         S.tab_cap = words;
+        if (X->types) {
+            S.nver = X->smem.alloc<uint32_t>(cols);
+            S.col_cap = cols;
+        }
         if (X->smem.failed) return DC_E_OOM;
         e = launch_ssa_graph(P, S, s);
-        uint64_t t[3] = {0, 0, 0};
-        for (uint32_t a = 1; a <= 3 && K; a++) total(a, &t[a - 1]);
+        uint64_t t[6] = {0, 0, 0, 0, 0, 0};
+        for (uint32_t a = 1; a <= (X->types ? 6u : 3u) && K; a++)
+            if (a != 4) total(a, &t[a - 1]);
         if (e != hipSuccess) return hip_fail(e);
         S.phis = X->smem.alloc<dc_phi_t>(t[0]);
         S.phi_args = X->smem.alloc<uint32_t>(t[1]);
@@ -1083,6 +1098,13 @@ static dc_status_t enqueue_ssa_stages(void *arg) {
         S.phi_cap = t[0];
         S.arg_cap = t[1];
         S.ops_cap = t[2];
+        if (X->types) {
+            S.aoff = X->smem.alloc<uint32_t>(t[0]);
+            S.vars = X->smem.alloc<dc_var_t>(t[4]);
+            S.tscr = X->smem.alloc<uint32_t>(3 * t[5]);
+            S.node_cap = t[4];
+            S.scr_cap = t[5];
+        }
         if (X->smem.failed) return DC_E_OOM;
         X->sized = true;
     } else {
@@ -1094,34 +1116,45 @@ static dc_status_t enqueue_ssa_stages(void *arg) {
     return e == hipSuccess ? DC_OK : hip_fail(e);
 }
 
-extern "C" dc_status_t dc_build_ssa(dc_ctx_t *ctx, const dc_kernel_t *kernels, uint32_t n_kernels,
-                                    const dc_instr_t *instrs, uint64_t n_records, const dc_options_t *opts,
-                                    void *stream, dc_ssa_t **out) {
+/* the variable and type stage, after the versions */
+static dc_status_t enqueue_types_stage(void *arg) {
+    dc_ssa *X = static_cast<dc_ssa *>(arg);
+    const hipError_t e = launch_types(X->c.b.P, X->S, X->c.b.stream);
+    return e == hipSuccess ? DC_OK : hip_fail(e);
+}
+
+static dc_status_t build_ssa(dc_ctx_t *ctx, const dc_kernel_t *kernels, uint32_t n_kernels, const dc_instr_t *instrs,
+                             uint64_t n_records, const dc_arg_t *args, uint64_t n_args, const dc_options_t *opts,
+                             void *stream, bool types, dc_ssa_t **out) {
     if (!out) return DC_E_INVAL;
     *out = nullptr;
     if (opts && (opts->flags & ~(DC_OPT_TIMING | DC_OPT_DIGEST))) return DC_E_INVAL;
     dc_ssa *X = new (std::nothrow) dc_ssa;
-    X->S.digest = opts && (opts->flags & DC_OPT_DIGEST) ? 1u : 0u;
     if (!X) return DC_E_OOM;
+    X->S.digest = opts && (opts->flags & DC_OPT_DIGEST) ? 1u : 0u;
+    X->types = types;
     dc_batch *B = &X->c.b;
     /* the graph plan, as dc_build_cfg makes it, plus the per-kernel bitmaps of
-     * the register slots the records name and the per-kernel version arrays */
+     * the register slots the records name and the per-kernel version arrays;
+     * the argument tables only where the types read them */
     std::vector<dc_kernel_t> ks_noargs(kernels, kernels + (kernels ? n_kernels : 0));
-    for (auto &k : ks_noargs) {
-        k.n_args = 0;
-        k.arg_begin = 0;
-    }
+    if (!types)
+        for (auto &k : ks_noargs) {
+            k.n_args = 0;
+            k.arg_begin = 0;
+        }
     dc_options_t o{};
     if (opts) o.flags = opts->flags & DC_OPT_TIMING;
-    dc_status_t st = plan_batch(B, ctx, kernels ? ks_noargs.data() : nullptr, n_kernels, instrs, n_records, nullptr, 0,
-                                &o, stream, true);
+    dc_status_t st = plan_batch(B, ctx, kernels ? ks_noargs.data() : nullptr, n_kernels, instrs, n_records,
+                                types ? args : nullptr, types ? n_args : 0, &o, stream, true);
     if (st == DC_OK) {
         const uint64_t K = n_kernels;
         B->P.kslots = B->mem.alloc<uint32_t>(std::max<uint64_t>(K, 1) * KSLOT_WORDS);
-        X->S.counts = B->mem.alloc<uint32_t>(4 * std::max<uint64_t>(K, 1));
-        X->S.offs = B->mem.alloc<uint64_t>(4 * (K + 1));
+        X->S.counts = B->mem.alloc<uint32_t>(SSA_ARRAYS * std::max<uint64_t>(K, 1));
+        X->S.offs = B->mem.alloc<uint64_t>(SSA_ARRAYS * (K + 1));
         X->S.status = B->mem.alloc<int32_t>(std::max<uint64_t>(K, 1));
         X->S.res = B->mem.alloc<dc_ssa_result_t>(std::max<uint64_t>(K, 1));
+        if (types) X->S.tres = B->mem.alloc<dc_types_result_t>(std::max<uint64_t>(K, 1));
         if (B->mem.failed) st = DC_E_OOM;
     }
     if (st == DC_OK) {
@@ -1135,6 +1168,7 @@ extern "C" dc_status_t dc_build_ssa(dc_ctx_t *ctx, const dc_kernel_t *kernels, u
     if (st == DC_OK) {
         B->after_graph = enqueue_ssa_stages;
         B->after_graph_arg = X;
+        if (types) B->after_fix = enqueue_types_stage;
         st = enqueue(B);
     }
     if (st != DC_OK) {
@@ -1144,6 +1178,18 @@ extern "C" dc_status_t dc_build_ssa(dc_ctx_t *ctx, const dc_kernel_t *kernels, u
     }
     *out = X;
     return DC_OK;
+}
+
+extern "C" dc_status_t dc_build_ssa(dc_ctx_t *ctx, const dc_kernel_t *kernels, uint32_t n_kernels,
+                                    const dc_instr_t *instrs, uint64_t n_records, const dc_options_t *opts,
+                                    void *stream, dc_ssa_t **out) {
+    return build_ssa(ctx, kernels, n_kernels, instrs, n_records, nullptr, 0, opts, stream, false, out);
+}
+
+extern "C" dc_status_t dc_build_types(dc_ctx_t *ctx, const dc_kernel_t *kernels, uint32_t n_kernels,
+                                      const dc_instr_t *instrs, uint64_t n_records, const dc_arg_t *args,
+                                      uint64_t n_args, const dc_options_t *opts, void *stream, dc_ssa_t **out) {
+    return build_ssa(ctx, kernels, n_kernels, instrs, n_records, args, n_args, opts, stream, true, out);
 }
 
 extern "C" dc_status_t dc_ssa_run(dc_ssa_t *X, const dc_instr_t *instrs) {
@@ -1173,7 +1219,7 @@ static dc_status_t fetch_ssa(dc_ssa *X) {
     const uint32_t K = B->K;
     const SsaPlan &S = X->S;
     X->res.resize(K);
-    X->offs.resize(4 * ((size_t)K + 1));
+    X->offs.resize(SSA_ARRAYS * ((size_t)K + 1));
     X->first_block.resize(K);
     hipError_t e = hipSuccess;
     if (K) e = hipMemcpy(X->res.data(), S.res, K * sizeof(dc_ssa_result_t), hipMemcpyDeviceToHost);
@@ -1297,8 +1343,35 @@ extern "C" dc_status_t dc_ssa_get_versions(dc_ssa_t *X, uint32_t k, uint32_t *us
 extern "C" dc_status_t dc_ssa_get_timing(dc_ssa_t *X, dc_timing_t *out) {
     if (!X) return DC_E_INVAL;
     dc_status_t st = dc_get_timing(&X->c.b, out);
-    if (st == DC_OK) out->ms_compact = 0;
+    if (st == DC_OK && !X->types) out->ms_compact = 0;
     return st;
+}
+
+extern "C" dc_status_t dc_types_get_results(dc_ssa_t *X, dc_types_result_t *out, uint32_t cap) {
+    if (!X || !X->types || (cap && !out)) return DC_E_INVAL;
+    dc_batch *B = &X->c.b;
+    dc_status_t st = dc_batch_wait(B);
+    if (st != DC_OK) return st;
+    const uint32_t n = std::min<uint32_t>(cap, B->K);
+    if (n && hipMemcpy(out, X->S.tres, n * sizeof(dc_types_result_t), hipMemcpyDeviceToHost) != hipSuccess)
+        return DC_E_HIP;
+    return DC_OK;
+}
+
+extern "C" dc_status_t dc_types_get_vars(dc_ssa_t *X, uint32_t k, dc_var_t *buf, uint32_t cap, uint32_t *n_total) {
+    if (!X || !X->types || !n_total || (cap && !buf) || k >= X->c.b.K) return DC_E_INVAL;
+    dc_status_t st = fetch_ssa(X);
+    if (st != DC_OK) return st;
+    dc_types_result_t r;
+    if (hipMemcpy(&r, X->S.tres + k, sizeof(r), hipMemcpyDeviceToHost) != hipSuccess) return DC_E_HIP;
+    const uint32_t K = X->c.b.K;
+    const uint32_t nn = r.status == DC_OK ? r.n_nodes : 0;
+    *n_total = nn;
+    const uint32_t m = std::min(cap, nn);
+    if (m && hipMemcpy(buf, X->S.vars + X->offs[5 * ((size_t)K + 1) + k], m * sizeof(dc_var_t),
+                       hipMemcpyDeviceToHost) != hipSuccess)
+        return DC_E_HIP;
+    return DC_OK;
 }
 
 extern "C" dc_status_t dc_ssa_timing_reset(dc_ssa_t *X) {

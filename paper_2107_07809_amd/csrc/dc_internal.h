@@ -138,8 +138,8 @@ struct SsaPlan {
     uint32_t *idom;                 /* per global block: immediate dominator (local id), block 0 -> 0,
                                        unreachable -> DC_SSA_NONE */
     uint32_t *scr;                  /* 3 per global block: preorder scratch of kernels whose graph is not in LDS */
-    uint32_t *counts;               /* 4 x K */
-    uint64_t *offs;                 /* 4 x (K + 1): exclusive scans of counts */
+    uint32_t *counts;               /* SSA_ARRAYS x K */
+    uint64_t *offs;                 /* SSA_ARRAYS x (K + 1): exclusive scans of counts */
     int32_t *status;                /* K */
     uint32_t *tab_a;                /* per (block, slot): first version in the block | merge flag << 31 */
     uint32_t *tab_b;                /* per (block, slot): version live at the block's end */
@@ -153,7 +153,22 @@ struct SsaPlan {
     uint8_t *opn;                   /* per position: uses | definitions << 4 */
     dc_ssa_result_t *res;           /* K */
     uint32_t digest;                /* compute the per-kernel digest */
+    /* variables and types (null without them) */
+    uint32_t *nver;                 /* per (kernel, register column): versions, version 0 included */
+    uint64_t col_cap;
+    uint32_t *aoff;                 /* per merge: its first argument, relative to the kernel's arguments */
+    uint32_t *tscr;                 /* 3 per node of the kernels with more than TY_LDS_NODES nodes: variable and
+                                       type-class parents, flags | type bits */
+    uint64_t scr_cap;
+    dc_var_t *vars;                 /* per node */
+    uint64_t node_cap;
+    dc_types_result_t *tres;        /* K */
 };
+/* count arrays of the version and type stages: table words, merges, merge
+ * arguments, operands, register columns, nodes, nodes of kernels whose
+ * nodes do not fit the type stage's LDS */
+constexpr uint32_t SSA_ARRAYS = 7;
+constexpr uint32_t TY_LDS_NODES = 2048;
 /* Device arrays of a text front end run (dc_text.hip).  Sizes come from the
  * counts of the first run on a text (line ends, .kernel lines, then per
  * kernel instructions, label-table slots and user arguments). */
@@ -205,5 +220,6 @@ hipError_t launch_struct(const Plan &P, const StructPlan &S, hipStream_t s);
 hipError_t launch_ssa_size(const Plan &P, const SsaPlan &S, hipStream_t s);    /* table sizes and offsets */
 hipError_t launch_ssa_graph(const Plan &P, const SsaPlan &S, hipStream_t s);   /* dominators, merges, numbering */
 hipError_t launch_ssa_emit(const Plan &P, const SsaPlan &S, hipStream_t s);    /* merges, arguments, versions */
+hipError_t launch_types(const Plan &P, const SsaPlan &S, hipStream_t s);       /* variables and types */
 
 }  // namespace dc

@@ -47,7 +47,7 @@
  * A kernel's graph sits in LDS when it has at most SB_LDS blocks, else in
  * global memory; the same code reads both through generic pointers.
  */
-#include "dc_device.h"
+#include "dc_ssa_ops.h"
 
 namespace dc {
 
@@ -56,115 +56,6 @@ constexpr uint32_t SB_LDS = 256;                      /* blocks of a kernel whos
 constexpr uint32_t SLOTS_MAX = KSLOT_WORDS * 32;      /* 384 >= DC_NSLOT */
 constexpr uint32_t SSA_G = (SLOTS_MAX + 63) / 64;     /* table columns per lane, at most */
 constexpr uint32_t PHI_BIT = 0x80000000u;
-
-/* ------------------------------------------------------------------ */
-/* operands                                                              */
-/* ------------------------------------------------------------------ */
-struct Rec {
-    uint64_t e;
-    uint32_t id[4];   /* r0, r1, r2, third source */
-};
-__device__ __forceinline__ Rec load_rec(const Plan &P, const dc_kernel_t &D, uint32_t i) {
-    const uint4 r = reinterpret_cast<const uint4 *>(P.instrs)[D.instr_begin + i];
-    Rec x;
-    x.e = OPTAB[r.x & 0xFFFFu];
-    x.id[0] = r.x >> 16;
-    x.id[1] = r.y & 0xFFFFu;
-    x.id[2] = r.y >> 16;
-    x.id[3] = r.z & 0xFFFFu;
-    return x;
-}
-
-/* f(q, slot) for each register slot the instruction reads: the dwords of
- * r1, r2, the third source and a stored r0 that name slots, then the
- * implicit vcc, exec, scc uses */
-template <typename F>
-__device__ __forceinline__ uint32_t for_uses(const Rec &x, F f) {
-    uint32_t q = 0;
-    const int order[4] = {1, 2, 3, 0};
-#pragma unroll
-    for (int t = 0; t < 4; t++) {
-        const int o = order[t];
-        const uint32_t role = e_role(x.e, o);
-        if (role == RO_NO || role == RO_SD || role == RO_VD) continue;
-        const uint32_t w = e_width(x.e, o), v = x.id[o];
-#pragma unroll
-        for (uint32_t j = 0; j < 4; j++)
-            if (j < w && v + j < (uint32_t)NSLOT) f(q++, v + j);
-    }
-    const uint32_t iu = e_iuse(x.e);
-    if (iu & IM_VCC) {
-        f(q++, 104u);
-        f(q++, 105u);
-    }
-    if (iu & IM_EXEC) {
-        f(q++, 106u);
-        f(q++, 107u);
-    }
-    if (iu & IM_SCC) f(q++, 108u);
-    return q;
-}
-
-/* f(q, slot, again) for each definition: the destination dwords, then the
- * implicit vcc, exec, scc; again = 1 when the destination already wrote the
- * slot in this instruction (an implicit pair that the destination names) */
-template <typename F>
-__device__ __forceinline__ uint32_t for_defs(const Rec &x, F f) {
-    uint32_t q = 0;
-    const uint32_t r0 = e_role(x.e, 0);
-    const bool ex = r0 == RO_SD || r0 == RO_VD;
-    const uint32_t w0 = ex ? e_width(x.e, 0) : 0u, v0 = x.id[0];
-#pragma unroll
-    for (uint32_t j = 0; j < 4; j++)
-        if (j < w0) f(q++, v0 + j, 0u);
-    auto again = [&](uint32_t v) { return (ex && v >= v0 && v < v0 + w0) ? 1u : 0u; };
-    const uint32_t idf = e_idef(x.e);
-    if (idf & IM_VCC) {
-        f(q++, 104u, again(104u));
-        f(q++, 105u, again(105u));
-    }
-    if (idf & IM_EXEC) {
-        f(q++, 106u, again(106u));
-        f(q++, 107u, again(107u));
-    }
-    if (idf & IM_SCC) f(q++, 108u, again(108u));
-    return q;
-}
-__device__ __forceinline__ uint32_t n_uses(const Rec &x) {
-    return for_uses(x, [](uint32_t, uint32_t) {});
-}
-__device__ __forceinline__ uint32_t n_defs(const Rec &x) {
-    return for_defs(x, [](uint32_t, uint32_t, uint32_t) {});
-}
-
-/* ------------------------------------------------------------------ */
-/* wavefront helpers                                                     */
-/* ------------------------------------------------------------------ */
-__device__ __forceinline__ uint64_t ssa_item(uint64_t kind, uint64_t index, uint64_t value) {
-    return mix64(mix64(kind * 0x9E3779B97F4A7C15ull + index) ^ value);
-}
-__device__ __forceinline__ uint64_t wave_sum64(uint64_t x) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
-    return x;
-}
-__device__ __forceinline__ uint32_t wave_sum32(uint32_t x) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
-    return x;
-}
-/* exclusive prefix over the lanes; *total = the sum over all lanes */
-__device__ __forceinline__ uint32_t wave_excl(uint32_t x, uint32_t *total) {
-    const uint32_t l = lane_id();
-    uint32_t y = x;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t t = __shfl_up(y, d, 64);
-        if (l >= (uint32_t)d) y += t;
-    }
-    *total = __shfl(y, 63, 64);
-    return y - x;
-}
 
 /* The kernel's register slots (those its records name, plus vcc, exec and
  * scc) in ascending order: rank[slot] = table column; slot[column] when
@@ -194,7 +85,8 @@ __device__ __forceinline__ uint32_t slot_count(const uint32_t *ks) {
     return n;
 }
 
-/* offsets of count array a (0 table words, 1 merges, 2 merge arguments, 3 operands) */
+/* offsets of count array a (0 table words, 1 merges, 2 merge arguments, 3 operands; with the types 4
+ * register columns, 5 nodes, 6 nodes of kernels over TY_LDS_NODES) */
 __device__ __forceinline__ uint64_t soff(const SsaPlan &S, uint32_t K, uint32_t a, uint32_t k) {
     return S.offs[(uint64_t)a * (K + 1) + k];
 }
@@ -205,9 +97,9 @@ __device__ __forceinline__ uint64_t soff(const SsaPlan &S, uint32_t K, uint32_t 
 __global__ __launch_bounds__(256) void k_ssa_size(Plan P, SsaPlan S) {
     const uint32_t k = blockIdx.x * 256 + threadIdx.x;
     if (k >= P.n_kernels) return;
-    uint32_t n = 0;
-    if (P.status[k] == DC_OK) n = P.n_blocks[k] * slot_count(P.kslots + (uint64_t)k * KSLOT_WORDS);
-    S.counts[k] = n;
+    const uint32_t U = P.status[k] == DC_OK ? slot_count(P.kslots + (uint64_t)k * KSLOT_WORDS) : 0u;
+    S.counts[k] = P.n_blocks[k] * U;
+    if (S.nver) S.counts[4ull * P.n_kernels + k] = U;
 }
 
 /* ------------------------------------------------------------------ */
@@ -266,11 +158,16 @@ __global__ __launch_bounds__(64) void k_ssa_graph(Plan P, SsaPlan S) {
     int32_t st = P.status[k];
     const uint64_t tab0 = soff(S, K, 0, k);
     if (st == DC_OK && soff(S, K, 0, k + 1) > S.tab_cap) st = DC_E_CAPACITY;
+    if (st == DC_OK && S.nver && soff(S, K, 4, k + 1) > S.col_cap) st = DC_E_CAPACITY;
     if (st != DC_OK) {
         S.status[k] = st;
         S.counts[(uint64_t)K + k] = 0;
         S.counts[2ull * K + k] = 0;
         S.counts[3ull * K + k] = 0;
+        if (S.nver) {
+            S.counts[5ull * K + k] = 0;
+            S.counts[6ull * K + k] = 0;
+        }
         return;
     }
     const uint32_t nb = P.n_blocks[k], fb = P.first_block[k], nreach = P.n_reach[k], pb = P.pos_begin[k];
@@ -431,6 +328,20 @@ __global__ __launch_bounds__(64) void k_ssa_graph(Plan P, SsaPlan S) {
             }
         }
     }
+    /* versions per column (version 0 included), for the types */
+    uint32_t nnodes = 0;
+    if (S.nver) {
+        uint32_t *nv = S.nver + soff(S, K, 4, k);
+#pragma unroll
+        for (uint32_t g = 0; g < SSA_G; g++) {
+            const uint32_t u = l + 64 * g;
+            if (g < G && u < U) {
+                nv[u] = run[g];
+                nnodes += run[g];
+            }
+        }
+        nnodes = wave_sum32(nnodes);
+    }
     uint32_t nops = 0;
     for (uint32_t i = l; i < n; i += 64) {
         const Rec x = load_rec(P, D, i);
@@ -445,6 +356,10 @@ __global__ __launch_bounds__(64) void k_ssa_graph(Plan P, SsaPlan S) {
     S.counts[(uint64_t)K + k] = nphi;
     S.counts[2ull * K + k] = nargs;
     S.counts[3ull * K + k] = nops;
+    if (S.nver) {
+        S.counts[5ull * K + k] = nnodes;
+        S.counts[6ull * K + k] = nnodes > TY_LDS_NODES ? nnodes : 0u;
+    }
 }
 
 /* ------------------------------------------------------------------ */
@@ -616,6 +531,7 @@ hipError_t launch_ssa_size(const Plan &P, const SsaPlan &S, hipStream_t s) {
     if (!K) return hipSuccess;
     hipLaunchKernelGGL(k_ssa_size, dim3((K + 255) / 256), dim3(256), 0, s, P, S);
     hipLaunchKernelGGL(k_ssa_scan, dim3(1), dim3(1024), 0, s, S, K, 0u);
+    if (S.nver) hipLaunchKernelGGL(k_ssa_scan, dim3(1), dim3(1024), 0, s, S, K, 4u);
     return hipGetLastError();
 }
 hipError_t launch_ssa_graph(const Plan &P, const SsaPlan &S, hipStream_t s) {
@@ -623,6 +539,7 @@ hipError_t launch_ssa_graph(const Plan &P, const SsaPlan &S, hipStream_t s) {
     if (!K) return hipSuccess;
     hipLaunchKernelGGL(k_ssa_graph, dim3(K), dim3(64), 0, s, P, S);
     hipLaunchKernelGGL(k_ssa_scan, dim3(3), dim3(1024), 0, s, S, K, 1u);
+    if (S.nver) hipLaunchKernelGGL(k_ssa_scan, dim3(2), dim3(1024), 0, s, S, K, 5u);
     return hipGetLastError();
 }
 hipError_t launch_ssa_emit(const Plan &P, const SsaPlan &S, hipStream_t s) {

@@ -39,6 +39,12 @@ SSA_NU, SSA_ND, SSA_NONE = 13, 9, 0xFFFFFFFF
 PHI_DTYPE = np.dtype([("block", "<u4"), ("slot", "<u2"), ("pad", "<u2"), ("version", "<u4")])
 SSA_RESULT_DTYPE = np.dtype([("status", "<i4"), ("n_blocks", "<u4"), ("n_phi", "<u4"), ("n_phi_args", "<u4"),
                              ("n_operands", "<u4"), ("pad", "<u4"), ("digest", "<u8")])
+# variables and types (dc_build_types)
+VF_MERGE, VF_LIVE = 1, 2
+VAR_DTYPE = np.dtype([("slot", "<u2"), ("type", "u1"), ("flags", "u1"), ("version", "<u4"), ("var", "<u4"),
+                      ("tclass", "<u4")])
+TYPES_RESULT_DTYPE = np.dtype([("status", "<i4"), ("n_nodes", "<u4"), ("n_vars", "<u4"), ("n_tclasses", "<u4"),
+                               ("n_live_merges", "<u4"), ("n_ternary", "<u4"), ("digest", "<u8")])
 # structuring (dc_structure)
 RG_LINEAR, RG_IF, RG_IFELSE, RG_WHILE, RG_LOOP = 1, 2, 3, 4, 5
 MERGE_DTYPE = np.dtype([("region", "<u4"), ("kind", "u1"), ("n", "u1"), ("pad", "<u2"), ("member", "<u4", (4,))])
@@ -159,6 +165,9 @@ SIGNATURES = [
     ("dc_ssa_get_timing", I32, [VP, ctypes.POINTER(Timing)]),
     ("dc_ssa_timing_reset", I32, [VP]),
     ("dc_ssa_free", None, [VP]),
+    ("dc_build_types", I32, [VP, VP, U32, VP, U64, VP, U64, ctypes.POINTER(Options), VP, ctypes.POINTER(VP)]),
+    ("dc_types_get_results", I32, [VP, VP, U32]),
+    ("dc_types_get_vars", I32, [VP, U32, VP, U32, ctypes.POINTER(U32)]),
     ("dc_server_create", I32, [VP, ctypes.POINTER(ServerOpts), ctypes.POINTER(VP)]),
     ("dc_server_submit", I32, [VP, VP, ctypes.POINTER(U64)]),
     ("dc_server_poll", I32, [VP, VP, U32, ctypes.POINTER(U32)]),
@@ -338,6 +347,20 @@ class Context:
         h = VP()
         check("dc_build_ssa", lib().dc_build_ssa(self.h, _np_ptr(kernels), len(kernels), _dev_ptr(instrs_dev),
                                                  n_records, ctypes.byref(o), _stream_ptr(stream), ctypes.byref(h)))
+        return Ssa(h, kernels, instrs_dev)
+
+    def build_types(self, kernels, instrs_dev, n_records, args=None, timing=False, digest=True,
+                    stream=None) -> "Ssa":
+        """Versions plus variables and types (dc_build_types); the object's
+        types() and vars(k) read the latter."""
+        kernels = np.ascontiguousarray(np.asarray(kernels, KERNEL_DTYPE))
+        args = np.ascontiguousarray(np.asarray(args if args is not None else np.zeros(0, ARG_DTYPE), ARG_DTYPE))
+        o = Options()
+        o.flags = (OPT_TIMING if timing else 0) | (OPT_DIGEST if digest else 0)
+        h = VP()
+        check("dc_build_types", lib().dc_build_types(self.h, _np_ptr(kernels), len(kernels), _dev_ptr(instrs_dev),
+                                                     n_records, _np_ptr(args), len(args), ctypes.byref(o),
+                                                     _stream_ptr(stream), ctypes.byref(h)))
         return Ssa(h, kernels, instrs_dev)
 
 
@@ -587,10 +610,19 @@ class Ssa:
                                                                ctypes.byref(m)))
         return use, dfn
 
+    def types(self) -> np.ndarray:
+        out = np.zeros(self.n_kernels, TYPES_RESULT_DTYPE)
+        check("dc_types_get_results", lib().dc_types_get_results(self.h, _np_ptr(out), self.n_kernels))
+        return out
+
+    def vars(self, k: int) -> np.ndarray:
+        return self._get("dc_types_get_vars", k, VAR_DTYPE)
+
     def timing(self) -> dict:
+        """Stage times; ms_compact is the variable and type stage."""
         t = Timing()
         check("dc_ssa_get_timing", lib().dc_ssa_get_timing(self.h, ctypes.byref(t)))
-        return {k: getattr(t, k) for k, _ in t._fields_ if k not in ("pad", "ms_pad", "ms_compact")}
+        return {k: getattr(t, k) for k, _ in t._fields_ if k not in ("pad", "ms_pad")}
 
     def timing_reset(self):
         check("dc_ssa_timing_reset", lib().dc_ssa_timing_reset(self.h))

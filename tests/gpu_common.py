@@ -111,3 +111,35 @@ def compare_struct_summaries(gpu_res, summ):
     for f in ("status", "n_blocks", "n_merges", "n_left", "root", "digest"):
         bad = np.nonzero(gpu_res[f] != summ[f])[0]
         assert len(bad) == 0, (f, bad[:10], gpu_res[f][bad[:10]], summ[f][bad[:10]])
+
+
+def _oracle_types_chunk(args):
+    cfg, i0, n = args
+    b = dcgen.generate(cfg, n, i0=i0, threads=1)
+    return oracle.types_batch(b)
+
+
+class OracleTypesRun:
+    """Oracle variable and type summaries for kernels [0, n) of a config, in
+    parallel worker processes started at construction."""
+
+    def __init__(self, cfg: int, n: int, procs: int = 0, jobs_per_proc: int = 4):
+        procs = procs or min(16, os.cpu_count() or 1)
+        step = max(1, (n + procs * jobs_per_proc - 1) // (procs * jobs_per_proc))
+        self.ex = ProcessPoolExecutor(procs)
+        self.futs = [self.ex.submit(_oracle_types_chunk, (cfg, i, min(step, n - i))) for i in range(0, n, step)]
+
+    def result(self):
+        parts = [f.result() for f in self.futs]
+        self.ex.shutdown()
+        return np.concatenate(parts)
+
+
+def compare_types_summaries(gpu_res, summ, digest: bool = True):
+    """Per-kernel status, node, variable, type-class, live-merge and ternary
+    counts and the digest over every node."""
+    assert len(gpu_res) == len(summ)
+    fields = ["status", "n_nodes", "n_vars", "n_tclasses", "n_live_merges", "n_ternary"] + (["digest"] if digest else [])
+    for f in fields:
+        bad = np.nonzero(gpu_res[f] != summ[f])[0]
+        assert len(bad) == 0, (f, bad[:10], gpu_res[f][bad[:10]], summ[f][bad[:10]])
