@@ -24,10 +24,12 @@
  *      follow from a few lane-parallel passes over that def-use graph: the
  *      graph is acyclic, so the passes reach its unique solution after as many
  *      passes as the longest def-use chain.
- *   4. Payloads.  Only instructions whose result can be other than TOP run in a
- *      wave-uniform loop, in order; every payload rule gives TOP when one of
- *      its inputs is TOP (and, except the move and select rules, when one is
- *      uninitialised), so the others are TOP without evaluation.
+ *   4. Payloads.  Only instructions whose result can be other than TOP run
+ *      their payload rule; every rule gives TOP when one of its inputs is TOP
+ *      (and, except the move and select rules, when one is uninitialised), so
+ *      the others are TOP without evaluation.  The rules run lane-parallel by
+ *      levels of the chunk's def-use graph: a lane runs once every lane whose
+ *      definition it reads has run.
  *   5. Emission on every visit.  The lanes build the chunk's access and
  *      built-in records and write them compacted (ballot prefix) into the
  *      block's region of the sparse outputs; a block's last visit runs on its

@@ -759,10 +759,10 @@ __device__ __forceinline__ void run_chunk(const Plan *__restrict__ P, WaveLds &L
     __builtin_amdgcn_wave_barrier();
 
     /* ---- payloads of the instructions whose result may be other than TOP ---- */
-    /* Payload sources A0 A1 B0 B1 C0 of each lane: a definition dword 0 or 1
-     * of an earlier lane is read from that lane's registers (dv0, dv1) as the
-     * loop produces it; dwords 2 and 3 (wide SMEM) from LDS; anything else
-     * (block state, constant, TOP) is gathered before the loop into sv. */
+    /* Payload sources A0 A1 B0 B1 C0 of each lane: a definition of an earlier
+     * lane of the chunk is read from the value table once that lane's level
+     * has run; anything else (block state, constant, TOP) is gathered first
+     * into sv. */
     const bool live = (alu && prule != PR_TOP && prule != PR_NONE && ((o0 >> 32) & FT_T)) ||
                       (alu && prule != PR_TOP && prule != PR_NONE && I.ndef == 2 && ((o1 >> 32) & FT_T)) || via;
     uint32_t dv0lo = 0xFFFFFFFFu, dv0hi = 0xFFFFFFFFu, dv1lo = 0xFFFFFFFFu, dv1hi = 0xFFFFFFFFu;
@@ -779,13 +779,13 @@ __device__ __forceinline__ void run_chunk(const Plan *__restrict__ P, WaveLds &L
             const uint64_t sv = x == IX_CONST ? C32(kq[q]) : (x < IX_DEF ? v : VTOP);
             svlo[q] = (uint32_t)sv;
             svhi[q] = (uint32_t)(sv >> 32);
-            /* source mode: 0 sv, 1 register of lane pl (k = 0 / 1 in bit 7), 2 LDS entry x */
+            /* source mode: 0 sv, 1 definition dword k (0 or 1, in bit 7) of lane pl, 2 table entry x */
             sd[q] = def && k < 2 ? (1u << 16) | pl | k << 7 : (def && k < 4 ? (2u << 16) | x : 0u);
         }
         /* A move whose source dwords are not definitions of this chunk
-         * (block state, constant) takes its payload now, outside the loop.
+         * (block state, constant) takes its payload now, before the levels.
          * Each lane also records which sources its rule reads (bit q of the
-         * mask for source q), so the loop fetches only those. */
+         * mask for source q), so the levels fetch only those. */
         const uint32_t m0 = sd[0] >> 16, m1 = sd[1] >> 16;
         const bool wide = I.ndef >= 2;
         const bool mv = live && prule == PR_MOV && m0 == 0u && (!wide || m1 == 0u);
@@ -799,56 +799,71 @@ __device__ __forceinline__ void run_chunk(const Plan *__restrict__ P, WaveLds &L
                               : (rr == PR_AND64 || rr == PR_OR64 || rr == PR_XOR64 || rr == PR_ANDN264) ? 0x0Fu
                               : rr == PR_SHL64 ? 0x0Du : 0x05u;
         sd[0] |= need << 18;
-        __builtin_amdgcn_wave_barrier();
-        uint64_t lm = ballot(live && !mv);
-        while (lm) {
-            const uint32_t i = (uint32_t)__builtin_ctzll(lm);
-            lm &= lm - 1;
-            const uint64_t ei = ((uint64_t)rdl(I.ehi, i) << 32) | rdl(I.elo, i);
-            const uint32_t ci = e_cls(ei), wi = e_width(ei, 0);
-            uint64_t vq[5];
-            const uint32_t nd = rdl(sd[0], i) >> 18;
+        const uint32_t nq = need;
+        /* Levels: a lane whose rule still has to run sits one level above the
+         * highest lane whose definition it reads (always an earlier lane), so
+         * the lanes of one level read only results of lower levels.  The
+         * levels run in order, each one lane-parallel; a result goes to the
+         * lane's own entries of the value table, where the next levels read
+         * it. */
+        const bool ev = live && !mv;
+        uint32_t lev = ev ? 1u : 0u;
+        for (;;) {
+            uint32_t nl = ev ? 1u : 0u;
 #pragma unroll
             for (int q = 0; q < 5; q++) {
-                vq[q] = VTOP;
-                if (!((nd >> q) & 1u)) continue;
-                const uint32_t d = rdl(sd[q], i);
-                const uint32_t mode = (d >> 16) & 3u;
-                if (mode == 1) {
-                    const uint32_t pl = d & 63u;
-                    vq[q] = (d & 128u) ? ((uint64_t)rdl(dv1hi, pl) << 32) | rdl(dv1lo, pl)
-                                       : ((uint64_t)rdl(dv0hi, pl) << 32) | rdl(dv0lo, pl);
-                } else if (mode == 2) {
-                    vq[q] = lds_val(L, d & 0xFFFFu);
-                } else {
-                    vq[q] = ((uint64_t)rdl(svhi[q], i) << 32) | rdl(svlo[q], i);
-                }
+                const uint32_t d = sd[q], mode = (d >> 16) & 3u;
+                const uint32_t pl = mode == 1u ? (d & 63u) : (((d & 0xFFFFu) - IX_DEF) & 63u);
+                const uint32_t lp = __shfl(lev, (int)pl, 64);
+                nl = (ev && ((nq >> q) & 1u) && mode != 0u) ? max(nl, lp + 1u) : nl;
             }
-            uint64_t v0 = VTOP, v1 = VTOP;
-            const bool me = l == i;
-            if (ci == C_SMEM) {
-                const uint32_t off = rdl(I.imm, i);
-                const bool ok = vq[0] == pv(T_SYSPTR, IG_LO, 0, 0, 0, 0, 0) && vq[1] == pv(T_SYSPTR, IG_HI, 0, 0, 0, 0, 0);
-                for (uint32_t j = 0; j < wi; j++) {
-                    uint32_t pr, ty;
-                    uint64_t va;
-                    smem_dword(K, wi, off, j, pr, ty, va);
-                    va = ok ? va : VTOP;
-                    if (j == 0) v0 = va;
-                    else if (j == 1) v1 = va;
-                    else lds_put_u64(L, &L.fv[IX_DEF + j * 64 + i], va);
-                }
-            } else {
-                eval_rule(K, e_prule(ei), e_vsrc(ei) == 1u, vq[0], vq[1], vq[2], vq[3], vq[4], v0, v1);
-            }
-            dv0lo = me ? (uint32_t)v0 : dv0lo;
-            dv0hi = me ? (uint32_t)(v0 >> 32) : dv0hi;
-            dv1lo = me && wi >= 2 ? (uint32_t)v1 : dv1lo;
-            dv1hi = me && wi >= 2 ? (uint32_t)(v1 >> 32) : dv1hi;
+            const bool ch = nl != lev;
+            lev = nl;
+            if (ballot(ch) == 0) break;
         }
+        uint32_t top = lev;
+#pragma unroll
+        for (int dd = 32; dd >= 1; dd >>= 1) top = max(top, (uint32_t)__shfl_xor(top, dd, 64));
+        top = rfl(top);
         L.fv[IX_DEF + l] = ((uint64_t)dv0hi << 32) | dv0lo;
         L.fv[IX_DEF + 64 + l] = ((uint64_t)dv1hi << 32) | dv1lo;
         __builtin_amdgcn_wave_barrier();
+        const uint64_t ei = e;
+        const uint32_t wi = e_width(ei, 0);
+        for (uint32_t lv = 1; lv <= top; lv++) {
+            uint64_t vq[5];
+#pragma unroll
+            for (int q = 0; q < 5; q++) {
+                const uint32_t d = sd[q], mode = (d >> 16) & 3u;
+                const uint32_t x = mode == 1u ? IX_DEF + ((d >> 7) & 1u) * 64u + (d & 63u)
+                                              : (mode == 2u ? (d & 0xFFFFu) : IX_ZERO);
+                const uint64_t tv = L.fv[x];
+                const uint64_t sv = ((uint64_t)svhi[q] << 32) | svlo[q];
+                vq[q] = ((nq >> q) & 1u) ? (mode != 0u ? tv : sv) : VTOP;
+            }
+            if (lev == lv) {
+                uint64_t v0 = VTOP, v1 = VTOP;
+                if (cls == C_SMEM) {
+                    const uint32_t off = I.imm;
+                    const bool ok = vq[0] == pv(T_SYSPTR, IG_LO, 0, 0, 0, 0, 0) &&
+                                    vq[1] == pv(T_SYSPTR, IG_HI, 0, 0, 0, 0, 0);
+                    for (uint32_t j = 0; j < wi; j++) {
+                        uint32_t pr, ty;
+                        uint64_t va;
+                        smem_dword(K, wi, off, j, pr, ty, va);
+                        va = ok ? va : VTOP;
+                        if (j == 0) v0 = va;
+                        else if (j == 1) v1 = va;
+                        else L.fv[IX_DEF + j * 64 + l] = va;
+                    }
+                } else {
+                    eval_rule(K, e_prule(ei), e_vsrc(ei) == 1u, vq[0], vq[1], vq[2], vq[3], vq[4], v0, v1);
+                }
+                L.fv[IX_DEF + l] = v0;
+                if (wi >= 2) L.fv[IX_DEF + 64 + l] = v1;
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
     }
     __builtin_amdgcn_wave_barrier();
 
@@ -893,13 +908,15 @@ __device__ __forceinline__ void run_chunk(const Plan *__restrict__ P, WaveLds &L
             dt = (v_arg(addr) < 64 ? L.argf[v_arg(addr)] : K.args[v_arg(addr)].flags) & 31u;
         }
         const uint64_t am = ballot(mem);
-        const uint32_t apos = E.ta + lanes_below(am);
-        /* a region holds every record its block can emit; the bound only
-         * keeps a wrong capacity from writing outside it */
-        uint4 *adst = mem && apos < E.acap ? reinterpret_cast<uint4 *>(P->acc_sparse) + E.ab + apos : dummy + l;
-        *adst = make_uint4(g0 + l - pos0, kind | space << 8 | width << 16 | dt << 24, (uint32_t)addr,
-                           (uint32_t)(addr >> 32));
-        E.ta += (uint32_t)__builtin_popcountll(am);
+        if (am) {   /* wave-uniform */
+            const uint32_t apos = E.ta + lanes_below(am);
+            /* a region holds every record its block can emit; the bound only
+             * keeps a wrong capacity from writing outside it */
+            uint4 *adst = mem && apos < E.acap ? reinterpret_cast<uint4 *>(P->acc_sparse) + E.ab + apos : dummy + l;
+            *adst = make_uint4(g0 + l - pos0, kind | space << 8 | width << 16 | dt << 24, (uint32_t)addr,
+                               (uint32_t)(addr >> 32));
+            E.ta += (uint32_t)__builtin_popcountll(am);
+        }
 
         /* built-ins: explicit definitions not overwritten by an implicit one */
         auto sys_kind = [&](uint32_t j, uint32_t &dim) -> int {
@@ -909,24 +926,28 @@ __device__ __forceinline__ void run_chunk(const Plan *__restrict__ P, WaveLds &L
                                  ((idf & IM_SCC) && slot == 108u);
             return j < I.ndef && !covered ? builtin_kind(L.fv[IX_DEF + j * 64 + l], dim) : -1;
         };
-        uint32_t ns = 0;
+        uint32_t skd[4], ns = 0;   /* kind | dim << 8 of each definition dword, 0xFF none */
 #pragma unroll
-        for (uint32_t j = 0; j < 4; j++) {
-            uint32_t dim;
-            ns += sys_kind(j, dim) >= 0 ? 1u : 0u;
-        }
-        uint32_t tot;
-        uint32_t spos = E.ts + wave_excl_scan(ns, tot);
         for (uint32_t j = 0; j < 4; j++) {
             uint32_t dim = 0;
             const int kd = sys_kind(j, dim);
-            const bool has = kd >= 0;
-            uint2 *sdst = has && spos < E.scap ? reinterpret_cast<uint2 *>(P->sys_sparse) + E.sb + spos
-                              : reinterpret_cast<uint2 *>(dummy + l);
-            *sdst = make_uint2(g0 + l - pos0, (r0 + j) | (uint32_t)(has ? kd : 0) << 16 | (has ? dim : 0u) << 24);
-            spos += has ? 1u : 0u;
+            skd[j] = kd >= 0 ? (uint32_t)kd | dim << 8 : 0xFFu;
+            ns += kd >= 0 ? 1u : 0u;
         }
-        E.ts += tot;
+        if (ballot(ns != 0)) {   /* wave-uniform: most chunks define no built-in */
+            uint32_t tot;
+            uint32_t spos = E.ts + wave_excl_scan(ns, tot);
+#pragma unroll
+            for (uint32_t j = 0; j < 4; j++) {
+                const bool has = skd[j] != 0xFFu;
+                uint2 *sdst = has && spos < E.scap ? reinterpret_cast<uint2 *>(P->sys_sparse) + E.sb + spos
+                                  : reinterpret_cast<uint2 *>(dummy + l);
+                *sdst = make_uint2(g0 + l - pos0,
+                                   (r0 + j) | (has ? (skd[j] & 0xFFu) : 0u) << 16 | (has ? skd[j] >> 8 : 0u) << 24);
+                spos += has ? 1u : 0u;
+            }
+            E.ts += tot;
+        }
     }
     __builtin_amdgcn_wave_barrier();
 
