@@ -226,19 +226,44 @@ __device__ bool label_find(const Labels &L, Sp name, uint32_t *index) {
     return false;
 }
 
-__device__ int find_op(Sp w, const char (*names)[24]) {
-    for (int op = 0; op < N_OPS; op++) {
-        const char *nm = names[op];
+/* Mnemonic lookup: an open-addressing table of OP_TAB slots in LDS, keyed by
+ * a 32-bit FNV-1a hash of the lower-case mnemonic, holding op + 1 (0 empty);
+ * a hit is confirmed by comparing the names. */
+constexpr uint32_t OP_TAB = 256;
+__device__ __forceinline__ uint32_t op_hash(const uint8_t *p, uint32_t n) {
+    uint32_t h = 2166136261u;
+    for (uint32_t i = 0; i < n; i++) h = (h ^ lower(p[i])) * 16777619u;
+    return h;
+}
+/* every thread of the group calls it; thread t inserts op t */
+__device__ void op_table_build(uint32_t *tab, const char (*names)[24]) {
+    const uint32_t t = threadIdx.x;
+    for (uint32_t i = t; i < OP_TAB; i += blockDim.x) tab[i] = 0;
+    __syncthreads();
+    for (uint32_t op = t; op < (uint32_t)N_OPS; op += blockDim.x) {
+        uint32_t n = 0;
+        while (names[op][n]) n++;
+        for (uint32_t slot = op_hash((const uint8_t *)names[op], n) & (OP_TAB - 1), m = 0; m < OP_TAB;
+             slot = (slot + 1) & (OP_TAB - 1), m++)
+            if (atomicCAS(&tab[slot], 0u, op + 1u) == 0u) break;
+    }
+    __syncthreads();
+}
+__device__ int find_op(Sp w, const char (*names)[24], const uint32_t *tab) {
+    for (uint32_t slot = op_hash(w.p, w.n) & (OP_TAB - 1), m = 0; m < OP_TAB; slot = (slot + 1) & (OP_TAB - 1), m++) {
+        const uint32_t e = tab[slot];
+        if (e == 0) return -1;
+        const char *nm = names[e - 1];
         uint32_t i = 0;
         for (; nm[i]; i++)
             if (i >= w.n || lower(w.p[i]) != (uint8_t)nm[i]) break;
-        if (!nm[i] && i == w.n) return op;
+        if (!nm[i] && i == w.n) return (int)e - 1;
     }
     return -1;
 }
 
 /* one instruction line -> record */
-__device__ dc_instr_t parse_instr(Sp line, const Labels &L, const char (*names)[24]) {
+__device__ dc_instr_t parse_instr(Sp line, const Labels &L, const char (*names)[24], const uint32_t *optab) {
     dc_instr_t r;
     r.op = TX_NONE;
     r.r0 = r.r1 = r.r2 = TX_NONE;
@@ -246,7 +271,7 @@ __device__ dc_instr_t parse_instr(Sp line, const Labels &L, const char (*names)[
     r.target = -1;
     Sp rest;
     const Sp w = word(line, &rest);
-    const int op = find_op(w, names);
+    const int op = find_op(w, names, optab);
     if (op < 0) return r;
     r.op = (uint16_t)op;
     const uint64_t e = OPTAB[op];
@@ -625,11 +650,14 @@ __global__ __launch_bounds__(TX_T) void k_tx_kernel1(TextPlan T) {
 __global__ __launch_bounds__(TX_T) void k_tx_kernel2(TextPlan T) {
     __shared__ uint32_t ws[4];
     __shared__ char names[N_OPS][24];
+    __shared__ uint32_t s_optab[OP_TAB];
     __shared__ uint32_t s_dims, s_cws, s_use;
     __shared__ uint8_t s_txt[TX_STAGE];
     const uint32_t k = blockIdx.x, K = T.n_kernels, t = threadIdx.x;
     if (k >= K || K > T.k_cap || *T.fail) return;
     for (uint32_t i = t; i < N_OPS * 24; i += TX_T) (&names[0][0])[i] = (&OPN[0][0])[i];
+    __syncthreads();
+    op_table_build(s_optab, names);
     if (t == 0) {
         s_dims = s_cws = s_use = 0;
     }
@@ -703,7 +731,7 @@ __global__ __launch_bounds__(TX_T) void k_tx_kernel2(TextPlan T) {
         if (is_i && icount + xi < ni) {
             Sp ln = line_clean(T, j);
             if (staged && ln.n) ln.p = s_txt + (ln.p - (T.text + cs));
-            T.instrs[ib + icount + xi] = parse_instr(ln, L, names);
+            T.instrs[ib + icount + xi] = parse_instr(ln, L, names, s_optab);
         }
         __syncthreads();
         icount += ti;
