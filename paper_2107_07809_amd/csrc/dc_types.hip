@@ -143,58 +143,27 @@ __device__ uint32_t smem_type(const Plan &P, const dc_kernel_t &D, uint32_t o) {
     return 0;
 }
 
+/* steps 2-6 of one kernel on forests and flags at pv, pt, fl: called with
+ * the LDS arrays or with global scratch, so that each copy uses the memory
+ * instructions of its own address space */
+struct TyShared {
+    const uint16_t *rank, *slot;
+    const uint32_t *vb;
+    uint32_t *w, *flag, *tern;
+    uint32_t (*red)[3];
+    unsigned long long *h;
+};
 template <bool DIGEST>
-__global__ __launch_bounds__(TY_THREADS) void k_types(Plan P, SsaPlan S) {
-    __shared__ uint16_t s_rank[TY_COLS], s_slot[TY_COLS];
-    __shared__ uint32_t s_vb[TY_COLS + 1];
-    __shared__ uint32_t l_pv[TY_LDS_NODES], l_pt[TY_LDS_NODES], l_fl[TY_LDS_NODES];
-    __shared__ uint32_t s_w[TY_WAVES], s_flag, s_tern;
-    __shared__ uint32_t s_red[TY_WAVES][3];
-    __shared__ unsigned long long s_h[TY_WAVES];
-    const uint32_t k = blockIdx.x, t = threadIdx.x, l = lane_id(), K = P.n_kernels;
-    const dc_ssa_result_t sr = S.res[k];
-    int32_t st = sr.status;
-    const uint64_t n0 = toff(S, K, 5, k), c0 = toff(S, K, 6, k);
-    if (st == DC_OK && (toff(S, K, 5, k + 1) > S.node_cap || toff(S, K, 6, k + 1) > S.scr_cap)) st = DC_E_CAPACITY;
-    if (st != DC_OK) {
-        if (t == 0) S.tres[k] = dc_types_result_t{st, 0, 0, 0, 0, 0, 0};
-        return;
-    }
-    const dc_kernel_t D = P.kernels[k];
-    const uint32_t fb = P.first_block[k], pb = P.pos_begin[k], n = P.pos_begin[k + 1] - pb;
-
-    /* 1. columns and their node bases */
-    const uint32_t *ks = P.kslots + (uint64_t)k * KSLOT_WORDS;
-    uint32_t U = 0;
-    for (uint32_t w = 0; w < KSLOT_WORDS; w++) U += __popc(slot_word(ks, w));
-    for (uint32_t v = t; v < (uint32_t)NSLOT; v += TY_THREADS) {
-        uint32_t below = 0;
-        for (uint32_t w = 0; w < (v >> 5); w++) below += __popc(slot_word(ks, w));
-        const uint32_t word = slot_word(ks, v >> 5), bit = v & 31u;
-        if ((word >> bit) & 1u) {
-            const uint32_t r = below + __popc(word & ((1u << bit) - 1u));
-            s_rank[v] = (uint16_t)r;
-            s_slot[r] = (uint16_t)v;
-        }
-    }
-    if (t < 64) {
-        const uint32_t *nv = S.nver + toff(S, K, 4, k);
-        uint32_t run = 0;
-        for (uint32_t c = 0; c < U; c += 64) {
-            const uint32_t u = c + l;
-            uint32_t tot;
-            const uint32_t ex = wave_excl(u < U ? nv[u] : 0u, &tot);
-            if (u < U) s_vb[u] = run + ex;
-            run += tot;
-        }
-        if (l == 0) s_vb[U] = run;
-    }
-    __syncthreads();
-    const uint32_t N = s_vb[U];
-    const bool lds = N <= TY_LDS_NODES;
-    uint32_t *pv = lds ? l_pv : S.tscr + 3 * c0;
-    uint32_t *pt = lds ? l_pt : S.tscr + 3 * c0 + N;
-    uint32_t *fl = lds ? l_fl : S.tscr + 3 * c0 + 2 * (uint64_t)N;
+__device__ __forceinline__ void types_body(const Plan &P, const SsaPlan &S, const dc_ssa_result_t &sr, uint32_t k,
+                                           const dc_kernel_t &D, uint32_t fb, uint32_t n, uint32_t U, uint32_t N,
+                                           uint64_t n0, uint32_t *pv, uint32_t *pt, uint32_t *fl, const TyShared &H) {
+    const uint32_t t = threadIdx.x, l = lane_id(), K = P.n_kernels;
+    const uint16_t *s_rank = H.rank, *s_slot = H.slot;
+    const uint32_t *s_vb = H.vb;
+    uint32_t *s_w = H.w;
+    uint32_t &s_flag = *H.flag, &s_tern = *H.tern;
+    uint32_t (*s_red)[3] = H.red;
+    unsigned long long *s_h = H.h;
     for (uint32_t x = t; x < N; x += TY_THREADS) {
         ast(pv + x, x);
         ast(pt + x, x);
@@ -393,6 +362,62 @@ __global__ __launch_bounds__(TY_THREADS) void k_types(Plan P, SsaPlan S) {
         }
         S.tres[k] = R;
     }
+}
+
+template <bool DIGEST>
+__global__ __launch_bounds__(TY_THREADS) void k_types(Plan P, SsaPlan S) {
+    __shared__ uint16_t s_rank[TY_COLS], s_slot[TY_COLS];
+    __shared__ uint32_t s_vb[TY_COLS + 1];
+    __shared__ uint32_t l_pv[TY_LDS_NODES], l_pt[TY_LDS_NODES], l_fl[TY_LDS_NODES];
+    __shared__ uint32_t s_w[TY_WAVES], s_flag, s_tern;
+    __shared__ uint32_t s_red[TY_WAVES][3];
+    __shared__ unsigned long long s_h[TY_WAVES];
+    const uint32_t k = blockIdx.x, t = threadIdx.x, l = lane_id(), K = P.n_kernels;
+    const dc_ssa_result_t sr = S.res[k];
+    int32_t st = sr.status;
+    const uint64_t n0 = toff(S, K, 5, k), c0 = toff(S, K, 6, k);
+    if (st == DC_OK && (toff(S, K, 5, k + 1) > S.node_cap || toff(S, K, 6, k + 1) > S.scr_cap)) st = DC_E_CAPACITY;
+    if (st != DC_OK) {
+        if (t == 0) S.tres[k] = dc_types_result_t{st, 0, 0, 0, 0, 0, 0};
+        return;
+    }
+    const dc_kernel_t D = P.kernels[k];
+    const uint32_t fb = P.first_block[k], pb = P.pos_begin[k], n = P.pos_begin[k + 1] - pb;
+
+    /* 1. columns and their node bases */
+    const uint32_t *ks = P.kslots + (uint64_t)k * KSLOT_WORDS;
+    uint32_t U = 0;
+    for (uint32_t w = 0; w < KSLOT_WORDS; w++) U += __popc(slot_word(ks, w));
+    for (uint32_t v = t; v < (uint32_t)NSLOT; v += TY_THREADS) {
+        uint32_t below = 0;
+        for (uint32_t w = 0; w < (v >> 5); w++) below += __popc(slot_word(ks, w));
+        const uint32_t word = slot_word(ks, v >> 5), bit = v & 31u;
+        if ((word >> bit) & 1u) {
+            const uint32_t r = below + __popc(word & ((1u << bit) - 1u));
+            s_rank[v] = (uint16_t)r;
+            s_slot[r] = (uint16_t)v;
+        }
+    }
+    if (t < 64) {
+        const uint32_t *nv = S.nver + toff(S, K, 4, k);
+        uint32_t run = 0;
+        for (uint32_t c = 0; c < U; c += 64) {
+            const uint32_t u = c + l;
+            uint32_t tot;
+            const uint32_t ex = wave_excl(u < U ? nv[u] : 0u, &tot);
+            if (u < U) s_vb[u] = run + ex;
+            run += tot;
+        }
+        if (l == 0) s_vb[U] = run;
+    }
+    __syncthreads();
+    const uint32_t N = s_vb[U];
+    const TyShared H{s_rank, s_slot, s_vb, s_w, &s_flag, &s_tern, s_red, s_h};
+    if (N <= TY_LDS_NODES)   /* uniform over the workgroup */
+        types_body<DIGEST>(P, S, sr, k, D, fb, n, U, N, n0, l_pv, l_pt, l_fl, H);
+    else
+        types_body<DIGEST>(P, S, sr, k, D, fb, n, U, N, n0, S.tscr + 3 * c0, S.tscr + 3 * c0 + N,
+                           S.tscr + 3 * c0 + 2 * (uint64_t)N, H);
 }
 
 hipError_t launch_types(const Plan &P, const SsaPlan &S, hipStream_t s) {
