@@ -7,7 +7,7 @@ import pytest
 
 import dcgen
 import oracle
-from gpu_common import compare_ssa_summaries, compare_summaries
+from gpu_common import compare_ssa_summaries, compare_struct_summaries, compare_summaries, compare_types_summaries
 
 pytestmark = pytest.mark.gpu
 
@@ -77,6 +77,16 @@ def test_versions_and_text_allocation_failures(ctx, batch, monkeypatch):
     o = oracle.parse_text(text)
     assert sweep(monkeypatch, lambda: ctx.parse_text(tdev, len(text)),
                  lambda t: (t.records().tobytes() == o["instrs"].tobytes()) or pytest.fail("records")) >= 5
+
+
+def test_types_and_structuring_allocation_failures(ctx, batch, monkeypatch):
+    b, dev = batch
+    ts = oracle.types_batch(b)
+    assert sweep(monkeypatch, lambda: ctx.build_types(b.kernels, dev, b.n_instr, b.args),
+                 lambda t: compare_types_summaries(t.types(), ts)) >= 5
+    st = oracle.structure_batch(b)
+    assert sweep(monkeypatch, lambda: ctx.structure(b.kernels, dev, b.n_instr),
+                 lambda x: compare_struct_summaries(x.results(), st)) >= 3
 
 
 def test_server_allocation_failures(ctx, batch, monkeypatch):
