@@ -143,3 +143,37 @@ def compare_types_summaries(gpu_res, summ, digest: bool = True):
     for f in fields:
         bad = np.nonzero(gpu_res[f] != summ[f])[0]
         assert len(bad) == 0, (f, bad[:10], gpu_res[f][bad[:10]], summ[f][bad[:10]])
+
+
+def fuzz_listing(text: bytes, seed: int, rate: float = 0.15) -> bytes:
+    """A listing with seeded random edits on a fraction of its lines: characters
+    deleted, inserted (from the characters the grammar gives meaning to, and
+    others), replaced or case-swapped, lines cut short, duplicated, joined or
+    dropped; no line is made longer than a few hundred bytes."""
+    rng = np.random.default_rng(seed)
+    alphabet = b" \t,:;[]/.-+_0123456789abcdefxsvABCDEFXSV\"*#@\r"
+    out = []
+    for line in text.split(b"\n"):
+        if rng.random() >= rate:
+            out.append(line)
+            continue
+        op = int(rng.integers(0, 8))
+        b = bytearray(line)
+        if op == 0 and b:
+            del b[int(rng.integers(0, len(b)))]
+        elif op == 1:
+            b.insert(int(rng.integers(0, len(b) + 1)), alphabet[int(rng.integers(0, len(alphabet)))])
+        elif op == 2 and b:
+            b[int(rng.integers(0, len(b)))] = alphabet[int(rng.integers(0, len(alphabet)))]
+        elif op == 3:
+            b = bytearray(bytes(b).swapcase())
+        elif op == 4 and b:
+            b = b[:int(rng.integers(0, len(b)))]
+        elif op == 5:
+            out.append(bytes(b))
+        elif op == 6:
+            b += b" " + bytes(b)
+        elif op == 7:
+            continue
+        out.append(bytes(b[:400]))
+    return b"\n".join(out)

@@ -11,7 +11,7 @@ import pytest
 import dcgen
 import hand_kernels as hk
 import oracle
-from gpu_common import compare_summaries
+from gpu_common import compare_summaries, fuzz_listing
 
 pytestmark = pytest.mark.gpu
 
@@ -152,3 +152,13 @@ def test_c2_full_text(ctx):
         assert mine.tobytes() == o["instrs"].tobytes(), i
         assert o["kernels"][0]["n_args"] == ki["n_args"] and o["kernels"][0]["dims"] == ki["dims"], i
     t.free()
+
+
+def test_fuzzed_listings(ctx):
+    """Rendered listings with seeded random edits on 15% of their lines
+    (malformed mnemonics, operands, labels, configuration lines, cut and
+    joined lines): the parser and the oracle's agree on every byte."""
+    base = dcgen.render(dcgen.concat([dcgen.generate(2, 40, i0=900).kernel(k) for k in range(40)] +
+                                     [k for _, k in hk.all_kernels(n_random=2)]))
+    for seed in range(12):
+        compare(ctx, fuzz_listing(base, seed), f"fuzz {seed}")

@@ -37,6 +37,10 @@ for text in (b".kernel a\n .text\n s_add_u32 s0,\n v_mov_b32 v1 v0 v2 v3 v4\n L:
              b".kernel\n.config\n .arg x, \"int\"\n .cws 1,2,3,4\n.text\n\n", b"", b"\n\n\r\n", b".text\n s_endpgm",
              b".kernel k\n .config\n .dims xyzw\n .arg p, \"float*\", float*, global\n .text\n global_load_dword v1, v[2:3], off offset:0x\n"):
     oracle.parse_text(text)
+from gpu_common import fuzz_listing
+base = dcgen.render(dcgen.concat([dcgen.generate(2, 12, i0=900, threads=2).kernel(k) for k in range(12)]))
+for seed in range(12):
+    oracle.parse_text(fuzz_listing(base, seed))
 print("SANITIZED RUN OK")
 """
 
