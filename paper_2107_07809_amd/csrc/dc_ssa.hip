@@ -148,55 +148,21 @@ __device__ __forceinline__ uint32_t dom_meet(const uint32_t *idom, const int32_t
 /* ------------------------------------------------------------------ */
 /* The sequential parts (dominators, preorder) run on every lane with the
  * same values: each lane reads back only what it stored itself. */
-__global__ __launch_bounds__(64) void k_ssa_graph(Plan P, SsaPlan S) {
-    __shared__ uint32_t l_rpo[SB_LDS], l_idom[SB_LDS], l_poff[SB_LDS + 1], l_pred[2 * SB_LDS], l_t1[SB_LDS],
-        l_t2[SB_LDS], l_pinv[SB_LDS];
-    __shared__ int32_t l_pos[SB_LDS];
-    __shared__ uint16_t s_rank[SLOTS_MAX];
-    __shared__ uint32_t s_cnt[SLOTS_MAX];
-    const uint32_t k = blockIdx.x, l = lane_id(), K = P.n_kernels;
-    int32_t st = P.status[k];
+/* the work of k_ssa_graph on one kernel's graph arrays (rpo, pos, poff,
+ * pred, idom and the preorder scratch), called with the arrays staged in LDS
+ * or with the global ones, so that each copy uses the memory instructions of
+ * its own address space */
+struct GraphOut {
+    uint32_t nphi, nargs, nops, nnodes;
+};
+__device__ __forceinline__ GraphOut ssa_graph_body(const Plan &P, const SsaPlan &S, uint32_t k, uint32_t nb,
+                                                   uint32_t fb, uint32_t nreach, uint32_t pb, uint32_t n,
+                                                   const dc_kernel_t &D, uint32_t U, const uint16_t *s_rank,
+                                                   uint32_t *s_cnt, const uint32_t *rpo, const int32_t *pos,
+                                                   const uint32_t *poff, const uint32_t *pred, uint32_t *idom,
+                                                   uint32_t *t1, uint32_t *t2, uint32_t *pinv) {
+    const uint32_t l = lane_id(), K = P.n_kernels;
     const uint64_t tab0 = soff(S, K, 0, k);
-    if (st == DC_OK && soff(S, K, 0, k + 1) > S.tab_cap) st = DC_E_CAPACITY;
-    if (st == DC_OK && S.nver && soff(S, K, 4, k + 1) > S.col_cap) st = DC_E_CAPACITY;
-    if (st != DC_OK) {
-        S.status[k] = st;
-        S.counts[(uint64_t)K + k] = 0;
-        S.counts[2ull * K + k] = 0;
-        S.counts[3ull * K + k] = 0;
-        if (S.nver) {
-            S.counts[5ull * K + k] = 0;
-            S.counts[6ull * K + k] = 0;
-        }
-        return;
-    }
-    const uint32_t nb = P.n_blocks[k], fb = P.first_block[k], nreach = P.n_reach[k], pb = P.pos_begin[k];
-    const uint32_t n = P.pos_begin[k + 1] - pb;
-    const dc_kernel_t D = P.kernels[k];
-    const uint32_t U = slot_columns(P.kslots + (uint64_t)k * KSLOT_WORDS, s_rank, nullptr);
-
-    /* the graph: staged in LDS when small */
-    const uint32_t pred0 = P.pred_cnt[fb], npred = P.pred_cnt[fb + nb] - pred0;
-    const bool lds = nb <= SB_LDS && npred <= 2 * SB_LDS;
-    if (lds) {
-        for (uint32_t b = l; b <= nb; b += 64) {
-            l_poff[b] = P.pred_cnt[fb + b] - pred0;
-            if (b < nb) {
-                l_rpo[b] = P.rpo[fb + b];
-                l_pos[b] = P.rpo_pos[fb + b];
-            }
-        }
-        for (uint32_t j = l; j < npred; j += 64) l_pred[j] = P.pred[pred0 + j];
-    }
-    const uint64_t cap = P.blk_cap;
-    const uint32_t *rpo = lds ? l_rpo : P.rpo + fb;
-    const int32_t *pos = lds ? l_pos : P.rpo_pos + fb;
-    const uint32_t *poff = lds ? l_poff : P.pred_cnt + fb;
-    const uint32_t *pred = lds ? l_pred : P.pred;
-    uint32_t *idom = lds ? l_idom : S.idom + fb;
-    uint32_t *t1 = lds ? l_t1 : S.scr + fb;
-    uint32_t *t2 = lds ? l_t2 : S.scr + cap + fb;
-    uint32_t *pinv = lds ? l_pinv : S.scr + 2 * cap + fb;
     for (uint32_t b = l; b < nb; b += 64) {
         idom[b] = b == 0 ? 0u : SSA_NONE;
         t1[b] = 1;
@@ -350,6 +316,57 @@ __global__ __launch_bounds__(64) void k_ssa_graph(Plan P, SsaPlan S) {
     nphi = wave_sum32(nphi);
     nargs = wave_sum32(nargs);
     nops = wave_sum32(nops);
+    return GraphOut{nphi, nargs, nops, nnodes};
+}
+
+__global__ __launch_bounds__(64) void k_ssa_graph(Plan P, SsaPlan S) {
+    __shared__ uint32_t l_rpo[SB_LDS], l_idom[SB_LDS], l_poff[SB_LDS + 1], l_pred[2 * SB_LDS], l_t1[SB_LDS],
+        l_t2[SB_LDS], l_pinv[SB_LDS];
+    __shared__ int32_t l_pos[SB_LDS];
+    __shared__ uint16_t s_rank[SLOTS_MAX];
+    __shared__ uint32_t s_cnt[SLOTS_MAX];
+    const uint32_t k = blockIdx.x, l = lane_id(), K = P.n_kernels;
+    int32_t st = P.status[k];
+    if (st == DC_OK && soff(S, K, 0, k + 1) > S.tab_cap) st = DC_E_CAPACITY;
+    if (st == DC_OK && S.nver && soff(S, K, 4, k + 1) > S.col_cap) st = DC_E_CAPACITY;
+    if (st != DC_OK) {
+        S.status[k] = st;
+        S.counts[(uint64_t)K + k] = 0;
+        S.counts[2ull * K + k] = 0;
+        S.counts[3ull * K + k] = 0;
+        if (S.nver) {
+            S.counts[5ull * K + k] = 0;
+            S.counts[6ull * K + k] = 0;
+        }
+        return;
+    }
+    const uint32_t nb = P.n_blocks[k], fb = P.first_block[k], nreach = P.n_reach[k], pb = P.pos_begin[k];
+    const uint32_t n = P.pos_begin[k + 1] - pb;
+    const dc_kernel_t D = P.kernels[k];
+    const uint32_t U = slot_columns(P.kslots + (uint64_t)k * KSLOT_WORDS, s_rank, nullptr);
+
+    /* the graph: staged in LDS when small */
+    const uint32_t pred0 = P.pred_cnt[fb], npred = P.pred_cnt[fb + nb] - pred0;
+    const bool lds = nb <= SB_LDS && npred <= 2 * SB_LDS;
+    if (lds) {
+        for (uint32_t b = l; b <= nb; b += 64) {
+            l_poff[b] = P.pred_cnt[fb + b] - pred0;
+            if (b < nb) {
+                l_rpo[b] = P.rpo[fb + b];
+                l_pos[b] = P.rpo_pos[fb + b];
+            }
+        }
+        for (uint32_t j = l; j < npred; j += 64) l_pred[j] = P.pred[pred0 + j];
+    }
+    const uint64_t cap = P.blk_cap;
+    GraphOut o;
+    if (lds)   /* uniform */
+        o = ssa_graph_body(P, S, k, nb, fb, nreach, pb, n, D, U, s_rank, s_cnt, l_rpo, l_pos, l_poff, l_pred, l_idom,
+                           l_t1, l_t2, l_pinv);
+    else
+        o = ssa_graph_body(P, S, k, nb, fb, nreach, pb, n, D, U, s_rank, s_cnt, P.rpo + fb, P.rpo_pos + fb,
+                           P.pred_cnt + fb, P.pred, S.idom + fb, S.scr + fb, S.scr + cap + fb, S.scr + 2 * cap + fb);
+    const uint32_t nphi = o.nphi, nargs = o.nargs, nops = o.nops, nnodes = o.nnodes;
     if (lds)
         for (uint32_t b = l; b < nb; b += 64) S.idom[fb + b] = l_idom[b];
     S.status[k] = DC_OK;

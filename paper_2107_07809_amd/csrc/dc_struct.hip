@@ -173,30 +173,11 @@ __device__ __forceinline__ uint64_t st_item(uint32_t j, const dc_merge_t &M) {
     return mix64(mix64(0x5354ull * 0x9E3779B97F4A7C15ull + j) ^ v);
 }
 
-__global__ __launch_bounds__(64) void k_struct(Plan P, StructPlan S) {
-    __shared__ int32_t l_succ[2 * SR_LDS];
-    __shared__ uint32_t l_npred[SR_LDS], l_fwd[SR_LDS], l_mark[SR_LDS], l_stack[2 * SR_LDS];
-    const uint32_t k = blockIdx.x, l = lane_id();
-    const int32_t st = P.status[k];
-    dc_struct_result_t res = {st, 0, 0, 0, SR_NONE, 0, 0};
-    if (st != DC_OK) {
-        S.res[k] = res;
-        return;
-    }
-    const uint32_t nb = P.n_blocks[k], fb = P.first_block[k];
-    /* ids: blocks, then one per merge -- at most nb - 1 merges that join
-     * regions and one loop merge per edge to itself (one per block at the
-     * start, one per joining merge) */
-    const uint32_t cap = 4 * nb + 2;
-    const uint64_t base = 4ull * fb + 2ull * k;
-    const bool lds = cap <= SR_LDS;
-    Rg g;
-    g.succ = lds ? l_succ : S.succ + 2 * base;
-    g.npred = lds ? l_npred : S.npred + base;
-    g.fwd = lds ? l_fwd : S.fwd + base;
-    g.mark = lds ? l_mark : S.mark + base;
-    g.stack = lds ? l_stack : S.stack + 2 * base;
-    dc_merge_t *out = S.merges + base;
+/* the search on one kernel's regions at g (in LDS or global memory: each
+ * copy uses the memory instructions of its own address space) */
+__device__ __forceinline__ void struct_body(const Plan &P, const StructPlan &S, uint32_t k, uint32_t nb, uint32_t fb,
+                                            uint32_t cap, dc_merge_t *out, dc_struct_result_t res, Rg g) {
+    const uint32_t l = lane_id();
     for (uint32_t r = l; r < cap; r += 64) {
         g.succ[2 * r] = g.succ[2 * r + 1] = -1;
         g.npred[r] = 0;
@@ -255,6 +236,42 @@ __global__ __launch_bounds__(64) void k_struct(Plan P, StructPlan S) {
     res.root = n_alive == 1 ? g.entry : SR_NONE;
     res.digest = h;
     S.res[k] = res;
+}
+
+__global__ __launch_bounds__(64) void k_struct(Plan P, StructPlan S) {
+    __shared__ int32_t l_succ[2 * SR_LDS];
+    __shared__ uint32_t l_npred[SR_LDS], l_fwd[SR_LDS], l_mark[SR_LDS], l_stack[2 * SR_LDS];
+    const uint32_t k = blockIdx.x, l = lane_id();
+    const int32_t st = P.status[k];
+    dc_struct_result_t res = {st, 0, 0, 0, SR_NONE, 0, 0};
+    if (st != DC_OK) {
+        S.res[k] = res;
+        return;
+    }
+    const uint32_t nb = P.n_blocks[k], fb = P.first_block[k];
+    /* ids: blocks, then one per merge -- at most nb - 1 merges that join
+     * regions and one loop merge per edge to itself (one per block at the
+     * start, one per joining merge) */
+    const uint32_t cap = 4 * nb + 2;
+    const uint64_t base = 4ull * fb + 2ull * k;
+    const bool lds = cap <= SR_LDS;
+    dc_merge_t *out = S.merges + base;
+    Rg g;
+    if (lds) {   /* uniform */
+        g.succ = l_succ;
+        g.npred = l_npred;
+        g.fwd = l_fwd;
+        g.mark = l_mark;
+        g.stack = l_stack;
+        struct_body(P, S, k, nb, fb, cap, out, res, g);
+    } else {
+        g.succ = S.succ + 2 * base;
+        g.npred = S.npred + base;
+        g.fwd = S.fwd + base;
+        g.mark = S.mark + base;
+        g.stack = S.stack + 2 * base;
+        struct_body(P, S, k, nb, fb, cap, out, res, g);
+    }
 }
 
 hipError_t launch_struct(const Plan &P, const StructPlan &S, hipStream_t s) {
