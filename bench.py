@@ -248,6 +248,16 @@ def graph_replay_ms(ctx, b, stream, reps=50):
     return ms
 
 
+def stage_roofline(alg_bytes, ms, kernel):
+    """HBM roofline of one stage: its algorithmic bytes over its time by the
+    HIP events, against MI355X's 8 TB/s."""
+    if not ms:
+        return None
+    gbs = alg_bytes / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": kernel, "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": gbs / HBM_PEAK_GBS}
+
+
 def ssa_workload(ctx, b, stream, steps=5, cpu_kernels=2048):
     """Register versions (dc_build_ssa) of a workload: whole runs (the graph
     stages, then the version stages) with the records in HBM; the version
@@ -293,6 +303,7 @@ def ssa_workload(ctx, b, stream, steps=5, cpu_kernels=2048):
             "counts_match_digest_run": bool(np.array_equal(dig["n_operands"], res["n_operands"]) and
                                             np.array_equal(dig["n_phi"], res["n_phi"])),
             "alg_bytes": alg, "ssa_stages_GBps": alg / (ssa_ms * 1e-3) / 1e9 if ssa_ms else None,
+            "roofline": stage_roofline(alg, ssa_ms, "k_ssa_graph + k_ssa_emit"),
             "cpu_oracle": {"instructions_per_s": sub.n_instr / cpu_dt, "cores": 1, "kernels": sub.n_kernels}}
 
 
@@ -345,6 +356,7 @@ def types_workload(ctx, b, stream, steps=5, cpu_kernels=2048):
             "counts_match_digest_run": bool(np.array_equal(dig["n_vars"], res["n_vars"]) and
                                             np.array_equal(dig["n_live_merges"], res["n_live_merges"])),
             "alg_bytes": alg, "type_stage_GBps": alg / (ty_ms * 1e-3) / 1e9 if ty_ms else None,
+            "roofline": stage_roofline(alg, ty_ms, "k_types"),
             "cpu_oracle": {"instructions_per_s": sub.n_instr / cpu_dt, "cores": 1, "kernels": sub.n_kernels}}
 
 
@@ -385,6 +397,7 @@ def text_workload(ctx, b, stream, steps=5, cpu_kernels=2048):
                          "records": tm["ms_fixpoint"] / runs},
             "descriptors_and_args_match": ok, "alg_bytes": alg,
             "alg_GBps": alg / (tm["ms_total"] / runs * 1e-3) / 1e9 if tm["ms_total"] else None,
+            "roofline": stage_roofline(alg, tm["ms_total"] / runs, "k_tx_* (whole front end)"),
             "cpu_oracle": {"bytes_per_s": len(sub) / cpu_dt, "cores": 1, "kernels": min(cpu_kernels, b.n_kernels)}}
 
 
@@ -415,8 +428,12 @@ def struct_workload(ctx, b, stream, steps=5, cpu_kernels=2048):
     t = time.perf_counter()
     osum = oracle.structure_batch(sub)
     cpu_dt = time.perf_counter() - t
+    st_ms = tm["ms_fixpoint"] / max(1, tm["runs"])
+    # the search reads 16 B of graph per block and the kernel's status, writes
+    # 24 B per merge and a 32 B result per kernel
+    alg = 16 * int(res["n_blocks"].sum()) + 24 * int(res["n_merges"].sum()) + 36 * b.n_kernels
     return {"instructions_per_s": b.n_instr / dt, "ms_per_step": dt * 1e3,
-            "struct_ms": tm["ms_fixpoint"] / max(1, tm["runs"]),
+            "struct_ms": st_ms, "alg_bytes": alg, "roofline": stage_roofline(alg, st_ms, "k_struct"),
             "graph_stages_ms": (tm["ms_decode"] + tm["ms_cfg"]) / max(1, tm["runs"]),
             "merges": int(res["n_merges"].sum()), "kernels_reduced_to_one_region": int((res["n_left"] == 1).sum()),
             "failed": int((res["status"] != 0).sum()), "rerun_identical": bool(res.tobytes() == res0.tobytes()),
