@@ -103,6 +103,21 @@ def test_c2_full_digest(ctx):
     compare_struct_summaries(res, orc.result())
 
 
+def test_c3_zipf_full(ctx):
+    """All 1,048,576 kernels of the Zipf(1.2) 20-20,000 workload (1.74e9
+    instructions) in one object, against the oracle's summaries."""
+    n = 1048576
+    orc = OracleStructRun(3, n, jobs_per_proc=16)
+    b = dcgen.generate(3, n)
+    dev = dc.to_device(b.instrs)
+    s = ctx.structure(b.kernels, dev, b.n_instr)
+    res = s.results()
+    s.free()
+    del dev
+    torch.cuda.empty_cache()
+    compare_struct_summaries(res, orc.result())
+
+
 def test_c4_very_large(ctx):
     """The 16 kernels of 1-4M instructions (up to ~17k blocks)."""
     orc = OracleStructRun(4, 16, procs=16, jobs_per_proc=1)

@@ -178,6 +178,25 @@ def test_types_c4_very_large(ctx):
     compare_types_summaries(res, orc.result())
 
 
+def test_types_c3_zipf_full(ctx):
+    """All 1,048,576 kernels of the Zipf(1.2) 20-20,000 workload (1.74e9
+    instructions) in one object: per-kernel counts and digest against the
+    oracle (worker processes, started first)."""
+    n = 1048576
+    orc = OracleTypesRun(3, n, jobs_per_proc=16)
+    b = dcgen.generate(3, n)
+    dev = dc.to_device(b.instrs)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    t = ctx.build_types(b.kernels, dev, b.n_instr, b.args)
+    res = t.types()
+    say(f"types c3: gpu done in {time.time() - t0:.1f}s, nodes {int(res['n_nodes'].sum())}")
+    t.free()
+    del dev
+    torch.cuda.empty_cache()
+    compare_types_summaries(res, orc.result())
+
+
 def test_types_need_a_types_object(ctx):
     b = dcgen.generate(1, 4)
     dev = dc.to_device(b.instrs)
