@@ -118,15 +118,6 @@ __device__ __forceinline__ uint32_t lookup(const uint32_t *pos_begin, uint32_t K
 /* ------------------------------------------------------------------ */
 constexpr uint32_t KM_KERNELS = 64;   /* kernels of a tile whose slot bitmaps are gathered in LDS */
 
-/* OR `bits` into word w of kernel k's slot bitmap: in the tile's LDS copy
- * when the kernel has one (kk < KM_KERNELS), else in global memory */
-__device__ __forceinline__ void mark_word(const Plan &P, uint32_t *km, uint32_t kk, uint32_t k, uint32_t w,
-                                          uint32_t bits) {
-    if (!bits) return;
-    if (kk < KM_KERNELS) atomicOr(&km[kk * KSLOT_WORDS + w], bits);
-    else atomicOr(&P.kslots[(uint64_t)k * KSLOT_WORDS + w], bits);
-}
-
 __global__ __launch_bounds__(256) void k_decode(Plan P) {
     __shared__ uint32_t lk[LK_CAP];
     __shared__ uint32_t km[KM_KERNELS * KSLOT_WORDS];
@@ -137,6 +128,9 @@ __global__ __launch_bounds__(256) void k_decode(Plan P) {
     lookup_setup(P.pos_begin, P.n_kernels, t0, t1, lk, &k0, &cnt);
     for (uint32_t i = threadIdx.x; i < KM_KERNELS * KSLOT_WORDS; i += blockDim.x) km[i] = 0;
     __syncthreads();
+    /* slot bitmaps gathered in LDS when the tile's kernels all have a copy
+     * there, else ORed straight into global memory */
+    const bool lds_marks = cnt != 0 && cnt <= KM_KERNELS;
     for (uint32_t g = t0 + threadIdx.x; g < t1; g += blockDim.x) {
         const uint32_t k = lookup(P.pos_begin, P.n_kernels, lk, k0, cnt, g);
         const uint32_t pb = P.pos_begin[k];
@@ -164,19 +158,27 @@ __global__ __launch_bounds__(256) void k_decode(Plan P) {
         if (cls == C_BR || cls == C_CBR) P.leader[pb + (uint32_t)target] = 1;
         if (!P.kslots) continue;
         /* the register slots the record names: each operand covers a run of
-         * at most four slots, in one or two bitmap words */
+         * at most four slots, in one or two bitmap words (masks computed with
+         * selects; an operand that names no slot gives empty masks) */
         const uint32_t id[4] = {r0, r1, r2, (uint32_t)imm};
-        const uint32_t kk = cnt ? k - k0 : KM_KERNELS;
 #pragma unroll
         for (int o = 0; o < 4; o++) {
             const uint32_t w = e_role(e, o) != RO_NO ? e_width(e, o) : 0u;
-            if (w == 0 || id[o] >= (uint32_t)NSLOT) continue;
-            const uint32_t first = id[o], last = min(id[o] + w, (uint32_t)NSLOT) - 1u;
+            const bool named = (w != 0) & (id[o] < (uint32_t)NSLOT);
+            const uint32_t first = named ? id[o] : 0u, last = named ? min(id[o] + w, (uint32_t)NSLOT) - 1u : 0u;
             const uint32_t wa = first >> 5, wb = last >> 5;
             const uint32_t hi_a = wa == wb ? (last & 31u) : 31u;
-            const uint32_t ma = (0xFFFFFFFFu >> (31u - hi_a)) & (0xFFFFFFFFu << (first & 31u));
-            mark_word(P, km, kk, k, wa, ma);
-            if (wb != wa) mark_word(P, km, kk, k, wb, 0xFFFFFFFFu >> (31u - (last & 31u)));
+            const uint32_t ma = named ? (0xFFFFFFFFu >> (31u - hi_a)) & (0xFFFFFFFFu << (first & 31u)) : 0u;
+            const uint32_t mb = named && wb != wa ? 0xFFFFFFFFu >> (31u - (last & 31u)) : 0u;
+            if (lds_marks) {   /* wave-uniform */
+                uint32_t *km_k = km + (k - k0) * KSLOT_WORDS;
+                if (ma) atomicOr(&km_k[wa], ma);
+                if (mb) atomicOr(&km_k[wb], mb);
+            } else {
+                uint32_t *ks_k = P.kslots + (uint64_t)k * KSLOT_WORDS;
+                if (ma) atomicOr(&ks_k[wa], ma);
+                if (mb) atomicOr(&ks_k[wb], mb);
+            }
         }
     }
     if (!P.kslots || !cnt) return;

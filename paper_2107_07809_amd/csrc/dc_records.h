@@ -10,58 +10,49 @@ namespace dc {
 /* ------------------------------------------------------------------ */
 /* record checks (per thread)                                           */
 /* ------------------------------------------------------------------ */
-__device__ inline bool sreg_ok(uint32_t id, uint32_t w) {
-    switch (w) {
-    case 1: return id <= 107u || id == 109u;
-    case 2: return (id & 1u) == 0 && (id <= 102u || id == 104u || id == 106u);
-    case 4: return (id & 3u) == 0 && id <= 100u;
-    }
-    return false;
+/* Written as selects over all the conditions rather than as branches: the
+ * lanes of a wavefront check different records, and branching on each lane's
+ * role and width costs more in exec-mask work than evaluating everything. */
+__device__ __forceinline__ bool sreg_ok(uint32_t id, uint32_t w) {
+    const bool w1 = (id <= 107u) | (id == 109u);
+    const bool w2 = ((id & 1u) == 0) & ((id <= 102u) | (id == 104u) | (id == 106u));
+    const bool w4 = ((id & 3u) == 0) & (id <= 100u);
+    return ((w == 1u) & w1) | ((w == 2u) & w2) | ((w == 4u) & w4);
 }
-__device__ inline bool vreg_ok(uint32_t id, uint32_t w) { return id >= 112u && id + w <= 368u; }
-__device__ inline bool inl_ok(uint32_t id) {
-    return (id >= 0x8000u && id <= 0x8050u) || (id >= 0x8060u && id <= 0x8067u);
+__device__ __forceinline__ bool vreg_ok(uint32_t id, uint32_t w) { return (id >= 112u) & (id + w <= 368u); }
+__device__ __forceinline__ bool inl_ok(uint32_t id) {
+    return ((id >= 0x8000u) & (id <= 0x8050u)) | ((id >= 0x8060u) & (id <= 0x8067u));
 }
-__device__ inline bool role_ok(uint32_t role, uint32_t id, uint32_t w, bool lit) {
-    switch (role) {
-    case RO_NO: return id == 0xFFFFu;
-    case RO_SD:
-    case RO_SU: return sreg_ok(id, w);
-    case RO_SC: return sreg_ok(id, w) || inl_ok(id) || (lit && id == 0xFFFEu);
-    case RO_VD:
-    case RO_VU: return vreg_ok(id, w);
-    case RO_VC: return vreg_ok(id, w) || sreg_ok(id, w) || inl_ok(id) || (lit && id == 0xFFFEu);
-    case RO_SADDR: return id == 0xFFFFu || (sreg_ok(id, 2) && id <= 102u);
-    }
-    return false;
+__device__ __forceinline__ bool role_ok(uint32_t role, uint32_t id, uint32_t w, bool lit) {
+    const bool none = id == 0xFFFFu, s = sreg_ok(id, w), v = vreg_ok(id, w), c = inl_ok(id) | (lit & (id == 0xFFFEu));
+    const bool saddr = none | (sreg_ok(id, 2) & (id <= 102u));
+    bool ok = false;
+    ok = role == RO_NO ? none : ok;
+    ok = (role == RO_SD) | (role == RO_SU) ? s : ok;
+    ok = role == RO_SC ? s | c : ok;
+    ok = (role == RO_VD) | (role == RO_VU) ? v : ok;
+    ok = role == RO_VC ? v | s | c : ok;
+    ok = role == RO_SADDR ? saddr : ok;
+    return ok;
 }
-/* 0 ok, 1 bad opcode, 2 bad operand, 3 bad target */
-__device__ inline uint32_t check_record(uint32_t op, uint32_t r0, uint32_t r1, uint32_t r2, int32_t imm, int32_t target,
-                                 uint32_t n) {
-    if (op >= (uint32_t)N_OPS) return 1;
-    const uint64_t e = OPTAB[op];
+/* 0 ok, 1 bad opcode, 2 bad operand, 3 bad target (the first that applies) */
+__device__ __forceinline__ uint32_t check_record(uint32_t op, uint32_t r0, uint32_t r1, uint32_t r2, int32_t imm,
+                                                 int32_t target, uint32_t n) {
+    const bool bad_op = op >= (uint32_t)N_OPS;
+    const uint64_t e = OPTAB[bad_op ? 0u : op];
     const uint32_t cls = e_cls(e);
-    if (cls == C_SMEM) {
-        const uint32_t w = e_width(e, 0);
-        if (!(sreg_ok(r0, w) && r0 + w <= 104u)) return 2;
-        if (!(sreg_ok(r1, 2) && r1 <= 102u)) return 2;
-        if (r2 != 0xFFFFu) return 2;
-    } else {
-        const bool lit = !e_immoff(e) && e_role(e, 3) == RO_NO;
-        if (!role_ok(e_role(e, 0), r0, e_width(e, 0), false)) return 2;
-        if (!role_ok(e_role(e, 1), r1, e_width(e, 1), lit)) return 2;
-        if (!role_ok(e_role(e, 2), r2, e_width(e, 2), lit)) return 2;
-        if (e_role(e, 3) != RO_NO) {
-            if (imm < 0 || imm > 0xFFFF) return 2;
-            if (!role_ok(e_role(e, 3), (uint32_t)imm, e_width(e, 3), false)) return 2;
-        }
-    }
-    if (cls == C_BR || cls == C_CBR) {
-        if (target < 0 || (uint32_t)target >= n) return 3;
-    } else if (target != -1) {
-        return 3;
-    }
-    return 0;
+    const uint32_t w0 = e_width(e, 0);
+    const bool smem_ok = sreg_ok(r0, w0) & (r0 + w0 <= 104u) & sreg_ok(r1, 2) & (r1 <= 102u) & (r2 == 0xFFFFu);
+    const bool lit = !e_immoff(e) && e_role(e, 3) == RO_NO;
+    const bool has3 = e_role(e, 3) != RO_NO;
+    const bool ok3 = !has3 | ((imm >= 0) & (imm <= 0xFFFF) &
+                              role_ok(e_role(e, 3), (uint32_t)imm & 0xFFFFu, e_width(e, 3), false));
+    const bool gen_ok = role_ok(e_role(e, 0), r0, w0, false) & role_ok(e_role(e, 1), r1, e_width(e, 1), lit) &
+                        role_ok(e_role(e, 2), r2, e_width(e, 2), lit) & ok3;
+    const bool opd_ok = cls == C_SMEM ? smem_ok : gen_ok;
+    const bool br = (cls == C_BR) | (cls == C_CBR);
+    const bool tgt_ok = br ? (target >= 0) & ((uint32_t)target < n) : target == -1;
+    return bad_op ? 1u : (!opd_ok ? 2u : (!tgt_ok ? 3u : 0u));
 }
 __device__ inline bool ends_block(uint32_t cls) { return cls == C_BR || cls == C_CBR || cls == C_END; }
 
