@@ -236,9 +236,27 @@ __device__ __forceinline__ uint64_t eff_n(uint64_t n, const uint32_t *n_dev) {
     return n_dev ? min(n, (uint64_t)*n_dev) : n;
 }
 
+/* a thread's SCAN_ITEMS consecutive items; a full tile of a 16-byte aligned
+ * array is read with 16-byte loads (one per 16 bytes of items) */
 template <typename T>
 __device__ __forceinline__ void load_items(const T *in, uint64_t n, uint64_t base, uint32_t v[SCAN_ITEMS]) {
     const uint64_t s = base + (uint64_t)threadIdx.x * SCAN_ITEMS;
+    const bool vec = base + SCAN_TILE <= n && (reinterpret_cast<uintptr_t>(in) & 15u) == 0;   /* uniform */
+    if (vec) {
+        constexpr int PER = 16 / (int)sizeof(T);   /* items per 16-byte load */
+        const uint4 *q = reinterpret_cast<const uint4 *>(in + s);
+#pragma unroll
+        for (int c = 0; c < SCAN_ITEMS / PER; c++) {
+            const uint4 x = q[c];
+            const uint32_t wds[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+            for (int j = 0; j < PER; j++) {
+                const uint32_t wd = wds[j * (int)sizeof(T) / 4];
+                v[c * PER + j] = sizeof(T) == 4 ? wd : (wd >> (8 * ((j * (int)sizeof(T)) & 3))) & ((1u << (8 * sizeof(T))) - 1u);
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int j = 0; j < SCAN_ITEMS; j++) v[j] = (s + j < n) ? (uint32_t)in[s + j] : 0u;
 }
@@ -271,11 +289,20 @@ __global__ __launch_bounds__(256) void k_scan_apply(const T *in, uint64_t n, con
     uint32_t excl;
     uint32_t tot = block_excl_scan(s, &excl);
     uint32_t run = tile_offs[blockIdx.x] + excl;
-    const uint64_t st = base + (uint64_t)threadIdx.x * SCAN_ITEMS;
+    /* the results go through LDS (17 words per thread's 16, against bank
+     * conflicts) so that each store instruction writes 256 consecutive words */
+    __shared__ uint32_t stage[256 * (SCAN_ITEMS + 1)];
+    const uint32_t t = threadIdx.x;
 #pragma unroll
     for (int j = 0; j < SCAN_ITEMS; j++) {
-        if (st + j < n) out[st + j] = run;
+        stage[t * (SCAN_ITEMS + 1) + j] = run;
         run += v[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; j++) {
+        const uint32_t q = (uint32_t)j * 256 + t;   /* item of the tile */
+        if (base + q < n) out[base + q] = stage[(q / SCAN_ITEMS) * (SCAN_ITEMS + 1) + q % SCAN_ITEMS];
     }
     if (total_out && blockIdx.x == gridDim.x - 1 && threadIdx.x == 255) *total_out = tile_offs[blockIdx.x] + tot;
 }
