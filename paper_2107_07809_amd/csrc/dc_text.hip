@@ -84,12 +84,6 @@ __device__ Sp field(Sp s, int k) {
         a = b + 1;
     }
 }
-__device__ int nfields(Sp s) {
-    if (!s.n) return 0;
-    int n = 1;
-    for (uint32_t i = 0; i < s.n; i++) n += s.p[i] == ',';
-    return n;
-}
 __device__ bool eq(Sp s, const char *lit) {
     uint32_t i = 0;
     for (; lit[i]; i++)
@@ -151,6 +145,14 @@ __device__ Sp line_clean(const TextPlan &T, uint64_t j) {
     if (e1 < s + 1 || e1 > T.n_bytes + 1) return Sp{T.text, 0};
     return clean(T.text + s, (uint32_t)(e1 - 1 - s));
 }
+/* line j, not cleaned, from a copy of text bytes [cs, ce) (in LDS) when the
+ * line lies in it, else from the text; empty as above */
+__device__ Sp line_staged(const TextPlan &T, uint64_t j, const uint8_t *stage, uint64_t cs, uint64_t ce) {
+    const uint64_t s = T.line_start[j], e1 = T.line_start[j + 1];
+    if (e1 < s + 1 || e1 > T.n_bytes + 1) return Sp{T.text, 0};
+    if (stage && s >= cs && e1 - 1 <= ce) return Sp{stage + (s - cs), (uint32_t)(e1 - 1 - s)};
+    return Sp{T.text + s, (uint32_t)(e1 - 1 - s)};
+}
 
 /* ------------------------------------------------------------------ */
 /* operands and records                                                  */
@@ -201,12 +203,16 @@ struct Labels {
     uint32_t *idx;
     uint32_t *line;       /* line of the definition, relative to the kernel's first line */
     uint32_t cap;         /* power of two, or 0 */
-    const TextPlan *T;
+    const uint8_t *text;  /* the listing and its line table (held here, not */
+    const uint64_t *line_start;   /* through the kernel argument, whose address */
+    uint64_t n_bytes;     /* would put a copy of it in scratch memory) */
     uint64_t l0, l1;
 };
 __device__ Sp label_name(const Labels &L, uint32_t rel) {
-    if (L.l0 + rel >= L.l1) return Sp{L.T->text, 0};
-    Sp c = line_clean(*L.T, L.l0 + rel);
+    if (L.l0 + rel >= L.l1) return Sp{L.text, 0};
+    const uint64_t j = L.l0 + rel, s = L.line_start[j], e1 = L.line_start[j + 1];
+    if (e1 < s + 1 || e1 > L.n_bytes + 1) return Sp{L.text, 0};
+    Sp c = clean(L.text + s, (uint32_t)(e1 - 1 - s));
     if (c.n) c.n--;   /* drop the ':' */
     return c;
 }
@@ -262,138 +268,147 @@ __device__ int find_op(Sp w, const char (*names)[24], const uint32_t *tab) {
     return -1;
 }
 
-/* one instruction line -> record */
-__device__ dc_instr_t parse_instr(Sp line, const Labels &L, const char (*names)[24], const uint32_t *optab) {
+/* A raw line (without its '\n') as its mnemonic and the trimmed rest, in one
+ * pass: the same spans as cleaning the line (cut at ';' or '//', trim) and
+ * then splitting off its first word; has_comma: the rest holds a comma. */
+__device__ void split_line(const uint8_t *p, uint32_t n, Sp *w, Sp *rest, bool *has_comma) {
+    constexpr uint32_t NONE = 0xFFFFFFFFu;
+    uint32_t st = NONE, last = 0, mend = NONE, rs = NONE, lastc = NONE;
+    for (uint32_t i = 0; i < n; i++) {
+        const uint8_t c = p[i];
+        if (c == ';' || (c == '/' && i + 1 < n && p[i + 1] == '/')) break;
+        if (!blank(c)) {
+            st = st == NONE ? i : st;
+            rs = (mend != NONE && rs == NONE) ? i : rs;
+            last = i + 1;
+            lastc = c == ',' ? i : lastc;
+        } else if (st != NONE && mend == NONE) {
+            mend = i;
+        }
+    }
+    if (st == NONE) {
+        *w = *rest = Sp{p, 0};
+        *has_comma = false;
+        return;
+    }
+    const uint32_t we = (mend != NONE && mend < last) ? mend : last;
+    *w = Sp{p + st, we - st};
+    *rest = rs != NONE ? Sp{p + rs, last - rs} : Sp{p + last, 0};
+    *has_comma = rs != NONE && lastc != NONE && lastc >= rs;
+}
+
+/* one instruction line (its mnemonic and operand text) -> record */
+__device__ __forceinline__ dc_instr_t parse_instr(Sp w, Sp rest, bool has_comma, const Labels &L, const char (*names)[24],
+                                 const uint32_t *optab) {
     dc_instr_t r;
     r.op = TX_NONE;
     r.r0 = r.r1 = r.r2 = TX_NONE;
     r.imm = 0;
     r.target = -1;
-    Sp rest;
-    const Sp w = word(line, &rest);
     const int op = find_op(w, names, optab);
     if (op < 0) return r;
     r.op = (uint16_t)op;
     const uint64_t e = OPTAB[op];
     /* operand words (a comma-separated field's first word; without commas
-     * every word) and modifiers (key:value words without '['; offset:N) */
+     * every word) and modifiers (key:value words without '['; offset:N), in
+     * one pass: a word is a run of characters other than blanks and commas,
+     * a field ends at a comma or at the end */
     bool bad_num = false;
     int nf = 0;
-    Sp f0{rest.p, 0}, f1{rest.p, 0}, f2{rest.p, 0}, f3{rest.p, 0};   /* operand words 0..3 (no template uses more) */
-    bool has_comma = false;
-    for (uint32_t i = 0; i < rest.n; i++) has_comma |= rest.p[i] == ',';
-    const int nfl = has_comma ? nfields(rest) : 1;
-    for (int k = 0; k < nfl; k++) {
-        Sp words = has_comma ? field(rest, k) : rest;
-        bool first = true;
-        while (words.n) {
-            Sp more;
-            const Sp mw = word(words, &more);
-            bool colon = false, bracket = false;
-            for (uint32_t i = 0; i < mw.n; i++) {
-                colon |= mw.p[i] == ':';
-                bracket |= mw.p[i] == '[';
-            }
-            if (colon && !bracket) {
-                if (mw.n > 7 && eq(Sp{mw.p, 7}, "offset:")) {
-                    int64_t v;
-                    if (to_int(Sp{mw.p + 7, mw.n - 7}, &v)) r.imm = (int32_t)(uint32_t)(uint64_t)v;
-                    else bad_num = true;
-                }
-            } else if (first || !has_comma) {
-                f0 = nf == 0 ? mw : f0;
-                f1 = nf == 1 ? mw : f1;
-                f2 = nf == 2 ? mw : f2;
-                f3 = nf == 3 ? mw : f3;
+    /* operand words 0..3 (no template uses more), as separate scalars: a
+     * select between whole spans would put them in scratch memory */
+    const uint8_t *p0 = rest.p, *p1 = rest.p, *p2 = rest.p, *p3 = rest.p;
+    uint32_t n0 = 0, n1 = 0, n2 = 0, n3 = 0;
+    auto put = [&](Sp v) {
+        p0 = nf == 0 ? v.p : p0;
+        n0 = nf == 0 ? v.n : n0;
+        p1 = nf == 1 ? v.p : p1;
+        n1 = nf == 1 ? v.n : n1;
+        p2 = nf == 2 ? v.p : p2;
+        n2 = nf == 2 ? v.n : n2;
+        p3 = nf == 3 ? v.p : p3;
+        n3 = nf == 3 ? v.n : n3;
+    };
+    bool first = true;   /* the current field has no operand word yet */
+    for (uint32_t i = 0;;) {
+        while (i < rest.n && blank(rest.p[i])) i++;
+        if (i >= rest.n || rest.p[i] == ',') {
+            if (has_comma && first) {
+                put(Sp{rest.p, 0});
                 nf++;
-                first = false;
             }
-            words = more;
+            if (i >= rest.n) break;
+            i++;
+            first = true;
+            continue;
         }
-        if (has_comma && first) {
-            const Sp z{rest.p, 0};
-            f0 = nf == 0 ? z : f0;
-            f1 = nf == 1 ? z : f1;
-            f2 = nf == 2 ? z : f2;
-            f3 = nf == 3 ? z : f3;
+        const uint32_t a = i;
+        bool colon = false, bracket = false;
+        for (; i < rest.n; i++) {
+            const uint8_t c = rest.p[i];
+            if (blank(c) || c == ',') break;
+            colon |= c == ':';
+            bracket |= c == '[';
+        }
+        const Sp mw{rest.p + a, i - a};
+        if (colon && !bracket) {
+            if (mw.n > 7 && eq(Sp{mw.p, 7}, "offset:")) {
+                int64_t v;
+                if (to_int(Sp{mw.p + 7, mw.n - 7}, &v)) r.imm = (int32_t)(uint32_t)(uint64_t)v;
+                else bad_num = true;
+            }
+        } else if (first || !has_comma) {
+            put(mw);
             nf++;
+            first = false;
         }
     }
     if (nf > 8) nf = 8;
     bool has_lit = false;
     int32_t lit = 0;
-#define OPD(k, fk) (((k) < nf && (fk).n) ? operand((fk), &has_lit, &lit) : TX_BAD)
+    /* which operand word goes where: 4 bits per word 0..3 (0 r0, 1 r1, 2 r2,
+     * 3 imm, 15 unused); the words are parsed in order, so the last literal
+     * among them is the one kept */
     const uint32_t cls = e_cls(e);
+    uint32_t map = 0xFFFFu;
     switch (cls) {
-    case C_SMEM: {
-        r.r0 = OPD(0, f0);
-        r.r1 = OPD(1, f1);
-        int64_t v;
-        if (nf > 2 && to_int(f2, &v)) r.imm = (int32_t)(uint32_t)(uint64_t)v;
-        else bad_num = true;
-        break;
+    case C_SMEM: map = 0xFF10u; break;
+    case C_SCMP: map = 0xFF21u; break;
+    case C_VCMP: map = 0xF21Fu; break;
+    case C_GLD: map = 0xF210u; break;
+    case C_FLD: case C_DSR: map = 0xFF10u; break;
+    case C_GST: map = 0xF201u; break;
+    case C_FST: case C_DSW: map = 0xFF01u; break;
+    case C_BR: case C_CBR: case C_NOP: case C_END: break;
+    default:
+        if (cls == C_VALU && (e_idef(e) & IM_VCC)) map = 0x21F0u;      /* dst, vcc, src0, src1 */
+        else if (e_role(e, 3) != RO_NO) map = 0x3210u;                 /* dst, src0, src1, src2 */
+        else if (e_role(e, 2) == RO_NO) map = 0xFF10u;                 /* dst, src */
+        else map = 0xF210u;                                            /* dst, src0, src1 */
     }
-    case C_BR:
-    case C_CBR: {
+    for (int k = 0; k < 4; k++) {
+        const uint32_t d = (map >> (4 * k)) & 15u;
+        if (d == 15u) continue;
+        const Sp fk{k == 0 ? p0 : (k == 1 ? p1 : (k == 2 ? p2 : p3)), k == 0 ? n0 : (k == 1 ? n1 : (k == 2 ? n2 : n3))};
+        const uint16_t v = (k < nf && fk.n) ? operand(fk, &has_lit, &lit) : TX_BAD;
+        if (d == 0) r.r0 = v;
+        else if (d == 1) r.r1 = v;
+        else if (d == 2) r.r2 = v;
+        else r.imm = (int32_t)v;
+    }
+    if (cls == C_SMEM) {
+        int64_t v;
+        if (nf > 2 && to_int(Sp{p2, n2}, &v)) r.imm = (int32_t)(uint32_t)(uint64_t)v;
+        else bad_num = true;
+    } else if (cls == C_BR || cls == C_CBR) {
         r.target = 0x7FFFFFFF;
         if (nf > 0) {
             uint32_t idx;
             int64_t v;
-            if (label_find(L, f0, &idx)) r.target = (int32_t)idx;
-            else if (to_int(f0, &v) && v >= 0 && v < 0x7FFFFFFF) r.target = (int32_t)v;
-        }
-        break;
-    }
-    case C_NOP:
-    case C_END: break;
-    case C_SCMP:
-        r.r1 = OPD(0, f0);
-        r.r2 = OPD(1, f1);
-        break;
-    case C_VCMP:
-        r.r1 = OPD(1, f1);
-        r.r2 = OPD(2, f2);
-        break;
-    case C_GLD:
-        r.r0 = OPD(0, f0);
-        r.r1 = OPD(1, f1);
-        r.r2 = OPD(2, f2);
-        break;
-    case C_FLD:
-    case C_DSR:
-        r.r0 = OPD(0, f0);
-        r.r1 = OPD(1, f1);
-        break;
-    case C_GST:
-        r.r1 = OPD(0, f0);
-        r.r0 = OPD(1, f1);
-        r.r2 = OPD(2, f2);
-        break;
-    case C_FST:
-    case C_DSW:
-        r.r1 = OPD(0, f0);
-        r.r0 = OPD(1, f1);
-        break;
-    default:
-        if (cls == C_VALU && (e_idef(e) & IM_VCC)) {   /* dst, vcc, src0, src1 */
-            r.r0 = OPD(0, f0);
-            r.r1 = OPD(2, f2);
-            r.r2 = OPD(3, f3);
-        } else if (e_role(e, 3) != RO_NO) {            /* dst, src0, src1, src2 */
-            r.r0 = OPD(0, f0);
-            r.r1 = OPD(1, f1);
-            r.r2 = OPD(2, f2);
-            r.imm = (int32_t)OPD(3, f3);
-        } else if (e_role(e, 2) == RO_NO) {            /* dst, src */
-            r.r0 = OPD(0, f0);
-            r.r1 = OPD(1, f1);
-        } else {                                       /* dst, src0, src1 */
-            r.r0 = OPD(0, f0);
-            r.r1 = OPD(1, f1);
-            r.r2 = OPD(2, f2);
+            if (label_find(L, Sp{p0, n0}, &idx)) r.target = (int32_t)idx;
+            else if (to_int(Sp{p0, n0}, &v) && v >= 0 && v < 0x7FFFFFFF) r.target = (int32_t)v;
         }
     }
-#undef OPD
     if (has_lit && !e_immoff(e) && e_role(e, 3) == RO_NO) r.imm = lit;
     if (bad_num) r.op = TX_NONE;
     return r;
@@ -476,14 +491,38 @@ __device__ uint32_t block_incl_max(uint32_t x, uint32_t *all_max, uint32_t *wsum
 /* ------------------------------------------------------------------ */
 /* lines                                                                 */
 /* ------------------------------------------------------------------ */
+/* bit 7 of each byte of w that is a '\n' (exact: no carries between bytes) */
+__device__ __forceinline__ uint32_t nl_bytes(uint32_t w) {
+    const uint32_t x = w ^ 0x0A0A0A0Au;
+    return ~(((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x) & 0x80808080u;
+}
+/* the 16 text bytes of a thread from byte t0 as four words: one 16-byte load
+ * when they lie in the text and the text is 16-byte aligned, else bytes
+ * (bytes past the end read as 0) */
+__device__ __forceinline__ uint4 text16(const TextPlan &T, uint64_t t0) {
+    if (t0 + 16 <= T.n_bytes && (reinterpret_cast<uintptr_t>(T.text) & 15u) == 0)
+        return *reinterpret_cast<const uint4 *>(T.text + t0);
+    uint32_t w[4] = {0, 0, 0, 0};
+    for (uint32_t i = 0; i < 16; i++)
+        if (t0 + i < T.n_bytes) w[i >> 2] |= (uint32_t)T.text[t0 + i] << (8 * (i & 3));
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+/* text bytes [cs, ce) (cs 16-byte aligned) into LDS by the workgroup: 16 bytes
+ * per load when the text is aligned and the last 16-byte unit lies in it */
+__device__ __forceinline__ void stage_text(const TextPlan &T, uint8_t *stage, uint64_t cs, uint64_t ce) {
+    if ((reinterpret_cast<uintptr_t>(T.text) & 15u) == 0 && ((ce + 15) & ~15ull) <= T.n_bytes) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(T.text + cs);
+        for (uint64_t q = threadIdx.x; 16 * q < ce - cs; q += blockDim.x) reinterpret_cast<uint4 *>(stage)[q] = src[q];
+    } else {
+        for (uint64_t i = threadIdx.x; i < ce - cs; i += blockDim.x) stage[i] = T.text[cs + i];
+    }
+}
+
 __global__ __launch_bounds__(256) void k_tx_count(TextPlan T) {
     __shared__ uint32_t ws[4];
-    const uint64_t t0 = (uint64_t)blockIdx.x * TX_TILE;
-    uint32_t c = 0;
-    for (uint32_t i = threadIdx.x; i < TX_TILE; i += 256) {
-        const uint64_t g = t0 + i;
-        c += (g < T.n_bytes && T.text[g] == '\n') ? 1u : 0u;
-    }
+    const uint4 v = text16(T, (uint64_t)blockIdx.x * TX_TILE + (uint64_t)threadIdx.x * 16);
+    const uint32_t c = __popc(nl_bytes(v.x)) + __popc(nl_bytes(v.y)) + __popc(nl_bytes(v.z)) + __popc(nl_bytes(v.w));
     uint32_t tot;
     block_excl_sum(c, &tot, ws);
     if (threadIdx.x == 0) T.tile_cnt[blockIdx.x] = tot;
@@ -519,30 +558,42 @@ __global__ __launch_bounds__(1024) void k_tx_scan(const uint32_t *in, uint64_t *
 __global__ __launch_bounds__(256) void k_tx_lines(TextPlan T) {
     __shared__ uint32_t ws[4];
     const uint64_t t0 = (uint64_t)blockIdx.x * TX_TILE + (uint64_t)threadIdx.x * 16;
-    uint32_t c = 0;
-    for (uint32_t i = 0; i < 16; i++) {
-        const uint64_t g = t0 + i;
-        c += (g < T.n_bytes && T.text[g] == '\n') ? 1u : 0u;
-    }
+    const uint4 v = text16(T, t0);
+    const uint32_t m[4] = {nl_bytes(v.x), nl_bytes(v.y), nl_bytes(v.z), nl_bytes(v.w)};
+    const uint32_t c = __popc(m[0]) + __popc(m[1]) + __popc(m[2]) + __popc(m[3]);
     uint32_t tot;
     const uint32_t ex = block_excl_sum(c, &tot, ws);
     uint64_t o = T.tile_off[blockIdx.x] + ex + 1;
-    for (uint32_t i = 0; i < 16; i++) {
-        const uint64_t g = t0 + i;
-        if (g < T.n_bytes && T.text[g] == '\n') {
+#pragma unroll
+    for (uint32_t q = 0; q < 4; q++)
+        for (uint32_t b = m[q]; b; b &= b - 1) {
+            const uint64_t g = t0 + 4 * q + (uint32_t)(__builtin_ctz(b) >> 3);
             if (o < T.n_lines) T.line_start[o] = g + 1;   /* more line ends than planned: flagged below */
             o++;
         }
-    }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         T.line_start[0] = 0;
         T.line_start[T.n_lines] = T.n_bytes + 1;
     }
 }
 
+/* kinds of lines; each workgroup's 256 consecutive lines are staged in LDS
+ * with 16-byte loads when their text fits */
 __global__ __launch_bounds__(256) void k_tx_classify(TextPlan T) {
-    for (uint64_t j = (uint64_t)blockIdx.x * 256 + threadIdx.x; j < T.n_lines; j += (uint64_t)gridDim.x * 256) {
-        const Sp c = line_clean(T, j);
+    __shared__ __align__(16) uint8_t s_txt[TX_STAGE];
+    for (uint64_t c0 = (uint64_t)blockIdx.x * 256; c0 < T.n_lines; c0 += (uint64_t)gridDim.x * 256) {
+        const uint64_t j = c0 + threadIdx.x;
+        const uint64_t cend = c0 + 256 < T.n_lines ? c0 + 256 : T.n_lines;
+        const uint64_t cs = T.line_start[c0] & ~15ull;
+        uint64_t ce = T.line_start[cend];
+        if (ce > T.n_bytes) ce = T.n_bytes;
+        const bool staged = ce >= cs && ce - cs <= TX_STAGE;
+        __syncthreads();   /* the previous chunk's lines are done */
+        if (staged) stage_text(T, s_txt, cs, ce);
+        __syncthreads();
+        if (j >= T.n_lines) continue;
+        const Sp raw = line_staged(T, j, staged ? s_txt : nullptr, cs, ce);
+        const Sp c = clean(raw.p, raw.n);
         uint8_t kd = K_EMPTY;
         if (c.n) {
             Sp rest;
@@ -647,12 +698,13 @@ __global__ __launch_bounds__(TX_T) void k_tx_kernel1(TextPlan T) {
     }
 }
 
-__global__ __launch_bounds__(TX_T) void k_tx_kernel2(TextPlan T) {
+/* at least four waves per SIMD: the parser's registers are capped at 128 */
+__global__ __launch_bounds__(TX_T, 4) void k_tx_kernel2(TextPlan T) {
     __shared__ uint32_t ws[4];
     __shared__ char names[N_OPS][24];
     __shared__ uint32_t s_optab[OP_TAB];
     __shared__ uint32_t s_dims, s_cws, s_use;
-    __shared__ uint8_t s_txt[TX_STAGE];
+    __shared__ __align__(16) uint8_t s_txt[TX_STAGE];
     const uint32_t k = blockIdx.x, K = T.n_kernels, t = threadIdx.x;
     if (k >= K || K > T.k_cap || *T.fail) return;
     for (uint32_t i = t; i < N_OPS * 24; i += TX_T) (&names[0][0])[i] = (&OPN[0][0])[i];
@@ -669,7 +721,7 @@ __global__ __launch_bounds__(TX_T) void k_tx_kernel2(TextPlan T) {
         if (t == 0) atomicOr(T.fail, 1u);
         return;
     }
-    Labels L{T.lab_key + lb, T.lab_idx + lb, T.lab_line + lb, cap, &T, l0, l1};
+    Labels L{T.lab_key + lb, T.lab_idx + lb, T.lab_line + lb, cap, T.text, T.line_start, T.n_bytes, l0, l1};
     __syncthreads();
     /* labels, configuration lines, argument order */
     uint32_t carry = 0, icount = 0, acount = 0;
@@ -721,17 +773,18 @@ __global__ __launch_bounds__(TX_T) void k_tx_kernel2(TextPlan T) {
         uint32_t ti;
         const uint32_t xi = block_excl_sum(is_i, &ti, ws);
         const uint64_t cend = c + TX_T < l1 ? c + TX_T : l1;
-        const uint64_t cs = T.line_start[c];
+        const uint64_t cs = T.line_start[c] & ~15ull;   /* 16-byte aligned start of the chunk's text */
         uint64_t ce = T.line_start[cend];
         if (ce > T.n_bytes) ce = T.n_bytes;
         const bool staged = ce >= cs && ce - cs <= TX_STAGE;
-        if (staged)
-            for (uint64_t i = t; i < ce - cs; i += TX_T) s_txt[i] = T.text[cs + i];
+        if (staged) stage_text(T, s_txt, cs, ce);
         __syncthreads();
         if (is_i && icount + xi < ni) {
-            Sp ln = line_clean(T, j);
-            if (staged && ln.n) ln.p = s_txt + (ln.p - (T.text + cs));
-            T.instrs[ib + icount + xi] = parse_instr(ln, L, names, s_optab);
+            const Sp ln = line_staged(T, j, staged ? s_txt : nullptr, cs, ce);
+            Sp w, rest;
+            bool has_comma;
+            split_line(ln.p, ln.n, &w, &rest, &has_comma);
+            T.instrs[ib + icount + xi] = parse_instr(w, rest, has_comma, L, names, s_optab);
         }
         __syncthreads();
         icount += ti;
