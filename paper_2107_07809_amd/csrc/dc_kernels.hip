@@ -117,6 +117,7 @@ __device__ __forceinline__ uint32_t lookup(const uint32_t *pos_begin, uint32_t K
 /* decode, check, leader flags                                          */
 /* ------------------------------------------------------------------ */
 constexpr uint32_t KM_KERNELS = 64;   /* kernels of a tile whose slot bitmaps are gathered in LDS */
+constexpr int DEC_PER = TILE_LK / 256;   /* positions per thread (256 threads per tile) */
 
 __global__ __launch_bounds__(256) void k_decode(Plan P) {
     __shared__ uint32_t lk[LK_CAP];
@@ -131,17 +132,38 @@ __global__ __launch_bounds__(256) void k_decode(Plan P) {
     /* slot bitmaps gathered in LDS when the tile's kernels all have a copy
      * there, else ORed straight into global memory */
     const bool lds_marks = cnt != 0 && cnt <= KM_KERNELS;
-    for (uint32_t g = t0 + threadIdx.x; g < t1; g += blockDim.x) {
-        const uint32_t k = lookup(P.pos_begin, P.n_kernels, lk, k0, cnt, g);
-        const uint32_t pb = P.pos_begin[k];
-        const uint32_t n = P.pos_begin[k + 1] - pb;
+    /* a thread's DEC_PER positions (256 apart): their kernels, then the
+     * kernels' ranges, then the records, each step's loads issued together */
+    uint32_t kk[DEC_PER], pbk[DEC_PER], nkr[DEC_PER];
+    uint64_t ibk[DEC_PER];
+    uint4 rr[DEC_PER];
+#pragma unroll
+    for (int j = 0; j < DEC_PER; j++) {
+        const uint32_t g = t0 + threadIdx.x + 256u * j;
+        kk[j] = g < t1 ? lookup(P.pos_begin, P.n_kernels, lk, k0, cnt, g) : k0;
+    }
+#pragma unroll
+    for (int j = 0; j < DEC_PER; j++) {
+        pbk[j] = P.pos_begin[kk[j]];
+        nkr[j] = P.pos_begin[kk[j] + 1] - pbk[j];
+        ibk[j] = P.kernels[kk[j]].instr_begin;
+    }
+#pragma unroll
+    for (int j = 0; j < DEC_PER; j++) {
+        const uint32_t g = t0 + threadIdx.x + 256u * j, i = g - pbk[j];
+        rr[j] = g < t1 && i < nkr[j] ? reinterpret_cast<const uint4 *>(P.instrs)[ibk[j] + i] : make_uint4(0, 0, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < DEC_PER; j++) {
+        const uint32_t g = t0 + threadIdx.x + 256u * j;
+        if (g >= t1) continue;
+        const uint32_t k = kk[j], pb = pbk[j], n = nkr[j];
         const uint32_t i = g - pb;
         if (i >= n) {   /* a position no kernel owns (a call whose descriptors failed their checks) */
             P.pcap[g] = 0;
             continue;
         }
-        const dc_kernel_t *D = &P.kernels[k];
-        const uint4 r = reinterpret_cast<const uint4 *>(P.instrs)[D->instr_begin + i];
+        const uint4 r = rr[j];
         const uint32_t op = r.x & 0xFFFFu, r0 = r.x >> 16, r1 = r.y & 0xFFFFu, r2 = r.y >> 16;
         const int32_t imm = (int32_t)r.z, target = (int32_t)r.w;
         const uint32_t bad = check_record(op, r0, r1, r2, imm, target, n);
@@ -359,9 +381,21 @@ __global__ __launch_bounds__(256) void k_number(Plan P, const uint32_t *excl) {
     const uint32_t t1 = min(P.n_pos, t0 + TILE_LK);
     uint32_t k0, cnt;
     lookup_setup(P.pos_begin, P.n_kernels, t0, t1, lk, &k0, &cnt);
-    for (uint32_t g = t0 + threadIdx.x; g < t1; g += blockDim.x) {
-        const uint32_t l = P.leader[g];
-        const uint32_t id = excl[g] + l - 1;
+    /* a thread's DEC_PER positions (256 apart), their loads issued together
+     * (block_id may be excl itself: each position reads its entry first) */
+    uint32_t lv[DEC_PER], xv[DEC_PER];
+#pragma unroll
+    for (int j = 0; j < DEC_PER; j++) {
+        const uint32_t g = t0 + threadIdx.x + 256u * j;
+        lv[j] = g < t1 ? P.leader[g] : 0u;
+        xv[j] = g < t1 ? excl[g] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < DEC_PER; j++) {
+        const uint32_t g = t0 + threadIdx.x + 256u * j;
+        if (g >= t1) continue;
+        const uint32_t l = lv[j];
+        const uint32_t id = xv[j] + l - 1;
         P.block_id[g] = id;
         if (l && id < P.blk_cap) {
             P.block_start[id] = g;
