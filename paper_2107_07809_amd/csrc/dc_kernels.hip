@@ -68,8 +68,10 @@ hipError_t launch_fill_u8(uint8_t *p, uint64_t n, uint8_t v, hipStream_t s) {
 /* ------------------------------------------------------------------ */
 /* position -> kernel lookup for a tile of positions                     */
 /* ------------------------------------------------------------------ */
-constexpr int TILE_LK = 1024;          /* positions per lookup tile */
-constexpr int LK_CAP = TILE_LK + 2;    /* kernel starts cached in LDS */
+constexpr int TILE_LK = 4096;          /* positions per lookup tile (one workgroup of 256 threads) */
+constexpr int LK_CAP = 1026;           /* kernel starts cached in LDS (more: searched in global memory) */
+constexpr int LK_PER = 4;              /* positions a thread handles together (256 apart) */
+constexpr int LK_ROUNDS = TILE_LK / (256 * LK_PER);
 
 /* last k in [lo, hi] with pos_begin[k] <= g (global memory) */
 __device__ uint32_t kernel_of_global(const uint32_t *pos_begin, uint32_t lo, uint32_t hi, uint32_t g) {
@@ -81,6 +83,24 @@ __device__ uint32_t kernel_of_global(const uint32_t *pos_begin, uint32_t lo, uin
     return lo;
 }
 
+/* last k in [lo, hi] with pos_begin[k] <= g, given pos_begin[lo] <= g: steps
+ * of doubling length from lo, then a binary search in the last one (few
+ * loads when the answer is near lo) */
+__device__ uint32_t kernel_of_gallop(const uint32_t *pos_begin, uint32_t lo, uint32_t hi, uint32_t g) {
+    uint32_t step = 1;
+    while (lo < hi) {
+        const uint32_t nx = hi - lo < step ? hi : lo + step;
+        if (pos_begin[nx] <= g) {
+            lo = nx;
+            step <<= 1;
+        } else {
+            hi = nx - 1;
+            break;
+        }
+    }
+    return kernel_of_global(pos_begin, lo, hi, g);
+}
+
 /* Cooperative setup for a tile [t0, t1): caches the starts of the kernels
  * that overlap it.  Returns k0 and the count (0 if they do not fit). */
 __device__ void lookup_setup(const uint32_t *pos_begin, uint32_t K, uint32_t t0, uint32_t t1, uint32_t *lk,
@@ -88,7 +108,7 @@ __device__ void lookup_setup(const uint32_t *pos_begin, uint32_t K, uint32_t t0,
     __shared__ uint32_t s_k0, s_k1;
     if (threadIdx.x == 0) {
         s_k0 = kernel_of_global(pos_begin, 0, K - 1, t0);
-        s_k1 = kernel_of_global(pos_begin, s_k0, K - 1, t1 - 1);
+        s_k1 = kernel_of_gallop(pos_begin, s_k0, K - 1, t1 - 1);
     }
     __syncthreads();
     uint32_t k0 = s_k0, cnt = s_k1 - s_k0 + 1;
@@ -116,8 +136,7 @@ __device__ __forceinline__ uint32_t lookup(const uint32_t *pos_begin, uint32_t K
 /* ------------------------------------------------------------------ */
 /* decode, check, leader flags                                          */
 /* ------------------------------------------------------------------ */
-constexpr uint32_t KM_KERNELS = 64;   /* kernels of a tile whose slot bitmaps are gathered in LDS */
-constexpr int DEC_PER = TILE_LK / 256;   /* positions per thread (256 threads per tile) */
+constexpr uint32_t KM_KERNELS = 128;   /* kernels of a tile whose slot bitmaps are gathered in LDS */
 
 __global__ __launch_bounds__(256) void k_decode(Plan P) {
     __shared__ uint32_t lk[LK_CAP];
@@ -132,74 +151,78 @@ __global__ __launch_bounds__(256) void k_decode(Plan P) {
     /* slot bitmaps gathered in LDS when the tile's kernels all have a copy
      * there, else ORed straight into global memory */
     const bool lds_marks = cnt != 0 && cnt <= KM_KERNELS;
-    /* a thread's DEC_PER positions (256 apart): their kernels, then the
-     * kernels' ranges, then the records, each step's loads issued together */
-    uint32_t kk[DEC_PER], pbk[DEC_PER], nkr[DEC_PER];
-    uint64_t ibk[DEC_PER];
-    uint4 rr[DEC_PER];
+    /* a thread's positions in rounds of LK_PER (256 apart): their kernels,
+     * then the kernels' ranges, then the records, each step's loads issued
+     * together */
+    for (int q = 0; q < LK_ROUNDS; q++) {
+        const uint32_t tr = t0 + 256u * LK_PER * q;
+        uint32_t kk[LK_PER], pbk[LK_PER], nkr[LK_PER];
+        uint64_t ibk[LK_PER];
+        uint4 rr[LK_PER];
 #pragma unroll
-    for (int j = 0; j < DEC_PER; j++) {
-        const uint32_t g = t0 + threadIdx.x + 256u * j;
-        kk[j] = g < t1 ? lookup(P.pos_begin, P.n_kernels, lk, k0, cnt, g) : k0;
-    }
-#pragma unroll
-    for (int j = 0; j < DEC_PER; j++) {
-        pbk[j] = P.pos_begin[kk[j]];
-        nkr[j] = P.pos_begin[kk[j] + 1] - pbk[j];
-        ibk[j] = P.kernels[kk[j]].instr_begin;
-    }
-#pragma unroll
-    for (int j = 0; j < DEC_PER; j++) {
-        const uint32_t g = t0 + threadIdx.x + 256u * j, i = g - pbk[j];
-        rr[j] = g < t1 && i < nkr[j] ? reinterpret_cast<const uint4 *>(P.instrs)[ibk[j] + i] : make_uint4(0, 0, 0, 0);
-    }
-#pragma unroll
-    for (int j = 0; j < DEC_PER; j++) {
-        const uint32_t g = t0 + threadIdx.x + 256u * j;
-        if (g >= t1) continue;
-        const uint32_t k = kk[j], pb = pbk[j], n = nkr[j];
-        const uint32_t i = g - pb;
-        if (i >= n) {   /* a position no kernel owns (a call whose descriptors failed their checks) */
-            P.pcap[g] = 0;
-            continue;
+        for (int j = 0; j < LK_PER; j++) {
+            const uint32_t g = tr + threadIdx.x + 256u * j;
+            kk[j] = g < t1 ? lookup(P.pos_begin, P.n_kernels, lk, k0, cnt, g) : k0;
         }
-        const uint4 r = rr[j];
-        const uint32_t op = r.x & 0xFFFFu, r0 = r.x >> 16, r1 = r.y & 0xFFFFu, r2 = r.y >> 16;
-        const int32_t imm = (int32_t)r.z, target = (int32_t)r.w;
-        const uint32_t bad = check_record(op, r0, r1, r2, imm, target, n);
-        if (i == 0) P.leader[g] = 1;
-        if (bad) {
-            P.pcap[g] = 0;
-            atomicMin(&P.kbad[k], (i << 2) | bad);
-            continue;
-        }
-        const uint64_t e = OPTAB[op];
-        const uint32_t cls = e_cls(e);
-        P.pcap[g] = (uint8_t)rec_cap(e);
-        if (ends_block(cls) && i + 1 < n) P.leader[g + 1] = 1;
-        if (cls == C_BR || cls == C_CBR) P.leader[pb + (uint32_t)target] = 1;
-        if (!P.kslots) continue;
-        /* the register slots the record names: each operand covers a run of
-         * at most four slots, in one or two bitmap words (masks computed with
-         * selects; an operand that names no slot gives empty masks) */
-        const uint32_t id[4] = {r0, r1, r2, (uint32_t)imm};
 #pragma unroll
-        for (int o = 0; o < 4; o++) {
-            const uint32_t w = e_role(e, o) != RO_NO ? e_width(e, o) : 0u;
-            const bool named = (w != 0) & (id[o] < (uint32_t)NSLOT);
-            const uint32_t first = named ? id[o] : 0u, last = named ? min(id[o] + w, (uint32_t)NSLOT) - 1u : 0u;
-            const uint32_t wa = first >> 5, wb = last >> 5;
-            const uint32_t hi_a = wa == wb ? (last & 31u) : 31u;
-            const uint32_t ma = named ? (0xFFFFFFFFu >> (31u - hi_a)) & (0xFFFFFFFFu << (first & 31u)) : 0u;
-            const uint32_t mb = named && wb != wa ? 0xFFFFFFFFu >> (31u - (last & 31u)) : 0u;
-            if (lds_marks) {   /* wave-uniform */
-                uint32_t *km_k = km + (k - k0) * KSLOT_WORDS;
-                if (ma) atomicOr(&km_k[wa], ma);
-                if (mb) atomicOr(&km_k[wb], mb);
-            } else {
-                uint32_t *ks_k = P.kslots + (uint64_t)k * KSLOT_WORDS;
-                if (ma) atomicOr(&ks_k[wa], ma);
-                if (mb) atomicOr(&ks_k[wb], mb);
+        for (int j = 0; j < LK_PER; j++) {
+            pbk[j] = P.pos_begin[kk[j]];
+            nkr[j] = P.pos_begin[kk[j] + 1] - pbk[j];
+            ibk[j] = P.kernels[kk[j]].instr_begin;
+        }
+#pragma unroll
+        for (int j = 0; j < LK_PER; j++) {
+            const uint32_t g = tr + threadIdx.x + 256u * j, i = g - pbk[j];
+            rr[j] = g < t1 && i < nkr[j] ? reinterpret_cast<const uint4 *>(P.instrs)[ibk[j] + i] : make_uint4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int j = 0; j < LK_PER; j++) {
+            const uint32_t g = tr + threadIdx.x + 256u * j;
+            if (g >= t1) continue;
+            const uint32_t k = kk[j], pb = pbk[j], n = nkr[j];
+            const uint32_t i = g - pb;
+            if (i >= n) {   /* a position no kernel owns (a call whose descriptors failed their checks) */
+                P.pcap[g] = 0;
+                continue;
+            }
+            const uint4 r = rr[j];
+            const uint32_t op = r.x & 0xFFFFu, r0 = r.x >> 16, r1 = r.y & 0xFFFFu, r2 = r.y >> 16;
+            const int32_t imm = (int32_t)r.z, target = (int32_t)r.w;
+            const uint32_t bad = check_record(op, r0, r1, r2, imm, target, n);
+            if (i == 0) P.leader[g] = 1;
+            if (bad) {
+                P.pcap[g] = 0;
+                atomicMin(&P.kbad[k], (i << 2) | bad);
+                continue;
+            }
+            const uint64_t e = OPTAB[op];
+            const uint32_t cls = e_cls(e);
+            P.pcap[g] = (uint8_t)rec_cap(e);
+            if (ends_block(cls) && i + 1 < n) P.leader[g + 1] = 1;
+            if (cls == C_BR || cls == C_CBR) P.leader[pb + (uint32_t)target] = 1;
+            if (!P.kslots) continue;
+            /* the register slots the record names: each operand covers a run of
+             * at most four slots, in one or two bitmap words (masks computed with
+             * selects; an operand that names no slot gives empty masks) */
+            const uint32_t id[4] = {r0, r1, r2, (uint32_t)imm};
+#pragma unroll
+            for (int o = 0; o < 4; o++) {
+                const uint32_t w = e_role(e, o) != RO_NO ? e_width(e, o) : 0u;
+                const bool named = (w != 0) & (id[o] < (uint32_t)NSLOT);
+                const uint32_t first = named ? id[o] : 0u, last = named ? min(id[o] + w, (uint32_t)NSLOT) - 1u : 0u;
+                const uint32_t wa = first >> 5, wb = last >> 5;
+                const uint32_t hi_a = wa == wb ? (last & 31u) : 31u;
+                const uint32_t ma = named ? (0xFFFFFFFFu >> (31u - hi_a)) & (0xFFFFFFFFu << (first & 31u)) : 0u;
+                const uint32_t mb = named && wb != wa ? 0xFFFFFFFFu >> (31u - (last & 31u)) : 0u;
+                if (lds_marks) {   /* wave-uniform */
+                    uint32_t *km_k = km + (k - k0) * KSLOT_WORDS;
+                    if (ma) atomicOr(&km_k[wa], ma);
+                    if (mb) atomicOr(&km_k[wb], mb);
+                } else {
+                    uint32_t *ks_k = P.kslots + (uint64_t)k * KSLOT_WORDS;
+                    if (ma) atomicOr(&ks_k[wa], ma);
+                    if (mb) atomicOr(&ks_k[wb], mb);
+                }
             }
         }
     }
@@ -381,25 +404,29 @@ __global__ __launch_bounds__(256) void k_number(Plan P, const uint32_t *excl) {
     const uint32_t t1 = min(P.n_pos, t0 + TILE_LK);
     uint32_t k0, cnt;
     lookup_setup(P.pos_begin, P.n_kernels, t0, t1, lk, &k0, &cnt);
-    /* a thread's DEC_PER positions (256 apart), their loads issued together
-     * (block_id may be excl itself: each position reads its entry first) */
-    uint32_t lv[DEC_PER], xv[DEC_PER];
+    /* a thread's positions in rounds of LK_PER (256 apart), each round's
+     * loads issued together (block_id may be excl itself: each position
+     * reads its entry first) */
+    for (int q = 0; q < LK_ROUNDS; q++) {
+        const uint32_t tr = t0 + 256u * LK_PER * q;
+        uint32_t lv[LK_PER], xv[LK_PER];
 #pragma unroll
-    for (int j = 0; j < DEC_PER; j++) {
-        const uint32_t g = t0 + threadIdx.x + 256u * j;
-        lv[j] = g < t1 ? P.leader[g] : 0u;
-        xv[j] = g < t1 ? excl[g] : 0u;
-    }
+        for (int j = 0; j < LK_PER; j++) {
+            const uint32_t g = tr + threadIdx.x + 256u * j;
+            lv[j] = g < t1 ? P.leader[g] : 0u;
+            xv[j] = g < t1 ? excl[g] : 0u;
+        }
 #pragma unroll
-    for (int j = 0; j < DEC_PER; j++) {
-        const uint32_t g = t0 + threadIdx.x + 256u * j;
-        if (g >= t1) continue;
-        const uint32_t l = lv[j];
-        const uint32_t id = xv[j] + l - 1;
-        P.block_id[g] = id;
-        if (l && id < P.blk_cap) {
-            P.block_start[id] = g;
-            P.block_kernel[id] = lookup(P.pos_begin, P.n_kernels, lk, k0, cnt, g);
+        for (int j = 0; j < LK_PER; j++) {
+            const uint32_t g = tr + threadIdx.x + 256u * j;
+            if (g >= t1) continue;
+            const uint32_t l = lv[j];
+            const uint32_t id = xv[j] + l - 1;
+            P.block_id[g] = id;
+            if (l && id < P.blk_cap) {
+                P.block_start[id] = g;
+                P.block_kernel[id] = lookup(P.pos_begin, P.n_kernels, lk, k0, cnt, g);
+            }
         }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0 && P.totals[0] <= P.blk_cap) P.block_start[P.totals[0]] = P.n_pos;
