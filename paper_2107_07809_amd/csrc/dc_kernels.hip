@@ -614,47 +614,64 @@ __global__ void k_order(Plan P) {
         P.n_reach[k] = 0;
         return;
     }
-    for (uint32_t b = 0; b < nb; b++) {
-        uint32_t lo = P.pred_cnt[fb + b], hi = P.pred_cnt[fb + b + 1];
-        for (uint32_t i = lo + 1; i < hi; i++) {
-            uint32_t x = P.pred[i], j = i;
-            while (j > lo && P.pred[j - 1] > x) {
-                P.pred[j] = P.pred[j - 1];
-                j--;
+    /* predecessor lists sorted (insertion sort; most have one or two
+     * entries), eight blocks' list bounds loaded together */
+    for (uint32_t b0 = 0; b0 < nb; b0 += 8) {
+        uint32_t pc[9];
+#pragma unroll
+        for (uint32_t j = 0; j < 9; j++) pc[j] = P.pred_cnt[fb + min(b0 + j, nb)];
+#pragma unroll
+        for (uint32_t j = 0; j < 8; j++) {
+            if (b0 + j >= nb) break;
+            const uint32_t lo = pc[j], hi = pc[j + 1];
+            for (uint32_t i = lo + 1; i < hi; i++) {
+                uint32_t x = P.pred[i], q = i;
+                while (q > lo && P.pred[q - 1] > x) {
+                    P.pred[q] = P.pred[q - 1];
+                    q--;
+                }
+                P.pred[q] = x;
             }
-            P.pred[j] = x;
+            P.dfs_seen[fb + b0 + j] = 0;
+            P.rpo_pos[fb + b0 + j] = -1;
         }
-        P.dfs_seen[fb + b] = 0;
-        P.rpo_pos[fb + b] = -1;
     }
-    /* explicit-stack emulation of the recursive DFS: an entry holds a block
-     * id and, in bits 31:30, the index of the next out-edge to examine */
+    /* Explicit-stack emulation of the recursive DFS.  The top entry lives in
+     * registers (block u, next out-edge e, its successor pair); an entry below
+     * it is stored as u | e << 30 and its successors are loaded again when it
+     * becomes the top.  The postorder fills rpo from the end, so that its
+     * last np entries are the reverse postorder. */
     uint32_t *stk = P.dfs_stack + fb;
-    uint32_t *post = P.rpo + fb;   /* postorder first, reversed below */
-    uint32_t sp = 0, np = 0;
-    stk[sp++] = 0;
+    uint32_t *rpo = P.rpo + fb;
+    const int2 *succ = reinterpret_cast<const int2 *>(P.succ) + fb;
+    uint32_t sp = 1, np = 0, u = 0, e = 0;
+    int2 sc = succ[0];
     P.dfs_seen[fb] = 1;
-    while (sp) {
-        const uint32_t top = stk[sp - 1];
-        const uint32_t u = top & 0x3FFFFFFFu, e = top >> 30;
+    for (;;) {
         if (e < 2) {
-            stk[sp - 1] = u | ((e + 1) << 30);
-            const int32_t s = P.succ[2 * (uint64_t)(fb + u) + e];
-            if (s >= 0 && !P.dfs_seen[fb + (uint32_t)s]) {
-                P.dfs_seen[fb + (uint32_t)s] = 1;
-                stk[sp++] = (uint32_t)s;
+            const int32_t x = e == 0 ? sc.x : sc.y;
+            e++;
+            if (x >= 0 && !P.dfs_seen[fb + (uint32_t)x]) {
+                P.dfs_seen[fb + (uint32_t)x] = 1;
+                stk[sp - 1] = u | (e << 30);
+                sp++;
+                u = (uint32_t)x;
+                e = 0;
+                sc = succ[u];
             }
         } else {
-            sp--;
-            post[np++] = u;
+            rpo[nb - 1 - np] = u;
+            np++;
+            if (--sp == 0) break;
+            const uint32_t top = stk[sp - 1];
+            u = top & 0x3FFFFFFFu;
+            e = top >> 30;
+            if (e < 2) sc = succ[u];
         }
     }
-    for (uint32_t i = 0; i < np / 2; i++) {
-        uint32_t t = post[i];
-        post[i] = post[np - 1 - i];
-        post[np - 1 - i] = t;
-    }
-    for (uint32_t i = 0; i < np; i++) P.rpo_pos[fb + post[i]] = (int32_t)i;
+    if (np < nb)
+        for (uint32_t i = 0; i < np; i++) rpo[i] = rpo[nb - np + i];
+    for (uint32_t i = 0; i < np; i++) P.rpo_pos[fb + rpo[i]] = (int32_t)i;
     P.n_reach[k] = np;
 }
 
