@@ -441,10 +441,11 @@ __global__ __launch_bounds__(256) void k_number(Plan P, const uint32_t *excl) {
 __device__ __forceinline__ uint32_t cap_pack(uint32_t c) { return (c & 1u) | (c >> 1) << 16; }
 
 __global__ __launch_bounds__(256) void k_cap_reduce(Plan P, uint32_t *sums_a, uint32_t *sums_s) {
-    const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE + (uint64_t)threadIdx.x * SCAN_ITEMS;
+    uint32_t c[SCAN_ITEMS];
+    load_items<uint8_t>(P.pcap, P.n_pos, (uint64_t)blockIdx.x * SCAN_TILE, c);
     uint32_t x = 0;
 #pragma unroll
-    for (int j = 0; j < SCAN_ITEMS; j++) x += base + j < P.n_pos ? cap_pack(P.pcap[base + j]) : 0u;
+    for (int j = 0; j < SCAN_ITEMS; j++) x += cap_pack(c[j]);
     uint32_t excl;
     const uint32_t tot = block_excl_scan(x, &excl);
     if (threadIdx.x == 0) {
@@ -456,11 +457,13 @@ __global__ __launch_bounds__(256) void k_cap_reduce(Plan P, uint32_t *sums_a, ui
 /* offs_a/offs_s: exclusive tile offsets */
 __global__ __launch_bounds__(256) void k_cap_apply(Plan P, const uint32_t *offs_a, const uint32_t *offs_s) {
     const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE + (uint64_t)threadIdx.x * SCAN_ITEMS;
-    uint32_t c[SCAN_ITEMS];
+    uint32_t c[SCAN_ITEMS], ld[SCAN_ITEMS];
+    load_items<uint8_t>(P.pcap, P.n_pos, (uint64_t)blockIdx.x * SCAN_TILE, c);
+    load_items<uint8_t>(P.leader, P.n_pos, (uint64_t)blockIdx.x * SCAN_TILE, ld);
     uint32_t x = 0;
 #pragma unroll
     for (int j = 0; j < SCAN_ITEMS; j++) {
-        c[j] = base + j < P.n_pos ? cap_pack(P.pcap[base + j]) : 0u;
+        c[j] = cap_pack(c[j]);
         x += c[j];
     }
     uint32_t excl;
@@ -468,7 +471,7 @@ __global__ __launch_bounds__(256) void k_cap_apply(Plan P, const uint32_t *offs_
     uint32_t ra = offs_a[blockIdx.x] + (excl & 0xFFFFu), rs = offs_s[blockIdx.x] + (excl >> 16);
 #pragma unroll
     for (int j = 0; j < SCAN_ITEMS; j++) {
-        if (base + j < P.n_pos && P.leader[base + j]) {
+        if (base + j < P.n_pos && ld[j]) {
             const uint32_t id = P.block_id[base + j];
             if (id < P.blk_cap) {
                 P.blk_acc_base[id] = ra;
@@ -751,26 +754,43 @@ __global__ void k_count_tail(Plan P) {
         P.sys_count[P.n_kernels] = 0;
     }
 }
-/* one thread per global block: its records, from its regions of the sparse
- * outputs to its dense offsets */
+/* the records of global blocks, from their regions of the sparse outputs to
+ * their dense offsets: a wavefront takes 64 blocks (one per lane for the
+ * counts and offsets), then copies each block's records with its 64 lanes
+ * (consecutive records on consecutive lanes) */
 __global__ __launch_bounds__(256) void k_compact(Plan P) {
     /* records that outgrew the plan: every kernel failed, nothing to copy
      * (the counts of the blocks are stale) */
     if (P.totals[0] > P.blk_cap || P.totals[1] > P.acc_cap || P.totals[2] > P.sys_cap) return;
     const uint32_t total = P.totals[0];
-    for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < total; b += gridDim.x * blockDim.x) {
-        uint32_t na = P.blk_acc[b], ns = P.blk_sys[b];
-        na = P.blk_acc_base[b] + na <= P.acc_cap && P.blk_acc_off[b] + na <= P.acc_cap ? na : 0u;
-        ns = P.blk_sys_base[b] + ns <= P.sys_cap && P.blk_sys_off[b] + ns <= P.sys_cap ? ns : 0u;
-        if (na) {
-            const uint4 *src = reinterpret_cast<const uint4 *>(P.acc_sparse) + P.blk_acc_base[b];
-            uint4 *dst = reinterpret_cast<uint4 *>(P.acc_dense) + P.blk_acc_off[b];
-            for (uint32_t i = 0; i < na; i++) dst[i] = src[i];
+    const uint32_t l = lane_id();
+    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nwaves = (gridDim.x * blockDim.x) >> 6;
+    const uint4 *acc_src = reinterpret_cast<const uint4 *>(P.acc_sparse);
+    uint4 *acc_dst = reinterpret_cast<uint4 *>(P.acc_dense);
+    const uint2 *sys_src = reinterpret_cast<const uint2 *>(P.sys_sparse);
+    uint2 *sys_dst = reinterpret_cast<uint2 *>(P.sys_dense);
+    for (uint32_t b0 = wave * 64; b0 < total; b0 += nwaves * 64) {   /* wave-uniform */
+        const uint32_t b = b0 + l;
+        uint32_t na = 0, ns = 0, sa = 0, da = 0, ss = 0, ds = 0;
+        if (b < total) {
+            na = P.blk_acc[b];
+            ns = P.blk_sys[b];
+            sa = P.blk_acc_base[b];
+            da = P.blk_acc_off[b];
+            ss = P.blk_sys_base[b];
+            ds = P.blk_sys_off[b];
+            na = sa + na <= P.acc_cap && da + na <= P.acc_cap ? na : 0u;
+            ns = ss + ns <= P.sys_cap && ds + ns <= P.sys_cap ? ns : 0u;
         }
-        if (ns) {
-            const uint2 *src = reinterpret_cast<const uint2 *>(P.sys_sparse) + P.blk_sys_base[b];
-            uint2 *dst = reinterpret_cast<uint2 *>(P.sys_dense) + P.blk_sys_off[b];
-            for (uint32_t i = 0; i < ns; i++) dst[i] = src[i];
+        for (uint64_t m = __ballot(na != 0); m; m &= m - 1) {
+            const int j = (int)__builtin_ctzll(m);
+            const uint32_t n = __shfl(na, j, 64), src = __shfl(sa, j, 64), dst = __shfl(da, j, 64);
+            for (uint32_t i = l; i < n; i += 64) acc_dst[(uint64_t)dst + i] = acc_src[(uint64_t)src + i];
+        }
+        for (uint64_t m = __ballot(ns != 0); m; m &= m - 1) {
+            const int j = (int)__builtin_ctzll(m);
+            const uint32_t n = __shfl(ns, j, 64), src = __shfl(ss, j, 64), dst = __shfl(ds, j, 64);
+            for (uint32_t i = l; i < n; i += 64) sys_dst[(uint64_t)dst + i] = sys_src[(uint64_t)src + i];
         }
     }
 }
