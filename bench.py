@@ -100,7 +100,7 @@ def cpu_baseline(cfg, n_kernels, idx, lens):
     equal share of each length stratum and is timed on the oracle alone."""
     from concurrent.futures import ProcessPoolExecutor
     avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
-    # one GPU's CPU share on the GPU boxes is 16 cores, whatever the host shows
+    # a one-GPU host grants that GPU's process 16 cores, whatever the machine shows
     cores = max(1, min(avail, 16))
     jobs = [(cfg, idx[w::cores]) for w in range(cores)]
     with ProcessPoolExecutor(cores) as ex:
