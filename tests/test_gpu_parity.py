@@ -404,6 +404,43 @@ def test_errors_do_not_poison_batch(ctx):
 
 
 
+def test_many_tiny_kernels_per_tile(ctx):
+    """Thousands of one- to three-instruction kernels (and empty ones) among a
+    few generated kernels: a 4,096-position lookup tile then holds more kernel
+    starts than its LDS cache (the per-position search in global memory) and
+    more kernels than the decode stage gathers slot marks for in LDS."""
+    rng = np.random.default_rng(5)
+    gen = dcgen.generate(2, 4, i0=300)
+    empty_args = np.zeros(0, dcgen.ARG_DTYPE)
+    end = _rec("s_endpgm")
+    smov = np.concatenate([_rec("s_mov_b32", r0=8, r1=4), end])
+    vmov = np.concatenate([_rec("v_mov_b32", r0=113, r1=112), _rec("s_mov_b32", r0=9, r1=6), end])
+    parts = []
+    for i in range(6000):
+        c = int(rng.integers(0, 10))
+        if c < 5:
+            parts.append((end, dcgen.descriptor(1), empty_args))
+        elif c < 8:
+            parts.append((smov, dcgen.descriptor(1), empty_args))
+        elif c < 9:
+            parts.append((vmov, dcgen.descriptor(2), empty_args))
+        else:
+            parts.append((np.zeros(0, dcgen.INSTR_DTYPE), dcgen.descriptor(0), empty_args))
+        if i % 1500 == 0:
+            parts.append(gen.kernel(i // 1500))
+    b = dcgen.concat(parts)
+    say(f"tiny kernels: {b.n_kernels} kernels, {b.n_instr} instructions")
+    assert b.n_kernels / max(1, b.n_instr) > 1026 / 4096
+    batch, dev = run(ctx, b, flags=dc.OPT_DIGEST)
+    res = batch.results()
+    acc, _ = batch.all_accesses()
+    sysv, _ = batch.all_sysvals()
+    s, oacc, osys = oracle.analyze_batch(b)
+    compare_summaries(res, s)
+    assert acc.tobytes() == oacc.tobytes() and sysv.tobytes() == osys.tobytes()
+    batch.free()
+
+
 def _nops_like(b):
     """Records of the same layout as b's (every kernel as long as b's) but
     each kernel one straight block of s_nop closed by s_endpgm: one block and
