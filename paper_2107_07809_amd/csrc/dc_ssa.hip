@@ -409,47 +409,67 @@ __global__ __launch_bounds__(64) void k_ssa_emit(Plan P, SsaPlan S) {
     if (DIGEST)
         for (uint32_t b = l; b < nb; b += 64) h += ssa_item(1, b, idom[b]);
 
-    /* merges (ascending block, then slot) and their arguments */
+    /* merges (ascending block, then slot) and their arguments.  Blocks go in
+     * groups of 64: lane l first finds whether block b0 + l is reachable and
+     * how many arguments its merges take (its reachable predecessors, plus the
+     * entry for block 0); the blocks of the group then run in order, each
+     * loading its table row (all columns at once) before emitting. */
     uint32_t np = 0, na = 0;
-    for (uint32_t b = 0; b < nb; b++) {
-        if (pos[b] < 0) continue;
-        uint32_t inc = b == 0 ? 1u : 0u;
-        for (uint32_t e = poff[b]; e < poff[b + 1]; e++) inc += pos[P.pred[e]] >= 0 ? 1u : 0u;
-        const uint64_t row = (uint64_t)b * U;
-        const uint32_t np_b = np;
-        for (uint32_t g = 0; g < G; g++) {
-            const uint32_t u = l + 64 * g;
-            const uint32_t a = u < U ? A[row + u] : 0u;
-            const bool ph = u < U && (a & PHI_BIT);
-            const uint64_t m = ballot(ph);
-            if (ph) {
-                const uint32_t idx = np + lanes_below(m), v = s_slot[u], ver = a & ~PHI_BIT;
-                dc_phi_t f;
-                f.block = b;
-                f.slot = (uint16_t)v;
-                f.pad = 0;
-                f.version = ver;
-                S.phis[po + idx] = f;
-                if (DIGEST) h += ssa_item(2, ((uint64_t)b << 16) | v, ver);
-                uint32_t *arg = S.phi_args + ao + na + (uint64_t)(idx - np_b) * inc;
-                uint32_t kk = 0;
-                if (b == 0) {
-                    arg[0] = 0;
-                    if (DIGEST) h += ssa_item(3, ((uint64_t)b << 24) | ((uint64_t)v << 12), 0);
-                    kk = 1;
-                }
-                for (uint32_t e = poff[b]; e < poff[b + 1]; e++) {
-                    const uint32_t p = P.pred[e];
-                    if (pos[p] < 0) continue;
-                    const uint32_t x = Bt[(uint64_t)p * U + u];
-                    arg[kk] = x;
-                    if (DIGEST) h += ssa_item(3, ((uint64_t)b << 24) | ((uint64_t)v << 12) | kk, x);
-                    kk++;
-                }
+    for (uint32_t b0 = 0; b0 < nb; b0 += 64) {
+        const uint32_t bl = b0 + l;
+        const bool rl = bl < nb && pos[bl < nb ? bl : 0] >= 0;
+        uint32_t incl = bl == 0 ? 1u : 0u;
+        if (rl)
+            for (uint32_t e = poff[bl]; e < poff[bl + 1]; e++) incl += pos[P.pred[e]] >= 0 ? 1u : 0u;
+        const uint64_t rm = ballot(rl);
+        const uint32_t bend = nb - b0 < 64u ? nb : b0 + 64u;
+        for (uint32_t b = b0; b < bend; b++) {
+            if (!((rm >> (b - b0)) & 1ull)) continue;
+            const uint32_t inc = (uint32_t)__shfl((int)incl, (int)(b - b0), 64);
+            const uint64_t row = (uint64_t)b * U;
+            const uint32_t np_b = np;
+            uint32_t av[SSA_G];
+#pragma unroll
+            for (uint32_t g = 0; g < SSA_G; g++) {
+                const uint32_t u = l + 64 * g;
+                av[g] = g < G && u < U ? A[row + u] : 0u;
             }
-            np += (uint32_t)__popcll(m);
+#pragma unroll
+            for (uint32_t g = 0; g < SSA_G; g++) {
+                if (g >= G) break;
+                const uint32_t u = l + 64 * g;
+                const uint32_t a = av[g];
+                const bool ph = u < U && (a & PHI_BIT);
+                const uint64_t m = ballot(ph);
+                if (ph) {
+                    const uint32_t idx = np + lanes_below(m), v = s_slot[u], ver = a & ~PHI_BIT;
+                    dc_phi_t f;
+                    f.block = b;
+                    f.slot = (uint16_t)v;
+                    f.pad = 0;
+                    f.version = ver;
+                    S.phis[po + idx] = f;
+                    if (DIGEST) h += ssa_item(2, ((uint64_t)b << 16) | v, ver);
+                    uint32_t *arg = S.phi_args + ao + na + (uint64_t)(idx - np_b) * inc;
+                    uint32_t kk = 0;
+                    if (b == 0) {
+                        arg[0] = 0;
+                        if (DIGEST) h += ssa_item(3, ((uint64_t)b << 24) | ((uint64_t)v << 12), 0);
+                        kk = 1;
+                    }
+                    for (uint32_t e = poff[b]; e < poff[b + 1]; e++) {
+                        const uint32_t p = P.pred[e];
+                        if (pos[p] < 0) continue;
+                        const uint32_t x = Bt[(uint64_t)p * U + u];
+                        arg[kk] = x;
+                        if (DIGEST) h += ssa_item(3, ((uint64_t)b << 24) | ((uint64_t)v << 12) | kk, x);
+                        kk++;
+                    }
+                }
+                np += (uint32_t)__popcll(m);
+            }
+            na += (np - np_b) * inc;
         }
-        na += (np - np_b) * inc;
     }
 
     /* every operand's version, block by block in index order */
