@@ -77,6 +77,44 @@ def test_edge_texts(ctx):
         t.free()
 
 
+def test_operand_word_edge_cases(ctx):
+    """The operand text split into words and fields: empty fields, trailing
+    and doubled commas, tabs, extra words inside a field, modifiers alone or
+    between operands, offsets in hex, negative or malformed, comments after
+    operands, blank-separated operands with a modifier."""
+    body = [
+        "v_add_u32 v1, , v3",
+        "v_add_u32 v1,v2,v3,",
+        "v_add_u32 v1,, v2, v3",
+        "v_add_u32\tv1,\tv2 ,\t v3",
+        "v_add_u32 v1 extra, v2 more words, v3",
+        "global_load_dword v1, v[2:3], off offset:0x10",
+        "global_load_dword v1, v[2:3], off offset:-4",
+        "global_load_dword v1, v[2:3], off offset:abc",
+        "global_load_dword v1, v[2:3], off offset:",
+        "global_load_dword v1, v[2:3], off glc offset:8 slc",
+        "global_store_dword v[2:3], v1, off offset:4 // comment, with a comma",
+        "s_load_dwordx2 s[2:3] s[4:5] 0x0",
+        "s_load_dwordx2 s[2:3] s[4:5] 0x8 ; trailing",
+        "ds_read_b32 v1, v2 offset:16",
+        "ds_write_b32 v2, v1 offset:65536",
+        "v_mov_b32 v1 , v0",
+        "v_mov_b32 , v0",
+        "v_mov_b32",
+        "s_mov_b32 s0, 0x7fffffff",
+        "s_mov_b32 s0, -17",
+        "s_mov_b32 s0, 64",
+        "s_mov_b32 s0, 65",
+        "v_mad_u32_u24 v1, v2, v3, v4",
+        "v_add_co_u32 v1, vcc, v2, v3",
+        "s_endpgm",
+    ]
+    text = (".kernel k\n.config\n.dims x\n.cws 64, 1, 1\n.arg _.global_offset_0, \"size_t\", long\n"
+            ".arg a, \"int*\", int*\n.text\n" + "\n".join("  " + x for x in body) + "\n").encode()
+    t, _, _ = compare(ctx, text, "operand words")
+    t.free()
+
+
 def test_rendered_workloads(ctx):
     """The small workload, a log-uniform sample, Zipf kernels with long ones,
     the dense control-flow shape (thousands of labels per kernel) and the
